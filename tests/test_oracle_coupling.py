@@ -1,0 +1,144 @@
+"""Pins of the oracle's coupling physics (Secs. 2.3.1-2.3.5): VIBB, momentum
+exchange, refilling and the near-contact treatments, against invariants and
+classical Stokes-flow results."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2206_11634_amd import workloads as W
+from paper_2206_11634_amd.workloads import Shape
+
+E19 = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+                (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+                (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], float)
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _feq(i, rho, u):
+    eu = E19[i] @ u
+    return W19[i] * rho * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u @ u))
+
+
+def _ball(r, pos, omega=None, vel=None):
+    sh = Shape(pts=np.zeros((1, 3)), K=np.array([r * r]), c0=1.0, rs=0.0,
+               volume=4 / 3 * np.pi * r ** 3, inertia_unit=np.ones(3), radius=r)
+    return W.make_particles([sh], pos, [1, 0, 0, 0], 1.0,
+                            omega=None if omega is None else np.asarray(omega)[None],
+                            vel=None if vel is None else np.asarray(vel)[None])
+
+
+def test_vibb_matches_geometric_interpolation():
+    """The closed-form VIBB coefficients are the linear inter/extrapolation,
+    at the departure point x_d = 2q - 1 (x_ff at -1, x_f at 0, wall at q), of
+    rho, u and fneq; u_d blends the two velocity estimates 1/3 : 2/3."""
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        d = int(rng.integers(1, 19))
+        db = d + 1 if d % 2 == 1 else d - 1
+        q = float(rng.uniform(0.01, 1.0))
+        rho_f, rho_ff = rng.uniform(0.95, 1.05, 2)
+        u_f, u_ff, uw = (rng.uniform(-0.05, 0.05, 3) for _ in range(3))
+        fd_f = _feq(d, rho_f, u_f) * (1 + 0.01 * rng.standard_normal())
+        fd_ff = _feq(d, rho_ff, u_ff) * (1 + 0.01 * rng.standard_normal())
+        xd = 2 * q - 1
+        if xd <= 0:
+            ustar = np.array([np.interp(xd, [-1, 0], [u_ff[a], u_f[a]]) for a in range(3)])
+            rho_d = np.interp(xd, [-1, 0], [rho_ff, rho_f])
+        else:
+            ustar = np.array([np.interp(xd, [0, q], [u_f[a], uw[a]]) for a in range(3)])
+            rho_d = rho_f
+        u2 = np.array([np.interp(xd, [-1, q], [u_ff[a], uw[a]]) for a in range(3)])
+        ud = ustar / 3 + 2 * u2 / 3
+        line = np.polyfit([-1.0, 0.0], [fd_ff - _feq(d, rho_ff, u_ff), fd_f - _feq(d, rho_f, u_f)], 1)
+        fneq = np.polyval(line, xd)
+        expect = _feq(d, rho_d, ud) + fneq + 6 * W19[d] * rho_f * (E19[db] @ uw)
+        got = O.vibb(d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw)
+        assert abs(got - expect) < 1e-14, (d, q)
+
+
+def test_comoving_particles_leave_uniform_flow_exact():
+    """Uniform flow f = feq(1, U) with particles translating at U: VIBB, the
+    moving-wall bounce-back and both refilling rules return feq(1, U), so the
+    populations stay exact and the momentum-exchange forces vanish."""
+    U = np.array([0.03, -0.02, 0.015])
+    lat, ps = W.tiny_case(7, dims=(20, 18, 16), periodic=(1, 1, 1), n_particles=2,
+                          diameter_range=(4, 6), u0=tuple(U), allow_near=False)
+    ps.vel[:] = U
+    ps.omega[:] = 0
+    o = O.Oracle(lat)
+    P = W.prescribed_state(ps, lat, 0.0)
+    o.classify(P)
+    f0 = o.f[:, 0].copy()
+    refilled = 0
+    for n in range(40):
+        F, T = o.step(P)
+        assert np.abs(F).max() < 1e-13
+        P = W.prescribed_state(ps, lat, n + 1.0)
+        o.classify(P)
+        refilled += len(o.refill_nodes)
+        fl = o.owner == 0
+        assert np.abs(o.f[:, fl] - f0[:, None]).max() < 1e-14
+    assert refilled > 20
+
+
+def test_missing_force_points_restore_isotropy_near_wall_and_particle():
+    """Particles at rest in fluid at rest, one 0.3 lu from a wall and the other
+    0.4 lu above it: with treatment 2 every lattice line through a body enters
+    and leaves it once, so F = T = 0 to rounding; without it the wall side
+    loses force points and a spurious force appears."""
+    sh1, sh2 = W.sphere_shape(8.0, 0.1), W.sphere_shape(7.0, 0.1)
+    lat = W.LatticeSpec(24, 20, 20, (1, 1, 0), tau=0.7)
+    pos = np.array([[10.2, 9.7, -0.5 + 4 + 0.3], [10.6, 9.9, 3.8 + 4 + 3.5 + 0.4]])
+    ps = W.make_particles([sh1, sh2], pos, np.array([[1, 0, 0, 0], [1, 0, 0, 0.]]), 1.5)
+    o = O.Oracle(lat, treat=O.TREAT_VIBB | O.TREAT_MISSING)
+    o.classify(ps)
+    assert np.all(np.bincount(o.links.kind, minlength=3) > 0)
+    F, T = o.step(ps)
+    assert np.abs(F).max() < 1e-13 and np.abs(T).max() < 1e-13
+    o2 = O.Oracle(lat, treat=O.TREAT_VIBB)
+    o2.classify(ps)
+    F2, _ = o2.step(ps)
+    assert np.abs(F2).max() > 0.1
+
+
+@pytest.mark.slow
+def test_hasimoto_drag_periodic_sphere_array():
+    """Fixed sphere (d = 10) in a periodic 32^3 cell driven by a body force:
+    drag / (6 pi mu a U) against Hasimoto's periodic-array factor, with U the
+    superficial velocity."""
+    L, r, tau, g = 32, 5.0, 0.8, 1e-6
+    nu = (tau - 0.5) / 3
+    phi = 4 / 3 * np.pi * r ** 3 / L ** 3
+    K = 1 / (1 - 1.7601 * phi ** (1 / 3) + phi - 1.5593 * phi ** 2 + 3.9799 * phi ** (8 / 3)
+             - 3.0734 * phi ** (10 / 3))
+    U_guess = g * (L ** 3 - 4 / 3 * np.pi * r ** 3) / (6 * np.pi * nu * r * K)
+    lat = W.LatticeSpec(L, L, L, (1, 1, 1), tau=tau, body_force=(g, 0, 0), u0=(U_guess, 0, 0))
+    ps = _ball(r, [L / 2 + 0.13, L / 2 - 0.21, L / 2 + 0.07])
+    o = O.Oracle(lat)
+    o.classify(ps)
+    for _ in range(1500):
+        F, _ = o.step(ps)
+    rho, u = o.moments()
+    fl = o.owner == 0
+    U = (rho[fl] * u[fl, 0]).sum() / L ** 3
+    ratio = F[0, 0] / (6 * np.pi * nu * r * U) / K
+    assert abs(ratio - 1) < 0.03, ratio
+    assert abs(F[0, 1]) < 1e-3 * F[0, 0] and abs(F[0, 2]) < 1e-3 * F[0, 0]
+
+
+@pytest.mark.slow
+def test_rotating_sphere_stokes_torque():
+    """Sphere (d = 10) spinning in place in fluid at rest: torque close to
+    Stokes' -8 pi mu a^3 omega (a periodic cell adds about 1-2%)."""
+    L, r, tau = 32, 5.0, 0.8
+    nu = (tau - 0.5) / 3
+    w = np.array([0.0, 0.0, 2e-4])
+    lat = W.LatticeSpec(L, L, L, (1, 1, 1), tau=tau)
+    ps = _ball(r, [L / 2 + 0.13, L / 2 - 0.21, L / 2 + 0.07], omega=w)
+    o = O.Oracle(lat)
+    o.classify(ps)
+    for _ in range(1000):
+        F, T = o.step(ps)
+    ratio = T[0, 2] / (-8 * np.pi * nu * r ** 3 * w[2])
+    assert 1.0 < ratio < 1.03, ratio
+    assert np.abs(T[0, :2]).max() < 1e-3 * abs(T[0, 2])
