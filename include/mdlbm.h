@@ -1,0 +1,232 @@
+/*
+ * mdlbm.h -- C-ABI of the MI355X (gfx950) library for the per-timestep
+ * lattice update of the coupled metaball-DEM / lattice Boltzmann method with a
+ * sharp interface (Zhang et al., arXiv 2206.11634).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  * Lattice units: dx = dt = 1, c_s^2 = 1/3, nu = (tau - 1/2)/3 (Sec. 2.2).
+ *  * Lattice D3Q19, directions numbered
+ *      0:(0,0,0) 1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1)
+ *      6:(0,0,-1) 7:(+1,+1,0) 8:(-1,-1,0) 9:(+1,-1,0) 10:(-1,+1,0)
+ *      11:(+1,0,+1) 12:(-1,0,-1) 13:(+1,0,-1) 14:(-1,0,+1) 15:(0,+1,+1)
+ *      16:(0,-1,-1) 17:(0,+1,-1) 18:(0,-1,+1);  opposite of odd i is i + 1.
+ *  * Node (i,j,k) sits at coordinates (i,j,k); cell index i + nx*(j + ny*k).
+ *    A non-periodic axis ends in no-slip walls half a cell outside the first
+ *    and last node (static halfway bounce-back).
+ *  * Population planes are structure-of-arrays: plane i of a buffer starts at
+ *    element i * cell_stride (lbm_sizes.cell_stride), x fastest.
+ *  * Every pointer named *_dev is device memory owned by the caller, unless
+ *    the entry point says otherwise.  The caller keeps it alive for as long as
+ *    the context may use it.  The library owns only its context and the small
+ *    scratch it allocates in lbm_init and frees in lbm_destroy (link and refill
+ *    lists, per-particle sums, contact histories).
+ *  * Work is enqueued on the stream given in lbm_config.stream and is
+ *    asynchronous unless an entry point says it synchronises.
+ *  * Every call returns an lbm_status.  Nothing is thrown across the ABI;
+ *    lbm_last_error() returns a message for the last failure.
+ *  * Particles are described by device arrays in FP64 (lbm_particles).  A
+ *    particle's body is {x : M(x) >= c0} with M the metaball function of
+ *    Eq. (metaball), M(x) = sum_i K_i / |x - x_i|^2 over its control points.
+ */
+#ifndef MDLBM_H
+#define MDLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,    /* an argument is out of range or inconsistent */
+    LBM_ENOMEM = 2,    /* the library could not allocate its scratch */
+    LBM_ECAPACITY = 3, /* a caller-provided output is too small */
+    LBM_ENUMERIC = 4,  /* non-finite values detected */
+    LBM_EDEVICE = 5,   /* a HIP runtime call or kernel launch failed */
+    LBM_ESTATE = 6     /* call out of order, or context in a failed state */
+} lbm_status;
+
+typedef enum {
+    LBM_STORE_F64 = 0, /* f_i in double; collision in double (plain method) */
+    LBM_STORE_F32 = 1, /* deviations f_i - w_i in float; float arithmetic */
+    LBM_STORE_F16 = 2  /* deviations (f_i - w_i) * h16_scale in half; float arithmetic */
+} lbm_storage;
+
+typedef enum {
+    LBM_TREAT_VIBB = 1,   /* velocity-interpolated bounce-back (Sec. 2.3.1); without
+                             it every cut link uses halfway bounce-back */
+    LBM_TREAT_MISSING = 2 /* treatment 2 of Sec. 2.3.5: momentum exchange on
+                             force points covered by another body or a wall */
+} lbm_treatment;
+
+typedef enum {
+    LBM_LINK_VIBB = 0,    /* x_f and x_ff fluid: VIBB reconstruction */
+    LBM_LINK_HALFWAY = 1, /* x_f fluid, x_ff not: halfway bounce-back (treatment 1) */
+    LBM_LINK_MISSING = 2  /* x_n covered: force-only missing point (treatment 2) */
+} lbm_link_kind;
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t periodic[3];   /* non-zero: periodic axis; zero: walls */
+    double tau;            /* BGK relaxation time, > 1/2 */
+    double rho0;           /* reference density (refill and treatment 2) */
+    double u0[3];          /* initial uniform velocity */
+    double body_force[3];  /* fluid body-force density (Guo forcing); 0 in the paper */
+    int32_t storage;       /* lbm_storage */
+    int32_t treatments;    /* bitmask of lbm_treatment */
+    int32_t n_particles;   /* number of particles (0 allowed) */
+    int32_t n_ctrl;        /* total control points over all particles */
+    int32_t box_half;      /* h: each particle's nodes lie within distance h-1 of its
+                              centre; bounds the per-particle node box */
+    double h16_scale;      /* scale of FP16 deviations (0: default 1024) */
+    void* stream;          /* hipStream_t, NULL for the null stream */
+} lbm_config;
+
+typedef struct {
+    int64_t ncell;             /* nx*ny*nz */
+    int64_t cell_stride;       /* elements between population planes (>= ncell) */
+    size_t population_bytes;   /* bytes of ONE population buffer (two are needed) */
+    size_t owner_bytes;        /* bytes of ONE owner plane (two are needed), uint32 */
+    size_t flag_bytes;         /* bytes of the fluid/solid flag plane, uint8 */
+} lbm_sizes;
+
+typedef struct {
+    void* f_dev[2];            /* two population buffers, population_bytes each */
+    uint32_t* owner_dev[2];    /* two owner planes, owner_bytes each */
+    uint8_t* flag_dev;         /* flag plane, flag_bytes */
+} lbm_buffers;
+
+/* Particle state, all device arrays in FP64 unless noted.  n_ctrl = ctrl_off[n]. */
+typedef struct {
+    int32_t n;
+    const int32_t* ctrl_off;  /* int32[n+1]: control points of particle p are
+                                 ctrl_off[p] .. ctrl_off[p+1]-1 */
+    const double* body_pts;   /* [n_ctrl][3] control points in the principal body
+                                 frame, origin at the centroid */
+    const double* K;          /* [n_ctrl] metaball weights, > 0 */
+    const double* c0;         /* [n] surface level of the fluid-side body */
+    const double* rs;         /* [n] sphero radius R_s of the DEM contact surface */
+    const double* mass;       /* [n] */
+    const double* volume;     /* [n] (relative gravity (m - rho_f V) g) */
+    const double* inertia;    /* [n][3] principal moments */
+    double* pos;              /* [n][3] centroid x_p; in [0, n) on periodic axes */
+    double* quat;             /* [n][4] (w,x,y,z) body -> world */
+    double* vel;              /* [n][3] */
+    double* omega;            /* [n][3] world-frame angular velocity */
+    double* world_pts;        /* [n_ctrl][3] world control points x_i; read by
+                                 lbm_classify_nodes, refreshed by dem_step */
+} lbm_particles;
+
+typedef struct {
+    int64_t n_links;    /* VIBB + HALFWAY + MISSING links of the classification */
+    int64_t n_refill;   /* nodes solid at the previous and fluid at this classification */
+    int64_t n_solid_changed; /* reserved, 0 */
+} lbm_counts;
+
+typedef struct {
+    double kn, eta_n;        /* normal spring stiffness and damping (Sec. 2.1.1) */
+    double kt, eta_t, mu_s;  /* tangential spring, damping, friction coefficient */
+    double ctol;             /* lower bound on M at the contact search point (Eq. opt) */
+    double newton_tol;       /* Newton step tolerance (lattice units) */
+    int32_t newton_iter;     /* Newton iteration limit */
+    double gravity[3];       /* g; particles feel (m - rho_f V) g (Sec. 3.1) */
+    double rho_f;            /* fluid density for the relative gravity */
+} dem_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Sizes of the caller-owned buffers for cfg.  Host only; no device work.
+ * EINVAL when a dimension is < 1. */
+int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out);
+
+/* Create a context for cfg on the current HIP device and initialise the
+ * populations of bufs->f_dev[0] to the equilibrium f_eq(rho0, u0) (Sec. 2.2),
+ * the owner planes to "fluid" and the flags to fluid.  Allocates the library's
+ * scratch (ENOMEM on failure).  EINVAL on tau <= 1/2, a dimension < 1, a null
+ * buffer, an unknown storage, box_half < 2, a periodic axis shorter than
+ * 2*box_half + 5 nodes, or n_particles >= 65535.  Synchronises the stream. */
+int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out);
+
+/* Release the context and the library's scratch (never the caller's buffers). */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the last failure on ctx (or of the last lbm_init when ctx is
+ * NULL).  The string lives until the next call on the same context. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Node classification, link sets and local refilling (Secs. 2.3.1, 2.3.3,
+ * 2.3.5) for the particle state P, in FP64:
+ *  * owner(x) = lowest p with M_p(x) >= c0_p, else fluid;
+ *  * a link (x_s, d, p) for every node x_s of p and direction d whose
+ *    neighbour x_n = x_s - e_d is fluid (VIBB when x_ff = x_n - e_d is fluid
+ *    too and VIBB is on, else HALFWAY), or is covered by another particle or
+ *    lies beyond a wall with M_p(x_n) < c0_p (MISSING, when treatment 2 is on);
+ *    q = (c0 - M(x_n)) / (M(x_s) - M(x_n)) (Eq. appq);
+ *  * every node solid at the previous classification and fluid now is refilled
+ *    (Sec. 2.3.3) from the populations of its fluid neighbours at the previous
+ *    time level, with u_new = v + omega x (x_new - x_p) of the particle that
+ *    covered it, then collided; the first call after lbm_init refills nothing.
+ * Coordinates on a periodic axis are taken at the image nearest x_p.
+ * Synchronises the stream to report counts (out may be NULL).  EINVAL when a
+ * particle's body reaches beyond box_half, K <= 0, or x_p lies outside
+ * [0, n) on a periodic axis; the previous classification then stays in force. */
+int lbm_classify_nodes(lbm_ctx* ctx, const lbm_particles* P, lbm_counts* out);
+
+/* One lattice step n -> n+1 on the links of the last classification:
+ * VIBB (Eqs. eqneq, neqd, rhod, u_d) or halfway reconstruction of the unknown
+ * populations, Galilean-invariant momentum exchange force and torque per
+ * particle (Eq. mem, and Eqs. fh_s_issue / th_s_issue for missing points),
+ * then fused pull-streaming and BGK collision (Eq. lbm_collide, with Guo
+ * forcing for body_force) of every fluid node.  Wall velocities come from
+ * P->vel, P->omega and P->pos.  Asynchronous. */
+int lbm_step(lbm_ctx* ctx, const lbm_particles* P);
+
+/* Copy the force F^h and torque T^h (FP64, [n][3] each, device pointers) of
+ * the last lbm_step into F_dev and T_dev.  Asynchronous. */
+int lbm_particle_forces(const lbm_ctx* ctx, double* F_dev, double* T_dev);
+
+/* n_sub velocity-Verlet substeps of length dt of the metaball DEM (Sec. 2.1)
+ * with F^h, T^h of the last lbm_step frozen (sub-cycling, Sec. 2.3.4),
+ * relative gravity, metaball-metaball and metaball-wall contacts with a
+ * linear spring-dashpot normal force and a Coulomb-limited tangential spring.
+ * Updates P->pos, quat, vel, omega and world_pts in place and the contact
+ * histories held by the context.  EINVAL on n_sub < 1 or dt <= 0.
+ * Asynchronous. */
+int dem_step(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_params* prm);
+
+/* ---- inspection (tests and tools) --------------------------------------- */
+
+/* Links of the last classification, in an unspecified order, into device
+ * arrays of capacity cap; *n_out (host) receives the count.  ECAPACITY when
+ * cap is too small (nothing written, *n_out still set).  Synchronises. */
+int lbm_get_links(const lbm_ctx* ctx, int64_t cap, int32_t* node_dev, int8_t* d_dev,
+                  int8_t* kind_dev, int32_t* part_dev, double* q_dev, int64_t* n_out);
+
+/* Nodes refilled by the last classification (unspecified order) and the
+ * particle that had covered each.  Same capacity rules as lbm_get_links. */
+int lbm_get_refill(const lbm_ctx* ctx, int64_t cap, int32_t* node_dev, int32_t* part_dev,
+                   int64_t* n_out);
+
+/* Owner of every node at the last classification: 0 fluid, p+1 particle p
+ * (int32, ncell entries).  Asynchronous. */
+int lbm_get_owner(const lbm_ctx* ctx, int32_t* owner_dev);
+
+/* Current post-collision populations as FP64 f_i (not deviations), Q planes of
+ * ncell (x fastest) into f_dev.  Asynchronous. */
+int lbm_get_populations(const lbm_ctx* ctx, double* f_dev);
+
+/* Overwrite the current populations from FP64 f_i planes (rounded to the
+ * storage format).  Asynchronous. */
+int lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
+
+/* Block until the context's stream has drained; EDEVICE on a device error. */
+int lbm_synchronize(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLBM_H */

@@ -1,0 +1,344 @@
+"""ctypes binding of libmdlbm (include/mdlbm.h).
+
+Argument marshalling only: every step of the lattice update runs in the HIP
+library.  Device memory comes from PyTorch (ROCm build) and work is enqueued
+on torch's current stream.  Loading fails loudly when the library has not been
+built or no GPU is present; there is no CPU fallback.
+
+Module-level functions carry the C-ABI names (lbm_init, lbm_classify_nodes,
+lbm_step, lbm_particle_forces, dem_step, ...); the `Lattice` and
+`DeviceParticles` classes hold the buffers those calls need.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libmdlbm.so"
+Q = 19
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ECAPACITY, LBM_ENUMERIC, LBM_EDEVICE, LBM_ESTATE = range(7)
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+TREAT_VIBB, TREAT_MISSING = 1, 2
+LINK_VIBB, LINK_HALFWAY, LINK_MISSING = 0, 1, 2
+
+_P = ctypes.c_void_p
+
+
+class LbmConfig(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("periodic", ctypes.c_int32 * 3), ("tau", ctypes.c_double),
+                ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 3),
+                ("body_force", ctypes.c_double * 3), ("storage", ctypes.c_int32),
+                ("treatments", ctypes.c_int32), ("n_particles", ctypes.c_int32),
+                ("n_ctrl", ctypes.c_int32), ("box_half", ctypes.c_int32),
+                ("h16_scale", ctypes.c_double), ("stream", _P)]
+
+
+class LbmSizes(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_int64), ("cell_stride", ctypes.c_int64),
+                ("population_bytes", ctypes.c_size_t), ("owner_bytes", ctypes.c_size_t),
+                ("flag_bytes", ctypes.c_size_t)]
+
+
+class LbmBuffers(ctypes.Structure):
+    _fields_ = [("f_dev", _P * 2), ("owner_dev", _P * 2), ("flag_dev", _P)]
+
+
+class LbmParticles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ctrl_off", _P), ("body_pts", _P), ("K", _P),
+                ("c0", _P), ("rs", _P), ("mass", _P), ("volume", _P), ("inertia", _P),
+                ("pos", _P), ("quat", _P), ("vel", _P), ("omega", _P), ("world_pts", _P)]
+
+
+class LbmCounts(ctypes.Structure):
+    _fields_ = [("n_links", ctypes.c_int64), ("n_refill", ctypes.c_int64),
+                ("n_solid_changed", ctypes.c_int64)]
+
+
+class DemParams(ctypes.Structure):
+    _fields_ = [("kn", ctypes.c_double), ("eta_n", ctypes.c_double), ("kt", ctypes.c_double),
+                ("eta_t", ctypes.c_double), ("mu_s", ctypes.c_double), ("ctol", ctypes.c_double),
+                ("newton_tol", ctypes.c_double), ("newton_iter", ctypes.c_int32),
+                ("gravity", ctypes.c_double * 3), ("rho_f", ctypes.c_double)]
+
+    @classmethod
+    def make(cls, kn=0.0, eta_n=0.0, kt=0.0, eta_t=0.0, mu_s=0.3, ctol=1e-3, newton_tol=1e-12,
+             newton_iter=50, gravity=(0.0, 0.0, 0.0), rho_f=1.0):
+        return cls(kn, eta_n, kt, eta_t, mu_s, ctol, newton_tol, newton_iter,
+                   (ctypes.c_double * 3)(*gravity), rho_f)
+
+
+EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_classify_nodes",
+           "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
+           "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize"]
+
+_lib = None
+
+
+def load(path: Path | None = None):
+    """Load the built library (no compute).  Raises when it is missing."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is not built; run `python -m paper_2206_11634_amd.build` "
+                           "(the lattice update has no CPU fallback)")
+    L = ctypes.CDLL(str(p))
+    sig = {
+        "lbm_query_sizes": [ctypes.POINTER(LbmConfig), ctypes.POINTER(LbmSizes)],
+        "lbm_init": [ctypes.POINTER(LbmConfig), ctypes.POINTER(LbmBuffers), ctypes.POINTER(_P)],
+        "lbm_destroy": [_P],
+        "lbm_classify_nodes": [_P, ctypes.POINTER(LbmParticles), ctypes.POINTER(LbmCounts)],
+        "lbm_step": [_P, ctypes.POINTER(LbmParticles)],
+        "lbm_particle_forces": [_P, _P, _P],
+        "dem_step": [_P, ctypes.POINTER(LbmParticles), ctypes.c_int, ctypes.c_double,
+                     ctypes.POINTER(DemParams)],
+        "lbm_get_links": [_P, ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)],
+        "lbm_get_refill": [_P, ctypes.c_int64, _P, _P, ctypes.POINTER(ctypes.c_int64)],
+        "lbm_get_owner": [_P, _P],
+        "lbm_get_populations": [_P, _P],
+        "lbm_set_populations": [_P, _P],
+        "lbm_synchronize": [_P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.lbm_last_error.argtypes = [_P]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    if path is None:
+        _lib = L
+    return L
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmdlbm status {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, ctx=None):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error(ctx)
+        raise LbmError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libmdlbm needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- C-ABI wrappers (same names) -------------------------------------------
+
+def lbm_query_sizes(cfg: LbmConfig) -> LbmSizes:
+    out = LbmSizes()
+    _check(load().lbm_query_sizes(ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def lbm_init(cfg: LbmConfig, bufs: LbmBuffers):
+    ctx = _P()
+    _check(load().lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm_destroy(ctx):
+    _check(load().lbm_destroy(ctx))
+
+
+def lbm_classify_nodes(ctx, parts: LbmParticles) -> LbmCounts:
+    out = LbmCounts()
+    _check(load().lbm_classify_nodes(ctx, ctypes.byref(parts), ctypes.byref(out)), ctx)
+    return out
+
+
+def lbm_step(ctx, parts: LbmParticles):
+    _check(load().lbm_step(ctx, ctypes.byref(parts)), ctx)
+
+
+def lbm_particle_forces(ctx, F, T):
+    _check(load().lbm_particle_forces(ctx, _ptr(F), _ptr(T)), ctx)
+
+
+def dem_step(ctx, parts: LbmParticles, n_sub: int, dt: float, prm: DemParams):
+    _check(load().dem_step(ctx, ctypes.byref(parts), int(n_sub), float(dt), ctypes.byref(prm)),
+           ctx)
+
+
+def lbm_synchronize(ctx):
+    _check(load().lbm_synchronize(ctx), ctx)
+
+
+# ---- buffers -----------------------------------------------------------------
+
+class DeviceParticles:
+    """FP64 device copies of a particle set, in the layout of lbm_particles."""
+
+    FIELDS = ("body_pts", "K", "c0", "rs", "mass", "volume", "inertia", "pos", "quat", "vel",
+              "omega", "world_pts")
+
+    def __init__(self, ps, device="cuda"):
+        torch = _torch()
+        self.n = ps.n
+        self.device = device
+        self.t = {"ctrl_off": torch.as_tensor(np.ascontiguousarray(ps.ctrl_off, np.int32),
+                                              device=device)}
+        for k in self.FIELDS:
+            a = np.ascontiguousarray(getattr(ps, k), np.float64)
+            if a.size == 0:
+                a = np.zeros(1)
+            self.t[k] = torch.as_tensor(a, device=device).contiguous()
+        self.struct = LbmParticles(ps.n, *[_ptr(self.t[k]) for k in ("ctrl_off",) + self.FIELDS])
+
+    def set_state(self, ps):
+        torch = _torch()
+        for k in ("pos", "quat", "vel", "omega", "world_pts"):
+            a = np.ascontiguousarray(getattr(ps, k), np.float64)
+            if a.size:
+                self.t[k].copy_(torch.as_tensor(a).reshape(self.t[k].shape))
+
+    def to_host(self, ps):
+        out = ps.copy()
+        for k in ("pos", "quat", "vel", "omega", "world_pts"):
+            if getattr(ps, k).size:
+                setattr(out, k, self.t[k].cpu().numpy().reshape(getattr(ps, k).shape).copy())
+        return out
+
+
+class Lattice:
+    """A lattice, its caller-owned device buffers and a library context."""
+
+    def __init__(self, lat, n_particles=0, n_ctrl=0, box_half=2, storage="f32",
+                 treatments=TREAT_VIBB | TREAT_MISSING, h16_scale=0.0, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.storage = storage
+        cfg = LbmConfig()
+        cfg.nx, cfg.ny, cfg.nz = lat.nx, lat.ny, lat.nz
+        cfg.periodic = (ctypes.c_int32 * 3)(*[int(bool(v)) for v in lat.periodic])
+        cfg.tau = float(lat.tau)
+        cfg.rho0 = float(lat.rho0)
+        cfg.u0 = (ctypes.c_double * 3)(*map(float, lat.u0))
+        cfg.body_force = (ctypes.c_double * 3)(*map(float, lat.body_force))
+        cfg.storage = STORAGE[storage]
+        cfg.treatments = int(treatments)
+        cfg.n_particles = int(n_particles)
+        cfg.n_ctrl = int(n_ctrl)
+        cfg.box_half = int(box_half)
+        cfg.h16_scale = float(h16_scale)
+        with torch.cuda.device(self.device):
+            cfg.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self.cfg = cfg
+        self.sizes = lbm_query_sizes(cfg)
+        self.ncell = int(self.sizes.ncell)
+        u8 = dict(dtype=torch.uint8, device=self.device)
+        self.f = [torch.empty(self.sizes.population_bytes, **u8) for _ in range(2)]
+        self.own = [torch.empty(self.sizes.owner_bytes // 4, dtype=torch.int32, device=self.device)
+                    for _ in range(2)]
+        self.flag = torch.empty(self.sizes.flag_bytes, **u8)
+        bufs = LbmBuffers((_P * 2)(*[t.data_ptr() for t in self.f]),
+                          (_P * 2)(*[t.data_ptr() for t in self.own]), self.flag.data_ptr())
+        self.ctx = lbm_init(cfg, bufs)
+        self.n_particles = int(n_particles)
+        self.F = torch.zeros((max(n_particles, 1), 3), dtype=torch.float64, device=self.device)
+        self.T = torch.zeros_like(self.F)
+
+    @classmethod
+    def for_particles(cls, lat, ps, **kw):
+        return cls(lat, n_particles=ps.n, n_ctrl=len(ps.K), box_half=ps.box_half(), **kw)
+
+    # the five calls of the hot path
+    def classify(self, parts: DeviceParticles) -> LbmCounts:
+        return lbm_classify_nodes(self.ctx, parts.struct)
+
+    def step(self, parts: DeviceParticles):
+        lbm_step(self.ctx, parts.struct)
+
+    def forces(self):
+        lbm_particle_forces(self.ctx, self.F, self.T)
+        return self.F[: self.n_particles], self.T[: self.n_particles]
+
+    def dem(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
+        dem_step(self.ctx, parts.struct, n_sub, dt, prm)
+
+    def sync(self):
+        lbm_synchronize(self.ctx)
+
+    # inspection
+    def owner(self) -> np.ndarray:
+        out = self.torch.empty(self.ncell, dtype=self.torch.int32, device=self.device)
+        _check(load().lbm_get_owner(self.ctx, _ptr(out)), self.ctx)
+        return out.cpu().numpy()
+
+    def populations(self) -> np.ndarray:
+        out = self.torch.empty((Q, self.ncell), dtype=self.torch.float64, device=self.device)
+        _check(load().lbm_get_populations(self.ctx, _ptr(out)), self.ctx)
+        return out.cpu().numpy()
+
+    def set_populations(self, f: np.ndarray):
+        t = self.torch.as_tensor(np.ascontiguousarray(f, np.float64), device=self.device)
+        _check(load().lbm_set_populations(self.ctx, _ptr(t)), self.ctx)
+        self.sync()
+
+    def links(self):
+        """Link records sorted into canonical order (particle, node, d)."""
+        n = ctypes.c_int64()
+        rc = load().lbm_get_links(self.ctx, 0, None, None, None, None, None, ctypes.byref(n))
+        if rc not in (LBM_OK, LBM_ECAPACITY):
+            _check(rc, self.ctx)
+        m = int(n.value)
+        torch = self.torch
+        if m == 0:
+            z = np.zeros(0)
+            return dict(node=z.astype(np.int32), d=z.astype(np.int8), kind=z.astype(np.int8),
+                        part=z.astype(np.int32), q=z)
+        node = torch.empty(m, dtype=torch.int32, device=self.device)
+        d = torch.empty(m, dtype=torch.int8, device=self.device)
+        kind = torch.empty(m, dtype=torch.int8, device=self.device)
+        part = torch.empty(m, dtype=torch.int32, device=self.device)
+        q = torch.empty(m, dtype=torch.float64, device=self.device)
+        _check(load().lbm_get_links(self.ctx, m, _ptr(node), _ptr(d), _ptr(kind), _ptr(part),
+                                    _ptr(q), ctypes.byref(n)), self.ctx)
+        out = dict(node=node.cpu().numpy(), d=d.cpu().numpy(), kind=kind.cpu().numpy(),
+                   part=part.cpu().numpy(), q=q.cpu().numpy())
+        order = np.lexsort((out["d"], out["node"], out["part"]))
+        return {k: v[order] for k, v in out.items()}
+
+    def refill(self):
+        n = ctypes.c_int64()
+        rc = load().lbm_get_refill(self.ctx, 0, None, None, ctypes.byref(n))
+        if rc not in (LBM_OK, LBM_ECAPACITY):
+            _check(rc, self.ctx)
+        m = int(n.value)
+        if m == 0:
+            return np.zeros(0, np.int32), np.zeros(0, np.int32)
+        torch = self.torch
+        node = torch.empty(m, dtype=torch.int32, device=self.device)
+        part = torch.empty(m, dtype=torch.int32, device=self.device)
+        _check(load().lbm_get_refill(self.ctx, m, _ptr(node), _ptr(part), ctypes.byref(n)),
+               self.ctx)
+        node, part = node.cpu().numpy(), part.cpu().numpy()
+        o = np.argsort(node, kind="stable")
+        return node[o], part[o]
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

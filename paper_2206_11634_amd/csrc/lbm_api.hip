@@ -1,0 +1,451 @@
+// C-ABI entry points of libmdlbm (declared in include/mdlbm.h): argument
+// checks, scratch management and the order of kernel launches for one
+// classification, one lattice step and one DEM sub-cycle.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace mdlbm;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(lbm_ctx* c, int code, const std::string& msg)
+{
+    if (c) {
+        c->last_error = msg;
+        if (code == LBM_EDEVICE) c->failed = true;
+    } else {
+        g_init_error = msg;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_bytes(int storage)
+{
+    switch (storage) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    case LBM_STORE_F16: return 2;
+    default: return 0;
+    }
+}
+
+PartDev to_dev(const lbm_particles* P)
+{
+    PartDev d;
+    d.n = P->n;
+    d.off = P->ctrl_off;
+    d.body_pts = P->body_pts;
+    d.K = P->K;
+    d.c0 = P->c0;
+    d.rs = P->rs;
+    d.mass = P->mass;
+    d.volume = P->volume;
+    d.inertia = P->inertia;
+    d.pos = P->pos;
+    d.quat = P->quat;
+    d.vel = P->vel;
+    d.omega = P->omega;
+    d.wpts = P->world_pts;
+    return d;
+}
+
+int check_particles(lbm_ctx* c, const lbm_particles* P, bool need_dem)
+{
+    if (!P) return fail(c, LBM_EINVAL, "null particle description");
+    if (P->n != c->cfg.n_particles)
+        return fail(c, LBM_EINVAL, "particle count differs from lbm_config.n_particles");
+    if (P->n == 0) return LBM_OK;
+    if (!P->ctrl_off || !P->K || !P->c0 || !P->pos || !P->vel || !P->omega || !P->world_pts)
+        return fail(c, LBM_EINVAL, "null particle array");
+    if (need_dem && (!P->body_pts || !P->rs || !P->mass || !P->volume || !P->inertia || !P->quat))
+        return fail(c, LBM_EINVAL, "null particle array needed by the DEM");
+    return LBM_OK;
+}
+
+template <class T>
+hipError_t alloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+std::string err_text(uint32_t bits)
+{
+    std::string s;
+    if (bits & 1u) s += "particle centre outside [0,n) on a periodic axis or not finite; ";
+    if (bits & 2u) s += "metaball weight K or surface level c0 not positive; ";
+    if (bits & 4u) s += "particle body reaches beyond box_half - 1 of its centre; ";
+    if (bits & 8u) s += "particle has no control points or more than 64; ";
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
+{
+    if (!cfg || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+        return fail(nullptr, LBM_EINVAL, "lattice dimensions must be >= 1");
+    const int64_t ncell = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    if (ncell >= (int64_t)1 << 31) return fail(nullptr, LBM_EINVAL, "more than 2^31 - 1 cells");
+    const size_t es = elem_bytes(cfg->storage);
+    if (!es) return fail(nullptr, LBM_EINVAL, "unknown storage");
+    out->ncell = ncell;
+    out->cell_stride = (ncell + 63) / 64 * 64;
+    out->population_bytes = (size_t)kQ * (size_t)out->cell_stride * es;
+    out->owner_bytes = (size_t)ncell * sizeof(uint32_t);
+    out->flag_bytes = (size_t)ncell;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
+{
+    if (!cfg || !bufs || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    *out = nullptr;
+    lbm_sizes sz;
+    int rc = lbm_query_sizes(cfg, &sz);
+    if (rc) return rc;
+    if (!(cfg->tau > 0.5)) return fail(nullptr, LBM_EINVAL, "tau must exceed 1/2");
+    if (!(cfg->rho0 > 0.0)) return fail(nullptr, LBM_EINVAL, "rho0 must be positive");
+    if (!bufs->f_dev[0] || !bufs->f_dev[1] || !bufs->owner_dev[0] || !bufs->owner_dev[1] ||
+        !bufs->flag_dev)
+        return fail(nullptr, LBM_EINVAL, "null buffer");
+    if (cfg->n_particles < 0 || cfg->n_particles >= 65535)
+        return fail(nullptr, LBM_EINVAL, "n_particles must be in [0, 65535)");
+    if (cfg->n_particles > 0 && cfg->box_half < 2)
+        return fail(nullptr, LBM_EINVAL, "box_half must be >= 2");
+    const int dims[3] = {cfg->nx, cfg->ny, cfg->nz};
+    for (int a = 0; a < 3; ++a)
+        if (cfg->n_particles > 0 && cfg->periodic[a] && dims[a] < 2 * cfg->box_half + 5)
+            return fail(nullptr, LBM_EINVAL,
+                        "a periodic axis must have at least 2*box_half + 5 nodes");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(nullptr, LBM_ENOMEM, "context allocation failed");
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)cfg->stream;
+    for (int a = 0; a < 3; ++a) {
+        c->geom.n[a] = dims[a];
+        c->geom.per[a] = cfg->periodic[a] ? 1 : 0;
+    }
+    c->geom.stride = sz.cell_stride;
+    c->geom.ncell = (uint32_t)sz.ncell;
+    Phys& ph = c->phys;
+    ph.tau = cfg->tau;
+    ph.omega = 1.0 / cfg->tau;
+    ph.omegaf = (float)ph.omega;
+    ph.rho0 = cfg->rho0;
+    for (int a = 0; a < 3; ++a) {
+        ph.F[a] = cfg->body_force[a];
+        ph.Ff[a] = (float)cfg->body_force[a];
+    }
+    if (cfg->storage == LBM_STORE_F16) {
+        ph.scale = cfg->h16_scale > 0.0 ? (float)cfg->h16_scale : 1024.0f;
+    } else {
+        ph.scale = 1.0f;
+    }
+    ph.inv_scale = 1.0f / ph.scale;
+    const int h = std::max(cfg->box_half, 2);
+    c->box.h = h;
+    c->box.S = 2 * h + 1;
+    c->box.vol = c->box.S * c->box.S * c->box.S;
+    c->box.tiles = (c->box.vol + 255) / 256;
+    for (int i = 0; i < 2; ++i) {
+        c->f[i] = bufs->f_dev[i];
+        c->own[i] = bufs->owner_dev[i];
+    }
+    c->flag = bufs->flag_dev;
+
+    const int np = cfg->n_particles;
+    const int64_t S2 = (int64_t)c->box.S * c->box.S;
+    c->link_cap = std::max<int64_t>(256, (32 * S2 + 255) / 256 * 256);
+    c->refill_cap = std::max<int64_t>(1 << 16, (int64_t)np * S2);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = alloc(&c->box_hist, (size_t)3 * 3 * std::max(np, 1));
+    if (e == hipSuccess) e = alloc(&c->link_cursor, (size_t)kCursorPad * std::max(np, 1));
+    if (e == hipSuccess && np) e = alloc(&c->links, (size_t)np * c->link_cap);
+    if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
+    if (e == hipSuccess) e = alloc(&c->refill_cursor, 1);
+    if (e == hipSuccess) e = alloc(&c->err, 1);
+    if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
+    if (e == hipSuccess) e = alloc(&c->fc, (size_t)6 * std::max(np, 1));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&c->host_stage,
+                          sizeof(uint32_t) * (2 + (size_t)kCursorPad * std::max(np, 1)),
+                          hipHostMallocDefault);
+    if (e != hipSuccess) {
+        std::string msg = std::string("scratch allocation failed: ") + hipGetErrorString(e);
+        lbm_destroy(c);
+        return fail(nullptr, LBM_ENOMEM, msg);
+    }
+    e = launch_init_equilibrium(c, c->f[0]);
+    if (e == hipSuccess) e = hipMemsetAsync(c->own[0], 0xFF, sz.owner_bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->own[1], 0xFF, sz.owner_bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sz.flag_bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->link_cursor, 0, sizeof(uint32_t) * kCursorPad * std::max(np, 1), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->FT, 0, sizeof(double) * 6 * std::max(np, 1), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->fc, 0, sizeof(double) * 6 * std::max(np, 1), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        std::string msg = std::string("initialisation failed: ") + hipGetErrorString(e);
+        lbm_destroy(c);
+        return fail(nullptr, LBM_EDEVICE, msg);
+    }
+    c->cur = 0;
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return LBM_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->box_hist);
+    (void)hipFree(c->links);
+    (void)hipFree(c->link_cursor);
+    (void)hipFree(c->refill);
+    (void)hipFree(c->refill_cursor);
+    (void)hipFree(c->err);
+    (void)hipFree(c->FT);
+    (void)hipFree(c->fc);
+    (void)hipFree(c->hist_pp);
+    (void)hipFree(c->hist_pw);
+    if (c->host_stage) (void)hipHostFree(c->host_stage);
+    delete c;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c)
+{
+    return c ? c->last_error.c_str() : g_init_error.c_str();
+}
+
+int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    int rc = check_particles(c, P, false);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    const PartDev Pd = to_dev(P);
+    const int64_t k = c->n_classify;
+    const int slot = (int)(k % 3), slot_prev = (int)((k + 2) % 3), slot_prev2 = (int)((k + 1) % 3);
+    uint32_t* own_new = c->own[k % 2];
+    const uint32_t* own_prev = c->own[(k + 1) % 2];
+    const size_t cur_bytes = sizeof(uint32_t) * kCursorPad * std::max(np, 1);
+
+    if (np > 0) {
+        HIPCHK(c, hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->stream));
+        HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
+        HIPCHK(c, launch_boxes(c, Pd, slot));
+        // check the boxes before touching the owner planes or the flags
+        HIPCHK(c, hipMemcpyAsync(c->host_stage, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->host_stage[0])
+            return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[0]));
+        if (k >= 2) HIPCHK(c, launch_clear_boxes(c, own_new, slot_prev2, np));
+        HIPCHK(c, launch_mark(c, own_new, Pd, slot));
+        if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
+        HIPCHK(c, launch_links(c, own_new, Pd, slot));
+        for (int attempt = 0;; ++attempt) {
+            HIPCHK(c, hipMemcpyAsync(c->host_stage, c->refill_cursor, sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->host_stage + 2, c->link_cursor, cur_bytes,
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            int64_t lmax = 0, ltot = 0;
+            for (int p = 0; p < np; ++p) {
+                const int64_t v = c->host_stage[2 + (size_t)p * kCursorPad];
+                lmax = std::max(lmax, v);
+                ltot += v;
+            }
+            const int64_t nref = c->host_stage[0];
+            const bool grow_links = lmax > c->link_cap;
+            const bool grow_refill = nref > c->refill_cap;
+            if (!grow_links && !grow_refill) {
+                c->link_max = lmax;
+                c->link_total = ltot;
+                c->refill_total = (k >= 1) ? nref : 0;
+                break;
+            }
+            if (attempt > 2) return fail(c, LBM_ENOMEM, "link/refill lists keep overflowing");
+            if (grow_links) {
+                HIPCHK(c, hipFree(c->links));
+                c->links = nullptr;
+                c->link_cap = (lmax + lmax / 4 + 255) / 256 * 256;
+                if (alloc(&c->links, (size_t)np * c->link_cap) != hipSuccess)
+                    return fail(c, LBM_ENOMEM, "link list allocation failed");
+                HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
+                HIPCHK(c, launch_links(c, own_new, Pd, slot));
+            }
+            if (grow_refill) {
+                HIPCHK(c, hipFree(c->refill));
+                c->refill = nullptr;
+                c->refill_cap = nref + nref / 4 + 1024;
+                if (alloc(&c->refill, (size_t)c->refill_cap) != hipSuccess)
+                    return fail(c, LBM_ENOMEM, "refill list allocation failed");
+                HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
+                if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
+            }
+        }
+        if (c->refill_total > 0) {
+            // populations of the time level the previous classification describes
+            const void* src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
+            HIPCHK(c, launch_refill(c, src, c->f[c->cur], own_prev, Pd));
+        }
+    } else {
+        c->link_max = c->link_total = c->refill_total = 0;
+    }
+    c->own_cur = (int)(k % 2);
+    c->n_classify = k + 1;
+    c->stepped_since_classify = false;
+    if (out) {
+        out->n_links = c->link_total;
+        out->n_refill = c->refill_total;
+        out->n_solid_changed = 0;
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, const lbm_particles* P)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    int rc = check_particles(c, P, false);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    HIPCHK(c, launch_zero_f64(c, c->FT, 6 * (int64_t)np));
+    if (np > 0 && c->n_classify > 0) HIPCHK(c, launch_boundary(c, c->f[c->cur], to_dev(P)));
+    HIPCHK(c, launch_stream_collide(c, c->f[c->cur], c->f[1 - c->cur]));
+    c->cur = 1 - c->cur;
+    c->stepped_since_classify = true;
+    return LBM_OK;
+}
+
+int lbm_particle_forces(const lbm_ctx* c, double* F_dev, double* T_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (!F_dev || !T_dev) return fail(const_cast<lbm_ctx*>(c), LBM_EINVAL, "null output");
+    HIPCHK(const_cast<lbm_ctx*>(c), launch_split_forces(c, F_dev, T_dev));
+    return LBM_OK;
+}
+
+int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_params* prm)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (!prm) return fail(c, LBM_EINVAL, "null DEM parameters");
+    if (n_sub < 1) return fail(c, LBM_EINVAL, "n_sub must be >= 1");
+    if (!(dt > 0.0)) return fail(c, LBM_EINVAL, "dt must be positive");
+    int rc = check_particles(c, P, true);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    if (np == 0) return LBM_OK;
+    if (!c->hist_pp) {
+        if (alloc(&c->hist_pp, (size_t)np * np * 8) != hipSuccess ||
+            alloc(&c->hist_pw, (size_t)np * 6 * 8) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "contact history allocation failed");
+        HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * np * np * 8, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));
+    }
+    HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm));
+    return LBM_OK;
+}
+
+int lbm_get_links(const lbm_ctx* cc, int64_t cap, int32_t* node_dev, int8_t* d_dev,
+                  int8_t* kind_dev, int32_t* part_dev, double* q_dev, int64_t* n_out)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c || !n_out) return fail(c, LBM_EINVAL, "null argument");
+    *n_out = c->link_total;
+    if (c->link_total == 0) return LBM_OK;
+    if (cap < c->link_total) return fail(c, LBM_ECAPACITY, "link output too small");
+    if (!node_dev || !d_dev || !kind_dev || !part_dev || !q_dev)
+        return fail(c, LBM_EINVAL, "null output");
+    const int np = c->cfg.n_particles;
+    std::vector<int64_t> off(np);
+    int64_t acc = 0;
+    for (int p = 0; p < np; ++p) {
+        off[p] = acc;
+        acc += c->host_stage[2 + (size_t)p * kCursorPad];
+    }
+    int64_t* off_dev = nullptr;
+    HIPCHK(c, alloc(&off_dev, np));
+    HIPCHK(c, hipMemcpyAsync(off_dev, off.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, launch_link_export(c, node_dev, d_dev, kind_dev, part_dev, q_dev, off_dev));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(off_dev));
+    return LBM_OK;
+}
+
+int lbm_get_refill(const lbm_ctx* cc, int64_t cap, int32_t* node_dev, int32_t* part_dev,
+                   int64_t* n_out)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c || !n_out) return fail(c, LBM_EINVAL, "null argument");
+    *n_out = c->refill_total;
+    if (c->refill_total == 0) return LBM_OK;
+    if (cap < c->refill_total) return fail(c, LBM_ECAPACITY, "refill output too small");
+    if (!node_dev || !part_dev) return fail(c, LBM_EINVAL, "null output");
+    HIPCHK(c, hipMemcpy2DAsync(node_dev, sizeof(int32_t), c->refill, sizeof(RefillRec),
+                               sizeof(int32_t), c->refill_total, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpy2DAsync(part_dev, sizeof(int32_t), (const char*)c->refill + sizeof(uint32_t),
+                               sizeof(RefillRec), sizeof(int32_t), c->refill_total,
+                               hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_owner(const lbm_ctx* cc, int32_t* owner_dev)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c || !owner_dev) return fail(c, LBM_EINVAL, "null argument");
+    HIPCHK(c, launch_owner_export(c, c->own[c->own_cur], owner_dev));
+    return LBM_OK;
+}
+
+int lbm_get_populations(const lbm_ctx* cc, double* f_dev)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c || !f_dev) return fail(c, LBM_EINVAL, "null argument");
+    HIPCHK(c, launch_get_populations(c, c->f[c->cur], f_dev));
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f_dev)
+{
+    if (!c || !f_dev) return fail(c, LBM_EINVAL, "null argument");
+    HIPCHK(c, launch_set_populations(c, c->f[c->cur], f_dev));
+    return LBM_OK;
+}
+
+int lbm_synchronize(lbm_ctx* c)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,447 @@
+// Metaball DEM of libmdlbm in FP64 on the GPU (Sec. 2.1, with the
+// sub-cycling of Sec. 2.3.4): velocity Verlet for translation, Euler's
+// equations in the principal body frame for rotation, linear spring-dashpot
+// normal force and Coulomb-limited tangential spring, metaball-metaball
+// contacts by Newton-Raphson on grad(M_i + M_j) = 0 (Eqs. opt, grad, cp, k0,
+// contactprop) and metaball-wall contacts by Newton on the in-plane gradient
+// (Eqs. metawall, metawallcp, k, contactprop2).
+//
+// One substep = four launches: half kick + drift + rotation (one thread per
+// particle), zero the contact sums, contacts (one thread per pair i < j and
+// one per particle-wall pair, FP64 atomics into the sums), second half kick.
+// The work is latency-bound (a few thousand particles at most), not HBM-bound.
+#include "lbm_internal.h"
+
+namespace mdlbm {
+namespace {
+
+constexpr int kHist = 8;  // active, xi[3], warm start[3], pad
+constexpr int kMaxPts = 64;
+
+struct DemP {
+    double kn, etan, kt, etat, mu, ctol, ntol;
+    int niter;
+    double g[3];
+    double rhof;
+};
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ void rotmat(const double* q, double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z);
+    R[1] = 2 * (x * y - w * z);
+    R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);
+    R[4] = 1 - 2 * (x * x + z * z);
+    R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);
+    R[7] = 2 * (y * z + w * x);
+    R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// M, grad M and the Hessian of a metaball with n points at X; pts may be
+// shifted by `sh` (a periodic image).
+__device__ void mb_d2(const double* pts, const double* K, int n, const double sh[3],
+                      const double X[3], double& M, double g[3], double H[9])
+{
+    M = 0.0;
+    for (int a = 0; a < 3; ++a) g[a] = 0.0;
+    for (int a = 0; a < 9; ++a) H[a] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r[3];
+        for (int a = 0; a < 3; ++a) r[a] = X[a] - (pts[3 * i + a] + sh[a]);
+        const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+        const double i2 = 1.0 / r2, i4 = i2 * i2, i6 = i4 * i2;
+        M += K[i] * i2;
+        for (int a = 0; a < 3; ++a) {
+            g[a] += -2.0 * K[i] * r[a] * i4;
+            for (int b = 0; b < 3; ++b)
+                H[3 * a + b] += K[i] * (8.0 * r[a] * r[b] * i6 - (a == b ? 2.0 * i4 : 0.0));
+        }
+    }
+}
+
+__device__ bool solve3(const double H[9], const double g[3], double dx[3])
+{
+    double c[9];
+    c[0] = H[4] * H[8] - H[5] * H[7];
+    c[1] = H[2] * H[7] - H[1] * H[8];
+    c[2] = H[1] * H[5] - H[2] * H[4];
+    c[3] = H[5] * H[6] - H[3] * H[8];
+    c[4] = H[0] * H[8] - H[2] * H[6];
+    c[5] = H[2] * H[3] - H[0] * H[5];
+    c[6] = H[3] * H[7] - H[4] * H[6];
+    c[7] = H[1] * H[6] - H[0] * H[7];
+    c[8] = H[0] * H[4] - H[1] * H[3];
+    const double det = H[0] * c[0] + H[1] * c[3] + H[2] * c[6];
+    if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+    for (int i = 0; i < 3; ++i) dx[i] = -(c[3 * i] * g[0] + c[3 * i + 1] * g[1] + c[3 * i + 2] * g[2]) / det;
+    return true;
+}
+
+__device__ double reach(const PartDev& P, int p)
+{
+    double sk = 0.0, r = 0.0;
+    for (int i = P.off[p]; i < P.off[p + 1]; ++i) {
+        const double* b = P.body_pts + 3 * (int64_t)i;
+        r = fmax(r, sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
+        sk += P.K[i];
+    }
+    return r + sqrt(sk);
+}
+
+// Normal spring-dashpot (clamped at zero) and tangential spring with Coulomb
+// limit; updates the spring xi in h[1..3]; returns the force on body i.
+__device__ void contact_force(const DemP& c, double delta, const double n[3], const double vrel[3],
+                              double dt, double* h, double Fi[3])
+{
+    const double vn = dot3(vrel, n);
+    double Fn = c.kn * delta - c.etan * vn;
+    if (Fn < 0.0) Fn = 0.0;
+    double vt[3], xi[3], Ft[3];
+    for (int a = 0; a < 3; ++a) vt[a] = vrel[a] - vn * n[a];
+    const double xin = h[1] * n[0] + h[2] * n[1] + h[3] * n[2];
+    for (int a = 0; a < 3; ++a) xi[a] = h[1 + a] - xin * n[a] + vt[a] * dt;
+    for (int a = 0; a < 3; ++a) Ft[a] = -c.kt * xi[a] - c.etat * vt[a];
+    const double ftn = sqrt(dot3(Ft, Ft));
+    if (ftn > c.mu * Fn && ftn > 0.0) {
+        const double s = c.mu * Fn / ftn;
+        for (int a = 0; a < 3; ++a) {
+            Ft[a] *= s;
+            xi[a] = -(Ft[a] + c.etat * vt[a]) / c.kt;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        h[1 + a] = xi[a];
+        Fi[a] = Fn * n[a] + Ft[a];
+    }
+}
+
+__device__ void half_kick(const PartDev& P, int p, const double* FTh, const double* fc,
+                          const DemP& c, double h, bool implicit)
+{
+    const double m = P.mass[p];
+    const double mrel = m - c.rhof * P.volume[p];
+    double T[3];
+    for (int a = 0; a < 3; ++a) {
+        const double F = FTh[6 * p + a] + mrel * c.g[a] + fc[6 * p + a];
+        P.vel[3 * p + a] += h * F / m;
+        T[a] = FTh[6 * p + 3 + a] + fc[6 * p + 3 + a];
+    }
+    double R[9];
+    rotmat(P.quat + 4 * p, R);
+    double w0[3], Tb[3], wb[3];
+    const double* om = P.omega + 3 * p;
+    for (int i = 0; i < 3; ++i) {
+        w0[i] = R[i] * om[0] + R[3 + i] * om[1] + R[6 + i] * om[2];
+        Tb[i] = R[i] * T[0] + R[3 + i] * T[1] + R[6 + i] * T[2];
+        wb[i] = w0[i];
+    }
+    const double* I = P.inertia + 3 * p;
+    const int iters = implicit ? 4 : 1;
+    for (int it = 0; it < iters; ++it) {
+        const double Iw[3] = {I[0] * wb[0], I[1] * wb[1], I[2] * wb[2]};
+        double cc[3];
+        cross3(wb, Iw, cc);
+        double nw[3];
+        for (int a = 0; a < 3; ++a) nw[a] = w0[a] + h * (Tb[a] - cc[a]) / I[a];
+        for (int a = 0; a < 3; ++a) wb[a] = nw[a];
+    }
+    for (int i = 0; i < 3; ++i) P.omega[3 * p + i] = R[3 * i] * wb[0] + R[3 * i + 1] * wb[1] + R[3 * i + 2] * wb[2];
+}
+
+__global__ void k_first_half(PartDev P, const double* FTh, const double* fc, DemP c, double dt,
+                             Geom g)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    half_kick(P, p, FTh, fc, c, 0.5 * dt, false);
+    for (int a = 0; a < 3; ++a) {
+        double x = P.pos[3 * p + a] + dt * P.vel[3 * p + a];
+        if (g.per[a]) {
+            if (x >= (double)g.n[a]) x -= g.n[a];
+            else if (x < 0.0) x += g.n[a];
+        }
+        P.pos[3 * p + a] = x;
+    }
+    const double* om = P.omega + 3 * p;
+    const double wn = sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]);
+    double dq[4];
+    dq[0] = cos(0.5 * wn * dt);
+    const double s = wn > 0.0 ? sin(0.5 * wn * dt) / wn : 0.0;
+    dq[1] = s * om[0];
+    dq[2] = s * om[1];
+    dq[3] = s * om[2];
+    double* q = P.quat + 4 * p;
+    double qn[4];
+    qn[0] = dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3];
+    qn[1] = dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2];
+    qn[2] = dq[0] * q[2] - dq[1] * q[3] + dq[2] * q[0] + dq[3] * q[1];
+    qn[3] = dq[0] * q[3] + dq[1] * q[2] - dq[2] * q[1] + dq[3] * q[0];
+    const double nrm = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+    for (int a = 0; a < 4; ++a) q[a] = qn[a] / nrm;
+    double R[9];
+    rotmat(q, R);
+    for (int i = P.off[p]; i < P.off[p + 1]; ++i) {
+        const double* b = P.body_pts + 3 * (int64_t)i;
+        for (int a = 0; a < 3; ++a)
+            P.wpts[3 * (int64_t)i + a] = P.pos[3 * p + a] + (R[3 * a] * b[0] + R[3 * a + 1] * b[1] + R[3 * a + 2] * b[2]);
+    }
+}
+
+__global__ void k_zero6(double* fc, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * n) fc[i] = 0.0;
+}
+
+__global__ void k_pairs(PartDev P, double* hist, double* fc, DemP c, double dt, Geom g)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = P.n;
+    if (t >= (int64_t)np * np) return;
+    const int i = (int)(t / np), j = (int)(t % np);
+    if (i >= j) return;
+    double* h = hist + t * kHist;
+    const double* xi = P.pos + 3 * i;
+    const double* xj = P.pos + 3 * j;
+    double sh[3], dv[3];
+    for (int a = 0; a < 3; ++a) {
+        const double d = xj[a] - xi[a];
+        sh[a] = 0.0;
+        if (g.per[a]) {
+            const double L = g.n[a];
+            if (d > 0.5 * L) sh[a] = -L;
+            else if (d < -0.5 * L) sh[a] = L;
+        }
+        dv[a] = d + sh[a];
+    }
+    const double rsi = P.rs[i], rsj = P.rs[j];
+    if (sqrt(dot3(dv, dv)) > reach(P, i) + reach(P, j) + rsi + rsj) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    const int ai = P.off[i], ni = min(P.off[i + 1] - ai, kMaxPts);
+    const int aj = P.off[j], nj = min(P.off[j + 1] - aj, kMaxPts);
+    const double* pi = P.wpts + 3 * (int64_t)ai;
+    const double* pj = P.wpts + 3 * (int64_t)aj;
+    const double z3[3] = {0.0, 0.0, 0.0};
+    double x[3];
+    if (h[0] != 0.0) {
+        for (int a = 0; a < 3; ++a) x[a] = xi[a] + h[4 + a];
+    } else {
+        double best = INFINITY;
+        for (int u = 0; u < ni; ++u)
+            for (int v = 0; v < nj; ++v) {
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double dd = pi[3 * u + a] - (pj[3 * v + a] + sh[a]);
+                    d2 += dd * dd;
+                }
+                if (d2 < best) {
+                    best = d2;
+                    for (int a = 0; a < 3; ++a) x[a] = 0.5 * (pi[3 * u + a] + pj[3 * v + a] + sh[a]);
+                }
+            }
+    }
+    double MA, MB, gA[3], gB[3], HA[9], HB[9];
+    bool conv = false;
+    for (int it = 0; it < c.niter; ++it) {
+        mb_d2(pi, P.K + ai, ni, z3, x, MA, gA, HA);
+        mb_d2(pj, P.K + aj, nj, sh, x, MB, gB, HB);
+        double gg[3], H[9], dx[3];
+        for (int a = 0; a < 3; ++a) gg[a] = gA[a] + gB[a];
+        for (int a = 0; a < 9; ++a) H[a] = HA[a] + HB[a];
+        if (!solve3(H, gg, dx)) break;
+        for (int a = 0; a < 3; ++a) x[a] += dx[a];
+        if (sqrt(dot3(dx, dx)) < c.ntol) {
+            conv = true;
+            break;
+        }
+    }
+    if (!conv) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    mb_d2(pi, P.K + ai, ni, z3, x, MA, gA, HA);
+    mb_d2(pj, P.K + aj, nj, sh, x, MB, gB, HB);
+    if (!(MA > c.ctol && MA < 1.0 && MB > c.ctol && MB < 1.0)) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    const double qA = (1.0 - MA) / dot3(gA, gA), qB = (1.0 - MB) / dot3(gB, gB);
+    double xa[3], dd[3];
+    for (int a = 0; a < 3; ++a) {
+        xa[a] = x[a] + qA * gA[a];
+        dd[a] = xa[a] - (x[a] + qB * gB[a]);
+    }
+    const double dist = sqrt(dot3(dd, dd));
+    h[0] = 1.0;
+    for (int a = 0; a < 3; ++a) h[4 + a] = x[a] - xi[a];
+    if (!(dist > 0.0)) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    const double delta = rsi + rsj - dist;
+    if (delta <= 0.0) {
+        h[1] = h[2] = h[3] = 0.0;
+        return;
+    }
+    double n[3], xcp[3], ra[3], rb[3];
+    for (int a = 0; a < 3; ++a) {
+        n[a] = dd[a] / dist;
+        xcp[a] = xa[a] - (rsi - 0.5 * delta) * n[a];
+        ra[a] = xcp[a] - xi[a];
+        rb[a] = xcp[a] - (xj[a] + sh[a]);
+    }
+    double ca[3], cb[3], vrel[3], Fi[3], tq[3];
+    cross3(P.omega + 3 * i, ra, ca);
+    cross3(P.omega + 3 * j, rb, cb);
+    for (int a = 0; a < 3; ++a) vrel[a] = (P.vel[3 * i + a] + ca[a]) - (P.vel[3 * j + a] + cb[a]);
+    contact_force(c, delta, n, vrel, dt, h, Fi);
+    for (int a = 0; a < 3; ++a) {
+        atomicAdd(fc + 6 * i + a, Fi[a]);
+        atomicAdd(fc + 6 * j + a, -Fi[a]);
+    }
+    cross3(ra, Fi, tq);
+    for (int a = 0; a < 3; ++a) atomicAdd(fc + 6 * i + 3 + a, tq[a]);
+    cross3(rb, Fi, tq);
+    for (int a = 0; a < 3; ++a) atomicAdd(fc + 6 * j + 3 + a, -tq[a]);
+}
+
+__global__ void k_walls(PartDev P, double* hist, double* fc, DemP c, double dt, Geom g)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.n * 6) return;
+    const int i = t / 6, ax = (t % 6) / 2, side = t % 2;
+    if (g.per[ax]) return;
+    double* h = hist + (int64_t)t * kHist;
+    const double plane = side ? g.n[ax] - 0.5 : -0.5, sgn = side ? -1.0 : 1.0;
+    const double* xi = P.pos + 3 * i;
+    if (sgn * (xi[ax] - plane) > reach(P, i) + P.rs[i]) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    const int ai = P.off[i], ni = min(P.off[i + 1] - ai, kMaxPts);
+    const double* pi = P.wpts + 3 * (int64_t)ai;
+    const double z3[3] = {0.0, 0.0, 0.0};
+    const int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+    double x[3];
+    if (h[0] != 0.0) {
+        for (int a = 0; a < 3; ++a) x[a] = xi[a] + h[4 + a];
+    } else {
+        double best = INFINITY;
+        for (int u = 0; u < ni; ++u) {
+            const double dd = fabs(pi[3 * u + ax] - plane);
+            if (dd < best) {
+                best = dd;
+                for (int a = 0; a < 3; ++a) x[a] = pi[3 * u + a];
+            }
+        }
+    }
+    x[ax] = plane;
+    double M, gr[3], H[9];
+    bool conv = false;
+    for (int it = 0; it < c.niter; ++it) {
+        mb_d2(pi, P.K + ai, ni, z3, x, M, gr, H);
+        const double h11 = H[3 * t1 + t1], h12 = H[3 * t1 + t2], h22 = H[3 * t2 + t2];
+        const double det = h11 * h22 - h12 * h12;
+        if (!(fabs(det) > 0.0) || !isfinite(det)) break;
+        const double d1 = -(h22 * gr[t1] - h12 * gr[t2]) / det;
+        const double d2 = -(-h12 * gr[t1] + h11 * gr[t2]) / det;
+        x[t1] += d1;
+        x[t2] += d2;
+        if (sqrt(d1 * d1 + d2 * d2) < c.ntol) {
+            conv = true;
+            break;
+        }
+    }
+    if (!conv) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    mb_d2(pi, P.K + ai, ni, z3, x, M, gr, H);
+    if (!(sgn * gr[ax] > 0.0)) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    h[0] = 1.0;
+    for (int a = 0; a < 3; ++a) h[4 + a] = x[a] - xi[a];
+    const double qR = (1.0 - M) / dot3(gr, gr);
+    const double delta = P.rs[i] - sgn * (qR * gr[ax]);
+    if (delta <= 0.0) {
+        h[1] = h[2] = h[3] = 0.0;
+        return;
+    }
+    double n[3] = {0.0, 0.0, 0.0}, xcp[3], ra[3];
+    n[ax] = sgn;
+    for (int a = 0; a < 3; ++a) {
+        xcp[a] = x[a] - 0.5 * delta * n[a];
+        ra[a] = xcp[a] - xi[a];
+    }
+    double ca[3], vrel[3], Fi[3], tq[3];
+    cross3(P.omega + 3 * i, ra, ca);
+    for (int a = 0; a < 3; ++a) vrel[a] = P.vel[3 * i + a] + ca[a];
+    contact_force(c, delta, n, vrel, dt, h, Fi);
+    cross3(ra, Fi, tq);
+    for (int a = 0; a < 3; ++a) {
+        atomicAdd(fc + 6 * i + a, Fi[a]);
+        atomicAdd(fc + 6 * i + 3 + a, tq[a]);
+    }
+}
+
+__global__ void k_second_half(PartDev P, const double* FTh, const double* fc, DemP c, double dt)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    half_kick(P, p, FTh, fc, c, 0.5 * dt, true);
+}
+
+}  // namespace
+
+hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, const dem_params& prm)
+{
+    const int np = P.n;
+    if (np == 0) return hipSuccess;
+    DemP c;
+    c.kn = prm.kn;
+    c.etan = prm.eta_n;
+    c.kt = prm.kt;
+    c.etat = prm.eta_t;
+    c.mu = prm.mu_s;
+    c.ctol = prm.ctol;
+    c.ntol = prm.newton_tol;
+    c.niter = prm.newton_iter;
+    for (int a = 0; a < 3; ++a) c.g[a] = prm.gravity[a];
+    c.rhof = prm.rho_f;
+    const uint32_t bp = (np + 63) / 64;
+    const int64_t npairs = (int64_t)np * np;
+    const uint32_t bpairs = (uint32_t)((npairs + 255) / 256);
+    const uint32_t bw = (np * 6 + 63) / 64;
+    for (int s = 0; s < n_sub; ++s) {
+        hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc, c,
+                           dt, ctx->geom);
+        hipLaunchKernelGGL(k_zero6, dim3(bp), dim3(64 * 6), 0, ctx->stream, ctx->fc, np);
+        if (np > 1)
+            hipLaunchKernelGGL(k_pairs, dim3(bpairs), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
+                               ctx->fc, c, dt, ctx->geom);
+        hipLaunchKernelGGL(k_walls, dim3(bw), dim3(64), 0, ctx->stream, P, ctx->hist_pw, ctx->fc, c,
+                           dt, ctx->geom);
+        hipLaunchKernelGGL(k_second_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
+                           c, dt);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mdlbm

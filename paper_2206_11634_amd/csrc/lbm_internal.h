@@ -1,0 +1,175 @@
+// Internal declarations shared by the translation units of libmdlbm (HIP,
+// gfx950).  Nothing here crosses the C-ABI.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mdlbm.h"
+
+namespace mdlbm {
+
+// ---------------------------------------------------------------------------
+// D3Q19 in the exported numbering (opposite of odd i is i + 1).
+// ---------------------------------------------------------------------------
+constexpr int kQ = 19;
+
+__host__ __device__ constexpr int cx(int i)
+{
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy(int i)
+{
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int cz(int i)
+{
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wgt(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+__host__ __device__ constexpr float wgtf(int i)
+{
+    return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+
+// Owner plane value of a fluid node (a solid node holds its particle index).
+constexpr uint32_t kFluid = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Records
+// ---------------------------------------------------------------------------
+struct alignas(16) LinkRec {
+    uint32_t node;   // solid node x_s
+    uint16_t part;   // particle index
+    uint8_t d;       // direction from x_n = x_s - e_d into the solid
+    uint8_t kind;    // lbm_link_kind
+    double q;        // wall fraction of Eq. (appq)
+};
+static_assert(sizeof(LinkRec) == 16, "link record is 16 bytes");
+
+struct RefillRec {
+    uint32_t node;
+    uint32_t part;
+};
+
+// Lattice geometry passed by value to kernels.
+struct Geom {
+    int n[3];
+    int per[3];
+    int64_t stride;   // elements between population planes
+    uint32_t ncell;
+};
+
+// Physical constants for one launch.
+struct Phys {
+    double tau, omega;     // omega = 1/tau
+    double F[3];           // body-force density
+    double rho0;
+    float omegaf;
+    float Ff[3];
+    float scale, inv_scale;  // FP16 deviation scale
+};
+
+// Device pointers of the particle state (a copy of lbm_particles).
+struct PartDev {
+    int n;
+    const int32_t* off;
+    const double* body_pts;
+    const double* K;
+    const double* c0;
+    const double* rs;
+    const double* mass;
+    const double* volume;
+    const double* inertia;
+    double* pos;
+    double* quat;
+    double* vel;
+    double* omega;
+    double* wpts;
+};
+
+// Per-particle node box: origin (unwrapped) and edge S = 2h + 1.
+struct BoxSpec {
+    int h, S, vol, tiles;  // tiles of 256 box cells
+};
+
+constexpr int kCursorPad = 32;  // one 128-byte line per per-particle counter
+
+}  // namespace mdlbm
+
+// The context (opaque across the ABI).
+struct lbm_ctx {
+    lbm_config cfg{};
+    hipStream_t stream = nullptr;
+    mdlbm::Geom geom{};
+    mdlbm::Phys phys{};
+    mdlbm::BoxSpec box{};
+    void* f[2] = {nullptr, nullptr};
+    uint32_t* own[2] = {nullptr, nullptr};
+    uint8_t* flag = nullptr;
+    int cur = 0;            // population buffer holding the current f+
+    int own_cur = 0;        // owner plane of the last classification
+    int64_t n_classify = 0; // classifications done
+    bool stepped_since_classify = false;
+    bool failed = false;
+
+    // library scratch
+    int* box_hist = nullptr;      // [3][np][3] box origins of the last three classifications
+    mdlbm::LinkRec* links = nullptr;
+    int64_t link_cap = 0;         // per particle
+    uint32_t* link_cursor = nullptr;  // [np * kCursorPad]
+    int64_t link_max = 0;         // max links of one particle at the last classification
+    int64_t link_total = 0;
+    mdlbm::RefillRec* refill = nullptr;
+    int64_t refill_cap = 0;
+    uint32_t* refill_cursor = nullptr;
+    int64_t refill_total = 0;
+    uint32_t* err = nullptr;      // error bits written by kernels
+    double* FT = nullptr;         // [np][6] force, torque of the last step
+    uint32_t* host_stage = nullptr; // pinned staging for counters
+    // DEM
+    double* hist_pp = nullptr;    // [np*np][8]
+    double* hist_pw = nullptr;    // [np*6][8]
+    double* fc = nullptr;         // [np][6] last contact force / torque
+    std::string last_error;
+};
+
+namespace mdlbm {
+
+// Launchers (lbm_stream.hip)
+hipError_t launch_init_equilibrium(lbm_ctx* c, void* f);
+hipError_t launch_stream_collide(lbm_ctx* c, const void* src, void* dst);
+hipError_t launch_boundary(lbm_ctx* c, void* f, const PartDev& P);
+hipError_t launch_refill(lbm_ctx* c, const void* fprev, void* fcur, const uint32_t* own_prev,
+                         const PartDev& P);
+hipError_t launch_get_populations(lbm_ctx* c, const void* f, double* out);
+hipError_t launch_set_populations(lbm_ctx* c, void* f, const double* in);
+hipError_t launch_zero_f64(lbm_ctx* c, double* p, int64_t n);
+hipError_t launch_split_forces(const lbm_ctx* c, double* F, double* T);
+
+// Launchers (lbm_classify.hip)
+hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot);
+hipError_t launch_clear_boxes(lbm_ctx* c, uint32_t* own, int slot, int np);
+hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot);
+hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* own_new, int slot,
+                         int np_prev);
+hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int slot);
+hipError_t launch_owner_export(const lbm_ctx* c, const uint32_t* own, int32_t* out);
+hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t* kind,
+                              int32_t* part, double* q, const int64_t* offsets_dev);
+
+// Launchers (lbm_dem.hip)
+hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);
+
+}  // namespace mdlbm

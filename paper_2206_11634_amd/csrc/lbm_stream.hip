@@ -1,0 +1,637 @@
+// Lattice kernels of libmdlbm for gfx950: fused pull-stream + BGK collision,
+// link reconstruction (VIBB / halfway) with momentum-exchange forces, local
+// refilling, and population import/export.
+//
+// Storage formats (template parameter S):
+//   LBM_STORE_F64  f_i in double, arithmetic in double (the plain method);
+//   LBM_STORE_F32  h_i = f_i - w_i in float, arithmetic in float;
+//   LBM_STORE_F16  h_i * scale in half, arithmetic in float.
+// Deviations keep the O(1) weights out of the stored values, so the rounding
+// error of a stored population is relative to |f - w| (a few 1e-3 at the
+// Mach numbers of interest) rather than to f.
+//
+// Layout: plane i of a buffer starts at element i * stride, x fastest.  Every
+// kernel is bound by HBM traffic; none of them is a contraction, so there is
+// no MFMA here.  A solid node's plane-i slot serves as the "ghost" that holds
+// the reconstructed population f_i(x_f, t+1) of the one fluid node
+// x_f = x_s + e_i that pulls from it, so the bulk kernel needs no link lookup.
+#include "lbm_internal.h"
+
+namespace mdlbm {
+namespace {
+
+template <int S>
+struct St;
+template <>
+struct St<LBM_STORE_F64> {
+    using T = double;
+    using A = double;
+    static constexpr bool dev = false;
+    static __device__ __forceinline__ double ld(const double* p, float) { return *p; }
+    static __device__ __forceinline__ void st(double* p, double v, float) { *p = v; }
+};
+template <>
+struct St<LBM_STORE_F32> {
+    using T = float;
+    using A = float;
+    static constexpr bool dev = true;
+    static __device__ __forceinline__ float ld(const float* p, float) { return *p; }
+    static __device__ __forceinline__ void st(float* p, float v, float) { *p = v; }
+};
+template <>
+struct St<LBM_STORE_F16> {
+    using T = __half;
+    using A = float;
+    static constexpr bool dev = true;
+    static __device__ __forceinline__ float ld(const __half* p, float inv)
+    {
+        return __half2float(*p) * inv;
+    }
+    static __device__ __forceinline__ void st(__half* p, float v, float sc)
+    {
+        *p = __float2half_rn(v * sc);
+    }
+};
+
+template <class A>
+__device__ __forceinline__ A W(int i);
+template <>
+__device__ __forceinline__ double W<double>(int i) { return wgt(i); }
+template <>
+__device__ __forceinline__ float W<float>(int i) { return wgtf(i); }
+
+// Equilibrium of direction i in the storage's form:
+//   plain:      feq = w rho (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u)
+//   deviation:  feq - w = w (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
+template <bool DEV, class A>
+__device__ __forceinline__ A eq_i(int i, A drho, A rho, A ux, A uy, A uz)
+{
+    const A eu = A(cx(i)) * ux + A(cy(i)) * uy + A(cz(i)) * uz;
+    const A uu = ux * ux + uy * uy + uz * uz;
+    const A poly = A(3) * eu + A(4.5) * eu * eu - A(1.5) * uu;
+    if constexpr (DEV)
+        return W<A>(i) * (drho + rho * poly);
+    else
+        return W<A>(i) * rho * (A(1) + poly);
+}
+
+// Moments of the values v[19] in the storage's form; `shift` is +1/2 for
+// pre-collision populations (u = (sum f e + F/2)/rho) and -1/2 for
+// post-collision ones (the collision turned the momentum into rho u + F/2).
+template <bool DEV, class A>
+__device__ __forceinline__ void moments(const A* v, A shift, const A* F, A& drho, A& rho, A& ux,
+                                        A& uy, A& uz)
+{
+    A s = A(0), jx = A(0), jy = A(0), jz = A(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        s += v[i];
+        if (cx(i)) jx += A(cx(i)) * v[i];
+        if (cy(i)) jy += A(cy(i)) * v[i];
+        if (cz(i)) jz += A(cz(i)) * v[i];
+    }
+    if constexpr (DEV) {
+        drho = s;
+        rho = A(1) + s;
+    } else {
+        rho = s;
+        drho = s - A(1);
+    }
+    const A ir = A(1) / rho;
+    ux = (jx + shift * F[0]) * ir;
+    uy = (jy + shift * F[1]) * ir;
+    uz = (jz + shift * F[2]) * ir;
+}
+
+// BGK collision with Guo forcing, in place:
+//   f+ = f + omega (feq - f) + (1 - omega/2) w [3 (e - u) + 9 (e.u) e].F
+template <bool DEV, class A>
+__device__ __forceinline__ void collide(A* v, A omega, const A* F)
+{
+    A drho, rho, ux, uy, uz;
+    moments<DEV, A>(v, A(0.5), F, drho, rho, ux, uy, uz);
+    const A uF = ux * F[0] + uy * F[1] + uz * F[2];
+    const A gf = A(1) - A(0.5) * omega;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const A eu = A(cx(i)) * ux + A(cy(i)) * uy + A(cz(i)) * uz;
+        const A eF = A(cx(i)) * F[0] + A(cy(i)) * F[1] + A(cz(i)) * F[2];
+        const A src = gf * W<A>(i) * (A(3) * (eF - uF) + A(9) * eu * eF);
+        v[i] = v[i] + omega * (eq_i<DEV, A>(i, drho, rho, ux, uy, uz) - v[i]) + src;
+    }
+}
+
+// Offsets of (c-1, c, c+1) along one axis and whether each lies in the domain.
+__device__ __forceinline__ void axis3(uint32_t c, uint32_t n, int per, uint32_t mul,
+                                      uint32_t o[3], bool v[3])
+{
+    o[1] = c * mul;
+    v[1] = true;
+    if (c > 0) {
+        o[0] = (c - 1) * mul;
+        v[0] = true;
+    } else {
+        o[0] = (n - 1) * mul;
+        v[0] = per != 0;
+    }
+    if (c + 1 < n) {
+        o[2] = (c + 1) * mul;
+        v[2] = true;
+    } else {
+        o[2] = 0;
+        v[2] = per != 0;
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD one
+// contiguous eighth of the lattice so that the cache lines two neighbouring
+// workgroups share (the +-1 shifts in x, rows in y) stay in one XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block()
+{
+    const uint32_t per = gridDim.x >> 3;
+    return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Bulk: one thread per node, pull f_i(x - e_i), collide, store.
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(256) void k_stream_collide(const typename St<S>::T* __restrict__ src,
+                                                        typename St<S>::T* __restrict__ dst,
+                                                        const uint8_t* __restrict__ flag, Geom g,
+                                                        Phys ph)
+{
+    using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
+    const uint32_t cell = xcd_block() * 256u + threadIdx.x;
+    if (cell >= g.ncell) return;
+    if (flag[cell]) return;  // solid: its slots are link ghosts, not fluid
+    const uint32_t nx = g.n[0], ny = g.n[1];
+    const uint32_t x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
+    uint32_t ox[3], oy[3], oz[3];
+    bool vx[3], vy[3], vz[3];
+    axis3(x, nx, g.per[0], 1u, ox, vx);
+    axis3(y, ny, g.per[1], nx, oy, vy);
+    axis3(z, g.n[2], g.per[2], nx * ny, oz, vz);
+    A f[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int sx = 1 - cx(i), sy = 1 - cy(i), sz = 1 - cz(i);
+        const bool ok = vx[sx] && vy[sy] && vz[sz];
+        // a source beyond a wall: static halfway bounce-back, f_i = f+_opp(i)(x)
+        const uint32_t s = ok ? ox[sx] + oy[sy] + oz[sz] : cell;
+        const int64_t plane = ok ? i : opp(i);
+        f[i] = St<S>::ld(src + plane * g.stride + s, ph.inv_scale);
+    }
+    A F[3];
+    A om;
+    if constexpr (DEV) {
+        F[0] = ph.Ff[0], F[1] = ph.Ff[1], F[2] = ph.Ff[2];
+        om = ph.omegaf;
+    } else {
+        F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
+        om = ph.omega;
+    }
+    collide<DEV, A>(f, om, F);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) St<S>::st(dst + (int64_t)i * g.stride + cell, f[i], ph.scale);
+}
+
+// ---------------------------------------------------------------------------
+// Links: one thread per link record of one particle (blockIdx.y).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double image_coord(int c, int L, int per, double center)
+{
+    if (!per) return (double)c;
+    const double d = (double)c - center;
+    if (d > 0.5 * L) return (double)(c - L);
+    if (d < -0.5 * L) return (double)(c + L);
+    return (double)c;
+}
+
+__device__ __forceinline__ bool wrap3(int c[3], const Geom& g)
+{
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (c[a] < 0 || c[a] >= g.n[a]) {
+            if (g.per[a])
+                c[a] = c[a] < 0 ? c[a] + g.n[a] : c[a] - g.n[a];
+            else
+                ok = false;
+        }
+    }
+    return ok;
+}
+
+__device__ __forceinline__ uint32_t node_of(const int c[3], const Geom& g)
+{
+    return (uint32_t)c[0] + (uint32_t)g.n[0] * ((uint32_t)c[1] + (uint32_t)g.n[1] * (uint32_t)c[2]);
+}
+
+template <int S>
+__device__ __forceinline__ void load_node(const typename St<S>::T* f, uint32_t node,
+                                          const Geom& g, float inv, typename St<S>::A* v)
+{
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) v[i] = St<S>::ld(f + (int64_t)i * g.stride + node, inv);
+}
+
+template <class A>
+__device__ __forceinline__ A pick(const A* v, int d)
+{
+    A r = A(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) r = (i == d) ? v[i] : r;
+    return r;
+}
+
+__device__ __forceinline__ double dsum_wave(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict__ f,
+                                                  const LinkRec* __restrict__ links,
+                                                  const uint32_t* __restrict__ cursor, int64_t cap,
+                                                  PartDev P, double* __restrict__ FT, Geom g,
+                                                  Phys ph)
+{
+    using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
+    const int p = blockIdx.y;
+    const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
+    if (blockIdx.x * 256u >= cnt) return;
+    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (l < cnt) {
+        const LinkRec r = links[(int64_t)p * cap + l];
+        const int d = r.d, db = opp(d);
+        int e[3];
+        // runtime direction: decode from the numbering
+        e[0] = (d == 1 || d == 7 || d == 9 || d == 11 || d == 13) ? 1
+             : (d == 2 || d == 8 || d == 10 || d == 12 || d == 14) ? -1 : 0;
+        e[1] = (d == 3 || d == 7 || d == 10 || d == 15 || d == 17) ? 1
+             : (d == 4 || d == 8 || d == 9 || d == 16 || d == 18) ? -1 : 0;
+        e[2] = (d == 5 || d == 11 || d == 14 || d == 15 || d == 18) ? 1
+             : (d == 6 || d == 12 || d == 13 || d == 16 || d == 17) ? -1 : 0;
+        const uint32_t nx = g.n[0], ny = g.n[1];
+        const int cs[3] = {(int)(r.node % nx), (int)((r.node / nx) % ny), (int)(r.node / (nx * ny))};
+        int cn[3] = {cs[0] - e[0], cs[1] - e[1], cs[2] - e[2]};
+        const double xp[3] = {P.pos[3 * p], P.pos[3 * p + 1], P.pos[3 * p + 2]};
+        const double vp[3] = {P.vel[3 * p], P.vel[3 * p + 1], P.vel[3 * p + 2]};
+        const double wp[3] = {P.omega[3 * p], P.omega[3 * p + 1], P.omega[3 * p + 2]};
+        wrap3(cn, g);  // for a missing point beyond a wall the node is virtual
+        double Xw[3], rr[3], uw[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // periodic axes are wrapped by wrap3; a node beyond a wall keeps
+            // its raw coordinate (a virtual missing force point)
+            const double Xn = image_coord(cn[a], g.n[a], g.per[a], xp[a]);
+            Xw[a] = Xn + r.q * (double)e[a];
+            rr[a] = Xw[a] - xp[a];
+        }
+        uw[0] = vp[0] + (wp[1] * rr[2] - wp[2] * rr[1]);
+        uw[1] = vp[1] + (wp[2] * rr[0] - wp[0] * rr[2]);
+        uw[2] = vp[2] + (wp[0] * rr[1] - wp[1] * rr[0]);
+        double out, in;
+        if (r.kind == LBM_LINK_MISSING) {
+            // treatment 2: equilibrium at (rho0, u_w) on both sides
+            out = eq_i<false, double>(d, ph.rho0 - 1.0, ph.rho0, uw[0], uw[1], uw[2]);
+            in = eq_i<false, double>(db, ph.rho0 - 1.0, ph.rho0, uw[0], uw[1], uw[2]);
+        } else {
+            A Fa[3];
+            if constexpr (DEV) {
+                Fa[0] = ph.Ff[0], Fa[1] = ph.Ff[1], Fa[2] = ph.Ff[2];
+            } else {
+                Fa[0] = ph.F[0], Fa[1] = ph.F[1], Fa[2] = ph.F[2];
+            }
+            const uint32_t xf = node_of(cn, g);
+            A v[kQ];
+            load_node<S>(f, xf, g, ph.inv_scale, v);
+            A drf, rf, uf[3];
+            moments<DEV, A>(v, A(-0.5), Fa, drf, rf, uf[0], uf[1], uf[2]);
+            const A fdf = pick(v, d);
+            const A uwa[3] = {A(uw[0]), A(uw[1]), A(uw[2])};
+            const A ebu = -(A(e[0]) * uwa[0] + A(e[1]) * uwa[1] + A(e[2]) * uwa[2]);
+            A unk;
+            if (r.kind == LBM_LINK_VIBB) {
+                int cf[3] = {cn[0] - e[0], cn[1] - e[1], cn[2] - e[2]};
+                wrap3(cf, g);
+                load_node<S>(f, node_of(cf, g), g, ph.inv_scale, v);
+                A drff, rff, uff[3];
+                moments<DEV, A>(v, A(-0.5), Fa, drff, rff, uff[0], uff[1], uff[2]);
+                const A fdff = pick(v, d);
+                const A q = A(r.q);
+                const A tq = A(2) * q, oq = A(1) - A(2) * q;
+                // non-equilibrium part extrapolated to x_d (Eq. neqd)
+                const A fneq = tq * (fdf - eq_i<DEV, A>(d, drf, rf, uf[0], uf[1], uf[2])) +
+                               oq * (fdff - eq_i<DEV, A>(d, drff, rff, uff[0], uff[1], uff[2]));
+                // density at x_d (Eq. rhod)
+                A drd, rd;
+                if (q <= A(0.5)) {
+                    drd = tq * drf + oq * drff;
+                    rd = tq * rf + oq * rff;
+                } else {
+                    drd = drf;
+                    rd = rf;
+                }
+                A ud[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const A us = (q <= A(0.5)) ? tq * uf[a] + oq * uff[a]
+                                               : (A(1) - q) / q * uf[a] + (tq - A(1)) / q * uwa[a];
+                    const A uss = (A(1) - q) / (A(1) + q) * uff[a] + tq / (A(1) + q) * uwa[a];
+                    ud[a] = us / A(3) + A(2) * uss / A(3);
+                }
+                unk = eq_i<DEV, A>(d, drd, rd, ud[0], ud[1], ud[2]) + fneq +
+                      A(6) * W<A>(d) * rf * ebu;
+            } else {
+                // treatment 1: halfway bounce-back with the moving-wall term
+                unk = fdf + A(6) * W<A>(d) * rf * ebu;
+            }
+            St<S>::st(f + (int64_t)db * g.stride + r.node, unk, ph.scale);
+            out = (double)fdf;
+            in = (double)unk;
+            if constexpr (DEV) {
+                out += wgt(d);
+                in += wgt(db);
+            }
+        }
+        // Galilean-invariant momentum exchange (Eq. mem)
+        double t[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[a] = ((double)e[a] - uw[a]) * out - (-(double)e[a] - uw[a]) * in;
+        acc[0] = t[0];
+        acc[1] = t[1];
+        acc[2] = t[2];
+        acc[3] = rr[1] * t[2] - rr[2] * t[1];
+        acc[4] = rr[2] * t[0] - rr[0] * t[2];
+        acc[5] = rr[0] * t[1] - rr[1] * t[0];
+    }
+    __shared__ double red[4][6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double s = dsum_wave(acc[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                         (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        atomicAdd(FT + 6 * p + threadIdx.x, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Refill: one thread per node uncovered since the previous classification.
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(256) void k_refill(const typename St<S>::T* __restrict__ prev,
+                                                typename St<S>::T* __restrict__ cur,
+                                                const RefillRec* __restrict__ rec, uint32_t cnt,
+                                                const uint32_t* __restrict__ own_prev, PartDev P,
+                                                Geom g, Phys ph)
+{
+    using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
+    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    if (l >= cnt) return;
+    const RefillRec r = rec[l];
+    const int p = r.part;
+    const uint32_t nx = g.n[0], ny = g.n[1];
+    const int c[3] = {(int)(r.node % nx), (int)((r.node / nx) % ny), (int)(r.node / (nx * ny))};
+    double rr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double xp = P.pos[3 * p + a];
+        rr[a] = image_coord(c[a], g.n[a], g.per[a], xp) - xp;
+    }
+    const double wp[3] = {P.omega[3 * p], P.omega[3 * p + 1], P.omega[3 * p + 2]};
+    const A un[3] = {A(P.vel[3 * p] + (wp[1] * rr[2] - wp[2] * rr[1])),
+                     A(P.vel[3 * p + 1] + (wp[2] * rr[0] - wp[0] * rr[2])),
+                     A(P.vel[3 * p + 2] + (wp[0] * rr[1] - wp[1] * rr[0]))};
+    const A r0 = A(ph.rho0), dr0 = A(ph.rho0 - 1.0);
+    A v[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        int cu[3] = {c[0] - cx(i), c[1] - cy(i), c[2] - cz(i)};
+        int cd[3] = {c[0] + cx(i), c[1] + cy(i), c[2] + cz(i)};
+        const bool iu = i > 0 && wrap3(cu, g);
+        const bool id = i > 0 && wrap3(cd, g);
+        const uint32_t nu = iu ? node_of(cu, g) : r.node;
+        const uint32_t nd = id ? node_of(cd, g) : r.node;
+        const bool up = iu && own_prev[nu] == kFluid;
+        const bool dn = id && own_prev[nd] == kFluid;
+        if (up) {
+            v[i] = St<S>::ld(prev + (int64_t)i * g.stride + nu, ph.inv_scale);  // streamed
+        } else if (dn) {
+            const A eu = A(cx(i)) * un[0] + A(cy(i)) * un[1] + A(cz(i)) * un[2];
+            v[i] = St<S>::ld(prev + (int64_t)opp(i) * g.stride + nd, ph.inv_scale) +
+                   A(6) * W<A>(i) * r0 * eu;  // bounce-back of the streamed opposite
+        } else {
+            v[i] = eq_i<DEV, A>(i, dr0, r0, un[0], un[1], un[2]);
+        }
+    }
+    A F[3];
+    A om;
+    if constexpr (DEV) {
+        F[0] = ph.Ff[0], F[1] = ph.Ff[1], F[2] = ph.Ff[2];
+        om = ph.omegaf;
+    } else {
+        F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
+        om = ph.omega;
+    }
+    collide<DEV, A>(v, om, F);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) St<S>::st(cur + (int64_t)i * g.stride + r.node, v[i], ph.scale);
+}
+
+// ---------------------------------------------------------------------------
+// Import / export
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ void k_init_eq(typename St<S>::T* f, Geom g, Phys ph, double u0x, double u0y, double u0z)
+{
+    using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= g.ncell) return;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const A v = eq_i<DEV, A>(i, A(ph.rho0 - 1.0), A(ph.rho0), A(u0x), A(u0y), A(u0z));
+        St<S>::st(f + (int64_t)i * g.stride + cell, v, ph.scale);
+    }
+}
+
+template <int S>
+__global__ void k_get(const typename St<S>::T* f, double* out, Geom g, Phys ph)
+{
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= g.ncell) return;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        double v = (double)St<S>::ld(f + (int64_t)i * g.stride + cell, ph.inv_scale);
+        if constexpr (St<S>::dev) v += wgt(i);
+        out[(int64_t)i * g.ncell + cell] = v;
+    }
+}
+
+template <int S>
+__global__ void k_set(typename St<S>::T* f, const double* in, Geom g, Phys ph)
+{
+    using A = typename St<S>::A;
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= g.ncell) return;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        double v = in[(int64_t)i * g.ncell + cell];
+        if constexpr (St<S>::dev) v -= wgt(i);
+        St<S>::st(f + (int64_t)i * g.stride + cell, A(v), ph.scale);
+    }
+}
+
+__global__ void k_zero(double* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_split(const double* FT, double* F, double* T, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    for (int a = 0; a < 3; ++a) {
+        F[3 * i + a] = FT[6 * i + a];
+        T[3 * i + a] = FT[6 * i + 3 + a];
+    }
+}
+
+inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
+
+template <template <int> class Fn, class... Args>
+hipError_t dispatch(int storage, Args&&... args)
+{
+    switch (storage) {
+    case LBM_STORE_F64: return Fn<LBM_STORE_F64>::run(args...);
+    case LBM_STORE_F32: return Fn<LBM_STORE_F32>::run(args...);
+    case LBM_STORE_F16: return Fn<LBM_STORE_F16>::run(args...);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+struct RunInit {
+    static hipError_t run(lbm_ctx* c, void* f)
+    {
+        hipLaunchKernelGGL(k_init_eq<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0, c->stream,
+                           (typename St<S>::T*)f, c->geom, c->phys, c->cfg.u0[0], c->cfg.u0[1],
+                           c->cfg.u0[2]);
+        return hipGetLastError();
+    }
+};
+
+template <int S>
+struct RunSC {
+    static hipError_t run(lbm_ctx* c, const void* src, void* dst)
+    {
+        uint32_t nb = blocks_for(c->geom.ncell);
+        nb = (nb + 7u) & ~7u;  // whole rounds over the 8 XCDs
+        hipLaunchKernelGGL(k_stream_collide<S>, dim3(nb), dim3(256), 0, c->stream,
+                           (const typename St<S>::T*)src, (typename St<S>::T*)dst, c->flag, c->geom,
+                           c->phys);
+        return hipGetLastError();
+    }
+};
+
+template <int S>
+struct RunBC {
+    static hipError_t run(lbm_ctx* c, void* f, const PartDev& P)
+    {
+        if (c->cfg.n_particles == 0 || c->link_max == 0) return hipSuccess;
+        dim3 grid(blocks_for(c->link_max), c->cfg.n_particles);
+        hipLaunchKernelGGL(k_boundary<S>, grid, dim3(256), 0, c->stream, (typename St<S>::T*)f,
+                           c->links, c->link_cursor, c->link_cap, P, c->FT, c->geom, c->phys);
+        return hipGetLastError();
+    }
+};
+
+template <int S>
+struct RunRefill {
+    static hipError_t run(lbm_ctx* c, const void* fprev, void* fcur, const uint32_t* own_prev,
+                          const PartDev& P)
+    {
+        if (c->refill_total == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_refill<S>, dim3(blocks_for(c->refill_total)), dim3(256), 0, c->stream,
+                           (const typename St<S>::T*)fprev, (typename St<S>::T*)fcur, c->refill,
+                           (uint32_t)c->refill_total, own_prev, P, c->geom, c->phys);
+        return hipGetLastError();
+    }
+};
+
+template <int S>
+struct RunGet {
+    static hipError_t run(lbm_ctx* c, const void* f, double* out)
+    {
+        hipLaunchKernelGGL(k_get<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0, c->stream,
+                           (const typename St<S>::T*)f, out, c->geom, c->phys);
+        return hipGetLastError();
+    }
+};
+
+template <int S>
+struct RunSet {
+    static hipError_t run(lbm_ctx* c, void* f, const double* in)
+    {
+        hipLaunchKernelGGL(k_set<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0, c->stream,
+                           (typename St<S>::T*)f, in, c->geom, c->phys);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+hipError_t launch_init_equilibrium(lbm_ctx* c, void* f)
+{
+    return dispatch<RunInit>(c->cfg.storage, c, f);
+}
+hipError_t launch_stream_collide(lbm_ctx* c, const void* src, void* dst)
+{
+    return dispatch<RunSC>(c->cfg.storage, c, src, dst);
+}
+hipError_t launch_boundary(lbm_ctx* c, void* f, const PartDev& P)
+{
+    return dispatch<RunBC>(c->cfg.storage, c, f, P);
+}
+hipError_t launch_refill(lbm_ctx* c, const void* fprev, void* fcur, const uint32_t* own_prev,
+                         const PartDev& P)
+{
+    return dispatch<RunRefill>(c->cfg.storage, c, fprev, fcur, own_prev, P);
+}
+hipError_t launch_get_populations(lbm_ctx* c, const void* f, double* out)
+{
+    return dispatch<RunGet>(c->cfg.storage, c, f, out);
+}
+hipError_t launch_set_populations(lbm_ctx* c, void* f, const double* in)
+{
+    return dispatch<RunSet>(c->cfg.storage, c, f, in);
+}
+hipError_t launch_zero_f64(lbm_ctx* c, double* p, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n)), dim3(256), 0, c->stream, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_split_forces(const lbm_ctx* c, double* F, double* T)
+{
+    const int n = c->cfg.n_particles;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split, dim3(blocks_for(n)), dim3(256), 0, c->stream, c->FT, F, T, n);
+    return hipGetLastError();
+}
+
+}  // namespace mdlbm

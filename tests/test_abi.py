@@ -1,0 +1,86 @@
+"""The C-ABI library loads and exports every entry point that include/mdlbm.h
+declares; host-only argument checks work without a GPU."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_2206_11634_amd import binding as B
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "mdlbm.h"
+
+
+def _declared():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not B.LIB_PATH.exists():
+        from paper_2206_11634_amd import build
+        build.build()
+    return B.load()
+
+
+def test_header_declares_the_hot_path_calls():
+    names = _declared()
+    for n in ("lbm_init", "lbm_classify_nodes", "lbm_step", "lbm_particle_forces", "dem_step"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(B.EXPORTS) == set(names)
+
+
+def _cfg(**kw):
+    c = B.LbmConfig()
+    c.nx, c.ny, c.nz = kw.get("dims", (16, 12, 10))
+    c.periodic = (ctypes.c_int32 * 3)(*kw.get("periodic", (1, 0, 1)))
+    c.tau = kw.get("tau", 0.8)
+    c.rho0 = 1.0
+    c.storage = kw.get("storage", 1)
+    c.treatments = 3
+    c.n_particles = kw.get("n_particles", 0)
+    c.box_half = kw.get("box_half", 4)
+    return c
+
+
+@pytest.mark.parametrize("storage,es", [(0, 8), (1, 4), (2, 2)])
+def test_query_sizes(lib, storage, es):
+    s = B.lbm_query_sizes(_cfg(storage=storage))
+    assert s.ncell == 16 * 12 * 10
+    assert s.cell_stride % 64 == 0 and s.cell_stride >= s.ncell
+    assert s.population_bytes == 19 * s.cell_stride * es
+    assert s.owner_bytes == 4 * s.ncell and s.flag_bytes == s.ncell
+
+
+def test_query_sizes_rejects_bad_input(lib):
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_query_sizes(_cfg(dims=(0, 4, 4)))
+    assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_query_sizes(_cfg(storage=7))
+    assert e.value.code == B.LBM_EINVAL
+
+
+def test_init_rejects_bad_arguments_before_touching_the_device(lib):
+    bufs = B.LbmBuffers()
+    ctx = ctypes.c_void_p()
+    for cfg in (_cfg(tau=0.5), _cfg(), _cfg(n_particles=2, box_half=7, dims=(16, 16, 16))):
+        rc = lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx))
+        assert rc == B.LBM_EINVAL
+        assert lib.lbm_last_error(None)
+    # a periodic axis too short for the particle box
+    fake = (B._P * 2)(1, 2)
+    bufs = B.LbmBuffers(fake, fake, 3)
+    cfg = _cfg(n_particles=1, box_half=6, dims=(16, 40, 40), periodic=(1, 0, 0))
+    assert lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)) == B.LBM_EINVAL
+    assert b"2*box_half" in lib.lbm_last_error(None)

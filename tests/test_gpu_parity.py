@@ -1,0 +1,188 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Geometry (owners, link records including q, refill sets) must be bit-exact.
+Populations and forces must agree within the storage's tolerance:
+  FP64 plain: populations 1e-12, force/torque relative 1e-10;
+  FP32 deviations: populations 2e-7, force/torque relative 1e-4;
+  FP16 deviations: populations 1e-4, force/torque relative 2e-2.
+Relative force error = max over steps of |F_gpu - F_oracle| divided by the
+largest |F_oracle| of that particle over the run.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2206_11634_amd import binding as B
+from paper_2206_11634_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+POP_TOL = {"f64": 1e-12, "f32": 2e-7, "f16": 1e-4}
+FORCE_TOL = {"f64": 1e-10, "f32": 1e-4, "f16": 2e-2}
+
+
+def _compare_geometry(gpu, ora, tag):
+    own = gpu.owner()
+    assert np.array_equal(own, ora.owner), f"{tag}: owner planes differ"
+    L = gpu.links()
+    R = ora.links
+    assert len(L["node"]) == len(R), f"{tag}: link count {len(L['node'])} vs {len(R)}"
+    assert np.array_equal(L["node"], R.node), tag
+    assert np.array_equal(L["d"], R.d), tag
+    assert np.array_equal(L["kind"], R.kind), tag
+    assert np.array_equal(L["part"], R.part), tag
+    assert np.array_equal(L["q"].view(np.uint64), R.q.view(np.uint64)), f"{tag}: q not bit-exact"
+    nodes, parts = gpu.refill()
+    assert np.array_equal(nodes, ora.refill_nodes), f"{tag}: refill sets differ"
+    if len(nodes):
+        assert np.array_equal(parts, ora.owner_prev[nodes] - 1)
+
+
+def _run(lat, ps, storage, steps, treat=3, check_geometry=True, tag=""):
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat)
+    parts = B.DeviceParticles(ps)
+    ora = O.Oracle(lat, treat=treat)
+    Fo_all, Fg_all, To_all, Tg_all = [], [], [], []
+    refilled = 0
+    for n in range(steps):
+        P = W.prescribed_state(ps, lat, float(n))
+        parts.set_state(P)
+        gpu.classify(parts)
+        ora.classify(P)
+        if check_geometry:
+            _compare_geometry(gpu, ora, f"{tag} step {n}")
+        refilled += len(ora.refill_nodes)
+        gpu.step(parts)
+        Fo, To = ora.step(P)
+        Fg, Tg = (t.cpu().numpy().copy() for t in gpu.forces())
+        Fo_all.append(Fo), To_all.append(To), Fg_all.append(Fg), Tg_all.append(Tg)
+    fg = gpu.populations()
+    fl = ora.owner == 0
+    pop_err = np.abs(fg[:, fl] - ora.f[:, fl]).max()
+    gpu.close()
+    res = dict(pop_err=pop_err, refilled=refilled)
+    for name, g, o in (("F", Fg_all, Fo_all), ("T", Tg_all, To_all)):
+        g, o = np.array(g), np.array(o)
+        scale = np.abs(o).max(axis=(0, 2))
+        err = np.abs(g - o).max(axis=(0, 2)) / np.maximum(scale, 1e-30)
+        res[name] = err.max() if len(err) else 0.0
+    return res
+
+
+GEOM_CASES = [
+    dict(seed=1, dims=(28, 20, 26), periodic=(1, 0, 1), n_particles=3),
+    dict(seed=2, dims=(27, 26, 28), periodic=(1, 1, 1), n_particles=3),
+    dict(seed=3, dims=(17, 21, 19), periodic=(0, 0, 0), n_particles=3),
+    dict(seed=4, dims=(24, 27, 18), periodic=(0, 1, 0), n_particles=4),
+]
+
+
+@pytest.mark.parametrize("case", GEOM_CASES, ids=lambda c: f"seed{c['seed']}")
+def test_geometry_and_plain_fp64_step_parity(case):
+    lat, ps = W.tiny_case(case["seed"], dims=case["dims"], periodic=case["periodic"],
+                          n_particles=case["n_particles"], diameter_range=(4.0, 7.0),
+                          speed=0.06, spin=0.006, u0=(0.02, -0.01, 0.005))
+    r = _run(lat, ps, "f64", 8, tag=f"seed{case['seed']}")
+    assert r["refilled"] > 0
+    assert r["pop_err"] < POP_TOL["f64"], r
+    assert r["F"] < FORCE_TOL["f64"] and r["T"] < FORCE_TOL["f64"], r
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_deviation_storage_parity(storage):
+    lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
+                          diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
+                          u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
+    r = _run(lat, ps, storage, 8, tag=storage)
+    assert r["pop_err"] < POP_TOL[storage], r
+    assert r["F"] < FORCE_TOL[storage] and r["T"] < FORCE_TOL[storage], r
+
+
+def test_ragged_multi_tile_lattice_with_walls_and_missing_points():
+    """45 x 38 x 33 nodes (not a multiple of the 256-thread tile), walls in y,
+    bodies close to each other and to a wall."""
+    lat, ps = W.tiny_case(12, dims=(45, 38, 33), periodic=(1, 0, 1), n_particles=6,
+                          diameter_range=(6.0, 10.0), speed=0.06, spin=0.006,
+                          u0=(0.02, 0.0, -0.01))
+    r = _run(lat, ps, "f32", 5, tag="ragged")
+    assert r["pop_err"] < POP_TOL["f32"], r
+    assert r["F"] < FORCE_TOL["f32"], r
+
+
+@pytest.mark.parametrize("treat", [B.TREAT_VIBB, B.TREAT_MISSING, 0])
+def test_treatment_switches(treat):
+    lat, ps = W.tiny_case(5, dims=(28, 26, 18), periodic=(1, 1, 0), n_particles=3,
+                          diameter_range=(5.0, 7.0), speed=0.06, spin=0.006, u0=(0.01, 0.0, 0.0))
+    r = _run(lat, ps, "f64", 4, treat=treat, tag=f"treat{treat}")
+    assert r["pop_err"] < POP_TOL["f64"] and r["F"] < FORCE_TOL["f64"], r
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_poiseuille_channel_without_particles(storage):
+    tau = 0.5 + np.sqrt(3.0) / 4.0
+    H, g = 12, 1e-6
+    lat = W.LatticeSpec(5, H, 3, (1, 0, 1), tau=tau, body_force=(g, 0, 0))
+    ps = W.make_particles([], np.zeros((0, 3)), np.zeros((0, 4)), 1.0)
+    gpu = B.Lattice(lat, storage=storage)
+    parts = B.DeviceParticles(ps)
+    ora = O.Oracle(lat)
+    ora.classify(ps)
+    gpu.classify(parts)
+    for _ in range(300):
+        gpu.step(parts)
+        ora.step(ps)
+    fg = gpu.populations()
+    assert np.abs(fg - ora.f).max() < (1e-13 if storage == "f64" else 1e-8)
+    gpu.close()
+
+
+def test_rest_state_is_exact_in_deviation_storage():
+    """Particles and fluid at rest: the FP32 and FP16 deviations stay exactly 0."""
+    lat, ps = W.tiny_case(11, dims=(28, 16, 14), periodic=(1, 0, 0), n_particles=3)
+    for storage in ("f32", "f16"):
+        gpu = B.Lattice.for_particles(lat, ps, storage=storage)
+        parts = B.DeviceParticles(ps)
+        for _ in range(5):
+            gpu.classify(parts)
+            gpu.step(parts)
+        F, T = (t.cpu().numpy() for t in gpu.forces())
+        own = gpu.owner()
+        f = gpu.populations()
+        w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+        assert np.abs(f[:, own == 0] - w[:, None]).max() < 1e-16
+        assert np.abs(F).max() < 1e-13 and np.abs(T).max() < 1e-12
+        gpu.close()
+
+
+def test_dem_parity_with_contacts():
+    lat = W.LatticeSpec(48, 40, 40, (1, 0, 1))
+    rng = np.random.default_rng(31)
+    shapes = [W.sphere_shape(10.0, 0.3)]
+    pts = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.5, 0.7, 0]])
+    shapes.append(W.metaball_shape(pts, rng.uniform(0.5, 1.5, 3) * 0.2, 0.3, d_eq=10.0,
+                                   samples_per_unit=3.0))
+    shapes.append(W.sphere_shape(8.0, 0.3))
+    pos = [[14.0, 20.0, 20.0], [24.6, 20.5, 19.8], [20.0, 4.0, 21.0]]
+    quats = [W.random_quaternion(rng) for _ in range(3)]
+    ps = W.make_particles(shapes, pos, quats, 1.5,
+                          vel=np.array([[0.02, 0, 0], [-0.02, 0.0, 0.0], [0.0, -0.02, 0.0]]),
+                          omega=np.array([[0, 0, 0.01], [0.0, 0.005, 0], [0.0, 0.0, 0.0]]))
+    kn = 2.0
+    prm_o = O.DemParams(kn=kn, eta_n=3.0, kt=kn / 2, eta_t=0.5, mu_s=0.3,
+                        gravity=(0.0, -1e-4, 0.0), rho_f=1.0)
+    prm_g = B.DemParams.make(kn=kn, eta_n=3.0, kt=kn / 2, eta_t=0.5, mu_s=0.3,
+                             gravity=(0.0, -1e-4, 0.0), rho_f=1.0)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    parts = B.DeviceParticles(ps)
+    dem = O.OracleDEM(ps, lat)
+    P = ps.copy()
+    Fh = np.zeros((3, 3))
+    for n in range(30):
+        gpu.dem(parts, 10, 0.1, prm_g)
+        dem.step(P, Fh, Fh, prm_o, 10, 0.1)
+    G = parts.to_host(ps)
+    gpu.close()
+    assert np.abs(dem.fc).max() > 0 or np.abs(P.vel - ps.vel).max() > 1e-3
+    for k in ("pos", "vel", "omega", "quat", "world_pts"):
+        a, b = getattr(G, k), getattr(P, k)
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
