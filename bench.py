@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled sharp-interface metaball LBM step on one MI355X.
+
+One step = lbm_classify_nodes (FP64 classification, links, refill) +
+lbm_step (VIBB / halfway reconstruction, momentum exchange, fused
+stream-collide) + lbm_particle_forces + dem_step (FP64 metaball DEM,
+sub-cycled), on the 512^3 sedimentation workload (1000 metaballs, 20% solids)
+with synthetic seeded inputs.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline (FP32/FP16-store vs plain), drag err; adjoint steps/s"
+HBM_PEAK_GBS = 8000.0
+BYTES = {"f64": 8, "f32": 4, "f16": 2}
+
+
+def run_storage(lat, ps, meta, storage, steps, warmup, profile=True):
+    import torch
+    from paper_2206_11634_amd import binding as B
+    from paper_2206_11634_amd import workloads as W
+
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage)
+    parts = B.DeviceParticles(ps)
+    prm = B.DemParams.make(**W.dem_defaults(ps, gravity=meta["gravity"]))
+    n_sub = int(meta.get("n_sub", 10))
+    gpu.classify(parts)
+
+    def one_step():
+        gpu.step(parts)
+        gpu.forces()
+        gpu.dem(parts, n_sub, 1.0 / n_sub, prm)
+        gpu.classify(parts)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    if profile:
+        gpu.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = gpu.profile_read() if profile else {}
+    if profile:
+        gpu.profile(False)
+    n_solid = int(torch.count_nonzero(gpu.flag[: gpu.ncell]).item())
+    counts = gpu.classify(parts)
+    gpu.close()
+    del gpu, parts
+    torch.cuda.empty_cache()
+    ms = (t1 - t0) * 1e3 / steps
+    return dict(ms_per_step=ms, n_solid=n_solid, prof=prof, n_links=int(counts.n_links),
+                n_refill=int(counts.n_refill))
+
+
+def bulk_roofline(res, lat, storage):
+    """Algorithmic bytes of one stream-collide launch: every fluid node reads
+    and writes 19 populations; every node reads its 1-byte flag."""
+    ncell = lat.ncell
+    nfluid = ncell - res["n_solid"]
+    bytes_launch = nfluid * 2 * 19 * BYTES[storage] + ncell * 1
+    ms, n = res["prof"]["bulk"]
+    avg_ms = ms / max(n, 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="k_stream_collide", avg_ms=round(avg_ms, 4),
+                bytes_per_launch=int(bytes_launch),
+                bytes_per_fluid_cell=2 * 19 * BYTES[storage] + 1)
+
+
+def cpu_baseline(seconds=15.0):
+    """The FP64 oracle on a bounded sample of the same workload: the
+    sedimentation layout at 128^3 with 8 metaballs at 20% solids."""
+    from oracle import oracle as O
+    from paper_2206_11634_amd import workloads as W
+
+    lat, ps, meta = W.config_c4(seed=44, n=128, per_axis=2)
+    o = O.Oracle(lat)
+    o.classify(ps)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(ps)
+        o.classify(ps)
+        steps += 1
+        if time.perf_counter() - t0 > seconds and steps >= 2:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=round(lat.ncell * steps / dt / 1e6, 3), unit="MLUPS",
+                cores=O.num_threads(), kind="oracle",
+                sample=f"FP64 oracle classify+step on the 128^3 sedimentation layout "
+                       f"(8 metaballs, 20% solids), {steps} steps in {dt:.1f} s")
+
+
+def drag_error(steps=200):
+    """Force/torque error of FP32 and FP16 storage against the FP64 oracle on
+    the 40x40x80 single-sphere box, the sphere moving down at 0.01 lu/step
+    (prescribed) and spinning slowly."""
+    from oracle import oracle as O
+    from paper_2206_11634_amd import binding as B
+    from paper_2206_11634_amd import workloads as W
+
+    lat, ps, meta = W.config_c1()
+    ps.vel[:] = [0.0, 0.0, -0.01]
+    ps.omega[:] = [0.0, 0.002, 0.0]
+    ora = O.Oracle(lat)
+    out = {}
+    traj = [W.prescribed_state(ps, lat, float(n)) for n in range(steps)]
+    Fo, To = [], []
+    for n in range(steps):
+        ora.classify(traj[n])
+        F, T = ora.step(traj[n])
+        Fo.append(F[0].copy())
+        To.append(T[0].copy())
+    Fo, To = np.array(Fo), np.array(To)
+    for storage in ("f32", "f16"):
+        gpu = B.Lattice.for_particles(lat, ps, storage=storage)
+        parts = B.DeviceParticles(ps)
+        Fg, Tg = [], []
+        for n in range(steps):
+            parts.set_state(traj[n])
+            gpu.classify(parts)
+            gpu.step(parts)
+            F, T = gpu.forces()
+            Fg.append(F[0].cpu().numpy().copy())
+            Tg.append(T[0].cpu().numpy().copy())
+        gpu.close()
+        eF = float(np.abs(np.array(Fg) - Fo).max() / np.abs(Fo).max())
+        eT = float(np.abs(np.array(Tg) - To).max() / np.abs(To).max())
+        out[storage] = dict(force=eF, torque=eT)
+    out["workload"] = f"c1 40x40x80 sphere d=10, prescribed descent, {steps} steps"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--variants", default="f16,f64",
+                    help="other storages timed on the same workload (comma list, or none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-drag", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the lattice update here runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2206_11634_amd import workloads as W
+
+    lat, ps, meta = W.WORKLOADS[args.workload]()
+    print(f"[bench] workload {meta['name']}: {lat.nx}x{lat.ny}x{lat.nz}, {ps.n} particles",
+          file=sys.stderr, flush=True)
+    main_res = run_storage(lat, ps, meta, args.storage, args.steps, args.warmup)
+    print(f"[bench] {args.storage}: {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s and s != "none" and s != args.storage]:
+        r = run_storage(lat, ps, meta, v, max(3, min(args.steps, 10)), 2)
+        variants[v] = r
+        print(f"[bench] {v}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    ncell = lat.ncell
+    mlups = ncell / (main_res["ms_per_step"] * 1e-3) / 1e6
+    nfluid = ncell - main_res["n_solid"]
+    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in main_res["prof"].items() if v[1]}
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic (seeded metaball suspension; no dataset)",
+        "config": {
+            "workload": meta["name"],
+            "lattice": [lat.nx, lat.ny, lat.nz],
+            "periodic": list(lat.periodic),
+            "particles": ps.n,
+            "storage": args.storage,
+            "tau": lat.tau,
+            "dem_substeps": meta.get("n_sub", 10),
+            "step": "classify + step + forces + dem",
+        },
+        "fluid_mlups": round(nfluid / (main_res["ms_per_step"] * 1e-3) / 1e6, 1),
+        "phase_ms_per_launch": phases,
+        "links": main_res["n_links"],
+        "refills_last_step": main_res["n_refill"],
+        "roofline": bulk_roofline(main_res, lat, args.storage),
+    }
+    for v, r in variants.items():
+        line.setdefault("storage_variants", {})[v] = dict(
+            mlups=round(ncell / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+            ms_per_step=round(r["ms_per_step"], 4),
+            roofline_frac=bulk_roofline(r, lat, v)["frac"])
+    if "f64" in variants:
+        line["speedup_vs_plain_f64"] = round(variants["f64"]["ms_per_step"] /
+                                             main_res["ms_per_step"], 3)
+    if not args.no_drag:
+        line["drag_err"] = drag_error()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

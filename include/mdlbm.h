@@ -225,6 +225,31 @@ int lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
 /* Block until the context's stream has drained; EDEVICE on a device error. */
 int lbm_synchronize(lbm_ctx* ctx);
 
+/* ---- kernel timing (hipEvent pairs around each launch group) ------------ */
+
+typedef enum {
+    LBM_PHASE_BULK = 0,      /* fused stream-collide of lbm_step (one kernel) */
+    LBM_PHASE_BOUNDARY = 1,  /* link reconstruction + momentum exchange of lbm_step */
+    LBM_PHASE_CLASSIFY = 2,  /* geometry kernels of lbm_classify_nodes */
+    LBM_PHASE_REFILL = 3,    /* refill kernel of lbm_classify_nodes */
+    LBM_PHASE_DEM = 4,       /* all substeps of one dem_step */
+    LBM_PHASE_COUNT = 8
+} lbm_phase;
+
+typedef struct {
+    double ms[LBM_PHASE_COUNT];        /* summed GPU time of the phase's launch groups */
+    int64_t launches[LBM_PHASE_COUNT]; /* number of launch groups timed */
+} lbm_profile;
+
+/* Start (on != 0) or stop timing; starting clears the accumulated figures.
+ * While on, every launch group is bracketed by hipEventRecord on the
+ * context's stream. */
+int lbm_profile_enable(lbm_ctx* ctx, int on);
+
+/* Synchronise the stream and return the figures accumulated since timing was
+ * started. */
+int lbm_profile_read(lbm_ctx* ctx, lbm_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

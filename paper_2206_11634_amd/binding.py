@@ -71,9 +71,16 @@ class DemParams(ctypes.Structure):
                    (ctypes.c_double * 3)(*gravity), rho_f)
 
 
+class LbmProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+
+
+PHASES = ("bulk", "boundary", "classify", "refill", "dem")
+
 EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_classify_nodes",
            "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
-           "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize"]
+           "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
+           "lbm_profile_enable", "lbm_profile_read"]
 
 _lib = None
 
@@ -103,6 +110,8 @@ def load(path: Path | None = None):
         "lbm_get_populations": [_P, _P],
         "lbm_set_populations": [_P, _P],
         "lbm_synchronize": [_P],
+        "lbm_profile_enable": [_P, ctypes.c_int],
+        "lbm_profile_read": [_P, ctypes.POINTER(LbmProfile)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -274,6 +283,14 @@ class Lattice:
 
     def sync(self):
         lbm_synchronize(self.ctx)
+
+    def profile(self, on: bool):
+        _check(load().lbm_profile_enable(self.ctx, int(bool(on))), self.ctx)
+
+    def profile_read(self) -> dict:
+        out = LbmProfile()
+        _check(load().lbm_profile_read(self.ctx, ctypes.byref(out)), self.ctx)
+        return {name: (out.ms[i], int(out.launches[i])) for i, name in enumerate(PHASES)}
 
     # inspection
     def owner(self) -> np.ndarray:

@@ -85,12 +85,46 @@ hipError_t alloc(T** p, size_t count)
     return hipMalloc((void**)p, count * sizeof(T));
 }
 
+hipEvent_t take_event(lbm_ctx* c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets the launches of one phase with a hipEvent pair while timing is on.
+struct PhaseTimer {
+    lbm_ctx* c;
+    int phase;
+    hipEvent_t start = nullptr;
+    PhaseTimer(lbm_ctx* ctx, int ph) : c(ctx), phase(ph)
+    {
+        if (c->prof) {
+            start = take_event(c);
+            if (start) (void)hipEventRecord(start, c->stream);
+        }
+    }
+    ~PhaseTimer()
+    {
+        if (!start) return;
+        hipEvent_t stop = take_event(c);
+        if (!stop) return;
+        (void)hipEventRecord(stop, c->stream);
+        c->timed.push_back({phase, start, stop});
+    }
+};
+
 std::string err_text(uint32_t bits)
 {
     std::string s;
     if (bits & 1u) s += "particle centre outside [0,n) on a periodic axis or not finite; ";
     if (bits & 2u) s += "metaball weight K or surface level c0 not positive; ";
-    if (bits & 4u) s += "particle body reaches beyond box_half - 1 of its centre; ";
+    if (bits & 4u) s += "particle body may reach beyond box_half - 1 of its centre; ";
     if (bits & 8u) s += "particle has no control points or more than 64; ";
     return s;
 }
@@ -180,6 +214,7 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     c->refill_cap = std::max<int64_t>(1 << 16, (int64_t)np * S2);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = alloc(&c->box_hist, (size_t)3 * 3 * std::max(np, 1));
+    if (e == hipSuccess) e = alloc(&c->ball_hist, (size_t)3 * 4 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->link_cursor, (size_t)kCursorPad * std::max(np, 1));
     if (e == hipSuccess && np) e = alloc(&c->links, (size_t)np * c->link_cap);
     if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
@@ -220,6 +255,7 @@ int lbm_destroy(lbm_ctx* c)
     if (!c) return LBM_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->box_hist);
+    (void)hipFree(c->ball_hist);
     (void)hipFree(c->links);
     (void)hipFree(c->link_cursor);
     (void)hipFree(c->refill);
@@ -230,6 +266,11 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->hist_pp);
     (void)hipFree(c->hist_pw);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
+    for (auto& t : c->timed) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
     delete c;
     return LBM_OK;
 }
@@ -264,10 +305,13 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->host_stage[0])
             return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[0]));
-        if (k >= 2) HIPCHK(c, launch_clear_boxes(c, own_new, slot_prev2, np));
-        HIPCHK(c, launch_mark(c, own_new, Pd, slot));
-        if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
-        HIPCHK(c, launch_links(c, own_new, Pd, slot));
+        {
+            PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
+            if (k >= 2) HIPCHK(c, launch_clear_boxes(c, own_new, slot_prev2, np));
+            HIPCHK(c, launch_mark(c, own_new, Pd, slot));
+            if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
+            HIPCHK(c, launch_links(c, own_new, Pd, slot));
+        }
         for (int attempt = 0;; ++attempt) {
             HIPCHK(c, hipMemcpyAsync(c->host_stage, c->refill_cursor, sizeof(uint32_t),
                                      hipMemcpyDeviceToHost, c->stream));
@@ -312,6 +356,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
         if (c->refill_total > 0) {
             // populations of the time level the previous classification describes
             const void* src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
+            PhaseTimer tm(c, LBM_PHASE_REFILL);
             HIPCHK(c, launch_refill(c, src, c->f[c->cur], own_prev, Pd));
         }
     } else {
@@ -335,9 +380,15 @@ int lbm_step(lbm_ctx* c, const lbm_particles* P)
     int rc = check_particles(c, P, false);
     if (rc) return rc;
     const int np = c->cfg.n_particles;
-    HIPCHK(c, launch_zero_f64(c, c->FT, 6 * (int64_t)np));
-    if (np > 0 && c->n_classify > 0) HIPCHK(c, launch_boundary(c, c->f[c->cur], to_dev(P)));
-    HIPCHK(c, launch_stream_collide(c, c->f[c->cur], c->f[1 - c->cur]));
+    {
+        PhaseTimer tm(c, LBM_PHASE_BOUNDARY);
+        HIPCHK(c, launch_zero_f64(c, c->FT, 6 * (int64_t)np));
+        if (np > 0 && c->n_classify > 0) HIPCHK(c, launch_boundary(c, c->f[c->cur], to_dev(P)));
+    }
+    {
+        PhaseTimer tm(c, LBM_PHASE_BULK);
+        HIPCHK(c, launch_stream_collide(c, c->f[c->cur], c->f[1 - c->cur]));
+    }
     c->cur = 1 - c->cur;
     c->stepped_since_classify = true;
     return LBM_OK;
@@ -369,6 +420,7 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
         HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * np * np * 8, c->stream));
         HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));
     }
+    PhaseTimer tm(c, LBM_PHASE_DEM);
     HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm));
     return LBM_OK;
 }
@@ -445,6 +497,50 @@ int lbm_synchronize(lbm_ctx* c)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+static int profile_collect(lbm_ctx* c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& t : c->timed) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, t.start, t.stop));
+        if (t.phase >= 0 && t.phase < LBM_PHASE_COUNT) {
+            c->prof_ms[t.phase] += ms;
+            c->prof_n[t.phase] += 1;
+        }
+        c->event_pool.push_back(t.start);
+        c->event_pool.push_back(t.stop);
+    }
+    c->timed.clear();
+    return LBM_OK;
+}
+
+int lbm_profile_enable(lbm_ctx* c, int on)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    int rc = profile_collect(c);
+    if (rc) return rc;
+    if (on) {
+        for (int i = 0; i < LBM_PHASE_COUNT; ++i) {
+            c->prof_ms[i] = 0.0;
+            c->prof_n[i] = 0;
+        }
+    }
+    c->prof = on != 0;
+    return LBM_OK;
+}
+
+int lbm_profile_read(lbm_ctx* c, lbm_profile* out)
+{
+    if (!c || !out) return fail(c, LBM_EINVAL, "null argument");
+    int rc = profile_collect(c);
+    if (rc) return rc;
+    for (int i = 0; i < LBM_PHASE_COUNT; ++i) {
+        out->ms[i] = c->prof_ms[i];
+        out->launches[i] = c->prof_n[i];
+    }
     return LBM_OK;
 }
 

@@ -10,7 +10,8 @@
 //
 // Work is organised per particle: a particle's nodes lie in a fixed-size box
 // of (2h+1)^3 nodes around floor(x_p), walked in tiles of 256 box cells, one
-// workgroup per (tile, particle).  Box coordinates are unwrapped, so on a
+// workgroup per (tile, particle); cells outside the particle's bounding ball
+// are skipped.  Box coordinates are unwrapped, so on a
 // periodic axis they are exactly the node's image nearest x_p (the box is
 // narrower than half the period).
 #pragma clang fp contract(off)
@@ -141,8 +142,12 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t count, uint32_t* curso
 
 // ---------------------------------------------------------------------------
 
-// Box origin of every particle, and input checks.
-__global__ void k_boxes(PartDev P, int h, int* boxes, uint32_t* err, Geom g)
+// Box origin and body radius of every particle, and input checks.  At
+// distance d > max|x_i - x_p| from the centre, M <= B(d) = sum K_i/(d - |x_i - x_p|)^2,
+// which decreases in d, so the body lies within the root R of B(R) = c0.  The
+// box must hold the ball of radius h - 1 (B(h-1) < c0); R itself lets the
+// kernels skip box cells that cannot be solid.
+__global__ void k_boxes(PartDev P, int h, int* boxes, double* ball, uint32_t* err, Geom g)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P.n) return;
@@ -155,11 +160,11 @@ __global__ void k_boxes(PartDev P, int h, int* boxes, uint32_t* err, Geom g)
     }
     const int a0 = P.off[p], n = P.off[p + 1] - a0;
     if (n < 1 || n > kMaxCtrl) bad |= 8u;
-    double sk = 0.0, rmax = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const double k = P.K[a0 + i];
-        if (!(k > 0.0)) bad |= 2u;
-        sk += k;
+    const double c0 = P.c0[p];
+    if (!(c0 > 0.0)) bad |= 2u;
+    double rmax = 0.0;
+    for (int i = 0; i < min(n, kMaxCtrl); ++i) {
+        if (!(P.K[a0 + i] > 0.0)) bad |= 2u;
         double r2 = 0.0;
         for (int a = 0; a < 3; ++a) {
             const double d = P.wpts[3 * (int64_t)(a0 + i) + a] - xp[a];
@@ -167,31 +172,67 @@ __global__ void k_boxes(PartDev P, int h, int* boxes, uint32_t* err, Geom g)
         }
         rmax = fmax(rmax, sqrt(r2));
     }
-    const double c0 = P.c0[p];
-    if (!(c0 > 0.0)) bad |= 2u;
-    // M >= c0 needs some control point within sqrt(sum K / c0)
-    const double R = rmax + sqrt(sk / c0);
-    if (!(R <= (double)(h - 1))) bad |= 4u;
+    auto bound = [&](double d) {
+        double s = 0.0;
+        for (int i = 0; i < min(n, kMaxCtrl); ++i) {
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double e = P.wpts[3 * (int64_t)(a0 + i) + a] - xp[a];
+                r2 += e * e;
+            }
+            const double t = d - sqrt(r2);
+            s += P.K[a0 + i] / (t * t);
+        }
+        return s;
+    };
+    const double lim = (double)(h - 1);
+    double R = lim;
+    if (!(lim > rmax) || !(bound(lim) < c0)) {
+        bad |= 4u;
+    } else {
+        double lo = rmax, hi = lim;
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (bound(mid) >= c0) lo = mid;
+            else hi = mid;
+        }
+        R = hi;
+    }
+    ball[4 * p + 0] = xp[0];
+    ball[4 * p + 1] = xp[1];
+    ball[4 * p + 2] = xp[2];
+    ball[4 * p + 3] = R + 1e-6;
     if (bad) atomicOr(err, bad);
 }
 
-__global__ __launch_bounds__(256) void k_clear(uint32_t* own, const int* boxes, BoxSpec b, Geom g)
+// Whether a box cell lies outside the particle's bounding ball (x_p, R) and so
+// cannot be one of its nodes.
+__device__ __forceinline__ bool outside_ball(const BoxCell& bc, const double* ball)
+{
+    const double dx = (double)bc.ii[0] - ball[0];
+    const double dy = (double)bc.ii[1] - ball[1];
+    const double dz = (double)bc.ii[2] - ball[2];
+    return (dx * dx + dy * dy) + dz * dz > ball[3] * ball[3];
+}
+
+__global__ __launch_bounds__(256) void k_clear(uint32_t* own, const int* boxes, const double* ball,
+                                               BoxSpec b, Geom g)
 {
     const int p = blockIdx.y;
     const int t = blockIdx.x * 256 + threadIdx.x;
     const BoxCell bc = box_cell(boxes + 3 * p, t, b, g);
-    if (bc.in) own[node_idx(bc.c, g)] = kFluid;
+    if (bc.in && !outside_ball(bc, ball + 4 * p)) own[node_idx(bc.c, g)] = kFluid;
 }
 
-__global__ __launch_bounds__(256) void k_mark(uint32_t* own, const int* boxes, PartDev P, BoxSpec b,
-                                              Geom g)
+__global__ __launch_bounds__(256) void k_mark(uint32_t* own, const int* boxes, const double* ball,
+                                              PartDev P, BoxSpec b, Geom g)
 {
     __shared__ double sp[4 * kMaxCtrl];
     const int p = blockIdx.y;
     const int n = stage_ctrl(P, p, sp);
     const int t = blockIdx.x * 256 + threadIdx.x;
     const BoxCell bc = box_cell(boxes + 3 * p, t, b, g);
-    if (!bc.in) return;
+    if (!bc.in || outside_ball(bc, ball + 4 * p)) return;
     const double M = metaball(sp, n, (double)bc.ii[0], (double)bc.ii[1], (double)bc.ii[2]);
     if (M >= P.c0[p]) atomicMin(own + node_idx(bc.c, g), (uint32_t)p);
 }
@@ -199,8 +240,8 @@ __global__ __launch_bounds__(256) void k_mark(uint32_t* own, const int* boxes, P
 // Over the previous boxes: flags of the new classification and the nodes that
 // particle p covered before and that are fluid now.
 __global__ __launch_bounds__(256) void k_finish(const uint32_t* own_prev, const uint32_t* own_new,
-                                                const int* boxes, BoxSpec b, Geom g,
-                                                uint8_t* flag, RefillRec* rec, int64_t cap,
+                                                const int* boxes, const double* ball, BoxSpec b,
+                                                Geom g, uint8_t* flag, RefillRec* rec, int64_t cap,
                                                 uint32_t* cursor)
 {
     const int p = blockIdx.y;
@@ -208,7 +249,7 @@ __global__ __launch_bounds__(256) void k_finish(const uint32_t* own_prev, const 
     const BoxCell bc = box_cell(boxes + 3 * p, t, b, g);
     bool refill = false;
     uint32_t node = 0;
-    if (bc.in) {
+    if (bc.in && !outside_ball(bc, ball + 4 * p)) {
         node = node_idx(bc.c, g);
         const uint32_t on = own_new[node];
         flag[node] = on != kFluid;
@@ -222,9 +263,10 @@ __global__ __launch_bounds__(256) void k_finish(const uint32_t* own_prev, const 
 }
 
 // Over the new boxes: flags, and the link records of every node of p.
-__global__ __launch_bounds__(256) void k_links(const uint32_t* own, const int* boxes, PartDev P,
-                                               BoxSpec b, Geom g, uint8_t* flag, LinkRec* links,
-                                               int64_t cap, uint32_t* cursors, int treat)
+__global__ __launch_bounds__(256) void k_links(const uint32_t* own, const int* boxes,
+                                               const double* ball, PartDev P, BoxSpec b, Geom g,
+                                               uint8_t* flag, LinkRec* links, int64_t cap,
+                                               uint32_t* cursors, int treat)
 {
     __shared__ double sp[4 * kMaxCtrl];
     const int p = blockIdx.y;
@@ -234,7 +276,7 @@ __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const int* b
     const double c0 = P.c0[p];
     bool mine = false;
     uint32_t node = 0;
-    if (bc.in) {
+    if (bc.in && !outside_ball(bc, ball + 4 * p)) {
         node = node_idx(bc.c, g);
         const uint32_t o = own[node];
         flag[node] = o != kFluid;
@@ -328,7 +370,8 @@ hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot)
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_boxes, dim3((np + 63) / 64), dim3(64), 0, c->stream, P, c->box.h,
-                       c->box_hist + (int64_t)slot * 3 * np, c->err, c->geom);
+                       c->box_hist + (int64_t)slot * 3 * np, c->ball_hist + (int64_t)slot * 4 * np,
+                       c->err, c->geom);
     return hipGetLastError();
 }
 
@@ -336,7 +379,8 @@ hipError_t launch_clear_boxes(lbm_ctx* c, uint32_t* own, int slot, int np)
 {
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_clear, dim3(c->box.tiles, np), dim3(256), 0, c->stream, own,
-                       c->box_hist + (int64_t)slot * 3 * np, c->box, c->geom);
+                       c->box_hist + (int64_t)slot * 3 * np, c->ball_hist + (int64_t)slot * 4 * np,
+                       c->box, c->geom);
     return hipGetLastError();
 }
 
@@ -345,7 +389,8 @@ hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot)
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mark, dim3(c->box.tiles, np), dim3(256), 0, c->stream, own,
-                       c->box_hist + (int64_t)slot * 3 * np, P, c->box, c->geom);
+                       c->box_hist + (int64_t)slot * 3 * np, c->ball_hist + (int64_t)slot * 4 * np,
+                       P, c->box, c->geom);
     return hipGetLastError();
 }
 
@@ -354,8 +399,9 @@ hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* o
 {
     if (np_prev == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish, dim3(c->box.tiles, np_prev), dim3(256), 0, c->stream, own_prev,
-                       own_new, c->box_hist + (int64_t)slot * 3 * np_prev, c->box, c->geom,
-                       c->flag, c->refill, c->refill_cap, c->refill_cursor);
+                       own_new, c->box_hist + (int64_t)slot * 3 * np_prev,
+                       c->ball_hist + (int64_t)slot * 4 * np_prev, c->box, c->geom, c->flag,
+                       c->refill, c->refill_cap, c->refill_cursor);
     return hipGetLastError();
 }
 
@@ -364,8 +410,9 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_links, dim3(c->box.tiles, np), dim3(256), 0, c->stream, own,
-                       c->box_hist + (int64_t)slot * 3 * np, P, c->box, c->geom, c->flag, c->links,
-                       c->link_cap, c->link_cursor, c->cfg.treatments);
+                       c->box_hist + (int64_t)slot * 3 * np, c->ball_hist + (int64_t)slot * 4 * np,
+                       P, c->box, c->geom, c->flag, c->links, c->link_cap, c->link_cursor,
+                       c->cfg.treatments);
     return hipGetLastError();
 }
 

@@ -126,6 +126,7 @@ struct lbm_ctx {
 
     // library scratch
     int* box_hist = nullptr;      // [3][np][3] box origins of the last three classifications
+    double* ball_hist = nullptr;  // [3][np][4] centre and bounding radius, same slots
     mdlbm::LinkRec* links = nullptr;
     int64_t link_cap = 0;         // per particle
     uint32_t* link_cursor = nullptr;  // [np * kCursorPad]
@@ -142,6 +143,16 @@ struct lbm_ctx {
     double* hist_pp = nullptr;    // [np*np][8]
     double* hist_pw = nullptr;    // [np*6][8]
     double* fc = nullptr;         // [np][6] last contact force / torque
+    // kernel timing
+    bool prof = false;
+    struct Timed {
+        int phase;
+        hipEvent_t start, stop;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    double prof_ms[LBM_PHASE_COUNT] = {};
+    int64_t prof_n[LBM_PHASE_COUNT] = {};
     std::string last_error;
 };
 

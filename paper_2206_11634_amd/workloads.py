@@ -99,11 +99,11 @@ class ParticleSet:
         self.world_pts = world_points(self.pos, self.quat, self.body_pts, self.ctrl_off)
 
     def box_half(self) -> int:
-        """Half-width h of the per-particle node box [floor(x_p)-h, floor(x_p)+h]
-        that contains every node of the body with one node to spare."""
+        """Half-width h of the per-particle node box [floor(x_p)-h, floor(x_p)+h]:
+        every body point lies within `radius` < h - 1 of x_p."""
         if self.n == 0:
-            return 1
-        return int(np.ceil(self.radius.max())) + 2
+            return 2
+        return int(np.floor(self.radius.max())) + 3
 
 
 # ----------------------------------------------------------------------------
@@ -197,6 +197,29 @@ def _mass_properties(pts, K, c0, samples_per_unit: float, reach: float):
     return V, c, inertia
 
 
+def body_radius(pts: np.ndarray, K: np.ndarray, c0: float) -> float:
+    """Radius about the origin beyond which no point reaches level c0.
+
+    At distance d > |x_i| from the origin, |x - x_i| >= d - |x_i|, so
+    M(x) <= sum_i K_i / (d - |x_i|)^2, which decreases in d; the root of that
+    bound at c0 (bisection) bounds the body."""
+    b = np.sqrt((np.asarray(pts, float) ** 2).sum(-1))
+    K = np.asarray(K, float)
+
+    def bound(d):
+        return float((K / (d - b) ** 2).sum())
+
+    lo = b.max() + 1e-9
+    hi = b.max() + np.sqrt(K.sum() / c0) + 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if bound(mid) >= c0:
+            lo = mid
+        else:
+            hi = mid
+    return hi
+
+
 def _finish_shape(pts, K, c0, rs, samples_per_unit) -> Shape:
     reach = float(np.sqrt(K.sum() / c0)) + 1.0
     V, c, I = _mass_properties(pts, K, c0, samples_per_unit, reach)
@@ -204,7 +227,7 @@ def _finish_shape(pts, K, c0, rs, samples_per_unit) -> Shape:
     if np.linalg.det(evecs) < 0:
         evecs[:, 0] = -evecs[:, 0]
     body = (pts - c) @ evecs            # principal frame, centroid origin
-    radius = float(np.sqrt(((body) ** 2).sum(-1)).max() + np.sqrt(K.sum() / c0))
+    radius = body_radius(body, K, c0)
     return Shape(pts=body, K=K.copy(), c0=float(c0), rs=float(rs), volume=V,
                  inertia_unit=evals, radius=radius)
 
@@ -543,3 +566,19 @@ WORKLOADS = {
     "c4": config_c4,
     "c5": config_c5,
 }
+
+
+def dem_defaults(ps: ParticleSet, gravity=(0.0, 0.0, 0.0), contact_time=20.0, restitution=0.5):
+    """Contact constants for a workload (the paper does not give them): a
+    linear normal spring whose contact lasts `contact_time` lattice steps for
+    the lightest particle, damping for the given restitution, k_t = k_n / 2,
+    mu_s = 0.3."""
+    m = float(ps.mass.min()) if ps.n else 1.0
+    meff = 0.5 * m
+    w0 = np.pi / contact_time
+    kn = meff * w0 * w0
+    lnr = np.log(restitution)
+    zeta = -lnr / np.sqrt(np.pi ** 2 + lnr ** 2)
+    eta = 2.0 * zeta * np.sqrt(meff * kn)
+    return dict(kn=kn, eta_n=eta, kt=0.5 * kn, eta_t=0.0, mu_s=0.3, ctol=1e-3,
+                newton_tol=1e-10, newton_iter=30, gravity=tuple(gravity), rho_f=1.0)
