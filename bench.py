@@ -63,15 +63,18 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True):
     torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     return dict(ms_per_step=ms, n_solid=n_solid, prof=prof, n_links=int(counts.n_links),
-                n_refill=int(counts.n_refill))
+                n_refill=int(counts.n_refill), n_cand=int(counts.n_candidates))
 
 
 def bulk_roofline(res, lat, storage):
     """Algorithmic bytes of one stream-collide launch: every fluid node reads
-    and writes 19 populations; every node reads its 1-byte flag."""
+    and writes 19 populations and writes its moments (rho - 1, u) (4 values in
+    the storage's arithmetic, read back by the link kernel); every node reads
+    its 1-byte flag.  The rest-state stores of solid nodes are not counted."""
     ncell = lat.ncell
     nfluid = ncell - res["n_solid"]
-    bytes_launch = nfluid * 2 * 19 * BYTES[storage] + ncell * 1
+    per_fluid = 2 * 19 * BYTES[storage] + 4 * BYTES[storage]
+    bytes_launch = nfluid * per_fluid + ncell * 1
     ms, n = res["prof"]["bulk"]
     avg_ms = ms / max(n, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
@@ -79,7 +82,7 @@ def bulk_roofline(res, lat, storage):
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                 kernel="k_stream_collide", avg_ms=round(avg_ms, 4),
                 bytes_per_launch=int(bytes_launch),
-                bytes_per_fluid_cell=2 * 19 * BYTES[storage] + 1)
+                bytes_per_fluid_cell=per_fluid, bytes_per_cell_flag=1)
 
 
 def cpu_baseline(seconds=15.0):
@@ -210,6 +213,8 @@ def main():
         "fluid_mlups": round(nfluid / (main_res["ms_per_step"] * 1e-3) / 1e6, 1),
         "phase_ms_per_launch": phases,
         "links": main_res["n_links"],
+        "link_candidates": main_res["n_cand"],
+        "solid_fraction": round(main_res["n_solid"] / ncell, 4),
         "refills_last_step": main_res["n_refill"],
         "roofline": bulk_roofline(main_res, lat, args.storage),
     }

@@ -91,12 +91,17 @@ typedef struct {
     size_t population_bytes;   /* bytes of ONE population buffer (two are needed) */
     size_t owner_bytes;        /* bytes of ONE owner plane (two are needed), uint32 */
     size_t flag_bytes;         /* bytes of the fluid/solid flag plane, uint8 */
+    size_t moment_bytes;       /* bytes of the moment plane: per node (rho - 1, u) in
+                                  the storage's arithmetic (double, float, or half
+                                  scaled like the FP16 deviations) */
 } lbm_sizes;
 
 typedef struct {
     void* f_dev[2];            /* two population buffers, population_bytes each */
     uint32_t* owner_dev[2];    /* two owner planes, owner_bytes each */
     uint8_t* flag_dev;         /* flag plane, flag_bytes */
+    void* moments_dev;         /* moment plane, moment_bytes: written by every collision,
+                                  read by the link reconstruction */
 } lbm_buffers;
 
 /* Particle state, all device arrays in FP64 unless noted.  n_ctrl = ctrl_off[n]. */
@@ -123,7 +128,7 @@ typedef struct {
 typedef struct {
     int64_t n_links;    /* VIBB + HALFWAY + MISSING links of the classification */
     int64_t n_refill;   /* nodes solid at the previous and fluid at this classification */
-    int64_t n_solid_changed; /* reserved, 0 */
+    int64_t n_candidates; /* solid nodes examined for links (not provably interior) */
 } lbm_counts;
 
 typedef struct {

@@ -40,11 +40,11 @@ class LbmConfig(ctypes.Structure):
 class LbmSizes(ctypes.Structure):
     _fields_ = [("ncell", ctypes.c_int64), ("cell_stride", ctypes.c_int64),
                 ("population_bytes", ctypes.c_size_t), ("owner_bytes", ctypes.c_size_t),
-                ("flag_bytes", ctypes.c_size_t)]
+                ("flag_bytes", ctypes.c_size_t), ("moment_bytes", ctypes.c_size_t)]
 
 
 class LbmBuffers(ctypes.Structure):
-    _fields_ = [("f_dev", _P * 2), ("owner_dev", _P * 2), ("flag_dev", _P)]
+    _fields_ = [("f_dev", _P * 2), ("owner_dev", _P * 2), ("flag_dev", _P), ("moments_dev", _P)]
 
 
 class LbmParticles(ctypes.Structure):
@@ -55,7 +55,7 @@ class LbmParticles(ctypes.Structure):
 
 class LbmCounts(ctypes.Structure):
     _fields_ = [("n_links", ctypes.c_int64), ("n_refill", ctypes.c_int64),
-                ("n_solid_changed", ctypes.c_int64)]
+                ("n_candidates", ctypes.c_int64)]
 
 
 class DemParams(ctypes.Structure):
@@ -256,8 +256,10 @@ class Lattice:
         self.own = [torch.empty(self.sizes.owner_bytes // 4, dtype=torch.int32, device=self.device)
                     for _ in range(2)]
         self.flag = torch.empty(self.sizes.flag_bytes, **u8)
+        self.mom = torch.empty(self.sizes.moment_bytes, **u8)
         bufs = LbmBuffers((_P * 2)(*[t.data_ptr() for t in self.f]),
-                          (_P * 2)(*[t.data_ptr() for t in self.own]), self.flag.data_ptr())
+                          (_P * 2)(*[t.data_ptr() for t in self.own]), self.flag.data_ptr(),
+                          self.mom.data_ptr())
         self.ctx = lbm_init(cfg, bufs)
         self.n_particles = int(n_particles)
         self.F = torch.zeros((max(n_particles, 1), 3), dtype=torch.float64, device=self.device)

@@ -147,6 +147,7 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
     out->population_bytes = (size_t)kQ * (size_t)out->cell_stride * es;
     out->owner_bytes = (size_t)ncell * sizeof(uint32_t);
     out->flag_bytes = (size_t)ncell;
+    out->moment_bytes = (size_t)ncell * 4 * es;
     return LBM_OK;
 }
 
@@ -160,7 +161,7 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (!(cfg->tau > 0.5)) return fail(nullptr, LBM_EINVAL, "tau must exceed 1/2");
     if (!(cfg->rho0 > 0.0)) return fail(nullptr, LBM_EINVAL, "rho0 must be positive");
     if (!bufs->f_dev[0] || !bufs->f_dev[1] || !bufs->owner_dev[0] || !bufs->owner_dev[1] ||
-        !bufs->flag_dev)
+        !bufs->flag_dev || !bufs->moments_dev)
         return fail(nullptr, LBM_EINVAL, "null buffer");
     if (cfg->n_particles < 0 || cfg->n_particles >= 65535)
         return fail(nullptr, LBM_EINVAL, "n_particles must be in [0, 65535)");
@@ -207,24 +208,36 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         c->own[i] = bufs->owner_dev[i];
     }
     c->flag = bufs->flag_dev;
+    c->mom = bufs->moments_dev;
 
     const int np = cfg->n_particles;
     const int64_t S2 = (int64_t)c->box.S * c->box.S;
+    // Clearing and refill detection walk each particle's ball unless the balls
+    // (radius below box_half) could cover most of the lattice, where one
+    // coalesced sweep of the whole lattice is cheaper.
+    {
+        const double r = (double)c->box.h - 1.0;
+        const double balls = (double)np * 4.18879 * r * r * r;
+        c->dense = balls > 0.5 * (double)sz.ncell;
+    }
     c->link_cap = std::max<int64_t>(256, (32 * S2 + 255) / 256 * 256);
+    c->cand_cap = std::max<int64_t>(256, (8 * S2 + 255) / 256 * 256);
     c->refill_cap = std::max<int64_t>(1 << 16, (int64_t)np * S2);
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = alloc(&c->box_hist, (size_t)3 * 3 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->ball_hist, (size_t)3 * 4 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->link_cursor, (size_t)kCursorPad * std::max(np, 1));
+    if (e == hipSuccess) e = alloc(&c->cand_cursor, (size_t)kCursorPad * std::max(np, 1));
+    if (e == hipSuccess && np) e = alloc(&c->cand, (size_t)np * c->cand_cap);
     if (e == hipSuccess && np) e = alloc(&c->links, (size_t)np * c->link_cap);
     if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
     if (e == hipSuccess) e = alloc(&c->refill_cursor, 1);
     if (e == hipSuccess) e = alloc(&c->err, 1);
     if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->fc, (size_t)6 * std::max(np, 1));
+    if (e == hipSuccess) e = alloc(&c->reach, (size_t)std::max(np, 1));
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&c->host_stage,
-                          sizeof(uint32_t) * (2 + (size_t)kCursorPad * std::max(np, 1)),
+                          sizeof(uint32_t) * (2 + 2 * (size_t)kCursorPad * std::max(np, 1)),
                           hipHostMallocDefault);
     if (e != hipSuccess) {
         std::string msg = std::string("scratch allocation failed: ") + hipGetErrorString(e);
@@ -254,15 +267,17 @@ int lbm_destroy(lbm_ctx* c)
 {
     if (!c) return LBM_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->box_hist);
     (void)hipFree(c->ball_hist);
     (void)hipFree(c->links);
+    (void)hipFree(c->cand);
+    (void)hipFree(c->cand_cursor);
     (void)hipFree(c->link_cursor);
     (void)hipFree(c->refill);
     (void)hipFree(c->refill_cursor);
     (void)hipFree(c->err);
     (void)hipFree(c->FT);
     (void)hipFree(c->fc);
+    (void)hipFree(c->reach);
     (void)hipFree(c->hist_pp);
     (void)hipFree(c->hist_pw);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -297,6 +312,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
     if (np > 0) {
         HIPCHK(c, hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->stream));
         HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
         HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
         HIPCHK(c, launch_boxes(c, Pd, slot));
         // check the boxes before touching the owner planes or the flags
@@ -312,34 +328,53 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
             HIPCHK(c, launch_links(c, own_new, Pd, slot));
         }
+        uint32_t* link_counts = c->host_stage + 2;
+        uint32_t* cand_counts = c->host_stage + 2 + (size_t)kCursorPad * np;
         for (int attempt = 0;; ++attempt) {
             HIPCHK(c, hipMemcpyAsync(c->host_stage, c->refill_cursor, sizeof(uint32_t),
                                      hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipMemcpyAsync(c->host_stage + 2, c->link_cursor, cur_bytes,
-                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(link_counts, c->link_cursor, cur_bytes, hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipMemcpyAsync(cand_counts, c->cand_cursor, cur_bytes, hipMemcpyDeviceToHost,
+                                     c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            int64_t lmax = 0, ltot = 0;
+            int64_t lmax = 0, ltot = 0, cmax = 0, ctot = 0;
             for (int p = 0; p < np; ++p) {
-                const int64_t v = c->host_stage[2 + (size_t)p * kCursorPad];
+                const int64_t v = link_counts[(size_t)p * kCursorPad];
                 lmax = std::max(lmax, v);
                 ltot += v;
+                cmax = std::max<int64_t>(cmax, cand_counts[(size_t)p * kCursorPad]);
+                ctot += cand_counts[(size_t)p * kCursorPad];
             }
             const int64_t nref = c->host_stage[0];
+            const bool grow_cand = cmax > c->cand_cap;
             const bool grow_links = lmax > c->link_cap;
             const bool grow_refill = nref > c->refill_cap;
-            if (!grow_links && !grow_refill) {
+            if (!grow_cand && !grow_links && !grow_refill) {
                 c->link_max = lmax;
                 c->link_total = ltot;
+                c->cand_total = ctot;
                 c->refill_total = (k >= 1) ? nref : 0;
                 break;
             }
             if (attempt > 2) return fail(c, LBM_ENOMEM, "link/refill lists keep overflowing");
+            if (grow_cand) {
+                HIPCHK(c, hipFree(c->cand));
+                c->cand = nullptr;
+                c->cand_cap = (cmax + cmax / 4 + 255) / 256 * 256;
+                if (alloc(&c->cand, (size_t)np * c->cand_cap) != hipSuccess)
+                    return fail(c, LBM_ENOMEM, "candidate list allocation failed");
+                HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
+                HIPCHK(c, launch_mark(c, own_new, Pd, slot));  // same owners, full list
+            }
             if (grow_links) {
                 HIPCHK(c, hipFree(c->links));
                 c->links = nullptr;
                 c->link_cap = (lmax + lmax / 4 + 255) / 256 * 256;
                 if (alloc(&c->links, (size_t)np * c->link_cap) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "link list allocation failed");
+            }
+            if (grow_cand || grow_links) {
                 HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
                 HIPCHK(c, launch_links(c, own_new, Pd, slot));
             }
@@ -368,7 +403,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
     if (out) {
         out->n_links = c->link_total;
         out->n_refill = c->refill_total;
-        out->n_solid_changed = 0;
+        out->n_candidates = c->cand_total;
     }
     return LBM_OK;
 }

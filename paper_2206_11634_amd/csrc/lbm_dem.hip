@@ -6,9 +6,10 @@
 // contactprop) and metaball-wall contacts by Newton on the in-plane gradient
 // (Eqs. metawall, metawallcp, k, contactprop2).
 //
-// One substep = four launches: half kick + drift + rotation (one thread per
-// particle), zero the contact sums, contacts (one thread per pair i < j and
-// one per particle-wall pair, FP64 atomics into the sums), second half kick.
+// One substep = three launches: half kick + drift + rotation + reset of the
+// contact sums (one thread per particle), contacts (one thread per pair i < j
+// and one per particle-wall pair, FP64 atomics into the sums), second half
+// kick.
 // The work is latency-bound (a few thousand particles at most), not HBM-bound.
 #include "lbm_internal.h"
 
@@ -161,12 +162,16 @@ __device__ void half_kick(const PartDev& P, int p, const double* FTh, const doub
     for (int i = 0; i < 3; ++i) P.omega[3 * p + i] = R[3 * i] * wb[0] + R[3 * i + 1] * wb[1] + R[3 * i + 2] * wb[2];
 }
 
-__global__ void k_first_half(PartDev P, const double* FTh, const double* fc, DemP c, double dt,
-                             Geom g)
+// First half kick, drift, rotation and world control points of particle p;
+// also its broad-phase reach and the reset of its contact sums.
+__global__ void k_first_half(PartDev P, const double* FTh, double* fc, double* reach_out, DemP c,
+                             double dt, Geom g)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P.n) return;
     half_kick(P, p, FTh, fc, c, 0.5 * dt, false);
+    for (int k = 0; k < 6; ++k) fc[6 * p + k] = 0.0;
+    reach_out[p] = reach(P, p);
     for (int a = 0; a < 3; ++a) {
         double x = P.pos[3 * p + a] + dt * P.vel[3 * p + a];
         if (g.per[a]) {
@@ -200,17 +205,21 @@ __global__ void k_first_half(PartDev P, const double* FTh, const double* fc, Dem
     }
 }
 
-__global__ void k_zero6(double* fc, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 6 * n) fc[i] = 0.0;
-}
+__device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, const double* rch,
+                             const DemP& c, double dt, const Geom& g);
 
-__global__ void k_pairs(PartDev P, double* hist, double* fc, DemP c, double dt, Geom g)
+// Threads [0, np*np) take the pairs i < j, threads [np*np, np*np + 6 np) the
+// particle-wall pairs.
+__global__ void k_contacts(PartDev P, double* hist, double* hist_w, double* fc, const double* rch,
+                           DemP c, double dt, Geom g)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int np = P.n;
-    if (t >= (int64_t)np * np) return;
+    if (t >= (int64_t)np * np) {
+        const int64_t w = t - (int64_t)np * np;
+        if (w < (int64_t)np * 6) wall_contact(P, (int)w, hist_w, fc, rch, c, dt, g);
+        return;
+    }
     const int i = (int)(t / np), j = (int)(t % np);
     if (i >= j) return;
     double* h = hist + t * kHist;
@@ -228,7 +237,7 @@ __global__ void k_pairs(PartDev P, double* hist, double* fc, DemP c, double dt, 
         dv[a] = d + sh[a];
     }
     const double rsi = P.rs[i], rsj = P.rs[j];
-    if (sqrt(dot3(dv, dv)) > reach(P, i) + reach(P, j) + rsi + rsj) {
+    if (sqrt(dot3(dv, dv)) > rch[i] + rch[j] + rsi + rsj) {
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
@@ -320,16 +329,15 @@ __global__ void k_pairs(PartDev P, double* hist, double* fc, DemP c, double dt, 
     for (int a = 0; a < 3; ++a) atomicAdd(fc + 6 * j + 3 + a, -tq[a]);
 }
 
-__global__ void k_walls(PartDev P, double* hist, double* fc, DemP c, double dt, Geom g)
+__device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, const double* rch,
+                             const DemP& c, double dt, const Geom& g)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P.n * 6) return;
     const int i = t / 6, ax = (t % 6) / 2, side = t % 2;
     if (g.per[ax]) return;
     double* h = hist + (int64_t)t * kHist;
     const double plane = side ? g.n[ax] - 0.5 : -0.5, sgn = side ? -1.0 : 1.0;
     const double* xi = P.pos + 3 * i;
-    if (sgn * (xi[ax] - plane) > reach(P, i) + P.rs[i]) {
+    if (sgn * (xi[ax] - plane) > rch[i] + P.rs[i]) {
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
@@ -426,18 +434,13 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
     for (int a = 0; a < 3; ++a) c.g[a] = prm.gravity[a];
     c.rhof = prm.rho_f;
     const uint32_t bp = (np + 63) / 64;
-    const int64_t npairs = (int64_t)np * np;
-    const uint32_t bpairs = (uint32_t)((npairs + 255) / 256);
-    const uint32_t bw = (np * 6 + 63) / 64;
+    const int64_t nthreads = (int64_t)np * np + 6 * (int64_t)np;
+    const uint32_t bc = (uint32_t)((nthreads + 255) / 256);
     for (int s = 0; s < n_sub; ++s) {
-        hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc, c,
-                           dt, ctx->geom);
-        hipLaunchKernelGGL(k_zero6, dim3(bp), dim3(64 * 6), 0, ctx->stream, ctx->fc, np);
-        if (np > 1)
-            hipLaunchKernelGGL(k_pairs, dim3(bpairs), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
-                               ctx->fc, c, dt, ctx->geom);
-        hipLaunchKernelGGL(k_walls, dim3(bw), dim3(64), 0, ctx->stream, P, ctx->hist_pw, ctx->fc, c,
-                           dt, ctx->geom);
+        hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
+                           ctx->reach, c, dt, ctx->geom);
+        hipLaunchKernelGGL(k_contacts, dim3(bc), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
+                           ctx->hist_pw, ctx->fc, ctx->reach, c, dt, ctx->geom);
         hipLaunchKernelGGL(k_second_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
                            c, dt);
     }

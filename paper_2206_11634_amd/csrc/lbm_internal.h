@@ -118,20 +118,26 @@ struct lbm_ctx {
     void* f[2] = {nullptr, nullptr};
     uint32_t* own[2] = {nullptr, nullptr};
     uint8_t* flag = nullptr;
+    void* mom = nullptr;    // per-node (rho - 1, u) of the current populations
     int cur = 0;            // population buffer holding the current f+
     int own_cur = 0;        // owner plane of the last classification
     int64_t n_classify = 0; // classifications done
     bool stepped_since_classify = false;
+    bool dense = false;     // particle balls cover most of the lattice: sweep it whole
     bool failed = false;
 
     // library scratch
-    int* box_hist = nullptr;      // [3][np][3] box origins of the last three classifications
-    double* ball_hist = nullptr;  // [3][np][4] centre and bounding radius, same slots
+    double* ball_hist = nullptr;  // [3][np][4] centre and bounding radius of each particle
+                                  // at the last three classifications
+    uint32_t* cand = nullptr;     // per particle: nodes that may carry links
+    int64_t cand_cap = 0;         // per particle
+    uint32_t* cand_cursor = nullptr;  // [np * kCursorPad]
     mdlbm::LinkRec* links = nullptr;
     int64_t link_cap = 0;         // per particle
     uint32_t* link_cursor = nullptr;  // [np * kCursorPad]
     int64_t link_max = 0;         // max links of one particle at the last classification
     int64_t link_total = 0;
+    int64_t cand_total = 0;
     mdlbm::RefillRec* refill = nullptr;
     int64_t refill_cap = 0;
     uint32_t* refill_cursor = nullptr;
@@ -143,6 +149,7 @@ struct lbm_ctx {
     double* hist_pp = nullptr;    // [np*np][8]
     double* hist_pw = nullptr;    // [np*6][8]
     double* fc = nullptr;         // [np][6] last contact force / torque
+    double* reach = nullptr;      // [np] broad-phase radius of each particle
     // kernel timing
     bool prof = false;
     struct Timed {

@@ -11,8 +11,10 @@
 // Mach numbers of interest) rather than to f.
 //
 // Layout: plane i of a buffer starts at element i * stride, x fastest.  Every
-// kernel is bound by HBM traffic; none of them is a contraction, so there is
-// no MFMA here.  A solid node's plane-i slot serves as the "ghost" that holds
+// collision also stores the node's moments (rho - 1, u) into a moment plane,
+// so a link needs two populations and two moment vectors instead of the 38
+// populations of x_f and x_ff.  Every kernel is bound by HBM traffic; none of
+// them is a contraction, so there is no MFMA here.  A solid node's plane-i slot serves as the "ghost" that holds
 // the reconstructed population f_i(x_f, t+1) of the one fluid node
 // x_f = x_s + e_i that pulls from it, so the bulk kernel needs no link lookup.
 #include "lbm_internal.h"
@@ -20,28 +22,59 @@
 namespace mdlbm {
 namespace {
 
+// Per-node moments (rho - 1, u) in the storage's arithmetic.
+struct alignas(16) Mom64 {
+    double d, x, y, z;
+};
+struct alignas(8) Mom16 {
+    __half2 a, b;
+};
+
 template <int S>
 struct St;
 template <>
 struct St<LBM_STORE_F64> {
     using T = double;
     using A = double;
+    using M = Mom64;
     static constexpr bool dev = false;
     static __device__ __forceinline__ double ld(const double* p, float) { return *p; }
     static __device__ __forceinline__ void st(double* p, double v, float) { *p = v; }
+    static __device__ __forceinline__ void st_mom(M* p, double d, double x, double y, double z, float)
+    {
+        *p = Mom64{d, x, y, z};
+    }
+    static __device__ __forceinline__ void ld_mom(const M* p, float, double& d, double& x, double& y,
+                                                  double& z)
+    {
+        const Mom64 m = *p;
+        d = m.d, x = m.x, y = m.y, z = m.z;
+    }
 };
 template <>
 struct St<LBM_STORE_F32> {
     using T = float;
     using A = float;
+    using M = float4;
     static constexpr bool dev = true;
     static __device__ __forceinline__ float ld(const float* p, float) { return *p; }
     static __device__ __forceinline__ void st(float* p, float v, float) { *p = v; }
+    static __device__ __forceinline__ void st_mom(M* p, float d, float x, float y, float z, float)
+    {
+        *p = make_float4(d, x, y, z);
+    }
+    static __device__ __forceinline__ void ld_mom(const M* p, float, float& d, float& x, float& y,
+                                                  float& z)
+    {
+        const float4 m = *p;
+        d = m.x, x = m.y, y = m.z, z = m.w;
+    }
 };
 template <>
 struct St<LBM_STORE_F16> {
     using T = __half;
     using A = float;
+    using M = Mom16;
     static constexpr bool dev = true;
     static __device__ __forceinline__ float ld(const __half* p, float inv)
     {
@@ -50,6 +83,20 @@ struct St<LBM_STORE_F16> {
     static __device__ __forceinline__ void st(__half* p, float v, float sc)
     {
         *p = __float2half_rn(v * sc);
+    }
+    static __device__ __forceinline__ void st_mom(M* p, float d, float x, float y, float z, float sc)
+    {
+        Mom16 m;
+        m.a = __floats2half2_rn(d * sc, x * sc);
+        m.b = __floats2half2_rn(y * sc, z * sc);
+        *p = m;
+    }
+    static __device__ __forceinline__ void ld_mom(const M* p, float inv, float& d, float& x, float& y,
+                                                  float& z)
+    {
+        const Mom16 m = *p;
+        const float2 a = __half22float2(m.a), b = __half22float2(m.b);
+        d = a.x * inv, x = a.y * inv, y = b.x * inv, z = b.y * inv;
     }
 };
 
@@ -106,9 +153,9 @@ __device__ __forceinline__ void moments(const A* v, A shift, const A* F, A& drho
 // BGK collision with Guo forcing, in place:
 //   f+ = f + omega (feq - f) + (1 - omega/2) w [3 (e - u) + 9 (e.u) e].F
 template <bool DEV, class A>
-__device__ __forceinline__ void collide(A* v, A omega, const A* F)
+__device__ __forceinline__ void collide(A* v, A omega, const A* F, A& drho, A& ux, A& uy, A& uz)
 {
-    A drho, rho, ux, uy, uz;
+    A rho;
     moments<DEV, A>(v, A(0.5), F, drho, rho, ux, uy, uz);
     const A uF = ux * F[0] + uy * F[1] + uz * F[2];
     const A gf = A(1) - A(0.5) * omega;
@@ -158,6 +205,7 @@ __device__ __forceinline__ uint32_t xcd_block()
 template <int S>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename St<S>::T* __restrict__ src,
                                                         typename St<S>::T* __restrict__ dst,
+                                                        typename St<S>::M* __restrict__ mom,
                                                         const uint8_t* __restrict__ flag, Geom g,
                                                         Phys ph)
 {
@@ -165,7 +213,19 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename St<S>::T*
     constexpr bool DEV = St<S>::dev;
     const uint32_t cell = xcd_block() * 256u + threadIdx.x;
     if (cell >= g.ncell) return;
-    if (flag[cell]) return;  // solid: its slots are link ghosts, not fluid
+    if (flag[cell]) {
+        // A solid node's slots are only ever read as link ghosts, which the
+        // boundary kernel writes before they are pulled.  Storing the rest
+        // state keeps every cache line of the wave fully written (partially
+        // written lines cost far more HBM time than the bytes saved) and keeps
+        // stale values from evolving inside the bodies.
+        const A rest = DEV ? A(0) : A(1);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            St<S>::st(dst + (int64_t)i * g.stride + cell, DEV ? A(0) : A(wgt(i)) * rest, ph.scale);
+        St<S>::st_mom(mom + cell, A(0), A(0), A(0), A(0), ph.scale);
+        return;
+    }
     const uint32_t nx = g.n[0], ny = g.n[1];
     const uint32_t x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
     uint32_t ox[3], oy[3], oz[3];
@@ -192,9 +252,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename St<S>::T*
         F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
         om = ph.omega;
     }
-    collide<DEV, A>(f, om, F);
+    A drho, ux, uy, uz;
+    collide<DEV, A>(f, om, F, drho, ux, uy, uz);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) St<S>::st(dst + (int64_t)i * g.stride + cell, f[i], ph.scale);
+    St<S>::st_mom(mom + cell, drho, ux, uy, uz, ph.scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,23 +291,6 @@ __device__ __forceinline__ uint32_t node_of(const int c[3], const Geom& g)
     return (uint32_t)c[0] + (uint32_t)g.n[0] * ((uint32_t)c[1] + (uint32_t)g.n[1] * (uint32_t)c[2]);
 }
 
-template <int S>
-__device__ __forceinline__ void load_node(const typename St<S>::T* f, uint32_t node,
-                                          const Geom& g, float inv, typename St<S>::A* v)
-{
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) v[i] = St<S>::ld(f + (int64_t)i * g.stride + node, inv);
-}
-
-template <class A>
-__device__ __forceinline__ A pick(const A* v, int d)
-{
-    A r = A(0);
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) r = (i == d) ? v[i] : r;
-    return r;
-}
-
 __device__ __forceinline__ double dsum_wave(double v)
 {
 #pragma unroll
@@ -255,6 +300,7 @@ __device__ __forceinline__ double dsum_wave(double v)
 
 template <int S>
 __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict__ f,
+                                                  const typename St<S>::M* __restrict__ mom,
                                                   const LinkRec* __restrict__ links,
                                                   const uint32_t* __restrict__ cursor, int64_t cap,
                                                   PartDev P, double* __restrict__ FT, Geom g,
@@ -303,28 +349,23 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
             out = eq_i<false, double>(d, ph.rho0 - 1.0, ph.rho0, uw[0], uw[1], uw[2]);
             in = eq_i<false, double>(db, ph.rho0 - 1.0, ph.rho0, uw[0], uw[1], uw[2]);
         } else {
-            A Fa[3];
-            if constexpr (DEV) {
-                Fa[0] = ph.Ff[0], Fa[1] = ph.Ff[1], Fa[2] = ph.Ff[2];
-            } else {
-                Fa[0] = ph.F[0], Fa[1] = ph.F[1], Fa[2] = ph.F[2];
-            }
+            // x_f: its outgoing population and moments at time t
             const uint32_t xf = node_of(cn, g);
-            A v[kQ];
-            load_node<S>(f, xf, g, ph.inv_scale, v);
-            A drf, rf, uf[3];
-            moments<DEV, A>(v, A(-0.5), Fa, drf, rf, uf[0], uf[1], uf[2]);
-            const A fdf = pick(v, d);
+            const A fdf = St<S>::ld(f + (int64_t)d * g.stride + xf, ph.inv_scale);
+            A drf, uf[3];
+            St<S>::ld_mom(mom + xf, ph.inv_scale, drf, uf[0], uf[1], uf[2]);
+            const A rf = A(1) + drf;
             const A uwa[3] = {A(uw[0]), A(uw[1]), A(uw[2])};
             const A ebu = -(A(e[0]) * uwa[0] + A(e[1]) * uwa[1] + A(e[2]) * uwa[2]);
             A unk;
             if (r.kind == LBM_LINK_VIBB) {
                 int cf[3] = {cn[0] - e[0], cn[1] - e[1], cn[2] - e[2]};
                 wrap3(cf, g);
-                load_node<S>(f, node_of(cf, g), g, ph.inv_scale, v);
-                A drff, rff, uff[3];
-                moments<DEV, A>(v, A(-0.5), Fa, drff, rff, uff[0], uff[1], uff[2]);
-                const A fdff = pick(v, d);
+                const uint32_t xff = node_of(cf, g);
+                const A fdff = St<S>::ld(f + (int64_t)d * g.stride + xff, ph.inv_scale);
+                A drff, uff[3];
+                St<S>::ld_mom(mom + xff, ph.inv_scale, drff, uff[0], uff[1], uff[2]);
+                const A rff = A(1) + drff;
                 const A q = A(r.q);
                 const A tq = A(2) * q, oq = A(1) - A(2) * q;
                 // non-equilibrium part extrapolated to x_d (Eq. neqd)
@@ -393,6 +434,7 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
 template <int S>
 __global__ __launch_bounds__(256) void k_refill(const typename St<S>::T* __restrict__ prev,
                                                 typename St<S>::T* __restrict__ cur,
+                                                typename St<S>::M* __restrict__ mom,
                                                 const RefillRec* __restrict__ rec, uint32_t cnt,
                                                 const uint32_t* __restrict__ own_prev, PartDev P,
                                                 Geom g, Phys ph)
@@ -446,16 +488,19 @@ __global__ __launch_bounds__(256) void k_refill(const typename St<S>::T* __restr
         F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
         om = ph.omega;
     }
-    collide<DEV, A>(v, om, F);
+    A drho, ux, uy, uz;
+    collide<DEV, A>(v, om, F, drho, ux, uy, uz);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) St<S>::st(cur + (int64_t)i * g.stride + r.node, v[i], ph.scale);
+    St<S>::st_mom(mom + r.node, drho, ux, uy, uz, ph.scale);
 }
 
 // ---------------------------------------------------------------------------
 // Import / export
 // ---------------------------------------------------------------------------
 template <int S>
-__global__ void k_init_eq(typename St<S>::T* f, Geom g, Phys ph, double u0x, double u0y, double u0z)
+__global__ void k_init_eq(typename St<S>::T* f, typename St<S>::M* mom, Geom g, Phys ph, double u0x,
+                          double u0y, double u0z)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
@@ -466,6 +511,9 @@ __global__ void k_init_eq(typename St<S>::T* f, Geom g, Phys ph, double u0x, dou
         const A v = eq_i<DEV, A>(i, A(ph.rho0 - 1.0), A(ph.rho0), A(u0x), A(u0y), A(u0z));
         St<S>::st(f + (int64_t)i * g.stride + cell, v, ph.scale);
     }
+    // the initial populations count as post-collision ones: u = (rho0 u0 - F/2) / rho0
+    St<S>::st_mom(mom + cell, A(ph.rho0 - 1.0), A(u0x - 0.5 * ph.F[0] / ph.rho0),
+                  A(u0y - 0.5 * ph.F[1] / ph.rho0), A(u0z - 0.5 * ph.F[2] / ph.rho0), ph.scale);
 }
 
 template <int S>
@@ -482,17 +530,27 @@ __global__ void k_get(const typename St<S>::T* f, double* out, Geom g, Phys ph)
 }
 
 template <int S>
-__global__ void k_set(typename St<S>::T* f, const double* in, Geom g, Phys ph)
+__global__ void k_set(typename St<S>::T* f, typename St<S>::M* mom, const double* in, Geom g,
+                      Phys ph)
 {
     using A = typename St<S>::A;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
     if (cell >= g.ncell) return;
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        double v = in[(int64_t)i * g.ncell + cell];
+        const double fi = in[(int64_t)i * g.ncell + cell];
+        rho += fi;
+        jx += cx(i) * fi;
+        jy += cy(i) * fi;
+        jz += cz(i) * fi;
+        double v = fi;
         if constexpr (St<S>::dev) v -= wgt(i);
         St<S>::st(f + (int64_t)i * g.stride + cell, A(v), ph.scale);
     }
+    // the given populations are post-collision: u = (sum f e - F/2) / rho
+    St<S>::st_mom(mom + cell, A(rho - 1.0), A((jx - 0.5 * ph.F[0]) / rho),
+                  A((jy - 0.5 * ph.F[1]) / rho), A((jz - 0.5 * ph.F[2]) / rho), ph.scale);
 }
 
 __global__ void k_zero(double* p, int64_t n)
@@ -529,8 +587,8 @@ struct RunInit {
     static hipError_t run(lbm_ctx* c, void* f)
     {
         hipLaunchKernelGGL(k_init_eq<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0, c->stream,
-                           (typename St<S>::T*)f, c->geom, c->phys, c->cfg.u0[0], c->cfg.u0[1],
-                           c->cfg.u0[2]);
+                           (typename St<S>::T*)f, (typename St<S>::M*)c->mom, c->geom, c->phys,
+                           c->cfg.u0[0], c->cfg.u0[1], c->cfg.u0[2]);
         return hipGetLastError();
     }
 };
@@ -542,8 +600,8 @@ struct RunSC {
         uint32_t nb = blocks_for(c->geom.ncell);
         nb = (nb + 7u) & ~7u;  // whole rounds over the 8 XCDs
         hipLaunchKernelGGL(k_stream_collide<S>, dim3(nb), dim3(256), 0, c->stream,
-                           (const typename St<S>::T*)src, (typename St<S>::T*)dst, c->flag, c->geom,
-                           c->phys);
+                           (const typename St<S>::T*)src, (typename St<S>::T*)dst,
+                           (typename St<S>::M*)c->mom, c->flag, c->geom, c->phys);
         return hipGetLastError();
     }
 };
@@ -555,7 +613,8 @@ struct RunBC {
         if (c->cfg.n_particles == 0 || c->link_max == 0) return hipSuccess;
         dim3 grid(blocks_for(c->link_max), c->cfg.n_particles);
         hipLaunchKernelGGL(k_boundary<S>, grid, dim3(256), 0, c->stream, (typename St<S>::T*)f,
-                           c->links, c->link_cursor, c->link_cap, P, c->FT, c->geom, c->phys);
+                           (const typename St<S>::M*)c->mom, c->links, c->link_cursor, c->link_cap,
+                           P, c->FT, c->geom, c->phys);
         return hipGetLastError();
     }
 };
@@ -567,7 +626,8 @@ struct RunRefill {
     {
         if (c->refill_total == 0) return hipSuccess;
         hipLaunchKernelGGL(k_refill<S>, dim3(blocks_for(c->refill_total)), dim3(256), 0, c->stream,
-                           (const typename St<S>::T*)fprev, (typename St<S>::T*)fcur, c->refill,
+                           (const typename St<S>::T*)fprev, (typename St<S>::T*)fcur,
+                           (typename St<S>::M*)c->mom, c->refill,
                            (uint32_t)c->refill_total, own_prev, P, c->geom, c->phys);
         return hipGetLastError();
     }
@@ -588,7 +648,7 @@ struct RunSet {
     static hipError_t run(lbm_ctx* c, void* f, const double* in)
     {
         hipLaunchKernelGGL(k_set<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0, c->stream,
-                           (typename St<S>::T*)f, in, c->geom, c->phys);
+                           (typename St<S>::T*)f, (typename St<S>::M*)c->mom, in, c->geom, c->phys);
         return hipGetLastError();
     }
 };

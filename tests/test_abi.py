@@ -60,6 +60,7 @@ def test_query_sizes(lib, storage, es):
     assert s.cell_stride % 64 == 0 and s.cell_stride >= s.ncell
     assert s.population_bytes == 19 * s.cell_stride * es
     assert s.owner_bytes == 4 * s.ncell and s.flag_bytes == s.ncell
+    assert s.moment_bytes == 4 * es * s.ncell
 
 
 def test_query_sizes_rejects_bad_input(lib):
@@ -80,7 +81,7 @@ def test_init_rejects_bad_arguments_before_touching_the_device(lib):
         assert lib.lbm_last_error(None)
     # a periodic axis too short for the particle box
     fake = (B._P * 2)(1, 2)
-    bufs = B.LbmBuffers(fake, fake, 3)
+    bufs = B.LbmBuffers(fake, fake, 3, 4)
     cfg = _cfg(n_particles=1, box_half=6, dims=(16, 40, 40), periodic=(1, 0, 0))
     assert lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)) == B.LBM_EINVAL
     assert b"2*box_half" in lib.lbm_last_error(None)
