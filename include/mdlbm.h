@@ -94,6 +94,9 @@ typedef struct {
     size_t moment_bytes;       /* bytes of the moment plane: per node (rho - 1, u) in
                                   the storage's arithmetic (double, float, or half
                                   scaled like the FP16 deviations) */
+    size_t checkpoint_bytes;   /* bytes of one raw checkpoint (populations + moments) */
+    size_t adjoint_bytes;      /* bytes of one adjoint field: Q planes of cell_stride
+                                  values in the storage's arithmetic (double or float) */
 } lbm_sizes;
 
 typedef struct {
@@ -230,6 +233,42 @@ int lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
 /* Block until the context's stream has drained; EDEVICE on a device error. */
 int lbm_synchronize(lbm_ctx* ctx);
 
+/* ---- differentiation form (not in the paper) -----------------------------
+ *
+ * The adjoint differentiates J = sum over taped steps n and particles p of
+ * wF_p . F^h_p(n) + wT_p . T^h_p(n) with respect to the fluid body force F,
+ * the relaxation time tau and the particle velocities v_p, holding the
+ * geometry schedule (owners, links, q, refill sets) of the taped run fixed;
+ * the velocities enter through the wall velocities of VIBB, halfway
+ * bounce-back, refilling and the momentum exchange.  Angular velocities and
+ * positions are not differentiated. */
+
+/* Copy the current populations and moments, raw, into dst_dev
+ * (checkpoint_bytes). */
+int lbm_checkpoint_save(const lbm_ctx* ctx, void* dst_dev);
+
+/* Restore populations and moments from a raw checkpoint, and forget the
+ * classification history: the next lbm_classify_nodes refills nothing, so
+ * classifying the checkpoint's particle state reproduces its geometry. */
+int lbm_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
+
+/* Record the next max_steps calls of lbm_step (populations after the link
+ * reconstruction, owners, links, particle pose and velocities) for
+ * lbm_adjoint.  Allocates the tape (ENOMEM when it does not fit). */
+int lbm_tape_begin(lbm_ctx* ctx, int max_steps);
+
+/* Run the adjoint backwards over the taped steps and release the tape.
+ *   P        particle state after the last taped step (the one the last
+ *            classification used: its velocities drive that refill);
+ *   weights  host [n][6]: (wF, wT) per particle, the same for every step;
+ *   lam_dev  adjoint field (adjoint_bytes): on entry dJ/df after the last taped
+ *            step (zeros for J above), on return dJ/df at the first taped step;
+ *   grad_dev device FP64 [4 + 3 n], accumulated into: dJ/dF (3), dJ/dtau,
+ *            dJ/dv_p (3 per particle).
+ * Synchronises.  ESTATE when nothing was taped. */
+int lbm_adjoint(lbm_ctx* ctx, const lbm_particles* P, const double* weights, void* lam_dev,
+                double* grad_dev);
+
 /* ---- kernel timing (hipEvent pairs around each launch group) ------------ */
 
 typedef enum {
@@ -238,6 +277,7 @@ typedef enum {
     LBM_PHASE_CLASSIFY = 2,  /* geometry kernels of lbm_classify_nodes */
     LBM_PHASE_REFILL = 3,    /* refill kernel of lbm_classify_nodes */
     LBM_PHASE_DEM = 4,       /* all substeps of one dem_step */
+    LBM_PHASE_ADJOINT = 5,   /* one adjoint step of lbm_adjoint */
     LBM_PHASE_COUNT = 8
 } lbm_phase;
 

@@ -1,0 +1,155 @@
+"""Gradient of a time-averaged hydrodynamic force (differentiation form).
+
+J(v, F, tau) = sum over steps n < T of wF . F^h(n) + wT . T^h(n) for a run in
+which the particles follow a prescribed rigid trajectory: their poses are
+those of a nominal velocity v0 (so the geometry schedule -- owners, links, q,
+refill sets -- is fixed), while the velocities the fluid sees (wall
+velocities of bounce-back, refilling and momentum exchange) are v.  The
+initial populations f(0) are data of the problem (by default the library's
+initial equilibrium for the nominal F), not a function of (v, F, tau).  The
+gradient with respect to v, the fluid body force F and the relaxation time
+tau comes from the library's adjoint, run backwards window by window with
+checkpoints every `window` steps and recomputation inside each window.
+
+`DragFunction` wraps this as a torch.autograd.Function of (v, F, tau).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as W
+
+
+@dataclasses.dataclass
+class Problem:
+    lat: W.LatticeSpec
+    ps: W.ParticleSet          # initial state; ps.vel is the nominal velocity v0
+    steps: int
+    window: int = 100
+    storage: str = "f32"
+    weights: np.ndarray = None  # [n][6]: (wF, wT) per particle per step
+    f0: np.ndarray = None       # [19][ncell] initial populations
+
+    def __post_init__(self):
+        if self.weights is None:
+            w = np.zeros((self.ps.n, 6))
+            w[0, 0] = 1.0 / self.steps    # mean x-force on particle 0
+            self.weights = w
+
+    def initial(self) -> np.ndarray:
+        if self.f0 is None:
+            g = B.Lattice.for_particles(self.lat, self.ps, storage="f64")
+            self.f0 = g.populations()
+            g.close()
+        return self.f0
+
+
+class _Run:
+    def __init__(self, prob: Problem, vel, body_force, tau):
+        self.prob = prob
+        self.vel = np.asarray(vel, float).reshape(prob.ps.n, 3)
+        lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
+                                  tau=float(tau))
+        self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage)
+        self.parts = B.DeviceParticles(prob.ps)
+
+    def state(self, n):
+        P = W.prescribed_state(self.prob.ps, self.prob.lat, float(n))
+        P.vel = self.vel.copy()
+        return P
+
+    def set(self, n):
+        self.parts.set_state(self.state(n))
+
+    def objective(self, F, T):
+        w = self.prob.weights
+        return float((w[:, :3] * F).sum() + (w[:, 3:] * T).sum())
+
+
+def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
+    """Run the forward pass; J, and the run (with its checkpoints) if keep."""
+    run = _Run(prob, vel, body_force, tau)
+    gpu, T = run.gpu, prob.steps
+    gpu.set_populations(prob.initial())
+    run.ckpt = {}
+    J = 0.0
+    run.set(0)
+    gpu.classify(run.parts)
+    for n in range(T):
+        if keep and n % prob.window == 0:
+            run.ckpt[n] = gpu.checkpoint()
+        run.set(n)
+        gpu.step(run.parts)
+        F, Tq = gpu.forces()
+        J += run.objective(F.cpu().numpy(), Tq.cpu().numpy())
+        run.set(n + 1)
+        gpu.classify(run.parts)
+    if not keep:
+        gpu.close()
+        return J, None
+    return J, run
+
+
+def backward(run: _Run):
+    """(dJ/dv [n][3], dJ/dF [3], dJ/dtau) by the adjoint, window by window from
+    the last checkpoint to the first, recomputing each window's steps."""
+    prob, gpu = run.prob, run.gpu
+    torch = gpu.torch
+    lam = gpu.adjoint_field()
+    g = torch.zeros(4 + 3 * prob.ps.n, dtype=torch.float64, device=gpu.device)
+    for w0 in sorted(run.ckpt, reverse=True):
+        w1 = min(w0 + prob.window, prob.steps)
+        gpu.restore(run.ckpt[w0])
+        run.set(w0)
+        gpu.classify(run.parts)   # reproduces the geometry at w0, refills nothing
+        gpu.tape_begin(w1 - w0)
+        for n in range(w0, w1):
+            run.set(n)
+            gpu.step(run.parts)
+            run.set(n + 1)
+            gpu.classify(run.parts)
+        gpu.adjoint(run.parts, prob.weights, lam, g)
+    out = g.cpu().numpy()
+    gpu.close()
+    return out[4:].reshape(prob.ps.n, 3), out[:3].copy(), float(out[3])
+
+
+def evaluate(prob: Problem, vel, body_force, tau, grad: bool = False):
+    """J, and with grad=True also (dJ/dv [n][3], dJ/dF [3], dJ/dtau)."""
+    J, run = forward(prob, vel, body_force, tau, keep=grad)
+    if not grad:
+        return J
+    return (J,) + backward(run)
+
+
+def _make_function():
+    import torch
+
+    class DragFunction(torch.autograd.Function):
+        """J = DragFunction.apply(v [n,3], F [3], tau [], problem): the forward
+        pass keeps checkpoints; the backward pass runs the adjoint."""
+
+        @staticmethod
+        def forward(ctx, vel, body_force, tau, prob):
+            J, run = forward(prob, vel.detach().cpu().numpy(), body_force.detach().cpu().numpy(),
+                             float(tau.detach().cpu()), keep=True)
+            ctx.run = run
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            dv, dF, dtau = backward(ctx.run)
+            ctx.run = None
+            return (gJ * torch.as_tensor(dv), gJ * torch.as_tensor(dF),
+                    gJ * torch.as_tensor(dtau), None)
+
+    return DragFunction
+
+
+def __getattr__(name):
+    if name == "DragFunction":
+        return _make_function()
+    raise AttributeError(name)

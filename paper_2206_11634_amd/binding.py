@@ -40,7 +40,8 @@ class LbmConfig(ctypes.Structure):
 class LbmSizes(ctypes.Structure):
     _fields_ = [("ncell", ctypes.c_int64), ("cell_stride", ctypes.c_int64),
                 ("population_bytes", ctypes.c_size_t), ("owner_bytes", ctypes.c_size_t),
-                ("flag_bytes", ctypes.c_size_t), ("moment_bytes", ctypes.c_size_t)]
+                ("flag_bytes", ctypes.c_size_t), ("moment_bytes", ctypes.c_size_t),
+                ("checkpoint_bytes", ctypes.c_size_t), ("adjoint_bytes", ctypes.c_size_t)]
 
 
 class LbmBuffers(ctypes.Structure):
@@ -75,12 +76,13 @@ class LbmProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
 
-PHASES = ("bulk", "boundary", "classify", "refill", "dem")
+PHASES = ("bulk", "boundary", "classify", "refill", "dem", "adjoint")
 
 EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_classify_nodes",
            "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
-           "lbm_profile_enable", "lbm_profile_read"]
+           "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
+           "lbm_tape_begin", "lbm_adjoint"]
 
 _lib = None
 
@@ -112,6 +114,10 @@ def load(path: Path | None = None):
         "lbm_synchronize": [_P],
         "lbm_profile_enable": [_P, ctypes.c_int],
         "lbm_profile_read": [_P, ctypes.POINTER(LbmProfile)],
+        "lbm_checkpoint_save": [_P, _P],
+        "lbm_checkpoint_load": [_P, _P],
+        "lbm_tape_begin": [_P, ctypes.c_int],
+        "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -350,6 +356,30 @@ class Lattice:
         node, part = node.cpu().numpy(), part.cpu().numpy()
         o = np.argsort(node, kind="stable")
         return node[o], part[o]
+
+    # differentiation form
+    def checkpoint(self):
+        t = self.torch.empty(self.sizes.checkpoint_bytes, dtype=self.torch.uint8, device=self.device)
+        _check(load().lbm_checkpoint_save(self.ctx, _ptr(t)), self.ctx)
+        return t
+
+    def restore(self, t):
+        _check(load().lbm_checkpoint_load(self.ctx, _ptr(t)), self.ctx)
+
+    def tape_begin(self, steps: int):
+        _check(load().lbm_tape_begin(self.ctx, int(steps)), self.ctx)
+
+    def adjoint_field(self):
+        """A zero adjoint field (Q planes in the storage's arithmetic)."""
+        dt = self.torch.float64 if self.storage == "f64" else self.torch.float32
+        es = 8 if self.storage == "f64" else 4
+        return self.torch.zeros(self.sizes.adjoint_bytes // es, dtype=dt, device=self.device)
+
+    def adjoint(self, parts: "DeviceParticles", weights: np.ndarray, lam, grad):
+        w = np.ascontiguousarray(weights, np.float64).reshape(-1)
+        _check(load().lbm_adjoint(self.ctx, ctypes.byref(parts.struct),
+                                  w.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(grad)),
+               self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -27,6 +27,7 @@ SOURCES = {
     "lbm_stream.hip": [],
     "lbm_classify.hip": ["-ffp-contract=off"],
     "lbm_dem.hip": [],
+    "lbm_adjoint.hip": [],
 }
 
 COMMON = [

@@ -1,0 +1,567 @@
+// Adjoint of the lattice step (differentiation form; not part of the paper).
+//
+// With the geometry schedule held fixed, one taped step maps the populations
+// f(n) (fluid nodes of the owners at n) to f(n+1) (fluid nodes of the owners
+// at n+1): link reconstruction from f(n), pull streaming and BGK + Guo
+// collision of the fluid nodes of n, and refilling + collision of the nodes
+// uncovered between n and n+1.  The objective adds, per step, the momentum
+// exchange force and torque of every particle weighted by (wF, wT).
+//
+// One adjoint step n <- n+1 runs three kernels:
+//  1. k_adj_pre    per node: recompute its pre-collision populations (pull, or
+//                  the refill rules), apply the transposed collision Jacobian
+//                  to lambda(n+1) -> Lambda (the adjoint of the pre-collision
+//                  populations), accumulate dJ/dtau, dJ/dF and, for refilled
+//                  nodes, dJ/dv;
+//  2. k_adj_gather per fluid node y of n: lambda(n)[j](y) collects Lambda of
+//                  the one node that read f_j(y): y + e_j (bulk pull, or
+//                  streaming and bounce-back refill of a node uncovered there),
+//                  or y itself through a wall;
+//  3. k_adj_links  per link: adjoint of its reconstructed population (Lambda
+//                  of the fluid node that pulled the ghost slot, plus the
+//                  objective), transposed through VIBB / halfway by forward-
+//                  mode dual numbers and added to lambda(n) at x_f and x_ff
+//                  with atomics; momentum-exchange and missing-point objective
+//                  terms; dJ/dv, dJ/dF.
+// Arithmetic is that of the storage (double for FP64, float otherwise);
+// parameter gradients are summed in FP64.
+#include "lbm_internal.h"
+#include "lbm_kernels.h"
+
+namespace mdlbm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers with N tangents
+// ---------------------------------------------------------------------------
+template <class A, int N>
+struct Dual {
+    A v;
+    A d[N];
+    __device__ Dual() = default;
+    __device__ Dual(A x) : v(x)
+    {
+#pragma unroll
+        for (int k = 0; k < N; ++k) d[k] = A(0);
+    }
+};
+template <class A, int N>
+__device__ __forceinline__ Dual<A, N> var(A v, int k)
+{
+    Dual<A, N> r(v);
+    r.d[k] = A(1);
+    return r;
+}
+template <class A, int N>
+__device__ __forceinline__ Dual<A, N> operator+(const Dual<A, N>& a, const Dual<A, N>& b)
+{
+    Dual<A, N> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+template <class A, int N>
+__device__ __forceinline__ Dual<A, N> operator-(const Dual<A, N>& a, const Dual<A, N>& b)
+{
+    Dual<A, N> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+template <class A, int N>
+__device__ __forceinline__ Dual<A, N> operator*(const Dual<A, N>& a, const Dual<A, N>& b)
+{
+    Dual<A, N> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+template <class A, int N>
+__device__ __forceinline__ Dual<A, N> operator/(const Dual<A, N>& a, const Dual<A, N>& b)
+{
+    Dual<A, N> r;
+    const A ib = A(1) / b.v;
+    r.v = a.v * ib;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+    return r;
+}
+
+// Equilibrium of direction d at (rho, u), in the deviation form (feq - w) when
+// DEV, generic scalar T.
+template <bool DEV, class A, class T>
+__device__ __forceinline__ T eq_t(int d, const int e[3], const T& rho, const T u[3])
+{
+    const T eu = T(A(e[0])) * u[0] + T(A(e[1])) * u[1] + T(A(e[2])) * u[2];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T poly = T(A(3)) * eu + T(A(4.5)) * (eu * eu) - T(A(1.5)) * uu;
+    const T w = T(W<A>(d));
+    if constexpr (DEV)
+        return w * ((rho - T(A(1))) + rho * poly);
+    else
+        return w * (rho + rho * poly);
+}
+
+// The reconstructed population of a link from its inputs: the formulas of
+// the forward link kernel (VIBB, Eqs. eqneq, neqd, rhod, u*_d, u**_d, u_d; or
+// halfway bounce-back), written for a generic scalar.
+template <bool DEV, class A, class T>
+__device__ T link_value(int kind, int d, const int e[3], A q, const T& fdf, const T& rf,
+                        const T* uf, const T& fdff, const T& rff, const T* uff, const T* uw)
+{
+    const T ebu = T(A(-e[0])) * uw[0] + T(A(-e[1])) * uw[1] + T(A(-e[2])) * uw[2];
+    const T mw = T(A(6) * W<A>(d)) * rf * ebu;
+    if (kind != LBM_LINK_VIBB) return fdf + mw;
+    const A tq = A(2) * q, oq = A(1) - A(2) * q;
+    const T fneq = T(tq) * (fdf - eq_t<DEV, A>(d, e, rf, uf)) +
+                   T(oq) * (fdff - eq_t<DEV, A>(d, e, rff, uff));
+    const T rd = (q <= A(0.5)) ? T(tq) * rf + T(oq) * rff : rf;
+    T ud[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T us = (q <= A(0.5)) ? T(tq) * uf[a] + T(oq) * uff[a]
+                                   : T((A(1) - q) / q) * uf[a] + T((tq - A(1)) / q) * uw[a];
+        const T uss = T((A(1) - q) / (A(1) + q)) * uff[a] + T(tq / (A(1) + q)) * uw[a];
+        ud[a] = us / T(A(3)) + T(A(2)) * uss / T(A(3));
+    }
+    return eq_t<DEV, A>(d, e, rd, ud) + fneq + mw;
+}
+
+__device__ __forceinline__ void dir_of(int d, int e[3])
+{
+    e[0] = (d == 1 || d == 7 || d == 9 || d == 11 || d == 13) ? 1
+         : (d == 2 || d == 8 || d == 10 || d == 12 || d == 14) ? -1 : 0;
+    e[1] = (d == 3 || d == 7 || d == 10 || d == 15 || d == 17) ? 1
+         : (d == 4 || d == 8 || d == 9 || d == 16 || d == 18) ? -1 : 0;
+    e[2] = (d == 5 || d == 11 || d == 14 || d == 15 || d == 18) ? 1
+         : (d == 6 || d == 12 || d == 13 || d == 16 || d == 17) ? -1 : 0;
+}
+
+// Sum n doubles over the block and add them to out[] (one atomic each).
+template <int NV>
+__device__ __forceinline__ void block_add(double (&v)[NV], double* const* out)
+{
+    __shared__ double red[4][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = dsum_wave(v[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                         (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        if (s != 0.0) atomicAdd(out[threadIdx.x], s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1. transposed collision (and refill) per node
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(256) void k_adj_pre(const typename St<S>::T* __restrict__ f,
+                                                 const uint32_t* __restrict__ own0,
+                                                 const uint32_t* __restrict__ own1,
+                                                 const typename St<S>::A* __restrict__ lam1,
+                                                 typename St<S>::A* __restrict__ Lam,
+                                                 const double* pos1, const double* vel1,
+                                                 const double* om1, Geom g, Phys ph,
+                                                 double* grad)
+{
+    using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dJ/dF (3), dJ/dtau
+    if (cell < g.ncell) {
+        if (own1[cell] != kFluid) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) Lam[(int64_t)i * g.stride + cell] = A(0);
+        } else {
+            const uint32_t o0 = own0[cell];
+            const uint32_t nx = g.n[0], ny = g.n[1];
+            const uint32_t x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
+            A lam[kQ], pre[kQ];
+            A un[3] = {A(0), A(0), A(0)};
+            uint64_t rule = 0;  // per direction of a refilled node: 1 bounce-back, 2 equilibrium
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) lam[i] = lam1[(int64_t)i * g.stride + cell];
+            const bool refill = o0 != kFluid;
+            if (!refill) {
+                uint32_t ox[3], oy[3], oz[3];
+                bool vx[3], vy[3], vz[3];
+                axis3(x, nx, g.per[0], 1u, ox, vx);
+                axis3(y, ny, g.per[1], nx, oy, vy);
+                axis3(z, g.n[2], g.per[2], nx * ny, oz, vz);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const int sx = 1 - cx(i), sy = 1 - cy(i), sz = 1 - cz(i);
+                    const bool ok = vx[sx] && vy[sy] && vz[sz];
+                    const uint32_t s = ok ? ox[sx] + oy[sy] + oz[sz] : cell;
+                    const int64_t plane = ok ? i : opp(i);
+                    pre[i] = St<S>::ld(f + plane * g.stride + s, ph.inv_scale);
+                }
+            } else {
+                const int p = (int)o0;
+                const int c[3] = {(int)x, (int)y, (int)z};
+                double rr[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double xp = pos1[3 * p + a];
+                    rr[a] = image_coord(c[a], g.n[a], g.per[a], xp) - xp;
+                }
+                const double* wp = om1 + 3 * p;
+                un[0] = A(vel1[3 * p] + (wp[1] * rr[2] - wp[2] * rr[1]));
+                un[1] = A(vel1[3 * p + 1] + (wp[2] * rr[0] - wp[0] * rr[2]));
+                un[2] = A(vel1[3 * p + 2] + (wp[0] * rr[1] - wp[1] * rr[0]));
+                const A r0 = A(ph.rho0), dr0 = A(ph.rho0 - 1.0);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    int cuu[3] = {c[0] - cx(i), c[1] - cy(i), c[2] - cz(i)};
+                    int cdd[3] = {c[0] + cx(i), c[1] + cy(i), c[2] + cz(i)};
+                    const bool iu = i > 0 && wrap3(cuu, g);
+                    const bool id = i > 0 && wrap3(cdd, g);
+                    const uint32_t nu = iu ? node_of(cuu, g) : cell;
+                    const uint32_t nd = id ? node_of(cdd, g) : cell;
+                    const bool up = iu && own0[nu] == kFluid;
+                    const bool dn = id && own0[nd] == kFluid;
+                    const A eu = A(cx(i)) * un[0] + A(cy(i)) * un[1] + A(cz(i)) * un[2];
+                    if (up) {
+                        pre[i] = St<S>::ld(f + (int64_t)i * g.stride + nu, ph.inv_scale);
+                    } else if (dn) {
+                        pre[i] = St<S>::ld(f + (int64_t)opp(i) * g.stride + nd, ph.inv_scale) +
+                                 A(6) * W<A>(i) * r0 * eu;
+                        rule |= 1ull << (2 * i);
+                    } else {
+                        pre[i] = eq_i<DEV, A>(i, dr0, r0, un[0], un[1], un[2]);
+                        rule |= 2ull << (2 * i);
+                    }
+                }
+            }
+            // transposed BGK + Guo collision at the pre-collision state
+            A F[3];
+            A om;
+            if constexpr (DEV) {
+                F[0] = ph.Ff[0], F[1] = ph.Ff[1], F[2] = ph.Ff[2];
+                om = ph.omegaf;
+            } else {
+                F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
+                om = ph.omega;
+            }
+            A drho, rho, u[3];
+            moments<DEV, A>(pre, A(0.5), F, drho, rho, u[0], u[1], u[2]);
+            const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            const A uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+            A a = A(0), B[3] = {A(0), A(0), A(0)}, G[3] = {A(0), A(0), A(0)};
+            A Fd[3] = {A(0), A(0), A(0)}, dom = A(0);
+            const A gf = A(1) - A(0.5) * om;
+            // feq - pre - S/2 sums to zero over i, so its weight in dJ/domega
+            // may be centred on the mean of lambda, which keeps the sum free of
+            // the cancellation of a large common adjoint density
+            A lbar = A(0);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) lbar += lam[i];
+            lbar *= A(1.0 / kQ);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const A e3[3] = {A(cx(i)), A(cy(i)), A(cz(i))};
+                const A eu = e3[0] * u[0] + e3[1] * u[1] + e3[2] * u[2];
+                const A eF = e3[0] * F[0] + e3[1] * F[1] + e3[2] * F[2];
+                const A P = A(1) + A(3) * eu + A(4.5) * eu * eu - A(1.5) * uu;
+                const A wl = W<A>(i) * lam[i];
+                a += wl * P;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    B[k] += wl * rho * (A(3) * e3[k] + A(9) * eu * e3[k] - A(3) * u[k]);
+                    G[k] += wl * (A(-3) * F[k] + A(9) * eF * e3[k]);
+                    Fd[k] += wl * (A(3) * (e3[k] - u[k]) + A(9) * eu * e3[k]);
+                }
+                const A St_i = W<A>(i) * (A(3) * (eF - uF) + A(9) * eu * eF);
+                const A feq = eq_i<DEV, A>(i, drho, rho, u[0], u[1], u[2]);
+                dom += (lam[i] - lbar) * (feq - pre[i] - A(0.5) * St_i);
+            }
+            A H[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) H[k] = om * B[k] + gf * G[k];
+            const A ir = A(1) / rho;
+            double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) {
+                const A ej[3] = {A(cx(j)), A(cy(j)), A(cz(j))};
+                const A lp = (A(1) - om) * lam[j] + om * a +
+                             (H[0] * (ej[0] - u[0]) + H[1] * (ej[1] - u[1]) + H[2] * (ej[2] - u[2])) * ir;
+                Lam[(int64_t)j * g.stride + cell] = lp;
+                // d pre_j / d u_new of a refilled node: 6 w rho0 e_j for the
+                // bounce-back rule, d feq_j(rho0, u_new)/du for the equilibrium
+                const uint32_t rj = (uint32_t)(rule >> (2 * j)) & 3u;
+                if (rj) {
+                    const A r0 = A(ph.rho0);
+                    const A eun = ej[0] * un[0] + ej[1] * un[1] + ej[2] * un[2];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const A cuk = (rj == 1u) ? A(6) * W<A>(j) * r0 * ej[k]
+                                                 : W<A>(j) * r0 * (A(3) * ej[k] + A(9) * eun * ej[k] - A(3) * un[k]);
+                        dv[k] += (double)(lp * cuk);
+                    }
+                }
+            }
+            if (refill) {
+                const int p = (int)o0;
+                for (int k = 0; k < 3; ++k)
+                    if (dv[k] != 0.0) atomicAdd(grad + 4 + 3 * p + k, dv[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k] = (double)(H[k] * A(0.5) * ir + gf * Fd[k]);
+            acc[3] = -(double)om * (double)om * (double)dom;  // dtau = -omega^2 domega
+        }
+    }
+    double* outs[4] = {grad + 0, grad + 1, grad + 2, grad + 3};
+    block_add<4>(acc, outs);
+}
+
+// ---------------------------------------------------------------------------
+// 2. gather of lambda(n) from Lambda
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(256) void k_adj_gather(const uint32_t* __restrict__ own0,
+                                                    const uint32_t* __restrict__ own1,
+                                                    const typename St<S>::A* __restrict__ Lam,
+                                                    typename St<S>::A* __restrict__ lam0, Geom g)
+{
+    using A = typename St<S>::A;
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= g.ncell) return;
+    if (own0[cell] != kFluid) {
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) lam0[(int64_t)j * g.stride + cell] = A(0);
+        return;
+    }
+    const uint32_t nx = g.n[0], ny = g.n[1];
+    const int c[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / (nx * ny))};
+#pragma unroll
+    for (int j = 0; j < kQ; ++j) {
+        int cxn[3] = {c[0] + cx(j), c[1] + cy(j), c[2] + cz(j)};
+        A acc = A(0);
+        if (wrap3(cxn, g)) {
+            const uint32_t xn = node_of(cxn, g);
+            if (own0[xn] == kFluid) {
+                acc += Lam[(int64_t)j * g.stride + xn];  // pulled by x = y + e_j
+            } else if (own1[xn] == kFluid) {
+                // x = y + e_j refilled: streams f_j(y), and bounces it back as
+                // direction opp(j) unless x + e_j was fluid
+                acc += Lam[(int64_t)j * g.stride + xn];
+                int cz2[3] = {cxn[0] + cx(j), cxn[1] + cy(j), cxn[2] + cz(j)};
+                const bool okz = wrap3(cz2, g);
+                if (!(okz && own0[node_of(cz2, g)] == kFluid))
+                    acc += Lam[(int64_t)opp(j) * g.stride + xn];
+            }
+        } else {
+            acc += Lam[(int64_t)opp(j) * g.stride + cell];  // wall: y pulls f_j(y) as opp(j)
+        }
+        lam0[(int64_t)j * g.stride + cell] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. links: reconstruction, momentum exchange and missing points
+// ---------------------------------------------------------------------------
+template <class A>
+__device__ __forceinline__ void atomic_add_a(A* p, A v)
+{
+    if (v != A(0)) atomicAdd(p, v);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __restrict__ f,
+                                                   const LinkRec* __restrict__ links,
+                                                   const uint32_t* __restrict__ cursor,
+                                                   int64_t cap, const double* pos,
+                                                   const double* vel, const double* om,
+                                                   const typename St<S>::A* __restrict__ Lam,
+                                                   typename St<S>::A* lam0, const double* wts,
+                                                   Geom g, Phys ph, double* grad)
+{
+    using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
+    using D13 = Dual<A, 13>;
+    const int p = blockIdx.y;
+    const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
+    if (blockIdx.x * 256u >= cnt) return;
+    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};  // dJ/dF (3), dJ/dv_p (3)
+    if (l < cnt) {
+        const LinkRec r = links[(int64_t)p * cap + l];
+        const int d = r.d, db = opp(d);
+        int e[3];
+        dir_of(d, e);
+        const uint32_t nx = g.n[0], ny = g.n[1];
+        const int cs[3] = {(int)(r.node % nx), (int)((r.node / nx) % ny), (int)(r.node / (nx * ny))};
+        int cn[3] = {cs[0] - e[0], cs[1] - e[1], cs[2] - e[2]};
+        wrap3(cn, g);
+        double rr[3], uw[3], Wv[3];
+        const double* xp = pos + 3 * p;
+        const double* wp = om + 3 * p;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double Xn = image_coord(cn[a], g.n[a], g.per[a], xp[a]);
+            rr[a] = Xn + r.q * (double)e[a] - xp[a];
+        }
+        uw[0] = vel[3 * p] + (wp[1] * rr[2] - wp[2] * rr[1]);
+        uw[1] = vel[3 * p + 1] + (wp[2] * rr[0] - wp[0] * rr[2]);
+        uw[2] = vel[3 * p + 2] + (wp[0] * rr[1] - wp[1] * rr[0]);
+        // objective weight of this force point: wF + wT x r (J = F.wF + (r x F).wT)
+        const double* wF = wts + 6 * p;
+        const double* wT = wts + 6 * p + 3;
+        Wv[0] = wF[0] + (wT[1] * rr[2] - wT[2] * rr[1]);
+        Wv[1] = wF[1] + (wT[2] * rr[0] - wT[0] * rr[2]);
+        Wv[2] = wF[2] + (wT[0] * rr[1] - wT[1] * rr[0]);
+        if (r.kind == LBM_LINK_MISSING) {
+            // J = [(e_d - u_w) feq_d(rho0, u_w) - (e_db - u_w) feq_db(rho0, u_w)] . W
+            using D3 = Dual<double, 3>;
+            D3 u3[3] = {var<double, 3>(uw[0], 0), var<double, 3>(uw[1], 1), var<double, 3>(uw[2], 2)};
+            int eb[3] = {-e[0], -e[1], -e[2]};
+            const D3 r0 = D3(ph.rho0);
+            const D3 fo = eq_t<false, double>(d, e, r0, u3);
+            const D3 fi = eq_t<false, double>(db, eb, r0, u3);
+            D3 J = D3(0.0);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                J = J + D3(Wv[a]) * ((D3((double)e[a]) - u3[a]) * fo - (D3((double)eb[a]) - u3[a]) * fi);
+            acc[3] = J.d[0], acc[4] = J.d[1], acc[5] = J.d[2];
+        } else {
+            A F[3];
+            if constexpr (DEV) {
+                F[0] = ph.Ff[0], F[1] = ph.Ff[1], F[2] = ph.Ff[2];
+            } else {
+                F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
+            }
+            const uint32_t xf = node_of(cn, g);
+            A v[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) v[i] = St<S>::ld(f + (int64_t)i * g.stride + xf, ph.inv_scale);
+            A drf, rf, uf[3];
+            moments<DEV, A>(v, A(-0.5), F, drf, rf, uf[0], uf[1], uf[2]);
+            A fdf = A(0);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) fdf = (i == d) ? v[i] : fdf;
+            uint32_t xff = xf;
+            A rff = A(1), uff[3] = {A(0), A(0), A(0)}, fdff = A(0), drff = A(0);
+            if (r.kind == LBM_LINK_VIBB) {
+                int cf[3] = {cn[0] - e[0], cn[1] - e[1], cn[2] - e[2]};
+                wrap3(cf, g);
+                xff = node_of(cf, g);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) v[i] = St<S>::ld(f + (int64_t)i * g.stride + xff, ph.inv_scale);
+                moments<DEV, A>(v, A(-0.5), F, drff, rff, uff[0], uff[1], uff[2]);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) fdff = (i == d) ? v[i] : fdff;
+            }
+            // value and gradient of the reconstructed population
+            D13 x_fdf = var<A, 13>(fdf, 0), x_rf = var<A, 13>(rf, 1);
+            D13 x_uf[3] = {var<A, 13>(uf[0], 2), var<A, 13>(uf[1], 3), var<A, 13>(uf[2], 4)};
+            D13 x_fdff = var<A, 13>(fdff, 5), x_rff = var<A, 13>(rff, 6);
+            D13 x_uff[3] = {var<A, 13>(uff[0], 7), var<A, 13>(uff[1], 8), var<A, 13>(uff[2], 9)};
+            D13 x_uw[3] = {var<A, 13>(A(uw[0]), 10), var<A, 13>(A(uw[1]), 11),
+                           var<A, 13>(A(uw[2]), 12)};
+            const D13 unk = link_value<DEV, A>(r.kind, d, e, A(r.q), x_fdf, x_rf, x_uf, x_fdff,
+                                               x_rff, x_uff, x_uw);
+            // momentum exchange of this link: [(e_d - u_w) out - (e_db - u_w) in] . W
+            double out = (double)fdf, in = (double)unk.v;
+            if constexpr (DEV) {
+                out += wgt(d);
+                in += wgt(db);
+            }
+            double d_out = 0.0, d_in = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                d_out += ((double)e[a] - uw[a]) * Wv[a];
+                d_in += ((double)e[a] + uw[a]) * Wv[a];
+                acc[3 + a] += -(out - in) * Wv[a];
+            }
+            // adjoint of the reconstructed value: the fluid node that pulled
+            // the ghost slot, plus the objective
+            const A lu = Lam[(int64_t)db * g.stride + xf] + A(d_in);
+            A gk[13];
+#pragma unroll
+            for (int k = 0; k < 13; ++k) gk[k] = lu * unk.d[k];
+            atomic_add_a(lam0 + (int64_t)d * g.stride + xf, gk[0] + A(d_out));
+            const A irf = A(1) / rf;
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) {
+                const A t = gk[1] + (gk[2] * (A(cx(j)) - uf[0]) + gk[3] * (A(cy(j)) - uf[1]) +
+                                     gk[4] * (A(cz(j)) - uf[2])) * irf;
+                atomic_add_a(lam0 + (int64_t)j * g.stride + xf, t);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[a] += -(double)(gk[2 + a] * A(0.5) * irf);
+            if (r.kind == LBM_LINK_VIBB) {
+                atomic_add_a(lam0 + (int64_t)d * g.stride + xff, gk[5]);
+                const A irff = A(1) / rff;
+#pragma unroll
+                for (int j = 0; j < kQ; ++j) {
+                    const A t = gk[6] + (gk[7] * (A(cx(j)) - uff[0]) + gk[8] * (A(cy(j)) - uff[1]) +
+                                         gk[9] * (A(cz(j)) - uff[2])) * irff;
+                    atomic_add_a(lam0 + (int64_t)j * g.stride + xff, t);
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) acc[a] += -(double)(gk[7 + a] * A(0.5) * irff);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[3 + a] += (double)gk[10 + a];
+            (void)drf;
+            (void)drff;
+        }
+    }
+    double* outs[6] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
+                       grad + 6 + 3 * p};
+    block_add<6>(acc, outs);
+}
+
+inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
+
+template <int S>
+struct RunAdj {
+    static hipError_t run(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1, const double* pos1,
+                          const double* vel1, const double* om1, const void* lam1, void* Lam,
+                          void* lam0, const double* wts, double* grad)
+    {
+        using T = typename St<S>::T;
+        using A = typename St<S>::A;
+        const uint32_t nb = blocks_for(c->geom.ncell);
+        hipLaunchKernelGGL(k_adj_pre<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f, ts.own,
+                           own1, (const A*)lam1, (A*)Lam, pos1, vel1, om1, c->geom, c->phys, grad);
+        hipLaunchKernelGGL(k_adj_gather<S>, dim3(nb), dim3(256), 0, c->stream, ts.own, own1,
+                           (const A*)Lam, (A*)lam0, c->geom);
+        if (c->cfg.n_particles > 0 && ts.link_max > 0) {
+            dim3 grid(blocks_for(ts.link_max), c->cfg.n_particles);
+            hipLaunchKernelGGL(k_adj_links<S>, grid, dim3(256), 0, c->stream, (const T*)ts.f,
+                               ts.links, ts.cursor, ts.link_cap, ts.part, ts.part + 3 * c->cfg.n_particles,
+                               ts.part + 6 * c->cfg.n_particles, (const A*)Lam, (A*)lam0, wts,
+                               c->geom, c->phys, grad);
+        }
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
+                               const double* pos1, const double* vel1, const double* om1,
+                               const void* lam1, void* Lam, void* lam0, const double* wts,
+                               double* grad)
+{
+    switch (c->cfg.storage) {
+    case LBM_STORE_F64:
+        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, Lam, lam0, wts, grad);
+    case LBM_STORE_F32:
+        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, Lam, lam0, wts, grad);
+    case LBM_STORE_F16:
+        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, Lam, lam0, wts, grad);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mdlbm

@@ -129,6 +129,57 @@ std::string err_text(uint32_t bits)
     return s;
 }
 
+void free_tape(lbm_ctx* c)
+{
+    for (auto& t : c->tape) {
+        (void)hipFree(t.f);
+        (void)hipFree(t.own);
+        (void)hipFree(t.links);
+        (void)hipFree(t.cursor);
+        (void)hipFree(t.part);
+    }
+    c->tape.clear();
+    c->tape_len = 0;
+    c->taping = false;
+}
+
+// Record the step about to stream: populations with the reconstructed ghost
+// slots, the owners of the last classification, its links, the particles.
+int record_tape_step(lbm_ctx* c, const lbm_particles* P)
+{
+    const int np = c->cfg.n_particles;
+    TapeStep& t = c->tape[c->tape_len];
+    HIPCHK(c, hipMemcpyAsync(t.f, c->f[c->cur], c->sizes.population_bytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(t.own, c->own[c->own_cur], c->sizes.owner_bytes,
+                             hipMemcpyDeviceToDevice, c->stream));
+    if (np > 0) {
+        const int64_t need = (int64_t)np * c->link_cap;
+        if (t.link_alloc < need) {
+            HIPCHK(c, hipFree(t.links));
+            t.links = nullptr;
+            if (alloc(&t.links, (size_t)need) != hipSuccess)
+                return fail(c, LBM_ENOMEM, "tape link allocation failed");
+            t.link_alloc = need;
+        }
+        t.link_cap = c->link_cap;
+        t.link_max = c->link_max;
+        if (c->link_max > 0)
+            HIPCHK(c, hipMemcpyAsync(t.links, c->links, sizeof(LinkRec) * (size_t)need,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.cursor, c->link_cursor, sizeof(uint32_t) * kCursorPad * (size_t)np,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.part, P->pos, sizeof(double) * 3 * np, hipMemcpyDeviceToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.part + 3 * np, P->vel, sizeof(double) * 3 * np,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.part + 6 * np, P->omega, sizeof(double) * 3 * np,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+    c->tape_len += 1;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -148,6 +199,8 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
     out->owner_bytes = (size_t)ncell * sizeof(uint32_t);
     out->flag_bytes = (size_t)ncell;
     out->moment_bytes = (size_t)ncell * 4 * es;
+    out->checkpoint_bytes = out->population_bytes + out->moment_bytes;
+    out->adjoint_bytes = (size_t)kQ * (size_t)out->cell_stride * (es == 8 ? 8 : 4);
     return LBM_OK;
 }
 
@@ -176,6 +229,7 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     lbm_ctx* c = new (std::nothrow) lbm_ctx;
     if (!c) return fail(nullptr, LBM_ENOMEM, "context allocation failed");
     c->cfg = *cfg;
+    c->sizes = sz;
     c->stream = (hipStream_t)cfg->stream;
     for (int a = 0; a < 3; ++a) {
         c->geom.n[a] = dims[a];
@@ -278,6 +332,16 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->FT);
     (void)hipFree(c->fc);
     (void)hipFree(c->reach);
+    for (auto& t : c->tape) {
+        (void)hipFree(t.f);
+        (void)hipFree(t.own);
+        (void)hipFree(t.links);
+        (void)hipFree(t.cursor);
+        (void)hipFree(t.part);
+    }
+    (void)hipFree(c->adj_scratch[0]);
+    (void)hipFree(c->adj_scratch[1]);
+    (void)hipFree(c->adj_wts);
     (void)hipFree(c->hist_pp);
     (void)hipFree(c->hist_pw);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -420,6 +484,10 @@ int lbm_step(lbm_ctx* c, const lbm_particles* P)
         HIPCHK(c, launch_zero_f64(c, c->FT, 6 * (int64_t)np));
         if (np > 0 && c->n_classify > 0) HIPCHK(c, launch_boundary(c, c->f[c->cur], to_dev(P)));
     }
+    if (c->taping && c->tape_len < (int)c->tape.size()) {
+        int rc2 = record_tape_step(c, P);
+        if (rc2) return rc2;
+    }
     {
         PhaseTimer tm(c, LBM_PHASE_BULK);
         HIPCHK(c, launch_stream_collide(c, c->f[c->cur], c->f[1 - c->cur]));
@@ -532,6 +600,102 @@ int lbm_synchronize(lbm_ctx* c)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_checkpoint_save(const lbm_ctx* cc, void* dst_dev)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c || !dst_dev) return fail(c, LBM_EINVAL, "null argument");
+    HIPCHK(c, hipMemcpyAsync(dst_dev, c->f[c->cur], c->sizes.population_bytes,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char*)dst_dev + c->sizes.population_bytes, c->mom,
+                             c->sizes.moment_bytes, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+int lbm_checkpoint_load(lbm_ctx* c, const void* src_dev)
+{
+    if (!c || !src_dev) return fail(c, LBM_EINVAL, "null argument");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src_dev, c->sizes.population_bytes,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->mom, (const char*)src_dev + c->sizes.population_bytes,
+                             c->sizes.moment_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->own[0], 0xFF, c->sizes.owner_bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->own[1], 0xFF, c->sizes.owner_bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, c->sizes.flag_bytes, c->stream));
+    c->n_classify = 0;
+    c->own_cur = 0;
+    c->stepped_since_classify = false;
+    c->link_max = c->link_total = c->refill_total = c->cand_total = 0;
+    return LBM_OK;
+}
+
+int lbm_tape_begin(lbm_ctx* c, int max_steps)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (max_steps < 1) return fail(c, LBM_EINVAL, "max_steps must be >= 1");
+    if (c->n_classify == 0) return fail(c, LBM_ESTATE, "classify before taping");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_tape(c);
+    const int np = c->cfg.n_particles;
+    c->tape.resize(max_steps);
+    for (auto& t : c->tape) {
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = hipMalloc(&t.f, c->sizes.population_bytes);
+        if (e == hipSuccess) e = alloc(&t.own, c->sizes.owner_bytes / sizeof(uint32_t));
+        if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
+        if (e == hipSuccess) e = alloc(&t.part, (size_t)9 * std::max(np, 1));
+        if (e != hipSuccess) {
+            free_tape(c);
+            return fail(c, LBM_ENOMEM, "tape allocation failed");
+        }
+    }
+    c->tape_len = 0;
+    c->taping = true;
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void* lam_dev,
+                double* grad_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (!lam_dev || !grad_dev) return fail(c, LBM_EINVAL, "null argument");
+    if (c->tape_len == 0) return fail(c, LBM_ESTATE, "nothing was taped");
+    int rc = check_particles(c, P, false);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    if (np > 0 && !weights) return fail(c, LBM_EINVAL, "null objective weights");
+    for (int i = 0; i < 2; ++i)
+        if (!c->adj_scratch[i] && hipMalloc(&c->adj_scratch[i], c->sizes.adjoint_bytes) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "adjoint scratch allocation failed");
+    if (!c->adj_wts && alloc(&c->adj_wts, (size_t)6 * std::max(np, 1)) != hipSuccess)
+        return fail(c, LBM_ENOMEM, "adjoint weight allocation failed");
+    if (np > 0)
+        HIPCHK(c, hipMemcpyAsync(c->adj_wts, weights, sizeof(double) * 6 * np,
+                                 hipMemcpyHostToDevice, c->stream));
+    void* bufs[2] = {lam_dev, c->adj_scratch[0]};
+    void* Lam = c->adj_scratch[1];
+    int in = 0;
+    for (int s = c->tape_len - 1; s >= 0; --s) {
+        const TapeStep& ts = c->tape[s];
+        const bool last = s + 1 >= c->tape_len;
+        const uint32_t* own1 = last ? c->own[c->own_cur] : c->tape[s + 1].own;
+        const double* pos1 = last ? P->pos : c->tape[s + 1].part;
+        const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
+        const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
+        PhaseTimer tm(c, LBM_PHASE_ADJOINT);
+        HIPCHK(c, launch_adjoint_step(c, ts, own1, pos1, vel1, om1, bufs[in], Lam, bufs[1 - in],
+                                      c->adj_wts, grad_dev));
+        in = 1 - in;
+    }
+    if (in != 0)
+        HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_tape(c);
     return LBM_OK;
 }
 

@@ -63,6 +63,19 @@ struct RefillRec {
     uint32_t part;
 };
 
+// One recorded lattice step for the adjoint: populations after the link
+// reconstruction (ghost slots filled), owners, links and particle state.
+struct TapeStep {
+    void* f = nullptr;
+    uint32_t* own = nullptr;
+    LinkRec* links = nullptr;
+    int64_t link_cap = 0;        // per particle, of this record
+    int64_t link_alloc = 0;      // records allocated
+    uint32_t* cursor = nullptr;  // [np * kCursorPad]
+    int64_t link_max = 0;
+    double* part = nullptr;      // [9 np]: pos, vel, omega
+};
+
 // Lattice geometry passed by value to kernels.
 struct Geom {
     int n[3];
@@ -160,6 +173,13 @@ struct lbm_ctx {
     std::vector<hipEvent_t> event_pool;
     double prof_ms[LBM_PHASE_COUNT] = {};
     int64_t prof_n[LBM_PHASE_COUNT] = {};
+    // differentiation form
+    lbm_sizes sizes{};
+    std::vector<mdlbm::TapeStep> tape;
+    int tape_len = 0;
+    bool taping = false;
+    void* adj_scratch[2] = {nullptr, nullptr};
+    double* adj_wts = nullptr;
     std::string last_error;
 };
 
@@ -186,6 +206,12 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
 hipError_t launch_owner_export(const lbm_ctx* c, const uint32_t* own, int32_t* out);
 hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t* kind,
                               int32_t* part, double* q, const int64_t* offsets_dev);
+
+// Launchers (lbm_adjoint.hip)
+hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
+                               const double* pos1, const double* vel1, const double* om1,
+                               const void* lam1, void* Lam, void* lam0, const double* wts,
+                               double* grad);
 
 // Launchers (lbm_dem.hip)
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);

@@ -1,0 +1,134 @@
+"""Adjoint gradients (differentiation form) against central finite
+differences of the forward pass and of the FP64 oracle, with the geometry
+schedule of the nominal trajectory held fixed."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2206_11634_amd import adjoint as AD
+from paper_2206_11634_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(storage, steps=48, window=20, n=28):
+    rng = np.random.default_rng(51)
+    lat = W.LatticeSpec(n, n - 4, n, (1, 0, 1), tau=0.7, body_force=(1e-5, 0.0, 0.0))
+    pts = np.array([[0.0, 0, 0], [1.0, 0, 0], [2.0, 0, 0], [1.0, 0.6, 0]])
+    sh = W.metaball_shape(pts, rng.uniform(0.5, 1.5, 4) * 0.12, 0.1, length=8.0,
+                          axis=np.array([1.0, 0, 0]), samples_per_unit=4.0)
+    sh2 = W.sphere_shape(6.0, 0.1)
+    # particle 1 dips 0.2 lattice units below the wall y = 0 (halfway and
+    # missing-point links), clear of particle 0 along z
+    ps = W.make_particles([sh, sh2], [[n / 2, (n - 4) / 2, n / 2], [n / 2 + 1.0, 2.8, n / 2 + 9.0]],
+                          [W.random_quaternion(rng), [1, 0, 0, 0]], 1.0,
+                          vel=np.array([[0.04, 0.006, -0.005], [0.03, 0.0, 0.01]]),
+                          omega=np.zeros((2, 3)))
+    w = np.zeros((2, 6))
+    w[0, 0] = 1.0 / steps
+    w[0, 4] = 0.5 / steps
+    w[1, 1] = 0.3 / steps
+    # initial populations: the fluid at rest, f_i = w_i (D3Q19 numbering: rest,
+    # 6 axis directions, 12 face diagonals)
+    wq = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    f0 = np.repeat(wq[:, None], lat.ncell, axis=1)
+    return AD.Problem(lat=lat, ps=ps, steps=steps, window=window, storage=storage, weights=w, f0=f0)
+
+
+def _fd(prob, v, F, tau, which, k, h, fn):
+    def at(dv):
+        vv, FF, tt = v.copy(), np.array(F, float), tau
+        if which == "v":
+            vv[k // 3, k % 3] += dv
+        elif which == "F":
+            FF[k] += dv
+        else:
+            tt += dv
+        return fn(prob, vv, FF, tt)
+    return (at(h) - at(-h)) / (2 * h)
+
+
+def _gpu_J(prob, v, F, tau):
+    return AD.evaluate(prob, v, F, tau, grad=False)
+
+
+def _check(prob, fd_prob, fn, rtol):
+    v = prob.ps.vel.copy()
+    F = np.array(prob.lat.body_force)
+    tau = prob.lat.tau
+    J, dv, dF, dtau = AD.evaluate(prob, v, F, tau, grad=True)
+    J64 = fn(fd_prob, v, F, tau)
+    assert abs(J - J64) <= 1e-4 * abs(J64) + 1e-12
+    scale = max(np.abs(dv).max(), 1e-12)
+    for k in range(6):
+        g = _fd(fd_prob, v, F, tau, "v", k, 1e-5, fn)
+        assert abs(dv[k // 3, k % 3] - g) <= rtol * scale, (k, dv[k // 3, k % 3], g)
+    gF = _fd(fd_prob, v, F, tau, "F", 0, 1e-6, fn)
+    assert abs(dF[0] - gF) <= rtol * abs(gF), (dF[0], gF)
+    gt = _fd(fd_prob, v, F, tau, "tau", 0, 1e-5, fn)
+    assert abs(dtau - gt) <= rtol * abs(gt), (dtau, gt)
+    return dv, dF, dtau
+
+
+def test_fp64_adjoint_matches_finite_differences():
+    prob = _problem("f64")
+    _check(prob, prob, _gpu_J, 2e-6)
+
+
+def test_fp32_adjoint_within_1e3_of_fp64_finite_differences():
+    prob = _problem("f32")
+    _check(prob, dataclasses.replace(prob, storage="f64"), _gpu_J, 1e-3)
+
+
+def _oracle_J(prob, v, F, tau):
+    lat = dataclasses.replace(prob.lat, body_force=tuple(F), tau=tau)
+    o = O.Oracle(lat)
+    o.f[...] = prob.f0
+    def state(n):
+        P = W.prescribed_state(prob.ps, prob.lat, float(n))
+        P.vel = np.asarray(v, float).copy()
+        return P
+    o.classify(state(0))
+    J = 0.0
+    for n in range(prob.steps):
+        Fh, Th = o.step(state(n))
+        J += float((prob.weights[:, :3] * Fh).sum() + (prob.weights[:, 3:] * Th).sum())
+        o.classify(state(n + 1))
+    return J
+
+
+def test_fp64_adjoint_matches_oracle_reference_gradient():
+    """The reference gradient is central differences of the FP64 CPU oracle."""
+    prob = _problem("f64", steps=30, window=12, n=26)
+    _check(prob, prob, _oracle_J, 5e-6)
+
+
+def test_windowed_recomputation_matches_a_single_window():
+    prob = _problem("f64", steps=30, window=7)
+    one = dataclasses.replace(prob, window=30)
+    v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
+    a = AD.evaluate(prob, v, F, tau, grad=True)
+    b = AD.evaluate(one, v, F, tau, grad=True)
+    assert abs(a[0] - b[0]) <= 1e-13 * abs(b[0])
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-10, atol=1e-12 * np.abs(b[1]).max())
+    np.testing.assert_allclose(a[2], b[2], rtol=1e-10)
+    # dJ/dtau sums a node-wise product whose terms cancel; atomics add the
+    # block partial sums in no fixed order
+    assert abs(a[3] - b[3]) <= 1e-7 * abs(b[3])
+
+
+def test_autograd_function_returns_the_adjoint_gradient():
+    import torch
+    prob = _problem("f64", steps=20, window=8)
+    v = torch.tensor(prob.ps.vel, dtype=torch.float64, requires_grad=True)
+    F = torch.tensor(prob.lat.body_force, dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(prob.lat.tau, dtype=torch.float64, requires_grad=True)
+    J = AD.DragFunction.apply(v, F, tau, prob)
+    (2.0 * J).backward()
+    ref = AD.evaluate(prob, prob.ps.vel, np.array(prob.lat.body_force), prob.lat.tau, grad=True)
+    assert abs(float(J.detach()) - ref[0]) <= 1e-13 * abs(ref[0])
+    np.testing.assert_allclose(v.grad.numpy(), 2 * ref[1], rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(F.grad.numpy(), 2 * ref[2], rtol=1e-10)
+    assert abs(float(tau.grad) - 2 * ref[3]) <= 1e-7 * abs(ref[3])
