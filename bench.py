@@ -168,6 +168,62 @@ def drag_error(steps=200):
     return out
 
 
+def adjoint_bench(fd_check=True):
+    """The differentiation form on the 128^3 channel: FP32 forward over 2000
+    steps with checkpoints every 100, then the adjoint window by window
+    (recomputation included), J = mean x-force on the particle.  With
+    fd_check the gradient is compared with central differences of the FP64
+    forward pass."""
+    import torch
+    from paper_2206_11634_amd import adjoint as AD
+    from paper_2206_11634_amd import workloads as W
+
+    lat, ps, meta = W.config_c5()
+    T, K = meta["steps"], meta["checkpoint"]
+    prob = AD.Problem(lat=lat, ps=ps, steps=T, window=K, storage=meta["storage"])
+    v, F, tau = ps.vel.copy(), np.array(lat.body_force), lat.tau
+    prob.initial()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, run = AD.forward(prob, v, F, tau, keep=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {}
+    dv, dF, dtau = AD.backward(run, stats)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    adj_ms, adj_n = stats.get("adjoint", (0.0, 0))
+    out = dict(workload=meta["name"], lattice=[lat.nx, lat.ny, lat.nz], steps=T, checkpoint=K,
+               storage=meta["storage"], J=J,
+               forward_steps_per_s=round(T / (t1 - t0), 1),
+               adjoint_steps_per_s=round(T / (t2 - t1), 1),
+               adjoint_kernels_ms_per_step=round(adj_ms / max(adj_n, 1), 4),
+               grad=dict(dJ_dU=dv[0].tolist(), dJ_dF=dF.tolist(), dJ_dtau=dtau))
+    print(f"[bench] adjoint: forward {t1 - t0:.2f} s, backward {t2 - t1:.2f} s",
+          file=sys.stderr, flush=True)
+    if fd_check:
+        import dataclasses
+        ref = dataclasses.replace(prob, storage="f64")
+
+        def fd(kind, h):
+            def at(d):
+                vv, FF, tt = v.copy(), F.copy(), tau
+                if kind == "U":
+                    vv[0, 0] += d
+                elif kind == "F":
+                    FF[0] += d
+                else:
+                    tt += d
+                return AD.evaluate(ref, vv, FF, tt)
+            return (at(h) - at(-h)) / (2 * h)
+
+        g = dict(U_x=(dv[0, 0], fd("U", 1e-4)), F_x=(dF[0], fd("F", 1e-7)),
+                 tau=(dtau, fd("tau", 1e-4)))
+        out["fd_rel_err"] = {k: float(abs(a - b) / abs(b)) for k, (a, b) in g.items()}
+        out["fd_reference"] = "central differences of the FP64-storage forward pass"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +235,7 @@ def main():
                     help="other storages timed on the same workload (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drag", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -247,6 +304,8 @@ def main():
                                              main_res["ms_per_step"], 3)
     if not args.no_drag:
         line["drag_err"] = drag_error()
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -254,10 +254,15 @@ int lbm_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
 
 /* Record the next max_steps calls of lbm_step (populations after the link
  * reconstruction, owners, links, particle pose and velocities) for
- * lbm_adjoint.  Allocates the tape (ENOMEM when it does not fit). */
+ * lbm_adjoint.  The tape's device memory (about population_bytes +
+ * owner_bytes + the link list per step) is allocated on the first call that
+ * needs more steps than are held and kept for later windows; max_steps = 0
+ * releases it (lbm_destroy does too).  ENOMEM when it does not fit, ESTATE
+ * before the first classification. */
 int lbm_tape_begin(lbm_ctx* ctx, int max_steps);
 
-/* Run the adjoint backwards over the taped steps and release the tape.
+/* Run the adjoint backwards over the taped steps; the tape's memory is kept
+ * for the next lbm_tape_begin.
  *   P        particle state after the last taped step (the one the last
  *            classification used: its velocities drive that refill);
  *   weights  host [n][6]: (wF, wT) per particle, the same for every step;

@@ -64,40 +64,42 @@ class _Run:
     def set(self, n):
         self.parts.set_state(self.state(n))
 
-    def objective(self, F, T):
-        w = self.prob.weights
-        return float((w[:, :3] * F).sum() + (w[:, 3:] * T).sum())
 
 
 def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
     """Run the forward pass; J, and the run (with its checkpoints) if keep."""
     run = _Run(prob, vel, body_force, tau)
-    gpu, T = run.gpu, prob.steps
+    gpu, T, n = run.gpu, prob.steps, prob.ps.n
+    torch = gpu.torch
     gpu.set_populations(prob.initial())
     run.ckpt = {}
-    J = 0.0
+    hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
     run.set(0)
     gpu.classify(run.parts)
-    for n in range(T):
-        if keep and n % prob.window == 0:
-            run.ckpt[n] = gpu.checkpoint()
-        run.set(n)
+    for k in range(T):
+        if keep and k % prob.window == 0:
+            run.ckpt[k] = gpu.checkpoint()
+        run.set(k)
         gpu.step(run.parts)
-        F, Tq = gpu.forces()
-        J += run.objective(F.cpu().numpy(), Tq.cpu().numpy())
-        run.set(n + 1)
+        gpu.forces(hist[k, 0], hist[k, 1])
+        run.set(k + 1)
         gpu.classify(run.parts)
+    w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
+    J = float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
     if not keep:
         gpu.close()
         return J, None
     return J, run
 
 
-def backward(run: _Run):
+def backward(run: _Run, stats: dict | None = None):
     """(dJ/dv [n][3], dJ/dF [3], dJ/dtau) by the adjoint, window by window from
-    the last checkpoint to the first, recomputing each window's steps."""
+    the last checkpoint to the first, recomputing each window's steps.  With
+    a dict for stats, the library's per-phase timers are read into it."""
     prob, gpu = run.prob, run.gpu
     torch = gpu.torch
+    if stats is not None:
+        gpu.profile(True)
     lam = gpu.adjoint_field()
     g = torch.zeros(4 + 3 * prob.ps.n, dtype=torch.float64, device=gpu.device)
     for w0 in sorted(run.ckpt, reverse=True):
@@ -113,6 +115,9 @@ def backward(run: _Run):
             gpu.classify(run.parts)
         gpu.adjoint(run.parts, prob.weights, lam, g)
     out = g.cpu().numpy()
+    if stats is not None:
+        stats.update(gpu.profile_read())
+        gpu.profile(False)
     gpu.close()
     return out[4:].reshape(prob.ps.n, 3), out[:3].copy(), float(out[3])
 

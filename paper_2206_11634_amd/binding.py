@@ -282,9 +282,14 @@ class Lattice:
     def step(self, parts: DeviceParticles):
         lbm_step(self.ctx, parts.struct)
 
-    def forces(self):
-        lbm_particle_forces(self.ctx, self.F, self.T)
-        return self.F[: self.n_particles], self.T[: self.n_particles]
+    def forces(self, F=None, T=None):
+        """The last step's F^h, T^h (device, [n][3] float64 each), copied into
+        F and T when given (contiguous device tensors), else into the
+        lattice's own buffers."""
+        if F is None:
+            F, T = self.F, self.T
+        lbm_particle_forces(self.ctx, F, T)
+        return F[: self.n_particles], T[: self.n_particles]
 
     def dem(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
         dem_step(self.ctx, parts.struct, n_sub, dt, prm)

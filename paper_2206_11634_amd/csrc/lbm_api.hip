@@ -140,6 +140,7 @@ void free_tape(lbm_ctx* c)
     }
     c->tape.clear();
     c->tape_len = 0;
+    c->tape_steps = 0;
     c->taping = false;
 }
 
@@ -484,7 +485,7 @@ int lbm_step(lbm_ctx* c, const lbm_particles* P)
         HIPCHK(c, launch_zero_f64(c, c->FT, 6 * (int64_t)np));
         if (np > 0 && c->n_classify > 0) HIPCHK(c, launch_boundary(c, c->f[c->cur], to_dev(P)));
     }
-    if (c->taping && c->tape_len < (int)c->tape.size()) {
+    if (c->taping && c->tape_len < c->tape_steps) {
         int rc2 = record_tape_step(c, P);
         if (rc2) return rc2;
     }
@@ -635,24 +636,32 @@ int lbm_checkpoint_load(lbm_ctx* c, const void* src_dev)
 int lbm_tape_begin(lbm_ctx* c, int max_steps)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
-    if (max_steps < 1) return fail(c, LBM_EINVAL, "max_steps must be >= 1");
-    if (c->n_classify == 0) return fail(c, LBM_ESTATE, "classify before taping");
+    if (max_steps < 0) return fail(c, LBM_EINVAL, "max_steps must be >= 0");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    free_tape(c);
+    if (max_steps == 0) {
+        free_tape(c);
+        return LBM_OK;
+    }
+    if (c->n_classify == 0) return fail(c, LBM_ESTATE, "classify before taping");
     const int np = c->cfg.n_particles;
-    c->tape.resize(max_steps);
-    for (auto& t : c->tape) {
-        hipError_t e = hipSuccess;
-        if (e == hipSuccess) e = hipMalloc(&t.f, c->sizes.population_bytes);
-        if (e == hipSuccess) e = alloc(&t.own, c->sizes.owner_bytes / sizeof(uint32_t));
-        if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
-        if (e == hipSuccess) e = alloc(&t.part, (size_t)9 * std::max(np, 1));
-        if (e != hipSuccess) {
-            free_tape(c);
-            return fail(c, LBM_ENOMEM, "tape allocation failed");
+    // entries allocated by an earlier window are reused as they are
+    const size_t have = c->tape.size();
+    if (have < (size_t)max_steps) {
+        c->tape.resize(max_steps);
+        for (size_t k = have; k < c->tape.size(); ++k) {
+            TapeStep& t = c->tape[k];
+            hipError_t e = hipMalloc(&t.f, c->sizes.population_bytes);
+            if (e == hipSuccess) e = alloc(&t.own, c->sizes.owner_bytes / sizeof(uint32_t));
+            if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
+            if (e == hipSuccess) e = alloc(&t.part, (size_t)9 * std::max(np, 1));
+            if (e != hipSuccess) {
+                free_tape(c);
+                return fail(c, LBM_ENOMEM, "tape allocation failed");
+            }
         }
     }
     c->tape_len = 0;
+    c->tape_steps = max_steps;
     c->taping = true;
     return LBM_OK;
 }
@@ -695,7 +704,8 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    free_tape(c);
+    c->tape_len = 0;
+    c->taping = false;
     return LBM_OK;
 }
 

@@ -176,7 +176,8 @@ struct lbm_ctx {
     // differentiation form
     lbm_sizes sizes{};
     std::vector<mdlbm::TapeStep> tape;
-    int tape_len = 0;
+    int tape_len = 0;    // steps recorded since lbm_tape_begin
+    int tape_steps = 0;  // steps to record (tape.size() may be larger)
     bool taping = false;
     void* adj_scratch[2] = {nullptr, nullptr};
     double* adj_wts = nullptr;
