@@ -141,7 +141,11 @@ class Oracle:
     """FP64 lattice + particles.  `f` is Q x N post-collision populations
     (x fastest), `owner` is 0 for fluid and p+1 for a node of particle p."""
 
-    def __init__(self, lat, Q: int = 19, treat: int = TREAT_VIBB | TREAT_MISSING):
+    def __init__(self, lat, Q: int = 19, treat: int = TREAT_VIBB | TREAT_MISSING,
+                 fields: bool = True):
+        """fields=False keeps the geometry only (owners, links, and the refill
+        set by its definition: solid before, fluid now), without population
+        arrays, for lattices whose FP64 populations would not fit in memory."""
         self.dims = np.array([lat.nx, lat.ny, lat.nz], np.int32)
         self.per = np.array([int(bool(v)) for v in lat.periodic], np.int32)
         self.N = int(lat.nx) * int(lat.ny) * int(lat.nz)
@@ -150,10 +154,12 @@ class Oracle:
         self.tau = float(lat.tau)
         self.rho0 = float(lat.rho0)
         self.Fb = _c(lat.body_force, np.float64)
-        self.f = np.zeros((Q, self.N), np.float64)
-        lib().ora_init_equilibrium(_p(self.dims), Q, self.rho0, _p(_c(lat.u0, np.float64)),
-                                   _p(self.f))
-        self.fprev = self.f.copy()
+        self.f = self.fprev = None
+        if fields:
+            self.f = np.zeros((Q, self.N), np.float64)
+            lib().ora_init_equilibrium(_p(self.dims), Q, self.rho0, _p(_c(lat.u0, np.float64)),
+                                       _p(self.f))
+            self.fprev = self.f.copy()
         self.owner = np.zeros(self.N, np.int32)
         self.owner_prev = None
         self.links = Links(*(np.zeros(0, t) for t in (np.int32, np.int8, np.int8, np.int32,
@@ -192,7 +198,9 @@ class Oracle:
         the previous classification (not on the first call)."""
         own = self.owners(ps)
         first = self.owner_prev is None and not getattr(self, "_classified", False)
-        if refill and not first:
+        if refill and not first and self.f is None:
+            self.refill_nodes = np.flatnonzero((self.owner > 0) & (own == 0)).astype(np.int32)
+        elif refill and not first:
             cap = max(1, self.N)
             nodes = np.zeros(cap, np.int32)
             n = lib().ora_refill(_p(self.dims), _p(self.per), self.Q, self.tau, _p(self.Fb),

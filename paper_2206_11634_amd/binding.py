@@ -311,9 +311,14 @@ class Lattice:
         _check(load().lbm_get_owner(self.ctx, _ptr(out)), self.ctx)
         return out.cpu().numpy()
 
-    def populations(self) -> np.ndarray:
+    def populations(self, nodes=None) -> np.ndarray:
+        """FP64 populations [19][ncell]; with nodes (indices), only those
+        columns are copied to the host."""
         out = self.torch.empty((Q, self.ncell), dtype=self.torch.float64, device=self.device)
         _check(load().lbm_get_populations(self.ctx, _ptr(out)), self.ctx)
+        if nodes is not None:
+            idx = self.torch.as_tensor(np.asarray(nodes, np.int64), device=self.device)
+            out = out[:, idx]
         return out.cpu().numpy()
 
     def set_populations(self, f: np.ndarray):

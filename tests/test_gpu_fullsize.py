@@ -1,0 +1,128 @@
+"""Parity at the full sizes of the five workloads, in the launch
+configuration the benchmark times.
+
+c1 (40x40x80, FP64), c2 (128x128x256, FP32) and c3 (256^3, 200 bodies, FP32
+and FP16) are compared with the full FP64 oracle over a few steps of a
+prescribed rigid trajectory: geometry bit-exact every step, forces, torques and
+populations within the storage's tolerance.  c4 (512^3, 1000 bodies, FP32) is
+too large for the oracle's FP64 populations, so its geometry (owner plane,
+every link record, the refill set) is compared bit-exactly on the whole
+lattice, and forces and populations are compared for sampled bodies: the
+oracle runs a sub-box around each sampled body holding every body that reaches
+into it, with margins wider than the distance information travels in the
+steps compared (two nodes per step: one by streaming, one through x_ff).
+DEM is compared on all c4 bodies."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2206_11634_amd import binding as B
+from paper_2206_11634_amd import workloads as W
+import oracle_windows as OW
+from test_gpu_parity import FORCE_TOL, POP_TOL, _compare_geometry, _run
+
+pytestmark = pytest.mark.gpu
+
+
+def _moving(ps, seed, speed, spin):
+    rng = np.random.default_rng(seed)
+    ps = ps.copy()
+    ps.vel = rng.normal(size=(ps.n, 3)) * speed
+    ps.omega = rng.normal(size=(ps.n, 3)) * spin
+    return ps
+
+
+def test_c1_full_size_fp64():
+    lat, ps, meta = W.config_c1()
+    ps = _moving(ps, 11, 0.02, 0.003)
+    r = _run(lat, ps, "f64", 30, tag="c1")
+    assert r["pop_err"] <= POP_TOL["f64"] and r["F"] <= FORCE_TOL["f64"] and r["T"] <= FORCE_TOL["f64"], r
+
+
+def test_c2_full_size_fp32():
+    lat, ps, meta = W.config_c2()
+    ps = _moving(ps, 12, 0.03, 0.002)
+    r = _run(lat, ps, "f32", 8, tag="c2")
+    assert r["pop_err"] <= POP_TOL["f32"] and r["F"] <= FORCE_TOL["f32"] and r["T"] <= FORCE_TOL["f32"], r
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_c3_full_size(storage):
+    lat, ps, meta = W.config_c3()
+    ps = _moving(ps, 13, 0.02, 0.002)
+    r = _run(lat, ps, storage, 3, tag=f"c3 {storage}")
+    assert r["refilled"] > 0
+    assert r["pop_err"] <= POP_TOL[storage], r
+    assert r["F"] <= FORCE_TOL[storage] and r["T"] <= FORCE_TOL[storage], r
+
+
+# ---------------------------------------------------------------------------
+# c4: whole-lattice geometry, sampled bodies for forces and populations
+# ---------------------------------------------------------------------------
+K_STEPS = 3
+
+
+def test_c4_full_size_geometry_and_sampled_bodies():
+    lat, ps, meta = W.config_c4()
+    ps = _moving(ps, 14, 0.02, 0.001)
+    margin = 2 * K_STEPS + 4
+    half_extra = 2 + margin
+    sample = OW.sample_bodies(lat, ps, half_extra)
+    traj = [W.prescribed_state(ps, lat, float(t)) for t in range(K_STEPS + 1)]
+
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    geo = O.Oracle(lat, fields=False)
+    Fg, Tg = [], []
+    for t in range(K_STEPS):
+        parts.set_state(traj[t])
+        counts = gpu.classify(parts)
+        if t < 2:
+            geo.classify(traj[t])
+            _compare_geometry(gpu, geo, f"c4 step {t}")
+            if t == 1:
+                assert len(geo.refill_nodes) > 0
+        gpu.step(parts)
+        F, T = gpu.forces()
+        Fg.append(F.cpu().numpy()[sample].copy())
+        Tg.append(T.cpu().numpy()[sample].copy())
+    assert counts.n_links > 2e7
+    del geo
+    Fg, Tg = np.array(Fg), np.array(Tg)
+
+    for si, p in enumerate(sample):
+        Fo, To, ora, lo, wdims, real = OW.run_window(lat, ps, traj, p, K_STEPS, half_extra)
+        eF = np.abs(Fg[:, si] - Fo).max() / np.abs(Fo).max()
+        eT = np.abs(Tg[:, si] - To).max() / np.abs(To).max()
+        assert eF <= FORCE_TOL["f32"] and eT <= FORCE_TOL["f32"], (p, eF, eT)
+        # populations in the core of the sub-box, away from its artificial faces
+        lnode, gnode = OW.core_fluid_nodes(lat, ora, lo, wdims, real, 2 * K_STEPS + 2)
+        pick = np.random.default_rng(p).choice(len(gnode), size=min(20000, len(gnode)),
+                                               replace=False)
+        fg = gpu.populations(gnode[pick])
+        err = np.abs(fg - ora.f[:, lnode[pick]]).max()
+        assert err <= POP_TOL["f32"], (p, err)
+    gpu.close()
+
+
+def test_c4_dem_full_size():
+    """All 1000 bodies: gravity, seeded velocities, contacts wherever the
+    seeded layout brings bodies together; no fluid loads (no lattice step has
+    run, so F^h = T^h = 0 on both sides)."""
+    lat, ps, meta = W.config_c4()
+    ps = _moving(ps, 15, 0.02, 0.002)
+    kw = W.dem_defaults(ps, gravity=meta["gravity"])
+    n_sub, dt = meta["n_sub"], 1.0 / meta["n_sub"]
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    dem = O.OracleDEM(ps, lat)
+    P = ps.copy()
+    zero = np.zeros((ps.n, 3))
+    for _ in range(20):
+        gpu.dem(parts, n_sub, dt, B.DemParams.make(**kw))
+        dem.step(P, zero, zero, O.DemParams(**kw), n_sub, dt)
+    G = parts.to_host(ps)
+    gpu.close()
+    for k in ("pos", "vel", "omega", "quat", "world_pts"):
+        a, b = getattr(G, k), getattr(P, k)
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
