@@ -154,7 +154,7 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out);
  * populations of bufs->f_dev[0] to the equilibrium f_eq(rho0, u0) (Sec. 2.2),
  * the owner planes to "fluid" and the flags to fluid.  Allocates the library's
  * scratch (ENOMEM on failure).  EINVAL on tau <= 1/2, a dimension < 1, a null
- * buffer, an unknown storage, box_half < 2, a periodic axis shorter than
+ * buffer, an unknown storage, box_half outside [2, 511], a periodic axis shorter than
  * 2*box_half + 5 nodes, or n_particles >= 65535.  Synchronises the stream. */
 int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out);
 

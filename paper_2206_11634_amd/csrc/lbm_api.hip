@@ -219,8 +219,8 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         return fail(nullptr, LBM_EINVAL, "null buffer");
     if (cfg->n_particles < 0 || cfg->n_particles >= 65535)
         return fail(nullptr, LBM_EINVAL, "n_particles must be in [0, 65535)");
-    if (cfg->n_particles > 0 && cfg->box_half < 2)
-        return fail(nullptr, LBM_EINVAL, "box_half must be >= 2");
+    if (cfg->n_particles > 0 && (cfg->box_half < 2 || cfg->box_half > kMaxBoxHalf))
+        return fail(nullptr, LBM_EINVAL, "box_half must lie in [2, 511]");
     const int dims[3] = {cfg->nx, cfg->ny, cfg->nz};
     for (int a = 0; a < 3; ++a)
         if (cfg->n_particles > 0 && cfg->periodic[a] && dims[a] < 2 * cfg->box_half + 5)

@@ -247,59 +247,179 @@ __global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball
     });
 }
 
-// Node owners: the lowest particle index with M_p >= c0_p.  The decision is
-// the FP64 sum's; an FP32 estimate settles every node whose M lies outside a
-// relative band of 1e-4 around c0 (its own error is below 1e-6) and the FP64
-// sum settles the rest.  Every solid node gets its flag, and the solid nodes
-// of p that may carry links of p go to p's candidate list: a node where the
-// lower bound sum_i K_i / (r_i + sqrt 2)^2 of M_p over all D3Q19 neighbours
-// (|e| <= sqrt 2) reaches c0 (with margin) has M_p >= c0 at every neighbour,
-// hence no link of any kind, and is left out.
+// Node owners: the lowest particle index with M_p >= c0_p.
+//
+// Which nodes are visited.  If every control point lies farther than
+// rho = sqrt(sum_i K_i / c0) from a node, M_p < c0 there, so p's body lies
+// in the union of the balls (x_i, rho); it also lies in the ball (x_p, R) of
+// k_boxes.  One workgroup takes one z plane of p's box: it tabulates, for
+// every row y of the plane, the x range of the union's hull on that row
+// intersected with the centre ball, prefix-sums the row lengths in LDS and
+// hands the flattened nodes to its lanes, so no lane idles at row ends.
+//
+// How a node is decided.  The FP64 sum alone decides, bit for bit; an FP32
+// estimate settles the nodes far from the decision.  The estimate works in
+// coordinates relative to o = floor(x_p) (node offsets are exact integers,
+// control points are rounded once, |x_i - o| <= R + 1 < h), so each
+// coordinate difference is off by at most delta = (2h + 4) 2^-24.  At a
+// distance r >= g = 0.0085 (2h + 4) from every control point the relative
+// error of r^2 is below 2.83 delta / r + 3 2^-24 <= 2e-5, of a term
+// K_i / r^2 (hardware reciprocal, 1 ulp) below 2.2e-5 and of the sum below
+// 2.6e-5 for up to 64 points.  So outside a relative band of 1e-4 around c0
+// the estimate decides what the FP64 sum decides; nodes in the band, or
+// within g of a control point, or of a box with h > 127, take the FP64 sum.
+//
+// Candidates for links.  M_p at any D3Q19 neighbour (|e| <= sqrt 2) is at
+// least sum_i K_i / (r_i + sqrt 2)^2.  A solid node where the FP32 value of
+// this bound clears c0 by the same margin (its relative error stays below
+// 3.5e-5 for h <= 127: the r_i + 1.4143 terms are never small) has M_p >= c0
+// at every neighbour, hence no link of any kind, and is left off p's
+// candidate list.  Every other solid node of p goes on the list.
+constexpr int kRows = 2 * kMaxBoxHalf + 1;
+
 __global__ __launch_bounds__(256) void k_mark(uint32_t* own, const double* ball, int h, PartDev P,
-                                              Geom g, uint8_t* flag, uint32_t* cand, int64_t cap,
-                                              uint32_t* cursors)
+                                              Geom g, uint8_t* flag, int store_flag, uint32_t* cand,
+                                              int64_t cap, uint32_t* cursors)
 {
     __shared__ double sp[4 * kMaxCtrl];
+    __shared__ float4 sf[kMaxCtrl];
+    __shared__ int rlo[kRows];
+    __shared__ int rstart[kRows + 1];
+    __shared__ int wsum[4];
     const int p = blockIdx.y;
     const int n = stage_ctrl(P, p, sp);
     const double c0 = P.c0[p];
+    const double bx = ball[4 * p + 0], by = ball[4 * p + 1], bz = ball[4 * p + 2];
+    const double R = ball[4 * p + 3];
+    const int ox = (int)floor(bx), oy = (int)floor(by), oz = (int)floor(bz);
+    const int zi = oz - h + (int)blockIdx.x;
+    const int S = 2 * h + 1;
+    double ksum = 0.0;
+    for (int i = 0; i < n; ++i) ksum += sp[4 * i + 3];
+    const double rho2 = ksum / c0 * (1.0 + 1e-6);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double dz = (double)zi - sp[4 * i + 2];
+        sf[i] = make_float4((float)(sp[4 * i + 0] - (double)ox), (float)(sp[4 * i + 1] - (double)oy),
+                            (float)(dz * dz), (float)sp[4 * i + 3]);
+    }
+    // row table: thread t takes rows 4t .. 4t + 3
+    const double dzc = (double)zi - bz;
+    const double r2z = R * R - dzc * dzc;
+    int len[4];
+    int tsum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = 4 * (int)threadIdx.x + k;
+        len[k] = 0;
+        if (r < S && r2z >= 0.0) {
+            const int yi = oy - h + r;
+            const double dyc = (double)yi - by;
+            const double r2x = r2z - dyc * dyc;
+            if (r2x >= 0.0) {
+                const double rx = sqrt(r2x);
+                double lo = 1e300, hi = -1e300;
+                for (int i = 0; i < n; ++i) {
+                    const double dy = (double)yi - sp[4 * i + 1];
+                    const double dz = (double)zi - sp[4 * i + 2];
+                    const double rem = rho2 - (dy * dy + dz * dz);
+                    if (rem >= 0.0) {
+                        const double w = sqrt(rem) + 1e-6;
+                        lo = fmin(lo, sp[4 * i + 0] - w);
+                        hi = fmax(hi, sp[4 * i + 0] + w);
+                    }
+                }
+                if (hi >= lo) {  // some control-point ball meets the row
+                    const int xlo = max((int)ceil(bx - rx), (int)ceil(lo));
+                    const int xhi = min((int)floor(bx + rx), (int)floor(hi));
+                    if (xhi >= xlo) {
+                        rlo[r] = xlo;
+                        len[k] = xhi - xlo + 1;
+                    }
+                }
+            }
+        }
+        tsum += len[k];
+    }
+    // block-wide exclusive scan of the per-thread sums
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = tsum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int off = incl - tsum;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = 4 * (int)threadIdx.x + k;
+        if (r < S) rstart[r] = off;
+        off += len[k];
+    }
+    if (threadIdx.x == 0) rstart[S] = total;
+    __syncthreads();
+    if (total == 0) return;  // uniform over the block
+
     uint32_t* list = cand + (int64_t)p * cap;
     uint32_t* cursor = cursors + (int64_t)p * kCursorPad;
     const float c0f = (float)c0;
-    walk_ball_plane(ball + 4 * p, h, [&](const int* ii, bool act) {
-        int c[3];
+    const float c0hi = c0f * 1.0001f, c0lo = c0f * 0.9999f;
+    const float gr = fmaxf(0.5f, 0.0085f * (float)(2 * h + 4));
+    const float guard2 = h <= 127 ? gr * gr : 3.0e38f;
+    int top = 1;
+    while (top <= S) top <<= 1;
+    for (int j0 = 0; j0 < total; j0 += 256) {
+        const int j = j0 + (int)threadIdx.x;
         bool keep = false;
         uint32_t node = 0;
-        if (act && wrap_cell(ii, g, c)) {
-            node = node_idx(c, g);
-            const double X = (double)ii[0], Y = (double)ii[1], Z = (double)ii[2];
-            // FP32 estimate of M and of its lower bound over the neighbours;
-            // their relative error is below 1e-6, so outside a 1e-4 band
-            // around c0 they decide exactly what the FP64 sum decides.
-            float Mf = 0.0f, lbf = 0.0f;
-            for (int i = 0; i < n; ++i) {
-                const float dx = (float)(X - sp[4 * i + 0]);
-                const float dy = (float)(Y - sp[4 * i + 1]);
-                const float dz = (float)(Z - sp[4 * i + 2]);
-                const float r2 = (dx * dx + dy * dy) + dz * dz;
-                const float k = (float)sp[4 * i + 3];
-                Mf += k / r2;
-                const float t = sqrtf(r2) + 1.4143f;
-                lbf += k / (t * t);
-            }
-            bool solid;
-            if (Mf >= c0f * 1.0001f) solid = true;
-            else if (Mf <= c0f * 0.9999f) solid = false;
-            else solid = metaball(sp, n, X, Y, Z) >= c0;
-            if (solid) {
-                atomicMin(own + node, (uint32_t)p);
-                flag[node] = 1;
-                keep = !(lbf >= c0f * 1.0001f);
+        if (j < total) {
+            // row of flattened node j: the last r with rstart[r] <= j
+            int r = 0;
+            for (int step = top >> 1; step > 0; step >>= 1)
+                if (r + step <= S && rstart[r + step] <= j) r += step;
+            const int ii[3] = {rlo[r] + (j - rstart[r]), oy - h + r, zi};
+            int c[3];
+            if (wrap_cell(ii, g, c)) {
+                node = node_idx(c, g);
+                const float X = (float)(ii[0] - ox), Y = (float)(ii[1] - oy);
+                float Mf = 0.0f, m2 = 3.0e38f;
+                for (int i = 0; i < n; ++i) {
+                    const float4 q = sf[i];
+                    const float dx = X - q.x, dy = Y - q.y;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, q.z));
+                    Mf = fmaf(q.w, __builtin_amdgcn_rcpf(r2), Mf);
+                    m2 = fminf(m2, r2);
+                }
+                const bool settled = Mf >= c0hi || Mf <= c0lo;  // false for NaN
+                const bool solid =
+                    (m2 < guard2 || !settled)
+                        ? metaball(sp, n, (double)ii[0], (double)ii[1], (double)ii[2]) >= c0
+                        : Mf >= c0hi;
+                if (solid) {
+                    atomicMin(own + node, (uint32_t)p);
+                    if (store_flag) flag[node] = 1;
+                    bool interior = false;
+                    if (h <= 127) {
+                        float lb = 0.0f;
+                        for (int i = 0; i < n; ++i) {
+                            const float4 q = sf[i];
+                            const float dx = X - q.x, dy = Y - q.y;
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, q.z));
+                            const float t = __builtin_amdgcn_sqrtf(r2) + 1.4143f;
+                            lb = fmaf(q.w, __builtin_amdgcn_rcpf(t * t), lb);
+                        }
+                        interior = lb >= c0hi;
+                    }
+                    keep = !interior;
+                }
             }
         }
         const uint32_t slot = wave_reserve(keep ? 1u : 0u, cursor);
         if (keep && slot < cap) list[slot] = node;
-    });
+    }
 }
 
 // Over the previous balls: flags of the new classification and the nodes that
@@ -327,10 +447,30 @@ __global__ __launch_bounds__(256) void k_finish(const uint32_t* own_prev, const 
     });
 }
 
+// Position of the k-th (from 0) set bit of m; m has more than k set bits.
+__device__ __forceinline__ int select_bit(uint64_t m, uint32_t k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = m & ((1ull << w) - 1ull);
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (k >= c) {
+            k -= c;
+            m >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
 // Link records of the candidate nodes of p (those p owns), written
 // direction-major within each wave: the links of one direction over a run of
 // neighbouring candidates are contiguous, so the link kernel's gathers
-// coalesce.  A grid of a few workgroups per particle strides over the list.
+// coalesce.  Each lane first finds the link directions of its candidate; the
+// wave then enumerates its links in that order and gives one link to each
+// lane (candidate data by lane shuffles), so the FP64 work of q runs on full
+// waves.  A grid of a few workgroups per particle strides over the list.
 __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double* ball, PartDev P,
                                                Geom g, const uint32_t* cand, int64_t cand_cap,
                                                const uint32_t* cand_cursors, LinkRec* links,
@@ -346,7 +486,6 @@ __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double
     LinkRec* out = links + (int64_t)p * cap;
     uint32_t* cursor = cursors + (int64_t)p * kCursorPad;
     const int lane = threadIdx.x & 63;
-    const uint64_t below = (1ull << lane) - 1ull;
     for (uint32_t base0 = blockIdx.x * 256u; base0 < count; base0 += gridDim.x * 256u) {
         const uint32_t k = base0 + threadIdx.x;
         uint32_t node = 0, mask = 0;
@@ -371,18 +510,13 @@ __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double
             }
             X = Xc[0], Y = Xc[1], Z = Xc[2];
             if (own[node] == (uint32_t)p) {
-                uint32_t on[kQ];
-                bool ok[kQ];
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
                     int cn[3];
-                    ok[d] = neighbour(c, ex_d(d), ey_d(d), ez_d(d), g, cn);
-                    on[d] = ok[d] ? own[node_idx(cn, g)] : kFluid;
-                }
-#pragma unroll
-                for (int d = 1; d < kQ; ++d) {
-                    if (ok[d] && on[d] == (uint32_t)p) continue;
-                    if (ok[d] && on[d] == kFluid) {
+                    const bool ok = neighbour(c, ex_d(d), ey_d(d), ez_d(d), g, cn);
+                    const uint32_t on = ok ? own[node_idx(cn, g)] : kFluid;
+                    if (ok && on == (uint32_t)p) continue;
+                    if (ok && on == kFluid) {
                         mask |= 1u << d;
                     } else if (treat & LBM_TREAT_MISSING) {
                         const double Mn = metaball(sp, n, X - ex_d(d), Y - ey_d(d), Z - ez_d(d));
@@ -391,21 +525,43 @@ __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double
                 }
             }
         }
-        // one reservation per wave, then direction-major positions
-        const uint32_t wbase = wave_base(__popc(mask), cursor);
         double Ms = 0.0;
         if (mask) Ms = metaball(sp, n, X, Y, Z);
-        uint32_t cum = 0;
+        // direction-major enumeration of the wave's links
+        uint64_t bal[kQ];
+        uint32_t cum[kQ + 1];
+        cum[0] = cum[1] = 0;
+        bal[0] = 0;
+#pragma unroll
         for (int d = 1; d < kQ; ++d) {
-            const bool has = (mask >> d) & 1u;
-            const uint64_t bal = __ballot(has);
-            if (bal == 0) continue;
-            if (has) {
+            bal[d] = __ballot((mask >> d) & 1u);
+            cum[d + 1] = cum[d] + (uint32_t)__popcll(bal[d]);
+        }
+        const uint32_t total = cum[kQ];
+        if (total == 0) continue;  // uniform over the wave
+        uint32_t wbase = 0;
+        if (lane == 0) wbase = atomicAdd(cursor, total);
+        wbase = __shfl(wbase, 0, 64);
+        for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            int d = 1;
+            uint64_t m = bal[1];
+#pragma unroll
+            for (int dd = 2; dd < kQ; ++dd)
+                if (cum[dd] <= j) {
+                    d = dd;
+                    m = bal[dd];
+                }
+            const int src = j < total ? select_bit(m, j - cum[d]) : lane;
+            const uint32_t snode = __shfl(node, src, 64);
+            const int sc[3] = {__shfl(c[0], src, 64), __shfl(c[1], src, 64), __shfl(c[2], src, 64)};
+            const double sX = __shfl(X, src, 64), sY = __shfl(Y, src, 64), sZ = __shfl(Z, src, 64);
+            const double sMs = __shfl(Ms, src, 64);
+            if (j < total) {
                 const int ex = ex_d(d), ey = ey_d(d), ez = ez_d(d);
-                const uint32_t slot = wbase + cum + (uint32_t)__popcll(bal & below);
-                const double Mn = metaball(sp, n, X - ex, Y - ey, Z - ez);
+                const double Mn = metaball(sp, n, sX - ex, sY - ey, sZ - ez);
                 int cn[3];
-                const bool ok = neighbour(c, ex, ey, ez, g, cn);
+                const bool ok = neighbour(sc, ex, ey, ez, g, cn);
                 int kind = LBM_LINK_MISSING;
                 if (ok && own[node_idx(cn, g)] == kFluid) {
                     int cff[3];
@@ -413,17 +569,17 @@ __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double
                     const bool ff = okf && own[node_idx(cff, g)] == kFluid;
                     kind = ((treat & LBM_TREAT_VIBB) && ff) ? LBM_LINK_VIBB : LBM_LINK_HALFWAY;
                 }
+                const uint32_t slot = wbase + j;
                 if (slot < cap) {
                     LinkRec r;
-                    r.node = node;
+                    r.node = snode;
                     r.part = (uint16_t)p;
                     r.d = (uint8_t)d;
                     r.kind = (uint8_t)kind;
-                    r.q = (c0 - Mn) / (Ms - Mn);
+                    r.q = (c0 - Mn) / (sMs - Mn);
                     out[slot] = r;
                 }
             }
-            cum += (uint32_t)__popcll(bal);
         }
     }
 }
@@ -502,9 +658,10 @@ hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot)
 {
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
+    // in dense mode the lattice sweep of k_finish_all writes every flag
     hipLaunchKernelGGL(k_mark, dim3(c->box.S, np), dim3(256), 0, c->stream, own,
                        c->ball_hist + (int64_t)slot * 4 * np, c->box.h, P, c->geom, c->flag,
-                       c->cand, c->cand_cap, c->cand_cursor);
+                       c->dense ? 0 : 1, c->cand, c->cand_cap, c->cand_cursor);
     return hipGetLastError();
 }
 

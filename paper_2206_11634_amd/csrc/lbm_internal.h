@@ -44,6 +44,9 @@ __host__ __device__ constexpr float wgtf(int i)
 }
 
 // Owner plane value of a fluid node (a solid node holds its particle index).
+// Largest per-particle box half-width h (the classification kernels keep a
+// table of the 2h + 1 rows of one box plane in LDS).
+constexpr int kMaxBoxHalf = 511;
 constexpr uint32_t kFluid = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
