@@ -83,7 +83,17 @@ typedef struct {
                               centre; bounds the per-particle node box */
     double h16_scale;      /* scale of FP16 deviations (0: default 1024) */
     void* stream;          /* hipStream_t, NULL for the null stream */
+    int32_t classify_mode; /* lbm_classify_mode; the same owners, links and refill
+                              sets either way, only the work differs */
 } lbm_config;
+
+typedef enum {
+    LBM_CLASSIFY_AUTO = 0,  /* lattice sweep when the particles' bounding balls
+                               cover more than half of the lattice */
+    LBM_CLASSIFY_SWEEP = 1, /* owners cleared, flags and refill set found by one
+                               sweep over every node */
+    LBM_CLASSIFY_BALLS = 2  /* all work inside each particle's bounding ball */
+} lbm_classify_mode;
 
 typedef struct {
     int64_t ncell;             /* nx*ny*nz */
@@ -154,7 +164,7 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out);
  * populations of bufs->f_dev[0] to the equilibrium f_eq(rho0, u0) (Sec. 2.2),
  * the owner planes to "fluid" and the flags to fluid.  Allocates the library's
  * scratch (ENOMEM on failure).  EINVAL on tau <= 1/2, a dimension < 1, a null
- * buffer, an unknown storage, box_half outside [2, 511], a periodic axis shorter than
+ * buffer, an unknown storage or classify_mode, box_half outside [2, 511], a periodic axis shorter than
  * 2*box_half + 5 nodes, or n_particles >= 65535.  Synchronises the stream. */
 int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out);
 

@@ -34,7 +34,7 @@ class LbmConfig(ctypes.Structure):
                 ("body_force", ctypes.c_double * 3), ("storage", ctypes.c_int32),
                 ("treatments", ctypes.c_int32), ("n_particles", ctypes.c_int32),
                 ("n_ctrl", ctypes.c_int32), ("box_half", ctypes.c_int32),
-                ("h16_scale", ctypes.c_double), ("stream", _P)]
+                ("h16_scale", ctypes.c_double), ("stream", _P), ("classify_mode", ctypes.c_int32)]
 
 
 class LbmSizes(ctypes.Structure):
@@ -76,6 +76,8 @@ class LbmProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
 
+CLASSIFY = {"auto": 0, "sweep": 1, "balls": 2}
+
 PHASES = ("bulk", "boundary", "classify", "refill", "dem", "adjoint")
 
 EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_classify_nodes",
@@ -96,6 +98,8 @@ def load(path: Path | None = None):
     if not p.exists():
         raise RuntimeError(f"{p} is not built; run `python -m paper_2206_11634_amd.build` "
                            "(the lattice update has no CPU fallback)")
+    # torch first: its HIP runtime must be the one the library binds to
+    import torch  # noqa: F401
     L = ctypes.CDLL(str(p))
     sig = {
         "lbm_query_sizes": [ctypes.POINTER(LbmConfig), ctypes.POINTER(LbmSizes)],
@@ -234,7 +238,8 @@ class Lattice:
     """A lattice, its caller-owned device buffers and a library context."""
 
     def __init__(self, lat, n_particles=0, n_ctrl=0, box_half=2, storage="f32",
-                 treatments=TREAT_VIBB | TREAT_MISSING, h16_scale=0.0, device="cuda"):
+                 treatments=TREAT_VIBB | TREAT_MISSING, h16_scale=0.0, device="cuda",
+                 classify="auto"):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -252,6 +257,7 @@ class Lattice:
         cfg.n_ctrl = int(n_ctrl)
         cfg.box_half = int(box_half)
         cfg.h16_scale = float(h16_scale)
+        cfg.classify_mode = CLASSIFY[classify]
         with torch.cuda.device(self.device):
             cfg.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         self.cfg = cfg

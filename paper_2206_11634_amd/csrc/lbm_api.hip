@@ -208,6 +208,8 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
 int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
 {
     if (!cfg || !bufs || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    if (cfg->classify_mode < LBM_CLASSIFY_AUTO || cfg->classify_mode > LBM_CLASSIFY_BALLS)
+        return fail(nullptr, LBM_EINVAL, "unknown classify_mode");
     *out = nullptr;
     lbm_sizes sz;
     int rc = lbm_query_sizes(cfg, &sz);
@@ -267,13 +269,15 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
 
     const int np = cfg->n_particles;
     const int64_t S2 = (int64_t)c->box.S * c->box.S;
-    // Clearing and refill detection walk each particle's ball unless the balls
-    // (radius below box_half) could cover most of the lattice, where one
-    // coalesced sweep of the whole lattice is cheaper.
-    {
+    // Clearing, flags and refill detection walk each particle's ball unless
+    // the balls (radius below box_half) could cover most of the lattice,
+    // where one coalesced sweep of the whole lattice is cheaper.
+    if (cfg->classify_mode == LBM_CLASSIFY_AUTO) {
         const double r = (double)c->box.h - 1.0;
         const double balls = (double)np * 4.18879 * r * r * r;
         c->dense = balls > 0.5 * (double)sz.ncell;
+    } else {
+        c->dense = cfg->classify_mode == LBM_CLASSIFY_SWEEP;
     }
     c->link_cap = std::max<int64_t>(256, (32 * S2 + 255) / 256 * 256);
     c->cand_cap = std::max<int64_t>(256, (8 * S2 + 255) / 256 * 256);

@@ -63,6 +63,15 @@ def test_query_sizes(lib, storage, es):
     assert s.moment_bytes == 4 * es * s.ncell
 
 
+def test_init_rejects_unknown_classify_mode(lib):
+    bufs = B.LbmBuffers()
+    ctx = ctypes.c_void_p()
+    cfg = _cfg()
+    cfg.classify_mode = 3
+    assert lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)) == B.LBM_EINVAL
+    assert b"classify_mode" in lib.lbm_last_error(None)
+
+
 def test_query_sizes_rejects_bad_input(lib):
     with pytest.raises(B.LbmError) as e:
         B.lbm_query_sizes(_cfg(dims=(0, 4, 4)))

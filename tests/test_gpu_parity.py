@@ -38,8 +38,8 @@ def _compare_geometry(gpu, ora, tag):
         assert np.array_equal(parts, ora.owner_prev[nodes] - 1)
 
 
-def _run(lat, ps, storage, steps, treat=3, check_geometry=True, tag=""):
-    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat)
+def _run(lat, ps, storage, steps, treat=3, check_geometry=True, tag="", classify="auto"):
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat, classify=classify)
     parts = B.DeviceParticles(ps)
     ora = O.Oracle(lat, treat=treat)
     Fo_all, Fg_all, To_all, Tg_all = [], [], [], []
@@ -77,12 +77,16 @@ GEOM_CASES = [
 ]
 
 
+@pytest.mark.parametrize("classify", ["balls", "sweep"])
 @pytest.mark.parametrize("case", GEOM_CASES, ids=lambda c: f"seed{c['seed']}")
-def test_geometry_and_plain_fp64_step_parity(case):
+def test_geometry_and_plain_fp64_step_parity(case, classify):
+    """Both classification schemes (owner clearing, flags and refill detection
+    by per-particle ball walks, or by one lattice sweep) must give the
+    oracle's geometry bit for bit."""
     lat, ps = W.tiny_case(case["seed"], dims=case["dims"], periodic=case["periodic"],
                           n_particles=case["n_particles"], diameter_range=(4.0, 7.0),
                           speed=0.06, spin=0.006, u0=(0.02, -0.01, 0.005))
-    r = _run(lat, ps, "f64", 8, tag=f"seed{case['seed']}")
+    r = _run(lat, ps, "f64", 8, tag=f"seed{case['seed']} {classify}", classify=classify)
     assert r["refilled"] > 0
     assert r["pop_err"] < POP_TOL["f64"], r
     assert r["F"] < FORCE_TOL["f64"] and r["T"] < FORCE_TOL["f64"], r
