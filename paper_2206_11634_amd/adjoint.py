@@ -39,6 +39,14 @@ class Problem:
             w[0, 0] = 1.0 / self.steps    # mean x-force on particle 0
             self.weights = w
 
+    def states(self):
+        """Nominal particle states at steps 0..T (poses of the prescribed
+        trajectory; the geometry schedule)."""
+        if getattr(self, "_states", None) is None:
+            self._states = [W.prescribed_state(self.ps, self.lat, float(n))
+                            for n in range(self.steps + 1)]
+        return self._states
+
     def initial(self) -> np.ndarray:
         if self.f0 is None:
             g = B.Lattice.for_particles(self.lat, self.ps, storage="f64")
@@ -54,16 +62,11 @@ class _Run:
         lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
                                   tau=float(tau))
         self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage)
-        self.parts = B.DeviceParticles(prob.ps)
+        # every state on the device: poses of the nominal trajectory, velocity v
+        self.traj = B.DeviceTrajectory(prob.states(), vel=self.vel)
 
-    def state(self, n):
-        P = W.prescribed_state(self.prob.ps, self.prob.lat, float(n))
-        P.vel = self.vel.copy()
-        return P
-
-    def set(self, n):
-        self.parts.set_state(self.state(n))
-
+    def parts(self, n):
+        return self.traj[n]
 
 
 def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
@@ -74,16 +77,13 @@ def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
     gpu.set_populations(prob.initial())
     run.ckpt = {}
     hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
-    run.set(0)
-    gpu.classify(run.parts)
+    gpu.classify(run.parts(0))
     for k in range(T):
         if keep and k % prob.window == 0:
             run.ckpt[k] = gpu.checkpoint()
-        run.set(k)
-        gpu.step(run.parts)
+        gpu.step(run.parts(k))
         gpu.forces(hist[k, 0], hist[k, 1])
-        run.set(k + 1)
-        gpu.classify(run.parts)
+        gpu.classify(run.parts(k + 1))
     w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
     J = float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
     if not keep:
@@ -105,15 +105,12 @@ def backward(run: _Run, stats: dict | None = None):
     for w0 in sorted(run.ckpt, reverse=True):
         w1 = min(w0 + prob.window, prob.steps)
         gpu.restore(run.ckpt[w0])
-        run.set(w0)
-        gpu.classify(run.parts)   # reproduces the geometry at w0, refills nothing
+        gpu.classify(run.parts(w0))   # reproduces the geometry at w0, refills nothing
         gpu.tape_begin(w1 - w0)
         for n in range(w0, w1):
-            run.set(n)
-            gpu.step(run.parts)
-            run.set(n + 1)
-            gpu.classify(run.parts)
-        gpu.adjoint(run.parts, prob.weights, lam, g)
+            gpu.step(run.parts(n))
+            gpu.classify(run.parts(n + 1))
+        gpu.adjoint(run.parts(w1), prob.weights, lam, g)
     out = g.cpu().numpy()
     if stats is not None:
         stats.update(gpu.profile_read())

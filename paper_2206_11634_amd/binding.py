@@ -234,6 +234,45 @@ class DeviceParticles:
         return out
 
 
+class DeviceTrajectory:
+    """A sequence of particle states of one particle set, resident on the
+    device: the shape data once, pose and world control points per state
+    ([T, ...] tensors), velocities either per state or one array for all.
+    Item t is an object with the lbm_particles `struct` of state t, usable
+    wherever a DeviceParticles is."""
+
+    class _State:
+        def __init__(self, struct, owner):
+            self.struct = struct
+            self._owner = owner   # keeps the tensors alive
+
+    def __init__(self, states, vel=None, omega=None, device="cuda"):
+        torch = _torch()
+        self.base = DeviceParticles(states[0], device=device)
+        self.n = states[0].n
+        stack = lambda k: torch.as_tensor(
+            np.ascontiguousarray(np.stack([getattr(s, k) for s in states]), np.float64),
+            device=device)
+        self.pos, self.quat, self.world = stack("pos"), stack("quat"), stack("world_pts")
+        one = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
+        self.vel = one(states[0].vel if vel is None else vel)
+        self.omega = one(states[0].omega if omega is None else omega)
+        b = self.base.t
+        self._items = []
+        for t in range(len(states)):
+            st = LbmParticles(self.n, _ptr(b["ctrl_off"]), _ptr(b["body_pts"]), _ptr(b["K"]),
+                              _ptr(b["c0"]), _ptr(b["rs"]), _ptr(b["mass"]), _ptr(b["volume"]),
+                              _ptr(b["inertia"]), _ptr(self.pos[t]), _ptr(self.quat[t]),
+                              _ptr(self.vel), _ptr(self.omega), _ptr(self.world[t]))
+            self._items.append(self._State(st, self))
+
+    def __len__(self):
+        return len(self._items)
+
+    def __getitem__(self, t):
+        return self._items[t]
+
+
 class Lattice:
     """A lattice, its caller-owned device buffers and a library context."""
 

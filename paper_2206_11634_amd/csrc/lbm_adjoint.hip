@@ -8,21 +8,22 @@
 // exchange force and torque of every particle weighted by (wF, wT).
 //
 // One adjoint step n <- n+1 runs three kernels:
-//  1. k_adj_pre    per node: recompute its pre-collision populations (pull, or
-//                  the refill rules), apply the transposed collision Jacobian
-//                  to lambda(n+1) -> Lambda (the adjoint of the pre-collision
-//                  populations), accumulate dJ/dtau, dJ/dF and, for refilled
-//                  nodes, dJ/dv;
-//  2. k_adj_gather per fluid node y of n: lambda(n)[j](y) collects Lambda of
-//                  the one node that read f_j(y): y + e_j (bulk pull, or
-//                  streaming and bounce-back refill of a node uncovered there),
-//                  or y itself through a wall;
-//  3. k_adj_links  per link: adjoint of its reconstructed population (Lambda
-//                  of the fluid node that pulled the ghost slot, plus the
-//                  objective), transposed through VIBB / halfway by forward-
-//                  mode dual numbers and added to lambda(n) at x_f and x_ff
-//                  with atomics; momentum-exchange and missing-point objective
-//                  terms; dJ/dv, dJ/dF.
+//  1. k_adj_node   per node x fluid at n: recompute its pulled pre-collision
+//                  populations, apply the transposed collision Jacobian to
+//                  lambda(n+1) -> Lambda (the adjoint of the pre-collision
+//                  populations), accumulate dJ/dtau, dJ/dF; then (every node)
+//                  push Lambda to the entries of lambda(n) that x read: entry
+//                  (j, x - e_j), of which x is the only writer (x itself for
+//                  entries read through a wall);
+//     k_adj_refill the same for the nodes refilled between n and n+1, whose
+//                  pre-collision populations come from the refill rules; also
+//                  dJ/dv of the wall velocity in those rules;
+//  2. k_adj_links  per link: adjoint of its reconstructed population (Lambda
+//                  of the fluid node that pulled the ghost slot, left in
+//                  lambda(n) at the solid node, plus the objective), transposed
+//                  through VIBB / halfway by forward-mode dual numbers and
+//                  added to lambda(n) at x_f and x_ff with atomics; momentum-
+//                  exchange and missing-point objective terms; dJ/dv, dJ/dF.
 // Arithmetic is that of the storage (double for FP64, float otherwise);
 // parameter gradients are summed in FP64.
 #include "lbm_internal.h"
@@ -160,213 +161,244 @@ __device__ __forceinline__ void block_add(double (&v)[NV], double* const* out)
 }
 
 // ---------------------------------------------------------------------------
-// 1. transposed collision (and refill) per node
+// 1. transposed collision per node, pushed to lambda(n)
 // ---------------------------------------------------------------------------
+
+// Lambda = (d post / d pre)^T lambda for BGK + Guo at the pre-collision state
+// pre, in closed form: Lambda_j = (1 - omega) lambda_j + omega a
+// + H . (e_j - u) / rho.  Returns the coefficients; adds dJ/dF (3) and dJ/dtau
+// to acc.
+template <class A>
+struct AdjCoef {
+    A om, a, H[3], u[3], ir;
+    __device__ __forceinline__ A operator()(int j, A lam_j) const
+    {
+        return (A(1) - om) * lam_j + om * a +
+               (H[0] * (A(cx(j)) - u[0]) + H[1] * (A(cy(j)) - u[1]) + H[2] * (A(cz(j)) - u[2])) * ir;
+    }
+};
+
+template <bool DEV, class A>
+__device__ __forceinline__ AdjCoef<A> adj_collide(const A lam[kQ], const A pre[kQ], const Phys& ph,
+                                                  double acc[4])
+{
+    A F[3];
+    A om;
+    if constexpr (DEV) {
+        F[0] = ph.Ff[0], F[1] = ph.Ff[1], F[2] = ph.Ff[2];
+        om = ph.omegaf;
+    } else {
+        F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
+        om = ph.omega;
+    }
+    A drho, rho, u[3];
+    moments<DEV, A>(pre, A(0.5), F, drho, rho, u[0], u[1], u[2]);
+    const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const A uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    A a = A(0), B[3] = {A(0), A(0), A(0)}, G[3] = {A(0), A(0), A(0)};
+    A Fd[3] = {A(0), A(0), A(0)}, dom = A(0);
+    const A gf = A(1) - A(0.5) * om;
+    // feq - pre - S/2 sums to zero over i, so its weight in dJ/domega may be
+    // centred on the mean of lambda, which keeps the sum free of the
+    // cancellation of a large common adjoint density
+    A lbar = A(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) lbar += lam[i];
+    lbar *= A(1.0 / kQ);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const A e3[3] = {A(cx(i)), A(cy(i)), A(cz(i))};
+        const A eu = e3[0] * u[0] + e3[1] * u[1] + e3[2] * u[2];
+        const A eF = e3[0] * F[0] + e3[1] * F[1] + e3[2] * F[2];
+        const A P = A(1) + A(3) * eu + A(4.5) * eu * eu - A(1.5) * uu;
+        const A wl = W<A>(i) * lam[i];
+        a += wl * P;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            B[k] += wl * rho * (A(3) * e3[k] + A(9) * eu * e3[k] - A(3) * u[k]);
+            G[k] += wl * (A(-3) * F[k] + A(9) * eF * e3[k]);
+            Fd[k] += wl * (A(3) * (e3[k] - u[k]) + A(9) * eu * e3[k]);
+        }
+        const A St_i = W<A>(i) * (A(3) * (eF - uF) + A(9) * eu * eF);
+        const A feq = eq_i<DEV, A>(i, drho, rho, u[0], u[1], u[2]);
+        dom += (lam[i] - lbar) * (feq - pre[i] - A(0.5) * St_i);
+    }
+    AdjCoef<A> co;
+    co.om = om;
+    co.a = a;
+    co.ir = A(1) / rho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        co.H[k] = om * B[k] + gf * G[k];
+        co.u[k] = u[k];
+        acc[k] += (double)(co.H[k] * A(0.5) * co.ir + gf * Fd[k]);
+    }
+    acc[3] += -(double)om * (double)om * (double)dom;  // dtau = -omega^2 domega
+    return co;
+}
+
+// Every node x.  A node fluid at n and n + 1 recomputes its pulled
+// pre-collision populations and takes the transposed collision; then x pushes
+// Lambda to the entries of lambda(n) it read.  Entry (j, y) is written by
+// exactly one node: x = y + e_j when that lies inside the lattice, else y
+// itself (read through a wall).  Its value is Lambda_j(x) for a node x fluid
+// at n (for a solid y that is the adjoint of the ghost slot, which the link
+// kernel takes and clears), and zero otherwise; k_adj_refill then rewrites the
+// entries its refilled nodes read.
 template <int S>
-__global__ __launch_bounds__(256) void k_adj_pre(const typename St<S>::T* __restrict__ f,
-                                                 const uint32_t* __restrict__ own0,
-                                                 const uint32_t* __restrict__ own1,
-                                                 const typename St<S>::A* __restrict__ lam1,
-                                                 typename St<S>::A* __restrict__ Lam,
-                                                 const double* pos1, const double* vel1,
-                                                 const double* om1, Geom g, Phys ph,
-                                                 double* grad)
+__global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __restrict__ f,
+                                                  const uint32_t* __restrict__ own0,
+                                                  const uint32_t* __restrict__ own1,
+                                                  const typename St<S>::A* __restrict__ lam1,
+                                                  typename St<S>::A* __restrict__ lam0, Geom g,
+                                                  Phys ph, double* grad)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dJ/dF (3), dJ/dtau
     if (cell < g.ncell) {
-        if (own1[cell] != kFluid) {
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) Lam[(int64_t)i * g.stride + cell] = A(0);
-        } else {
-            const uint32_t o0 = own0[cell];
-            const uint32_t nx = g.n[0], ny = g.n[1];
-            const uint32_t x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
-            A lam[kQ], pre[kQ];
-            A un[3] = {A(0), A(0), A(0)};
-            uint64_t rule = 0;  // per direction of a refilled node: 1 bounce-back, 2 equilibrium
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) lam[i] = lam1[(int64_t)i * g.stride + cell];
-            const bool refill = o0 != kFluid;
-            if (!refill) {
-                uint32_t ox[3], oy[3], oz[3];
-                bool vx[3], vy[3], vz[3];
-                axis3(x, nx, g.per[0], 1u, ox, vx);
-                axis3(y, ny, g.per[1], nx, oy, vy);
-                axis3(z, g.n[2], g.per[2], nx * ny, oz, vz);
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    const int sx = 1 - cx(i), sy = 1 - cy(i), sz = 1 - cz(i);
-                    const bool ok = vx[sx] && vy[sy] && vz[sz];
-                    const uint32_t s = ok ? ox[sx] + oy[sy] + oz[sz] : cell;
-                    const int64_t plane = ok ? i : opp(i);
-                    pre[i] = St<S>::ld(f + plane * g.stride + s, ph.inv_scale);
-                }
-            } else {
-                const int p = (int)o0;
-                const int c[3] = {(int)x, (int)y, (int)z};
-                double rr[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const double xp = pos1[3 * p + a];
-                    rr[a] = image_coord(c[a], g.n[a], g.per[a], xp) - xp;
-                }
-                const double* wp = om1 + 3 * p;
-                un[0] = A(vel1[3 * p] + (wp[1] * rr[2] - wp[2] * rr[1]));
-                un[1] = A(vel1[3 * p + 1] + (wp[2] * rr[0] - wp[0] * rr[2]));
-                un[2] = A(vel1[3 * p + 2] + (wp[0] * rr[1] - wp[1] * rr[0]));
-                const A r0 = A(ph.rho0), dr0 = A(ph.rho0 - 1.0);
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    int cuu[3] = {c[0] - cx(i), c[1] - cy(i), c[2] - cz(i)};
-                    int cdd[3] = {c[0] + cx(i), c[1] + cy(i), c[2] + cz(i)};
-                    const bool iu = i > 0 && wrap3(cuu, g);
-                    const bool id = i > 0 && wrap3(cdd, g);
-                    const uint32_t nu = iu ? node_of(cuu, g) : cell;
-                    const uint32_t nd = id ? node_of(cdd, g) : cell;
-                    const bool up = iu && own0[nu] == kFluid;
-                    const bool dn = id && own0[nd] == kFluid;
-                    const A eu = A(cx(i)) * un[0] + A(cy(i)) * un[1] + A(cz(i)) * un[2];
-                    if (up) {
-                        pre[i] = St<S>::ld(f + (int64_t)i * g.stride + nu, ph.inv_scale);
-                    } else if (dn) {
-                        pre[i] = St<S>::ld(f + (int64_t)opp(i) * g.stride + nd, ph.inv_scale) +
-                                 A(6) * W<A>(i) * r0 * eu;
-                        rule |= 1ull << (2 * i);
-                    } else {
-                        pre[i] = eq_i<DEV, A>(i, dr0, r0, un[0], un[1], un[2]);
-                        rule |= 2ull << (2 * i);
-                    }
-                }
-            }
-            // transposed BGK + Guo collision at the pre-collision state
-            A F[3];
-            A om;
-            if constexpr (DEV) {
-                F[0] = ph.Ff[0], F[1] = ph.Ff[1], F[2] = ph.Ff[2];
-                om = ph.omegaf;
-            } else {
-                F[0] = ph.F[0], F[1] = ph.F[1], F[2] = ph.F[2];
-                om = ph.omega;
-            }
-            A drho, rho, u[3];
-            moments<DEV, A>(pre, A(0.5), F, drho, rho, u[0], u[1], u[2]);
-            const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            const A uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-            A a = A(0), B[3] = {A(0), A(0), A(0)}, G[3] = {A(0), A(0), A(0)};
-            A Fd[3] = {A(0), A(0), A(0)}, dom = A(0);
-            const A gf = A(1) - A(0.5) * om;
-            // feq - pre - S/2 sums to zero over i, so its weight in dJ/domega
-            // may be centred on the mean of lambda, which keeps the sum free of
-            // the cancellation of a large common adjoint density
-            A lbar = A(0);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) lbar += lam[i];
-            lbar *= A(1.0 / kQ);
+        const uint32_t nx = g.n[0], ny = g.n[1];
+        const uint32_t x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
+        uint32_t ox[3], oy[3], oz[3];
+        bool vx[3], vy[3], vz[3];
+        axis3(x, nx, g.per[0], 1u, ox, vx);
+        axis3(y, ny, g.per[1], nx, oy, vy);
+        axis3(z, g.n[2], g.per[2], nx * ny, oz, vz);
+        const bool live = own0[cell] == kFluid && own1[cell] == kFluid;
+        A lam[kQ] = {};
+        AdjCoef<A> co{};
+        if (live) {
+            A pre[kQ];
 #pragma unroll
             for (int i = 0; i < kQ; ++i) {
-                const A e3[3] = {A(cx(i)), A(cy(i)), A(cz(i))};
-                const A eu = e3[0] * u[0] + e3[1] * u[1] + e3[2] * u[2];
-                const A eF = e3[0] * F[0] + e3[1] * F[1] + e3[2] * F[2];
-                const A P = A(1) + A(3) * eu + A(4.5) * eu * eu - A(1.5) * uu;
-                const A wl = W<A>(i) * lam[i];
-                a += wl * P;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    B[k] += wl * rho * (A(3) * e3[k] + A(9) * eu * e3[k] - A(3) * u[k]);
-                    G[k] += wl * (A(-3) * F[k] + A(9) * eF * e3[k]);
-                    Fd[k] += wl * (A(3) * (e3[k] - u[k]) + A(9) * eu * e3[k]);
-                }
-                const A St_i = W<A>(i) * (A(3) * (eF - uF) + A(9) * eu * eF);
-                const A feq = eq_i<DEV, A>(i, drho, rho, u[0], u[1], u[2]);
-                dom += (lam[i] - lbar) * (feq - pre[i] - A(0.5) * St_i);
+                lam[i] = lam1[(int64_t)i * g.stride + cell];
+                const int sx = 1 - cx(i), sy = 1 - cy(i), sz = 1 - cz(i);
+                const bool ok = vx[sx] && vy[sy] && vz[sz];
+                const uint32_t s = ok ? ox[sx] + oy[sy] + oz[sz] : cell;
+                const int64_t plane = ok ? i : opp(i);
+                pre[i] = St<S>::ld(f + plane * g.stride + s, ph.inv_scale);
             }
-            A H[3];
+            co = adj_collide<DEV, A>(lam, pre, ph, acc);
+        }
 #pragma unroll
-            for (int k = 0; k < 3; ++k) H[k] = om * B[k] + gf * G[k];
-            const A ir = A(1) / rho;
-            double dv[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int j = 0; j < kQ; ++j) {
-                const A ej[3] = {A(cx(j)), A(cy(j)), A(cz(j))};
-                const A lp = (A(1) - om) * lam[j] + om * a +
-                             (H[0] * (ej[0] - u[0]) + H[1] * (ej[1] - u[1]) + H[2] * (ej[2] - u[2])) * ir;
-                Lam[(int64_t)j * g.stride + cell] = lp;
-                // d pre_j / d u_new of a refilled node: 6 w rho0 e_j for the
-                // bounce-back rule, d feq_j(rho0, u_new)/du for the equilibrium
-                const uint32_t rj = (uint32_t)(rule >> (2 * j)) & 3u;
-                if (rj) {
-                    const A r0 = A(ph.rho0);
-                    const A eun = ej[0] * un[0] + ej[1] * un[1] + ej[2] * un[2];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const A cuk = (rj == 1u) ? A(6) * W<A>(j) * r0 * ej[k]
-                                                 : W<A>(j) * r0 * (A(3) * ej[k] + A(9) * eun * ej[k] - A(3) * un[k]);
-                        dv[k] += (double)(lp * cuk);
-                    }
-                }
-            }
-            if (refill) {
-                const int p = (int)o0;
-                for (int k = 0; k < 3; ++k)
-                    if (dv[k] != 0.0) atomicAdd(grad + 4 + 3 * p + k, dv[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) acc[k] = (double)(H[k] * A(0.5) * ir + gf * Fd[k]);
-            acc[3] = -(double)om * (double)om * (double)dom;  // dtau = -omega^2 domega
+        for (int j = 0; j < kQ; ++j) {
+            const A v = live ? co(j, lam[j]) : A(0);
+            const int sx = 1 - cx(j), sy = 1 - cy(j), sz = 1 - cz(j);  // x - e_j
+            if (vx[sx] && vy[sy] && vz[sz])
+                lam0[(int64_t)j * g.stride + ox[sx] + oy[sy] + oz[sz]] = v;
+            else  // x pulled f_j through a wall: its own f_opp(j)
+                lam0[(int64_t)opp(j) * g.stride + cell] = v;
         }
     }
     double* outs[4] = {grad + 0, grad + 1, grad + 2, grad + 3};
     block_add<4>(acc, outs);
 }
 
-// ---------------------------------------------------------------------------
-// 2. gather of lambda(n) from Lambda
-// ---------------------------------------------------------------------------
+// Nodes refilled between n and n + 1 (solid at n, fluid at n + 1): their
+// pre-collision populations follow the refill rules (streamed from a node
+// fluid at n, bounce-back of the opposite streamed population with the wall
+// term, or the equilibrium at (rho0, u_wall)); transposed collision, dJ/dF,
+// dJ/dtau, and dJ/dv of the wall velocity in the bounce-back and equilibrium
+// rules.  The entries (j, x - e_j) of lambda(n) at nodes fluid at n get the
+// adjoint of the streamed f_j, plus that of the bounce-back of direction
+// opp(j) unless x + e_j was fluid.
 template <int S>
-__global__ __launch_bounds__(256) void k_adj_gather(const uint32_t* __restrict__ own0,
+__global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __restrict__ f,
+                                                    const uint32_t* __restrict__ own0,
                                                     const uint32_t* __restrict__ own1,
-                                                    const typename St<S>::A* __restrict__ Lam,
-                                                    typename St<S>::A* __restrict__ lam0, Geom g)
+                                                    const typename St<S>::A* __restrict__ lam1,
+                                                    typename St<S>::A* __restrict__ lam0,
+                                                    const double* pos1, const double* vel1,
+                                                    const double* om1, Geom g, Phys ph,
+                                                    double* grad)
 {
     using A = typename St<S>::A;
+    constexpr bool DEV = St<S>::dev;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
-    if (cell >= g.ncell) return;
-    if (own0[cell] != kFluid) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint32_t o0 = cell < g.ncell ? own0[cell] : kFluid;
+    if (o0 != kFluid && own1[cell] == kFluid) {
+        const uint32_t nx = g.n[0], ny = g.n[1];
+        const int c[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / (nx * ny))};
+        const int p = (int)o0;
+        double rr[3];
 #pragma unroll
-        for (int j = 0; j < kQ; ++j) lam0[(int64_t)j * g.stride + cell] = A(0);
-        return;
-    }
-    const uint32_t nx = g.n[0], ny = g.n[1];
-    const int c[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / (nx * ny))};
-#pragma unroll
-    for (int j = 0; j < kQ; ++j) {
-        int cxn[3] = {c[0] + cx(j), c[1] + cy(j), c[2] + cz(j)};
-        A acc = A(0);
-        if (wrap3(cxn, g)) {
-            const uint32_t xn = node_of(cxn, g);
-            if (own0[xn] == kFluid) {
-                acc += Lam[(int64_t)j * g.stride + xn];  // pulled by x = y + e_j
-            } else if (own1[xn] == kFluid) {
-                // x = y + e_j refilled: streams f_j(y), and bounces it back as
-                // direction opp(j) unless x + e_j was fluid
-                acc += Lam[(int64_t)j * g.stride + xn];
-                int cz2[3] = {cxn[0] + cx(j), cxn[1] + cy(j), cxn[2] + cz(j)};
-                const bool okz = wrap3(cz2, g);
-                if (!(okz && own0[node_of(cz2, g)] == kFluid))
-                    acc += Lam[(int64_t)opp(j) * g.stride + xn];
-            }
-        } else {
-            acc += Lam[(int64_t)opp(j) * g.stride + cell];  // wall: y pulls f_j(y) as opp(j)
+        for (int a = 0; a < 3; ++a) {
+            const double xp = pos1[3 * p + a];
+            rr[a] = image_coord(c[a], g.n[a], g.per[a], xp) - xp;
         }
-        lam0[(int64_t)j * g.stride + cell] = acc;
+        const double* wp = om1 + 3 * p;
+        const A un[3] = {A(vel1[3 * p] + (wp[1] * rr[2] - wp[2] * rr[1])),
+                         A(vel1[3 * p + 1] + (wp[2] * rr[0] - wp[0] * rr[2])),
+                         A(vel1[3 * p + 2] + (wp[0] * rr[1] - wp[1] * rr[0]))};
+        const A r0 = A(ph.rho0), dr0 = A(ph.rho0 - 1.0);
+        A lam[kQ], pre[kQ];
+        uint32_t nu[kQ];
+        uint64_t rule = 0;  // per direction: 0 streamed, 1 bounce-back, 2 equilibrium
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            lam[i] = lam1[(int64_t)i * g.stride + cell];
+            int cuu[3] = {c[0] - cx(i), c[1] - cy(i), c[2] - cz(i)};
+            int cdd[3] = {c[0] + cx(i), c[1] + cy(i), c[2] + cz(i)};
+            const bool iu = i > 0 && wrap3(cuu, g);
+            const bool id = i > 0 && wrap3(cdd, g);
+            nu[i] = iu ? node_of(cuu, g) : kFluid;
+            const uint32_t nd = id ? node_of(cdd, g) : cell;
+            const bool up = iu && own0[nu[i]] == kFluid;
+            const bool dn = id && own0[nd] == kFluid;
+            if (!up) nu[i] = kFluid;
+            const A eu = A(cx(i)) * un[0] + A(cy(i)) * un[1] + A(cz(i)) * un[2];
+            if (up) {
+                pre[i] = St<S>::ld(f + (int64_t)i * g.stride + nu[i], ph.inv_scale);
+            } else if (dn) {
+                pre[i] = St<S>::ld(f + (int64_t)opp(i) * g.stride + nd, ph.inv_scale) +
+                         A(6) * W<A>(i) * r0 * eu;
+                rule |= 1ull << (2 * i);
+            } else {
+                pre[i] = eq_i<DEV, A>(i, dr0, r0, un[0], un[1], un[2]);
+                rule |= 2ull << (2 * i);
+            }
+        }
+        const AdjCoef<A> co = adj_collide<DEV, A>(lam, pre, ph, acc);
+        A Lp[kQ];
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) Lp[j] = co(j, lam[j]);
+        // d pre_j / d u_new: 6 w rho0 e_j for the bounce-back rule, d feq_j(rho0,
+        // u_new)/du for the equilibrium
+        double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) {
+            const uint32_t rj = (uint32_t)(rule >> (2 * j)) & 3u;
+            if (rj) {
+                const A ej[3] = {A(cx(j)), A(cy(j)), A(cz(j))};
+                const A eun = ej[0] * un[0] + ej[1] * un[1] + ej[2] * un[2];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const A cuk = (rj == 1u) ? A(6) * W<A>(j) * r0 * ej[k]
+                                             : W<A>(j) * r0 * (A(3) * ej[k] + A(9) * eun * ej[k] - A(3) * un[k]);
+                    dv[k] += (double)(Lp[j] * cuk);
+                }
+            }
+        }
+        for (int k = 0; k < 3; ++k)
+            if (dv[k] != 0.0) atomicAdd(grad + 4 + 3 * p + k, dv[k]);
+        // entries read through the streaming rule of direction j (x - e_j fluid
+        // at n): f_j(x - e_j) also fed the bounce-back of opp(j) when x + e_j
+        // was not fluid
+#pragma unroll
+        for (int j = 1; j < kQ; ++j)
+            if (nu[j] != kFluid) {
+                const bool bb = ((rule >> (2 * opp(j))) & 3u) == 1u;
+                lam0[(int64_t)j * g.stride + nu[j]] = bb ? Lp[j] + Lp[opp(j)] : Lp[j];
+            }
     }
+    double* outs[4] = {grad + 0, grad + 1, grad + 2, grad + 3};
+    block_add<4>(acc, outs);
 }
 
 // ---------------------------------------------------------------------------
-// 3. links: reconstruction, momentum exchange and missing points
+// 2. links: reconstruction, momentum exchange and missing points
 // ---------------------------------------------------------------------------
 template <class A>
 __device__ __forceinline__ void atomic_add_a(A* p, A v)
@@ -380,7 +412,6 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
                                                    const uint32_t* __restrict__ cursor,
                                                    int64_t cap, const double* pos,
                                                    const double* vel, const double* om,
-                                                   const typename St<S>::A* __restrict__ Lam,
                                                    typename St<S>::A* lam0, const double* wts,
                                                    Geom g, Phys ph, double* grad)
 {
@@ -483,7 +514,11 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
             }
             // adjoint of the reconstructed value: the fluid node that pulled
             // the ghost slot, plus the objective
-            const A lu = Lam[(int64_t)db * g.stride + xf] + A(d_in);
+            // the node kernel left the adjoint of the ghost slot (x_s, opp d),
+            // which x_f pulled, in lambda(n) at x_s; take it and clear it
+            A* ghost = lam0 + (int64_t)db * g.stride + r.node;
+            const A lu = *ghost + A(d_in);
+            *ghost = A(0);
             A gk[13];
 #pragma unroll
             for (int k = 0; k < 13; ++k) gk[k] = lu * unk.d[k];
@@ -525,21 +560,22 @@ inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
 template <int S>
 struct RunAdj {
     static hipError_t run(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1, const double* pos1,
-                          const double* vel1, const double* om1, const void* lam1, void* Lam,
+                          const double* vel1, const double* om1, const void* lam1,
                           void* lam0, const double* wts, double* grad)
     {
         using T = typename St<S>::T;
         using A = typename St<S>::A;
         const uint32_t nb = blocks_for(c->geom.ncell);
-        hipLaunchKernelGGL(k_adj_pre<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f, ts.own,
-                           own1, (const A*)lam1, (A*)Lam, pos1, vel1, om1, c->geom, c->phys, grad);
-        hipLaunchKernelGGL(k_adj_gather<S>, dim3(nb), dim3(256), 0, c->stream, ts.own, own1,
-                           (const A*)Lam, (A*)lam0, c->geom);
+        hipLaunchKernelGGL(k_adj_node<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f, ts.own,
+                           own1, (const A*)lam1, (A*)lam0, c->geom, c->phys, grad);
+        hipLaunchKernelGGL(k_adj_refill<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f,
+                           ts.own, own1, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom,
+                           c->phys, grad);
         if (c->cfg.n_particles > 0 && ts.link_max > 0) {
             dim3 grid(blocks_for(ts.link_max), c->cfg.n_particles);
             hipLaunchKernelGGL(k_adj_links<S>, grid, dim3(256), 0, c->stream, (const T*)ts.f,
                                ts.links, ts.cursor, ts.link_cap, ts.part, ts.part + 3 * c->cfg.n_particles,
-                               ts.part + 6 * c->cfg.n_particles, (const A*)Lam, (A*)lam0, wts,
+                               ts.part + 6 * c->cfg.n_particles, (A*)lam0, wts,
                                c->geom, c->phys, grad);
         }
         return hipGetLastError();
@@ -550,16 +586,16 @@ struct RunAdj {
 
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
-                               const void* lam1, void* Lam, void* lam0, const double* wts,
+                               const void* lam1, void* lam0, const double* wts,
                                double* grad)
 {
     switch (c->cfg.storage) {
     case LBM_STORE_F64:
-        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, Lam, lam0, wts, grad);
+        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad);
     case LBM_STORE_F32:
-        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, Lam, lam0, wts, grad);
+        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad);
     case LBM_STORE_F16:
-        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, Lam, lam0, wts, grad);
+        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad);
     default: return hipErrorInvalidValue;
     }
 }

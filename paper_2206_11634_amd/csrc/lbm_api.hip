@@ -344,8 +344,7 @@ int lbm_destroy(lbm_ctx* c)
         (void)hipFree(t.cursor);
         (void)hipFree(t.part);
     }
-    (void)hipFree(c->adj_scratch[0]);
-    (void)hipFree(c->adj_scratch[1]);
+    (void)hipFree(c->adj_scratch);
     (void)hipFree(c->adj_wts);
     (void)hipFree(c->hist_pp);
     (void)hipFree(c->hist_pw);
@@ -681,16 +680,14 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
     if (rc) return rc;
     const int np = c->cfg.n_particles;
     if (np > 0 && !weights) return fail(c, LBM_EINVAL, "null objective weights");
-    for (int i = 0; i < 2; ++i)
-        if (!c->adj_scratch[i] && hipMalloc(&c->adj_scratch[i], c->sizes.adjoint_bytes) != hipSuccess)
-            return fail(c, LBM_ENOMEM, "adjoint scratch allocation failed");
+    if (!c->adj_scratch && hipMalloc(&c->adj_scratch, c->sizes.adjoint_bytes) != hipSuccess)
+        return fail(c, LBM_ENOMEM, "adjoint scratch allocation failed");
     if (!c->adj_wts && alloc(&c->adj_wts, (size_t)6 * std::max(np, 1)) != hipSuccess)
         return fail(c, LBM_ENOMEM, "adjoint weight allocation failed");
     if (np > 0)
         HIPCHK(c, hipMemcpyAsync(c->adj_wts, weights, sizeof(double) * 6 * np,
                                  hipMemcpyHostToDevice, c->stream));
-    void* bufs[2] = {lam_dev, c->adj_scratch[0]};
-    void* Lam = c->adj_scratch[1];
+    void* bufs[2] = {lam_dev, c->adj_scratch};
     int in = 0;
     for (int s = c->tape_len - 1; s >= 0; --s) {
         const TapeStep& ts = c->tape[s];
@@ -700,7 +697,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
-        HIPCHK(c, launch_adjoint_step(c, ts, own1, pos1, vel1, om1, bufs[in], Lam, bufs[1 - in],
+        HIPCHK(c, launch_adjoint_step(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
                                       c->adj_wts, grad_dev));
         in = 1 - in;
     }

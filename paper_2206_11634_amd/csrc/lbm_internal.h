@@ -182,7 +182,7 @@ struct lbm_ctx {
     int tape_len = 0;    // steps recorded since lbm_tape_begin
     int tape_steps = 0;  // steps to record (tape.size() may be larger)
     bool taping = false;
-    void* adj_scratch[2] = {nullptr, nullptr};
+    void* adj_scratch = nullptr;  // the second adjoint field of the ping-pong
     double* adj_wts = nullptr;
     std::string last_error;
 };
@@ -214,8 +214,7 @@ hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t
 // Launchers (lbm_adjoint.hip)
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
-                               const void* lam1, void* Lam, void* lam0, const double* wts,
-                               double* grad);
+                               const void* lam1, void* lam0, const double* wts, double* grad);
 
 // Launchers (lbm_dem.hip)
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);
