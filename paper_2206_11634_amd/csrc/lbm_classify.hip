@@ -174,6 +174,21 @@ __device__ __forceinline__ uint32_t wave_base(uint32_t count, uint32_t* cursor)
     return __shfl(base, 63, 64);
 }
 
+// Block (bx, by) of a gx x gy work grid launched as a 1D grid of a multiple of
+// 8 workgroups.  The hardware hands workgroup b to XCD b % 8; mapping XCD k to
+// the k-th eighth of the work keeps all blocks of a particle (by) on one XCD,
+// so the owner rows its candidates share are fetched into one L2.  False for
+// the padding workgroups.
+__device__ __forceinline__ bool xcd_tile(uint32_t gx, uint32_t gy, uint32_t& bx, uint32_t& by)
+{
+    const uint32_t per = gridDim.x >> 3;
+    const uint32_t logical = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (logical >= gx * gy) return false;
+    bx = logical % gx;
+    by = logical / gx;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 
 // Box origin and body radius of every particle, and input checks.  At
@@ -277,7 +292,7 @@ __global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball
 // candidate list.  Every other solid node of p goes on the list.
 constexpr int kRows = 2 * kMaxBoxHalf + 1;
 
-__global__ __launch_bounds__(256) void k_mark(uint32_t* own, const double* ball, int h, PartDev P,
+__global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ball, int h, PartDev P,
                                               Geom g, uint8_t* flag, int store_flag, uint32_t* cand,
                                               int64_t cap, uint32_t* cursors)
 {
@@ -471,13 +486,16 @@ __device__ __forceinline__ int select_bit(uint64_t m, uint32_t k)
 // wave then enumerates its links in that order and gives one link to each
 // lane (candidate data by lane shuffles), so the FP64 work of q runs on full
 // waves.  A grid of a few workgroups per particle strides over the list.
-__global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double* ball, PartDev P,
+__global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const double* ball, PartDev P,
                                                Geom g, const uint32_t* cand, int64_t cand_cap,
                                                const uint32_t* cand_cursors, LinkRec* links,
-                                               int64_t cap, uint32_t* cursors, int treat)
+                                               int64_t cap, uint32_t* cursors, int treat,
+                                               uint32_t gx)
 {
     __shared__ double sp[4 * kMaxCtrl];
-    const int p = blockIdx.y;
+    uint32_t bx, by;
+    if (!xcd_tile(gx, (uint32_t)P.n, bx, by)) return;  // uniform over the block
+    const int p = (int)by;
     const int n = stage_ctrl(P, p, sp);
     const double c0 = P.c0[p];
     const double* B = ball + 4 * p;
@@ -486,7 +504,7 @@ __global__ __launch_bounds__(256) void k_links(const uint32_t* own, const double
     LinkRec* out = links + (int64_t)p * cap;
     uint32_t* cursor = cursors + (int64_t)p * kCursorPad;
     const int lane = threadIdx.x & 63;
-    for (uint32_t base0 = blockIdx.x * 256u; base0 < count; base0 += gridDim.x * 256u) {
+    for (uint32_t base0 = bx * 256u; base0 < count; base0 += gx * 256u) {
         const uint32_t k = base0 + threadIdx.x;
         uint32_t node = 0, mask = 0;
         int c[3] = {0, 0, 0};
@@ -686,9 +704,11 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
     const uint32_t per = (uint32_t)std::min<int64_t>(16, (c->cand_cap + 255) / 256);
-    hipLaunchKernelGGL(k_links, dim3(per, np), dim3(256), 0, c->stream, own,
+    const uint32_t nb = (per * (uint32_t)np + 7u) & ~7u;
+    hipLaunchKernelGGL(k_links, dim3(nb), dim3(256), 0, c->stream, own,
                        c->ball_hist + (int64_t)slot * 4 * np, P, c->geom, c->cand, c->cand_cap,
-                       c->cand_cursor, c->links, c->link_cap, c->link_cursor, c->cfg.treatments);
+                       c->cand_cursor, c->links, c->link_cap, c->link_cursor, c->cfg.treatments,
+                       per);
     return hipGetLastError();
 }
 

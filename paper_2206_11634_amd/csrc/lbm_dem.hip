@@ -73,6 +73,57 @@ __device__ void mb_d2(const double* pts, const double* K, int n, const double sh
     }
 }
 
+// A body's control points for the Newton iterations: read from global
+// memory each time, or (up to kRegPts points) held in registers, which
+// removes the memory latency from the serial iteration.  Both evaluate
+// exactly the sums of mb_d2 in the same order.
+struct BodyG {
+    const double* pts;
+    const double* K;
+    int n;
+    __device__ void eval(const double sh[3], const double X[3], double& M, double g[3],
+                         double H[9]) const
+    {
+        mb_d2(pts, K, n, sh, X, M, g, H);
+    }
+};
+
+constexpr int kRegPts = 6;
+struct BodyR {
+    double p[kRegPts][3], k[kRegPts];
+    int n;
+    __device__ BodyR(const double* pts, const double* K, int n_) : n(n_)
+    {
+#pragma unroll
+        for (int i = 0; i < kRegPts; ++i) {
+            const bool on = i < n;
+            for (int a = 0; a < 3; ++a) p[i][a] = on ? pts[3 * i + a] : 0.0;
+            k[i] = on ? K[i] : 0.0;
+        }
+    }
+    __device__ __forceinline__ void eval(const double sh[3], const double X[3], double& M,
+                                         double g[3], double H[9]) const
+    {
+        M = 0.0;
+        for (int a = 0; a < 3; ++a) g[a] = 0.0;
+        for (int a = 0; a < 9; ++a) H[a] = 0.0;
+#pragma unroll
+        for (int i = 0; i < kRegPts; ++i) {
+            if (i >= n) break;
+            double r[3];
+            for (int a = 0; a < 3; ++a) r[a] = X[a] - (p[i][a] + sh[a]);
+            const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+            const double i2 = 1.0 / r2, i4 = i2 * i2, i6 = i4 * i2;
+            M += k[i] * i2;
+            for (int a = 0; a < 3; ++a) {
+                g[a] += -2.0 * k[i] * r[a] * i4;
+                for (int b = 0; b < 3; ++b)
+                    H[3 * a + b] += k[i] * (8.0 * r[a] * r[b] * i6 - (a == b ? 2.0 * i4 : 0.0));
+            }
+        }
+    }
+};
+
 __device__ bool solve3(const double H[9], const double g[3], double dx[3])
 {
     double c[9];
@@ -208,67 +259,19 @@ __global__ void k_first_half(PartDev P, const double* FTh, double* fc, double* r
 __device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, const double* rch,
                              const DemP& c, double dt, const Geom& g);
 
-// Threads [0, np*np) take the pairs i < j, threads [np*np, np*np + 6 np) the
-// particle-wall pairs.
-__global__ void k_contacts(PartDev P, double* hist, double* hist_w, double* fc, const double* rch,
-                           DemP c, double dt, Geom g)
+// Newton on grad(M_A + M_B) = 0 from x, the contact test and the force of
+// pair (i, j); A and B supply the two bodies' metaball sums.
+template <class BA, class BB>
+__device__ __forceinline__ void pair_contact(const BA& A, const BB& B, double x[3], double* h, const double* xi,
+                             const double* xj, const double sh[3], int i, int j, double rsi,
+                             double rsj, const PartDev& P, const DemP& c, double dt, double* fc)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int np = P.n;
-    if (t >= (int64_t)np * np) {
-        const int64_t w = t - (int64_t)np * np;
-        if (w < (int64_t)np * 6) wall_contact(P, (int)w, hist_w, fc, rch, c, dt, g);
-        return;
-    }
-    const int i = (int)(t / np), j = (int)(t % np);
-    if (i >= j) return;
-    double* h = hist + t * kHist;
-    const double* xi = P.pos + 3 * i;
-    const double* xj = P.pos + 3 * j;
-    double sh[3], dv[3];
-    for (int a = 0; a < 3; ++a) {
-        const double d = xj[a] - xi[a];
-        sh[a] = 0.0;
-        if (g.per[a]) {
-            const double L = g.n[a];
-            if (d > 0.5 * L) sh[a] = -L;
-            else if (d < -0.5 * L) sh[a] = L;
-        }
-        dv[a] = d + sh[a];
-    }
-    const double rsi = P.rs[i], rsj = P.rs[j];
-    if (sqrt(dot3(dv, dv)) > rch[i] + rch[j] + rsi + rsj) {
-        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
-        return;
-    }
-    const int ai = P.off[i], ni = min(P.off[i + 1] - ai, kMaxPts);
-    const int aj = P.off[j], nj = min(P.off[j + 1] - aj, kMaxPts);
-    const double* pi = P.wpts + 3 * (int64_t)ai;
-    const double* pj = P.wpts + 3 * (int64_t)aj;
     const double z3[3] = {0.0, 0.0, 0.0};
-    double x[3];
-    if (h[0] != 0.0) {
-        for (int a = 0; a < 3; ++a) x[a] = xi[a] + h[4 + a];
-    } else {
-        double best = INFINITY;
-        for (int u = 0; u < ni; ++u)
-            for (int v = 0; v < nj; ++v) {
-                double d2 = 0.0;
-                for (int a = 0; a < 3; ++a) {
-                    const double dd = pi[3 * u + a] - (pj[3 * v + a] + sh[a]);
-                    d2 += dd * dd;
-                }
-                if (d2 < best) {
-                    best = d2;
-                    for (int a = 0; a < 3; ++a) x[a] = 0.5 * (pi[3 * u + a] + pj[3 * v + a] + sh[a]);
-                }
-            }
-    }
     double MA, MB, gA[3], gB[3], HA[9], HB[9];
     bool conv = false;
     for (int it = 0; it < c.niter; ++it) {
-        mb_d2(pi, P.K + ai, ni, z3, x, MA, gA, HA);
-        mb_d2(pj, P.K + aj, nj, sh, x, MB, gB, HB);
+        A.eval(z3, x, MA, gA, HA);
+        B.eval(sh, x, MB, gB, HB);
         double gg[3], H[9], dx[3];
         for (int a = 0; a < 3; ++a) gg[a] = gA[a] + gB[a];
         for (int a = 0; a < 9; ++a) H[a] = HA[a] + HB[a];
@@ -283,8 +286,8 @@ __global__ void k_contacts(PartDev P, double* hist, double* hist_w, double* fc, 
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
-    mb_d2(pi, P.K + ai, ni, z3, x, MA, gA, HA);
-    mb_d2(pj, P.K + aj, nj, sh, x, MB, gB, HB);
+    A.eval(z3, x, MA, gA, HA);
+    B.eval(sh, x, MB, gB, HB);
     if (!(MA > c.ctol && MA < 1.0 && MB > c.ctol && MB < 1.0)) {
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
@@ -329,40 +332,85 @@ __global__ void k_contacts(PartDev P, double* hist, double* hist_w, double* fc, 
     for (int a = 0; a < 3; ++a) atomicAdd(fc + 6 * j + 3 + a, -tq[a]);
 }
 
-__device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, const double* rch,
-                             const DemP& c, double dt, const Geom& g)
+// Threads [0, np*np) take the pairs i < j, threads [np*np, np*np + 6 np) the
+// particle-wall pairs.
+__global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, double* hist_w, double* fc, const double* rch,
+                           DemP c, double dt, Geom g)
 {
-    const int i = t / 6, ax = (t % 6) / 2, side = t % 2;
-    if (g.per[ax]) return;
-    double* h = hist + (int64_t)t * kHist;
-    const double plane = side ? g.n[ax] - 0.5 : -0.5, sgn = side ? -1.0 : 1.0;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = P.n;
+    if (t >= (int64_t)np * np) {
+        const int64_t w = t - (int64_t)np * np;
+        if (w < (int64_t)np * 6) wall_contact(P, (int)w, hist_w, fc, rch, c, dt, g);
+        return;
+    }
+    const int i = (int)(t / np), j = (int)(t % np);
+    if (i >= j) return;
+    double* h = hist + t * kHist;
     const double* xi = P.pos + 3 * i;
-    if (sgn * (xi[ax] - plane) > rch[i] + P.rs[i]) {
-        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+    const double* xj = P.pos + 3 * j;
+    double sh[3], dv[3];
+    for (int a = 0; a < 3; ++a) {
+        const double d = xj[a] - xi[a];
+        sh[a] = 0.0;
+        if (g.per[a]) {
+            const double L = g.n[a];
+            if (d > 0.5 * L) sh[a] = -L;
+            else if (d < -0.5 * L) sh[a] = L;
+        }
+        dv[a] = d + sh[a];
+    }
+    const double rsi = P.rs[i], rsj = P.rs[j];
+    if (sqrt(dot3(dv, dv)) > rch[i] + rch[j] + rsi + rsj) {
+        // out of reach: forget the pair (most of the n^2 records are zero
+        // already, so read one double instead of writing eight)
+        if (h[0] != 0.0)
+            for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
     const int ai = P.off[i], ni = min(P.off[i + 1] - ai, kMaxPts);
+    const int aj = P.off[j], nj = min(P.off[j + 1] - aj, kMaxPts);
     const double* pi = P.wpts + 3 * (int64_t)ai;
-    const double z3[3] = {0.0, 0.0, 0.0};
-    const int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+    const double* pj = P.wpts + 3 * (int64_t)aj;
     double x[3];
     if (h[0] != 0.0) {
         for (int a = 0; a < 3; ++a) x[a] = xi[a] + h[4 + a];
     } else {
         double best = INFINITY;
-        for (int u = 0; u < ni; ++u) {
-            const double dd = fabs(pi[3 * u + ax] - plane);
-            if (dd < best) {
-                best = dd;
-                for (int a = 0; a < 3; ++a) x[a] = pi[3 * u + a];
+        for (int u = 0; u < ni; ++u)
+            for (int v = 0; v < nj; ++v) {
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double dd = pi[3 * u + a] - (pj[3 * v + a] + sh[a]);
+                    d2 += dd * dd;
+                }
+                if (d2 < best) {
+                    best = d2;
+                    for (int a = 0; a < 3; ++a) x[a] = 0.5 * (pi[3 * u + a] + pj[3 * v + a] + sh[a]);
+                }
             }
-        }
     }
-    x[ax] = plane;
+    if (ni <= kRegPts && nj <= kRegPts)
+        pair_contact(BodyR(pi, P.K + ai, ni), BodyR(pj, P.K + aj, nj), x, h, xi, xj, sh, i, j, rsi,
+                     rsj, P, c, dt, fc);
+    else
+        pair_contact(BodyG{pi, P.K + ai, ni}, BodyG{pj, P.K + aj, nj}, x, h, xi, xj, sh, i, j,
+                     rsi, rsj, P, c, dt, fc);
+}
+
+// In-plane Newton for the point of the wall plane where M is largest, the
+// contact test and the force of body i on wall (ax, side); A supplies the
+// body's metaball sums.
+template <class BA>
+__device__ __forceinline__ void wall_newton(const BA& A, double x[3], double* h, const double* xi, int i, int ax,
+                            int t1, int t2, double sgn, const PartDev& P, const DemP& c, double dt,
+                            double* fc)
+{
+    const double z3[3] = {0.0, 0.0, 0.0};
     double M, gr[3], H[9];
     bool conv = false;
     for (int it = 0; it < c.niter; ++it) {
-        mb_d2(pi, P.K + ai, ni, z3, x, M, gr, H);
+        A.eval(z3, x, M, gr, H);
         const double h11 = H[3 * t1 + t1], h12 = H[3 * t1 + t2], h22 = H[3 * t2 + t2];
         const double det = h11 * h22 - h12 * h12;
         if (!(fabs(det) > 0.0) || !isfinite(det)) break;
@@ -379,7 +427,7 @@ __device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, 
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
-    mb_d2(pi, P.K + ai, ni, z3, x, M, gr, H);
+    A.eval(z3, x, M, gr, H);
     if (!(sgn * gr[ax] > 0.0)) {
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
@@ -407,6 +455,42 @@ __device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, 
         atomicAdd(fc + 6 * i + a, Fi[a]);
         atomicAdd(fc + 6 * i + 3 + a, tq[a]);
     }
+}
+
+__device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, const double* rch,
+                             const DemP& c, double dt, const Geom& g)
+{
+    const int i = t / 6, ax = (t % 6) / 2, side = t % 2;
+    if (g.per[ax]) return;
+    double* h = hist + (int64_t)t * kHist;
+    const double plane = side ? g.n[ax] - 0.5 : -0.5, sgn = side ? -1.0 : 1.0;
+    const double* xi = P.pos + 3 * i;
+    if (sgn * (xi[ax] - plane) > rch[i] + P.rs[i]) {
+        if (h[0] != 0.0)
+            for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    const int ai = P.off[i], ni = min(P.off[i + 1] - ai, kMaxPts);
+    const double* pi = P.wpts + 3 * (int64_t)ai;
+    const int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+    double x[3];
+    if (h[0] != 0.0) {
+        for (int a = 0; a < 3; ++a) x[a] = xi[a] + h[4 + a];
+    } else {
+        double best = INFINITY;
+        for (int u = 0; u < ni; ++u) {
+            const double dd = fabs(pi[3 * u + ax] - plane);
+            if (dd < best) {
+                best = dd;
+                for (int a = 0; a < 3; ++a) x[a] = pi[3 * u + a];
+            }
+        }
+    }
+    x[ax] = plane;
+    if (ni <= kRegPts)
+        wall_newton(BodyR(pi, P.K + ai, ni), x, h, xi, i, ax, t1, t2, sgn, P, c, dt, fc);
+    else
+        wall_newton(BodyG{pi, P.K + ai, ni}, x, h, xi, i, ax, t1, t2, sgn, P, c, dt, fc);
 }
 
 __global__ void k_second_half(PartDev P, const double* FTh, const double* fc, DemP c, double dt)
