@@ -196,10 +196,18 @@ __device__ __forceinline__ bool xcd_tile(uint32_t gx, uint32_t gy, uint32_t& bx,
 // which decreases in d, so the body lies within the root R of B(R) = c0.  The
 // box must hold the ball of radius h - 1 (B(h-1) < c0); R itself lets the
 // kernels skip box cells that cannot be solid.
-__global__ void k_boxes(PartDev P, int h, double* ball, uint32_t* err, Geom g)
+__device__ __forceinline__ double wave_sum_d(double v)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave per particle, a lane per control point (n <= 64).
+__global__ __launch_bounds__(64) void k_boxes(PartDev P, int h, double* ball, uint32_t* err, Geom g)
+{
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
     uint32_t bad = 0;
     double xp[3];
     for (int a = 0; a < 3; ++a) {
@@ -210,47 +218,49 @@ __global__ void k_boxes(PartDev P, int h, double* ball, uint32_t* err, Geom g)
     if (n < 1 || n > kMaxCtrl) bad |= 8u;
     const double c0 = P.c0[p];
     if (!(c0 > 0.0)) bad |= 2u;
-    double rmax = 0.0;
-    for (int i = 0; i < min(n, kMaxCtrl); ++i) {
-        if (!(P.K[a0 + i] > 0.0)) bad |= 2u;
+    // this lane's control point: distance to the centre and weight
+    double ri = 0.0, Ki = 0.0;
+    if (lane < min(n, kMaxCtrl)) {
+        Ki = P.K[a0 + lane];
+        if (!(Ki > 0.0)) bad |= 2u;
         double r2 = 0.0;
         for (int a = 0; a < 3; ++a) {
-            const double d = P.wpts[3 * (int64_t)(a0 + i) + a] - xp[a];
+            const double d = P.wpts[3 * (int64_t)(a0 + lane) + a] - xp[a];
             r2 += d * d;
         }
-        rmax = fmax(rmax, sqrt(r2));
+        ri = sqrt(r2);
     }
+    double rmax = ri;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
     auto bound = [&](double d) {
-        double s = 0.0;
-        for (int i = 0; i < min(n, kMaxCtrl); ++i) {
-            double r2 = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                const double e = P.wpts[3 * (int64_t)(a0 + i) + a] - xp[a];
-                r2 += e * e;
-            }
-            const double t = d - sqrt(r2);
-            s += P.K[a0 + i] / (t * t);
-        }
-        return s;
+        const double t = d - ri;
+        return wave_sum_d(Ki > 0.0 ? Ki / (t * t) : 0.0);
     };
     const double lim = (double)(h - 1);
     double R = lim;
     if (!(lim > rmax) || !(bound(lim) < c0)) {
         bad |= 4u;
     } else {
+        // bisection keeps B(hi) < c0, so hi bounds the body at every step;
+        // 40 halvings of an interval below 2 h leave it under 1e-9
         double lo = rmax, hi = lim;
-        for (int it = 0; it < 64; ++it) {
+        for (int it = 0; it < 40; ++it) {
             const double mid = 0.5 * (lo + hi);
             if (bound(mid) >= c0) lo = mid;
             else hi = mid;
         }
         R = hi;
     }
-    ball[4 * p + 0] = xp[0];
-    ball[4 * p + 1] = xp[1];
-    ball[4 * p + 2] = xp[2];
-    ball[4 * p + 3] = R + 1e-6;
-    if (bad) atomicOr(err, bad);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) bad |= __shfl_xor(bad, o, 64);
+    if (lane == 0) {
+        ball[4 * p + 0] = xp[0];
+        ball[4 * p + 1] = xp[1];
+        ball[4 * p + 2] = xp[2];
+        ball[4 * p + 3] = R + 1e-6;
+        if (bad) atomicOr(err, bad);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball, int h, Geom g)
@@ -602,26 +612,43 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const dou
     }
 }
 
-// The same as k_finish over the whole lattice (one node per thread), used when
-// the balls cover most of the lattice and a coalesced sweep is cheaper.
+// The same as k_finish over the whole lattice (four consecutive nodes per
+// thread, 16-byte owner loads), used when the balls cover most of the lattice
+// and a coalesced sweep is cheaper.
 __global__ __launch_bounds__(256) void k_finish_all(const uint32_t* own_prev,
                                                     const uint32_t* own_new, Geom g, uint8_t* flag,
                                                     RefillRec* rec, int64_t cap, uint32_t* cursor)
 {
-    const uint32_t node = blockIdx.x * 256u + threadIdx.x;
-    bool refill = false;
-    uint32_t op = kFluid;
-    if (node < g.ncell) {
-        const uint32_t on = own_new[node];
-        op = own_prev[node];
-        flag[node] = on != kFluid;
-        refill = op != kFluid && on == kFluid;
+    const uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u;
+    uint32_t on[4] = {kFluid, kFluid, kFluid, kFluid}, op[4] = {kFluid, kFluid, kFluid, kFluid};
+    if (base + 3u < g.ncell) {
+        const uint4 a = *reinterpret_cast<const uint4*>(own_new + base);
+        const uint4 b = *reinterpret_cast<const uint4*>(own_prev + base);
+        on[0] = a.x, on[1] = a.y, on[2] = a.z, on[3] = a.w;
+        op[0] = b.x, op[1] = b.y, op[2] = b.z, op[3] = b.w;
+        *reinterpret_cast<uchar4*>(flag + base) =
+            make_uchar4(on[0] != kFluid, on[1] != kFluid, on[2] != kFluid, on[3] != kFluid);
+    } else {
+        for (int k = 0; k < 4; ++k)
+            if (base + k < g.ncell) {
+                on[k] = own_new[base + k];
+                op[k] = own_prev[base + k];
+                flag[base + k] = on[k] != kFluid;
+            }
     }
-    const uint32_t slot = wave_reserve(refill ? 1u : 0u, cursor);
-    if (refill && slot < cap) {
-        rec[slot].node = node;
-        rec[slot].part = op;
-    }
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt += (op[k] != kFluid && on[k] == kFluid) ? 1u : 0u;
+    uint32_t slot = wave_reserve(cnt, cursor);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (op[k] != kFluid && on[k] == kFluid) {
+            if (slot < cap) {
+                rec[slot].node = base + k;
+                rec[slot].part = op[k];
+            }
+            ++slot;
+        }
 }
 
 __global__ void k_owner_export(const uint32_t* own, int32_t* out, uint32_t ncell)
@@ -657,7 +684,7 @@ hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot)
 {
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_boxes, dim3((np + 63) / 64), dim3(64), 0, c->stream, P, c->box.h,
+    hipLaunchKernelGGL(k_boxes, dim3(np), dim3(64), 0, c->stream, P, c->box.h,
                        c->ball_hist + (int64_t)slot * 4 * np, c->err, c->geom);
     return hipGetLastError();
 }
@@ -688,7 +715,8 @@ hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* o
 {
     if (np_prev == 0) return hipSuccess;
     if (c->dense) {
-        hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->geom.ncell)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_finish_all, dim3(blocks_for((c->geom.ncell + 3) / 4)), dim3(256), 0,
+                           c->stream,
                            own_prev, own_new, c->geom, c->flag, c->refill, c->refill_cap,
                            c->refill_cursor);
         return hipGetLastError();
