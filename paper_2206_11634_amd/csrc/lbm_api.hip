@@ -393,7 +393,9 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
             if (k >= 2) HIPCHK(c, launch_clear_boxes(c, own_new, slot_prev2, np));
             HIPCHK(c, launch_mark(c, own_new, Pd, slot));
-            if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
+            // the lattice sweep also runs on a first classification (own_prev
+            // is all fluid then): in dense mode it writes every flag
+            if (k >= 1 || c->dense) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
             HIPCHK(c, launch_links(c, own_new, Pd, slot));
         }
         uint32_t* link_counts = c->host_stage + 2;

@@ -301,6 +301,7 @@ __global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball
 // at every neighbour, hence no link of any kind, and is left off p's
 // candidate list.  Every other solid node of p goes on the list.
 constexpr int kRows = 2 * kMaxBoxHalf + 1;
+constexpr uint32_t kCandBuf = 2048;
 
 __global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ball, int h, PartDev P,
                                               Geom g, uint8_t* flag, int store_flag, uint32_t* cand,
@@ -311,6 +312,8 @@ __global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ba
     __shared__ int rlo[kRows];
     __shared__ int rstart[kRows + 1];
     __shared__ int wsum[4];
+    __shared__ uint32_t cbuf[kCandBuf];  // this plane's candidates, in walk order
+    __shared__ uint32_t ccount;
     const int p = blockIdx.y;
     const int n = stage_ctrl(P, p, sp);
     const double c0 = P.c0[p];
@@ -384,7 +387,10 @@ __global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ba
         if (r < S) rstart[r] = off;
         off += len[k];
     }
-    if (threadIdx.x == 0) rstart[S] = total;
+    if (threadIdx.x == 0) {
+        rstart[S] = total;
+        ccount = 0;
+    }
     __syncthreads();
     if (total == 0) return;  // uniform over the block
 
@@ -442,9 +448,30 @@ __global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ba
                 }
             }
         }
-        const uint32_t slot = wave_reserve(keep ? 1u : 0u, cursor);
-        if (keep && slot < cap) list[slot] = node;
+        // candidates gather in LDS so that the plane's list stays contiguous
+        // and in row order (neighbouring candidates then share owner rows in
+        // k_links); a full buffer spills lanes straight to the list
+        const uint64_t m = __ballot(keep);
+        uint32_t wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&ccount, (uint32_t)__popcll(m));
+        wbase = __shfl(wbase, 0, 64);
+        if (keep) {
+            const uint32_t idx = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            if (idx < kCandBuf) {
+                cbuf[idx] = node;
+            } else {
+                const uint32_t slot = atomicAdd(cursor, 1u);
+                if (slot < cap) list[slot] = node;
+            }
+        }
     }
+    __syncthreads();
+    __shared__ uint32_t gbase;
+    const uint32_t nb = min(ccount, (uint32_t)kCandBuf);
+    if (threadIdx.x == 0) gbase = nb ? atomicAdd(cursor, nb) : 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        if (gbase + i < cap) list[gbase + i] = cbuf[i];
 }
 
 // Over the previous balls: flags of the new classification and the nodes that
@@ -716,9 +743,8 @@ hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* o
     if (np_prev == 0) return hipSuccess;
     if (c->dense) {
         hipLaunchKernelGGL(k_finish_all, dim3(blocks_for((c->geom.ncell + 3) / 4)), dim3(256), 0,
-                           c->stream,
-                           own_prev, own_new, c->geom, c->flag, c->refill, c->refill_cap,
-                           c->refill_cursor);
+                           c->stream, own_prev, own_new, c->geom, c->flag, c->refill,
+                           c->refill_cap, c->refill_cursor);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_finish, dim3(c->box.S, np_prev), dim3(256), 0, c->stream, own_prev,
