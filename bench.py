@@ -34,12 +34,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def run_storage(lat, ps, meta, storage, steps, warmup, profile=True):
+def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=3):
     import torch
     from paper_2206_11634_amd import binding as B
     from paper_2206_11634_amd import workloads as W
 
-    gpu = B.Lattice.for_particles(lat, ps, storage=storage)
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treatments)
     parts = B.DeviceParticles(ps)
     prm = B.DemParams.make(**W.dem_defaults(ps, gravity=meta["gravity"]))
     n_sub = int(meta.get("n_sub", 10))
@@ -169,6 +169,42 @@ def drag_error(steps=200):
         out[storage] = dict(force=eF, torque=eT)
     out["workload"] = f"c1 40x40x80 sphere d=10, prescribed descent, {steps} steps"
     return out
+
+
+def exact_q_effect(lat, ps, meta, steps=200):
+    """q from Eq. calq (bracketed Newton) instead of Eq. appq: the drag change
+    on the 40x40x80 sphere descent (FP32, prescribed motion), and the cost on
+    the benchmark workload (classification phase, 5 steps)."""
+    from paper_2206_11634_amd import binding as B
+    from paper_2206_11634_amd import workloads as W
+
+    l1, p1, _ = W.config_c1()
+    p1.vel[:] = [0.0, 0.0, -0.01]
+    p1.omega[:] = [0.0, 0.002, 0.0]
+    traj = [W.prescribed_state(p1, l1, float(n)) for n in range(steps)]
+    Fz = {}
+    for name, treat in (("linear", 3), ("exact", 7)):
+        gpu = B.Lattice.for_particles(l1, p1, storage="f32", treatments=treat)
+        parts = B.DeviceParticles(p1)
+        out = []
+        for n in range(steps):
+            parts.set_state(traj[n])
+            gpu.classify(parts)
+            gpu.step(parts)
+            F, _ = gpu.forces()
+            out.append(F[0].cpu().numpy().copy())
+        gpu.close()
+        Fz[name] = np.array(out)
+    lin, ex = Fz["linear"], Fz["exact"]
+    tail = slice(steps // 2, None)
+    res = dict(
+        drag_mean_rel_diff=float(abs(lin[tail, 2].mean() - ex[tail, 2].mean()) / abs(ex[tail, 2].mean())),
+        force_series_rel_diff=float(np.abs(lin - ex).max() / np.abs(ex).max()),
+        sphere_workload=f"c1 40x40x80 sphere d=10, prescribed descent 0.01 lu/step, {steps} steps, FP32")
+    r = run_storage(lat, ps, meta, "f32", 5, 1, treatments=7)
+    res["ms_per_step"] = round(r["ms_per_step"], 4)
+    res["classify_ms"] = round(r["prof"]["classify"][0] / max(r["prof"]["classify"][1], 1), 4)
+    return res
 
 
 def adjoint_bench(fd_check=True):
@@ -307,6 +343,8 @@ def main():
                                              main_res["ms_per_step"], 3)
     if not args.no_drag:
         line["drag_err"] = drag_error()
+    if not args.no_drag:
+        line["exact_q"] = exact_q_effect(lat, ps, meta)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:

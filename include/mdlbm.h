@@ -58,8 +58,11 @@ typedef enum {
 typedef enum {
     LBM_TREAT_VIBB = 1,   /* velocity-interpolated bounce-back (Sec. 2.3.1); without
                              it every cut link uses halfway bounce-back */
-    LBM_TREAT_MISSING = 2 /* treatment 2 of Sec. 2.3.5: momentum exchange on
+    LBM_TREAT_MISSING = 2, /* treatment 2 of Sec. 2.3.5: momentum exchange on
                              force points covered by another body or a wall */
+    LBM_TREAT_EXACT_Q = 4 /* q as the root of Eq. (calq), M(x_n + q e_d) = c0, by a
+                             bracketed Newton iteration from the linear estimate,
+                             instead of Eq. (appq) */
 } lbm_treatment;
 
 typedef enum {

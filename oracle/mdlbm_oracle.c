@@ -363,7 +363,50 @@ void ora_classify(const int* dims, const int* per, int np, const int* off, const
 /* ------------------------------------------------------------------------ */
 
 enum { KIND_VIBB = 0, KIND_HALFWAY = 1, KIND_MISSING = 2 };
-enum { TREAT_VIBB = 1, TREAT_MISSING = 2 };
+enum { TREAT_VIBB = 1, TREAT_MISSING = 2, TREAT_EXACT_Q = 4 };
+
+/* q of Eq. (calq): the root of g(q) = M(x_n + q e_d) - c0 on [0, 1], where
+ * g(0) = M(x_n) - c0 < 0 <= g(1) = M(x_s) - c0.  Newton-Raphson from the
+ * linear estimate of Eq. (appq), kept inside the bracket [a, b] of the sign
+ * change (a step that leaves it is replaced by the midpoint); it stops when a
+ * step is below 1e-13 or after 60 steps.  Along the line,
+ * dM/dq = sum_i -2 K_i ((x - x_i) . e_d) / r_i^4.
+ * READING (bit-exactness): every value is formed in the order written here,
+ * with no contraction; the GPU computes the same sequence. */
+static double exact_q(int n, const double* pts, const double* K, const double Xn[3],
+                      const int e[3], double c0, double Mn, double Ms)
+{
+    double a = 0.0, b = 1.0;
+    double q = (c0 - Mn) / (Ms - Mn);
+    int it, i;
+    for (it = 0; it < 60; ++it) {
+        double M = 0.0, dM = 0.0, g, qn;
+        for (i = 0; i < n; ++i) {
+            double dx = (Xn[0] + q * (double)e[0]) - pts[3 * i + 0];
+            double dy = (Xn[1] + q * (double)e[1]) - pts[3 * i + 1];
+            double dz = (Xn[2] + q * (double)e[2]) - pts[3 * i + 2];
+            double r2 = (dx * dx + dy * dy) + dz * dz;
+            double t = K[i] / r2;
+            double se = (dx * (double)e[0] + dy * (double)e[1]) + dz * (double)e[2];
+            M = M + t;
+            dM = dM - ((2.0 * t) * se) / r2;
+        }
+        g = M - c0;
+        if (g == 0.0) break;
+        if (g < 0.0)
+            a = q;
+        else
+            b = q;
+        qn = q - g / dM;
+        if (!(qn > a && qn < b)) qn = 0.5 * (a + b);
+        if (fabs(qn - q) < 1e-13) {
+            q = qn;
+            break;
+        }
+        q = qn;
+    }
+    return q;
+}
 
 /* Links in canonical order: particle, then solid node x_s, then direction d.
  *   x_n = x_s - e_d fluid           -> VIBB when x_ff = x_n - e_d is fluid and
@@ -371,7 +414,8 @@ enum { TREAT_VIBB = 1, TREAT_MISSING = 2 };
  *                                      Sec. 2.3.5);
  *   x_n beyond a wall, or solid of  -> MISSING (treatment 2, Sec. 2.3.5) when
  *   another particle                   M_j(x_n) < c0_j and treatment 2 is on.
- * q = (c0 - M(x_n)) / (M(x_s) - M(x_n)) for every kind (Eq. appq).
+ * q = (c0 - M(x_n)) / (M(x_s) - M(x_n)) for every kind (Eq. appq), or with
+ * treatment bit 4 the root of Eq. (calq) by exact_q.
  * Returns the number of links; entries beyond `cap` are not stored. */
 long ora_links(const int* dims, const int* per, int Q, int treat, int np, const int* off,
                const double* pts, const double* K, const double* c0, const double* xp,
@@ -432,7 +476,9 @@ long ora_links(const int* dims, const int* per, int Q, int treat, int np, const 
                     ld[count] = (int8_t)d;
                     lkind[count] = (int8_t)kind;
                     lpart[count] = p;
-                    lq[count] = (c0[p] - Mn) / (Ms - Mn);
+                    lq[count] = (treat & TREAT_EXACT_Q)
+                                    ? exact_q(n, P, Kp, Xn, s.e[d], c0[p], Mn, Ms)
+                                    : (c0[p] - Mn) / (Ms - Mn);
                 }
                 ++count;
             }

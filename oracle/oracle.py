@@ -29,7 +29,7 @@ BUILD = HERE / "_build"
 LIB = BUILD / "libmdlbm_oracle.so"
 
 KIND_VIBB, KIND_HALFWAY, KIND_MISSING = 0, 1, 2
-TREAT_VIBB, TREAT_MISSING = 1, 2
+TREAT_VIBB, TREAT_MISSING, TREAT_EXACT_Q = 1, 2, 4
 
 _lib = None
 

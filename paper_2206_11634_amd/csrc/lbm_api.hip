@@ -210,6 +210,8 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (!cfg || !bufs || !out) return fail(nullptr, LBM_EINVAL, "null argument");
     if (cfg->classify_mode < LBM_CLASSIFY_AUTO || cfg->classify_mode > LBM_CLASSIFY_BALLS)
         return fail(nullptr, LBM_EINVAL, "unknown classify_mode");
+    if (cfg->treatments & ~(LBM_TREAT_VIBB | LBM_TREAT_MISSING | LBM_TREAT_EXACT_Q))
+        return fail(nullptr, LBM_EINVAL, "unknown treatment bits");
     *out = nullptr;
     lbm_sizes sz;
     int rc = lbm_query_sizes(cfg, &sz);

@@ -499,6 +499,47 @@ __global__ __launch_bounds__(256) void k_finish(const uint32_t* own_prev, const 
     });
 }
 
+// q of Eq. (calq): the root of g(q) = M(x_n + q e_d) - c0 on [0, 1] (g(0) < 0
+// <= g(1)), by Newton-Raphson from the estimate of Eq. (appq), kept inside the
+// bracket of the sign change (a step that leaves it becomes the midpoint),
+// stopping on a step below 1e-13 or after 60 steps.  Along the line
+// dM/dq = sum_i -2 K_i ((x - x_i) . e_d) / r_i^4.  Every value is formed in
+// the order written (this file has no contraction), so any IEEE
+// implementation of the same sequence gets the same bits.
+__device__ double exact_q(const double* sp, int n, const double Xn[3], const int e[3], double c0,
+                          double Mn, double Ms)
+{
+    double a = 0.0, b = 1.0;
+    double q = (c0 - Mn) / (Ms - Mn);
+    for (int it = 0; it < 60; ++it) {
+        double M = 0.0, dM = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double dx = (Xn[0] + q * (double)e[0]) - sp[4 * i + 0];
+            const double dy = (Xn[1] + q * (double)e[1]) - sp[4 * i + 1];
+            const double dz = (Xn[2] + q * (double)e[2]) - sp[4 * i + 2];
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            const double t = sp[4 * i + 3] / r2;
+            const double se = (dx * (double)e[0] + dy * (double)e[1]) + dz * (double)e[2];
+            M = M + t;
+            dM = dM - ((2.0 * t) * se) / r2;
+        }
+        const double g = M - c0;
+        if (g == 0.0) break;
+        if (g < 0.0)
+            a = q;
+        else
+            b = q;
+        double qn = q - g / dM;
+        if (!(qn > a && qn < b)) qn = 0.5 * (a + b);
+        if (fabs(qn - q) < 1e-13) {
+            q = qn;
+            break;
+        }
+        q = qn;
+    }
+    return q;
+}
+
 // Position of the k-th (from 0) set bit of m; m has more than k set bits.
 __device__ __forceinline__ int select_bit(uint64_t m, uint32_t k)
 {
@@ -631,7 +672,13 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const dou
                     r.part = (uint16_t)p;
                     r.d = (uint8_t)d;
                     r.kind = (uint8_t)kind;
-                    r.q = (c0 - Mn) / (sMs - Mn);
+                    if (treat & LBM_TREAT_EXACT_Q) {
+                        const double Xn[3] = {sX - ex, sY - ey, sZ - ez};
+                        const int e[3] = {ex, ey, ez};
+                        r.q = exact_q(sp, n, Xn, e, c0, Mn, sMs);
+                    } else {
+                        r.q = (c0 - Mn) / (sMs - Mn);
+                    }
                     out[slot] = r;
                 }
             }

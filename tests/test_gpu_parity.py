@@ -113,7 +113,8 @@ def test_ragged_multi_tile_lattice_with_walls_and_missing_points():
     assert r["F"] < FORCE_TOL["f32"], r
 
 
-@pytest.mark.parametrize("treat", [B.TREAT_VIBB, B.TREAT_MISSING, 0])
+@pytest.mark.parametrize("treat", [B.TREAT_VIBB, B.TREAT_MISSING, 0,
+                                   B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_EXACT_Q])
 def test_treatment_switches(treat):
     lat, ps = W.tiny_case(5, dims=(28, 26, 18), periodic=(1, 1, 0), n_particles=3,
                           diameter_range=(5.0, 7.0), speed=0.06, spin=0.006, u0=(0.01, 0.0, 0.0))

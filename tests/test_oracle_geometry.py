@@ -195,3 +195,53 @@ def test_q_sphere_against_exact_crossing():
     errs = np.array(errs)
     assert np.all((L.q > 0) & (L.q <= 1))
     assert 0.005 < np.median(errs) < 0.1, np.median(errs)
+
+
+def test_exact_q_sphere_matches_the_quadratic_root():
+    """With treatment bit 4, q solves Eq. calq; for a sphere that root is the
+    smaller root of |x_n + q e - x_p|^2 = r^2 (r = sqrt(K / c0)), which the
+    Newton iteration must reach to rounding.  Links keep their kinds and
+    nodes; only q changes."""
+    sh = W.sphere_shape(15.0, 0.1)
+    lat = W.LatticeSpec(24, 24, 24, (1, 1, 1))
+    ps = W.make_particles([sh], [12.3, 11.8, 12.1], [1, 0, 0, 0], 1.0)
+    lin = O.Oracle(lat).classify(ps).links
+    ex = O.Oracle(lat, treat=O.TREAT_VIBB | O.TREAT_MISSING | O.TREAT_EXACT_Q).classify(ps).links
+    assert np.array_equal(lin.node, ex.node) and np.array_equal(lin.d, ex.d)
+    assert np.array_equal(lin.kind, ex.kind)
+    r = np.sqrt(sh.K[0] / sh.c0)
+    worst = 0.0
+    for l in range(len(ex)):
+        xs, d = ex.node[l], ex.d[l]
+        cs = np.array([xs % 24, (xs // 24) % 24, xs // 576], float)
+        e = np.array(E19[d], float)
+        xn = cs - e - ps.pos[0]
+        a, b, c = e @ e, 2 * xn @ e, xn @ xn - r * r
+        t = (-b - np.sqrt(b * b - 4 * a * c)) / (2 * a)
+        worst = max(worst, abs(ex.q[l] - t))
+    assert worst < 1e-12, worst
+    assert np.all((ex.q >= 0) & (ex.q <= 1))
+
+
+def test_exact_q_solves_calq_for_metaballs():
+    """For multi-point metaballs: M(x_n + q e) = c0 at the returned q (to a
+    relative 1e-12), and for bodies much larger than the lattice spacing the
+    linear estimate of Eq. appq differs from it by a few percent on average,
+    as the paper reports."""
+    lat, ps = W.tiny_case(6, dims=(44, 42, 40), periodic=(1, 1, 1), n_particles=2,
+                          diameter_range=(16.0, 20.0))
+    lin = O.Oracle(lat).classify(ps).links
+    ex = O.Oracle(lat, treat=O.TREAT_VIBB | O.TREAT_MISSING | O.TREAT_EXACT_Q).classify(ps).links
+    nx, ny = lat.nx, lat.ny
+    rel = []
+    for l in range(len(ex)):
+        p, xs, d = ex.part[l], ex.node[l], ex.d[l]
+        a, b = ps.ctrl_off[p], ps.ctrl_off[p + 1]
+        cs = [xs % nx, (xs // nx) % ny, xs // (nx * ny)]
+        Xs = np.array([_image(cs[ax], lat.dims[ax], lat.periodic[ax], ps.pos[p][ax])
+                       for ax in range(3)])
+        Xn = Xs - np.array(E19[d])
+        M = _M(ps.world_pts[a:b], ps.K[a:b], Xn + ex.q[l] * np.array(E19[d], float))
+        assert abs(M - ps.c0[p]) <= 1e-12 * ps.c0[p], (l, M, ps.c0[p])
+        rel.append(abs(lin.q[l] - ex.q[l]) / max(ex.q[l], 1e-3))
+    assert 0.003 < np.median(rel) < 0.1, np.median(rel)
