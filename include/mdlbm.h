@@ -60,9 +60,13 @@ typedef enum {
                              it every cut link uses halfway bounce-back */
     LBM_TREAT_MISSING = 2, /* treatment 2 of Sec. 2.3.5: momentum exchange on
                              force points covered by another body or a wall */
-    LBM_TREAT_EXACT_Q = 4 /* q as the root of Eq. (calq), M(x_n + q e_d) = c0, by a
+    LBM_TREAT_EXACT_Q = 4, /* q as the root of Eq. (calq), M(x_n + q e_d) = c0, by a
                              bracketed Newton iteration from the linear estimate,
                              instead of Eq. (appq) */
+    LBM_TREAT_NEQ_SPLIT = 8 /* for q > 1/2 the non-equilibrium part at x_d is taken
+                             from x_f alone, the case split Eq. (rhod) makes for the
+                             density, instead of extrapolating Eq. (neqd) with weights
+                             2q > 1 and 1 - 2q < 0; off: Eq. (neqd) for every q */
 } lbm_treatment;
 
 typedef enum {

@@ -363,7 +363,7 @@ void ora_classify(const int* dims, const int* per, int np, const int* off, const
 /* ------------------------------------------------------------------------ */
 
 enum { KIND_VIBB = 0, KIND_HALFWAY = 1, KIND_MISSING = 2 };
-enum { TREAT_VIBB = 1, TREAT_MISSING = 2, TREAT_EXACT_Q = 4 };
+enum { TREAT_VIBB = 1, TREAT_MISSING = 2, TREAT_EXACT_Q = 4, TREAT_NEQ_SPLIT = 8 };
 
 /* q of Eq. (calq): the root of g(q) = M(x_n + q e_d) - c0 on [0, 1], where
  * g(0) = M(x_n) - c0 < 0 <= g(1) = M(x_s) - c0.  Newton-Raphson from the
@@ -539,15 +539,22 @@ static void link_geometry(const grid_t* g, const stencil_t* s, long xs, int d, i
  *   u_d    = u*_d / 3 + 2 u**_d / 3.
  * READING: rho_f, u_f, rho_ff, u_ff are the moments at time t of the node's
  * populations and feq(x) = feq(rho(x), u(x)); rho_f in the moving-wall term is
- * the local density at x_f. */
+ * the local density at x_f.
+ * Option (treatment bit 8, `split`): for q > 1/2, fneq_d(x_d) = f+_d(x_f) -
+ * feq_d(x_f), the same case split that rho_d makes; without it the formula
+ * above extrapolates with weights 2q > 1 and 1-2q < 0 and, at tau near 1/2,
+ * a two-node gap between parallel faces amplifies the non-equilibrium part. */
 static double vibb(const stencil_t* s, int d, double q, double fd_f, double rho_f,
                    const double u_f[3], double fd_ff, double rho_ff, const double u_ff[3],
-                   const double uw[3])
+                   const double uw[3], int split)
 {
     double fneq, rho_d, us[3], uss[3], ud[3], eu;
     int a, db = s->opp[d];
-    fneq = 2.0 * q * (fd_f - feq(s, d, rho_f, u_f)) +
-           (1.0 - 2.0 * q) * (fd_ff - feq(s, d, rho_ff, u_ff));
+    if (split && q > 0.5)
+        fneq = fd_f - feq(s, d, rho_f, u_f);
+    else
+        fneq = 2.0 * q * (fd_f - feq(s, d, rho_f, u_f)) +
+               (1.0 - 2.0 * q) * (fd_ff - feq(s, d, rho_ff, u_ff));
     rho_d = (q <= 0.5) ? 2.0 * q * rho_f + (1.0 - 2.0 * q) * rho_ff : rho_f;
     for (a = 0; a < 3; ++a) {
         us[a] = (q <= 0.5) ? 2.0 * q * u_f[a] + (1.0 - 2.0 * q) * u_ff[a]
@@ -560,11 +567,11 @@ static double vibb(const stencil_t* s, int d, double q, double fd_f, double rho_
 }
 
 double ora_vibb(int Q, int d, double q, double fd_f, double rho_f, const double* u_f, double fd_ff,
-                double rho_ff, const double* u_ff, const double* uw)
+                double rho_ff, const double* u_ff, const double* uw, int treat)
 {
     stencil_t s;
     stencil_make(Q, &s);
-    return vibb(&s, d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw);
+    return vibb(&s, d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw, (treat & TREAT_NEQ_SPLIT) != 0);
 }
 
 /* Binary search of (node, d) among links [lo, hi) sorted by node then d. */
@@ -586,7 +593,7 @@ static long find_link(const int32_t* lnode, const int8_t* ld, long lo, long hi, 
  * collision of every fluid node into fout.  Domain walls use static halfway
  * bounce-back.  Populations of solid nodes are copied through unchanged.
  * Returns 0, or -1 when a solid source has no link. */
-int ora_step(const int* dims, const int* per, int Q, double tau, const double* Fb, double rho0,
+int ora_step(const int* dims, const int* per, int Q, int treat, double tau, const double* Fb, double rho0,
              const double* f, const int32_t* owner, long nl, const int32_t* lnode, const int8_t* ld,
              const int8_t* lkind, const int32_t* lpart, const double* lq, int np, const double* xp,
              const double* v, const double* w, double* fout, double* unk, double* Fh, double* Th)
@@ -616,7 +623,7 @@ int ora_step(const int* dims, const int* per, int Q, double tau, const double* F
                 xff = gidx(&g, cff);
                 moments_post(&s, f, g.N, xff, Fb, &rho_ff, u_ff);
                 unk[l] = vibb(&s, d, lq[l], fd_f, rho_f, u_f, f[(long)d * g.N + xff], rho_ff,
-                              u_ff, uw);
+                              u_ff, uw, (treat & TREAT_NEQ_SPLIT) != 0);
             } else {
                 /* treatment 1: halfway bounce-back with the moving-wall term */
                 int db = s.opp[d];
@@ -845,8 +852,19 @@ static void contact_force(const double* prm, double delta, const double n[3], co
 /* Metaball-metaball contact (Eqs. opt, grad, cp, k0, contactprop).  Solves
  * grad(M_i + M_j) = 0 by Newton-Raphson from the previous point or, for a new
  * pair, from the midpoint of the closest control-point pair; requires
- * ctol < M < 1 for both bodies there.  READING: the contact point is the
- * middle of the overlap, x_c_i - (R_si - delta/2) n. */
+ * M > ctol for both bodies there.  READING: the contact point is the middle
+ * of the overlap, x_c_i - (R_si - delta/2) n.
+ * READING (separation): at the stationary point grad M_i = -grad M_j, so the
+ * two projected surface points of Eq. cp lie on one line, whose direction
+ * n = (grad M_i - grad M_j)/|...| points from body j to body i.  The
+ * separation is the signed length (x_c_i - x_c_j).n: equal to the norm of
+ * Eq. contactprop while x_m is outside both internal bodies (the constraint
+ * M < 1 of Eq. opt), and negative once x_m has entered one of them, which
+ * happens before the bodies touch when two flat faces meet at an angle;
+ * dropping the contact there (the literal constraint) lets such bodies pass
+ * into each other.  A point whose overlap would exceed 2 (R_si + R_sj) is
+ * not a contact (a stationary point inside one body, where the projection
+ * of Eq. k0 does not hold). */
 static int pair_geometry(const double* prm, const mb_t* A, const mb_t* B, double rsA, double rsB,
                          const double* warm, int has_warm, double xm_out[3], double* delta,
                          double n[3], double xcp[3])
@@ -886,22 +904,23 @@ static int pair_geometry(const double* prm, const mb_t* A, const mb_t* B, double
     for (a = 0; a < 3; ++a) xm_out[a] = x[a];
     metaball_d2(A->n, A->pts, A->K, x, &MA, gA, HA);
     metaball_d2(B->n, B->pts, B->K, x, &MB, gB, HB);
-    if (!(MA > prm[P_CTOL] && MA < 1.0 && MB > prm[P_CTOL] && MB < 1.0)) return 0;
+    if (!(MA > prm[P_CTOL] && MB > prm[P_CTOL])) return 0;
     {
         double qA = (1.0 - MA) / dot3(gA, gA), qB = (1.0 - MB) / dot3(gB, gB);
-        double xa[3], xb[3], dd[3], dist;
+        double xa[3], xb[3], dd[3], u[3], un, sep;
         for (a = 0; a < 3; ++a) {
             xa[a] = x[a] + qA * gA[a];
             xb[a] = x[a] + qB * gB[a];
             dd[a] = xa[a] - xb[a];
+            u[a] = gA[a] - gB[a];
         }
-        dist = sqrt(dot3(dd, dd));
-        *delta = rsA + rsB - dist;
-        if (!(dist > 0.0)) return 0;
-        for (a = 0; a < 3; ++a) {
-            n[a] = dd[a] / dist;
-            xcp[a] = xa[a] - (rsA - 0.5 * (*delta)) * n[a];
-        }
+        un = sqrt(dot3(u, u));
+        if (!(un > 0.0)) return 0;
+        for (a = 0; a < 3; ++a) n[a] = u[a] / un;
+        sep = dot3(dd, n);
+        *delta = rsA + rsB - sep;
+        if (!(*delta <= 2.0 * (rsA + rsB))) return 0;
+        for (a = 0; a < 3; ++a) xcp[a] = xa[a] - (rsA - 0.5 * (*delta)) * n[a];
     }
     return 1;
 }

@@ -29,7 +29,7 @@ BUILD = HERE / "_build"
 LIB = BUILD / "libmdlbm_oracle.so"
 
 KIND_VIBB, KIND_HALFWAY, KIND_MISSING = 0, 1, 2
-TREAT_VIBB, TREAT_MISSING, TREAT_EXACT_Q = 1, 2, 4
+TREAT_VIBB, TREAT_MISSING, TREAT_EXACT_Q, TREAT_NEQ_SPLIT = 1, 2, 4, 8
 
 _lib = None
 
@@ -56,12 +56,13 @@ def lib():
         L.ora_metaball.argtypes = [ctypes.c_int, P, P, P]
         L.ora_vibb.restype = ctypes.c_double
         L.ora_vibb.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                               ctypes.c_double, P, ctypes.c_double, ctypes.c_double, P, P]
+                               ctypes.c_double, P, ctypes.c_double, ctypes.c_double, P, P,
+                               ctypes.c_int]
         L.ora_links.restype = ctypes.c_long
         L.ora_links.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P,
                                 ctypes.c_long, P, P, P, P, P]
         L.ora_step.restype = ctypes.c_int
-        L.ora_step.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, ctypes.c_double, P, P,
+        L.ora_step.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, P, ctypes.c_double, P, P,
                                ctypes.c_long, P, P, P, P, P, ctypes.c_int, P, P, P, P, P, P, P]
         L.ora_refill.restype = ctypes.c_long
         L.ora_refill.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, ctypes.c_double, P, P, P,
@@ -105,9 +106,9 @@ def metaball(pts, K, X) -> float:
     return lib().ora_metaball(len(K), _p(pts), _p(K), _p(X))
 
 
-def vibb(d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw, Q=19) -> float:
+def vibb(d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw, Q=19, treat=0) -> float:
     return lib().ora_vibb(Q, d, q, fd_f, rho_f, _p(_c(u_f, np.float64)), fd_ff, rho_ff,
-                          _p(_c(u_ff, np.float64)), _p(_c(uw, np.float64)))
+                          _p(_c(u_ff, np.float64)), _p(_c(uw, np.float64)), int(treat))
 
 
 def num_threads() -> int:
@@ -224,7 +225,8 @@ class Oracle:
         unk = np.zeros(max(nl, 1))
         F = np.zeros((ps.n, 3))
         T = np.zeros((ps.n, 3))
-        rc = lib().ora_step(_p(self.dims), _p(self.per), self.Q, self.tau, _p(self.Fb), self.rho0,
+        rc = lib().ora_step(_p(self.dims), _p(self.per), self.Q, self.treat, self.tau, _p(self.Fb),
+                            self.rho0,
                             _p(self.f), _p(self.owner), nl, _p(L.node), _p(L.d), _p(L.kind),
                             _p(L.part), _p(L.q), ps.n, _p(_c(ps.pos, np.float64)),
                             _p(_c(ps.vel, np.float64)), _p(_c(ps.omega, np.float64)), _p(fout),

@@ -32,6 +32,7 @@ class Problem:
     storage: str = "f32"
     weights: np.ndarray = None  # [n][6]: (wF, wT) per particle per step
     f0: np.ndarray = None       # [19][ncell] initial populations
+    treatments: int = B.TREAT_VIBB | B.TREAT_MISSING
 
     def __post_init__(self):
         if self.weights is None:
@@ -61,7 +62,8 @@ class _Run:
         self.vel = np.asarray(vel, float).reshape(prob.ps.n, 3)
         lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
                                   tau=float(tau))
-        self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage)
+        self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage,
+                                           treatments=prob.treatments)
         # every state on the device: poses of the nominal trajectory, velocity v
         self.traj = B.DeviceTrajectory(prob.states(), vel=self.vel)
 

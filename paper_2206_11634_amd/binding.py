@@ -21,7 +21,7 @@ Q = 19
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ECAPACITY, LBM_ENUMERIC, LBM_EDEVICE, LBM_ESTATE = range(7)
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
-TREAT_VIBB, TREAT_MISSING, TREAT_EXACT_Q = 1, 2, 4
+TREAT_VIBB, TREAT_MISSING, TREAT_EXACT_Q, TREAT_NEQ_SPLIT = 1, 2, 4, 8
 LINK_VIBB, LINK_HALFWAY, LINK_MISSING = 0, 1, 2
 
 _P = ctypes.c_void_p

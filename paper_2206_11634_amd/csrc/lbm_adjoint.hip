@@ -111,14 +111,16 @@ __device__ __forceinline__ T eq_t(int d, const int e[3], const T& rho, const T u
 // halfway bounce-back), written for a generic scalar.
 template <bool DEV, class A, class T>
 __device__ T link_value(int kind, int d, const int e[3], A q, const T& fdf, const T& rf,
-                        const T* uf, const T& fdff, const T& rff, const T* uff, const T* uw)
+                        const T* uf, const T& fdff, const T& rff, const T* uff, const T* uw,
+                        bool neq_split)
 {
     const T ebu = T(A(-e[0])) * uw[0] + T(A(-e[1])) * uw[1] + T(A(-e[2])) * uw[2];
     const T mw = T(A(6) * W<A>(d)) * rf * ebu;
     if (kind != LBM_LINK_VIBB) return fdf + mw;
     const A tq = A(2) * q, oq = A(1) - A(2) * q;
-    const T fneq = T(tq) * (fdf - eq_t<DEV, A>(d, e, rf, uf)) +
-                   T(oq) * (fdff - eq_t<DEV, A>(d, e, rff, uff));
+    const bool hold = neq_split && q > A(0.5);
+    const T fneq = T(hold ? A(1) : tq) * (fdf - eq_t<DEV, A>(d, e, rf, uf)) +
+                   T(hold ? A(0) : oq) * (fdff - eq_t<DEV, A>(d, e, rff, uff));
     const T rd = (q <= A(0.5)) ? T(tq) * rf + T(oq) * rff : rf;
     T ud[3];
 #pragma unroll
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
             D13 x_uw[3] = {var<A, 13>(A(uw[0]), 10), var<A, 13>(A(uw[1]), 11),
                            var<A, 13>(A(uw[2]), 12)};
             const D13 unk = link_value<DEV, A>(r.kind, d, e, A(r.q), x_fdf, x_rf, x_uf, x_fdff,
-                                               x_rff, x_uff, x_uw);
+                                               x_rff, x_uff, x_uw, ph.neq_split != 0);
             // momentum exchange of this link: [(e_d - u_w) out - (e_db - u_w) in] . W
             double out = (double)fdf, in = (double)unk.v;
             if constexpr (DEV) {

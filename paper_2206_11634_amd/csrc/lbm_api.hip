@@ -210,7 +210,8 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (!cfg || !bufs || !out) return fail(nullptr, LBM_EINVAL, "null argument");
     if (cfg->classify_mode < LBM_CLASSIFY_AUTO || cfg->classify_mode > LBM_CLASSIFY_BALLS)
         return fail(nullptr, LBM_EINVAL, "unknown classify_mode");
-    if (cfg->treatments & ~(LBM_TREAT_VIBB | LBM_TREAT_MISSING | LBM_TREAT_EXACT_Q))
+    if (cfg->treatments &
+        ~(LBM_TREAT_VIBB | LBM_TREAT_MISSING | LBM_TREAT_EXACT_Q | LBM_TREAT_NEQ_SPLIT))
         return fail(nullptr, LBM_EINVAL, "unknown treatment bits");
     *out = nullptr;
     lbm_sizes sz;
@@ -257,6 +258,7 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         ph.scale = 1.0f;
     }
     ph.inv_scale = 1.0f / ph.scale;
+    ph.neq_split = (cfg->treatments & LBM_TREAT_NEQ_SPLIT) ? 1 : 0;
     const int h = std::max(cfg->box_half, 2);
     c->box.h = h;
     c->box.S = 2 * h + 1;

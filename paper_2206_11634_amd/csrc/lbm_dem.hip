@@ -288,31 +288,43 @@ __device__ __forceinline__ void pair_contact(const BA& A, const BB& B, double x[
     }
     A.eval(z3, x, MA, gA, HA);
     B.eval(sh, x, MB, gB, HB);
-    if (!(MA > c.ctol && MA < 1.0 && MB > c.ctol && MB < 1.0)) {
+    // both bodies' fields above ctol at the stationary point (Eq. opt); the
+    // separation is signed along the common line of the two projections of
+    // Eq. cp, n = (grad M_i - grad M_j)/|.| from body j to body i, so that a
+    // stationary point already inside one internal body (two flat faces
+    // meeting at an angle) reads as an overlap rather than as no contact;
+    // overlaps beyond 2 (R_si + R_sj) are stationary points inside a body,
+    // where the projection of Eq. k0 does not hold, and are not contacts
+    if (!(MA > c.ctol && MB > c.ctol)) {
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
     const double qA = (1.0 - MA) / dot3(gA, gA), qB = (1.0 - MB) / dot3(gB, gB);
-    double xa[3], dd[3];
+    double xa[3], dd[3], n[3];
     for (int a = 0; a < 3; ++a) {
         xa[a] = x[a] + qA * gA[a];
         dd[a] = xa[a] - (x[a] + qB * gB[a]);
+        n[a] = gA[a] - gB[a];
     }
-    const double dist = sqrt(dot3(dd, dd));
-    h[0] = 1.0;
-    for (int a = 0; a < 3; ++a) h[4 + a] = x[a] - xi[a];
-    if (!(dist > 0.0)) {
+    const double un = sqrt(dot3(n, n));
+    if (!(un > 0.0)) {
         for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
     }
-    const double delta = rsi + rsj - dist;
+    for (int a = 0; a < 3; ++a) n[a] = n[a] / un;
+    const double delta = rsi + rsj - dot3(dd, n);
+    if (!(delta <= 2.0 * (rsi + rsj))) {
+        for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+        return;
+    }
+    h[0] = 1.0;
+    for (int a = 0; a < 3; ++a) h[4 + a] = x[a] - xi[a];
     if (delta <= 0.0) {
         h[1] = h[2] = h[3] = 0.0;
         return;
     }
-    double n[3], xcp[3], ra[3], rb[3];
+    double xcp[3], ra[3], rb[3];
     for (int a = 0; a < 3; ++a) {
-        n[a] = dd[a] / dist;
         xcp[a] = xa[a] - (rsi - 0.5 * delta) * n[a];
         ra[a] = xcp[a] - xi[a];
         rb[a] = xcp[a] - (xj[a] + sh[a]);

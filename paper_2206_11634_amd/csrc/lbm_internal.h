@@ -95,6 +95,7 @@ struct Phys {
     float omegaf;
     float Ff[3];
     float scale, inv_scale;  // FP16 deviation scale
+    int neq_split;           // VIBB: fneq(x_d) = fneq(x_f) for q > 1/2 (treatment bit 8)
 };
 
 // Device pointers of the particle state (a copy of lbm_particles).

@@ -165,9 +165,12 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
                 const A rff = A(1) + drff;
                 const A q = A(r.q);
                 const A tq = A(2) * q, oq = A(1) - A(2) * q;
-                // non-equilibrium part extrapolated to x_d (Eq. neqd)
-                const A fneq = tq * (fdf - eq_i<DEV, A>(d, drf, rf, uf[0], uf[1], uf[2])) +
-                               oq * (fdff - eq_i<DEV, A>(d, drff, rff, uff[0], uff[1], uff[2]));
+                // non-equilibrium part extrapolated to x_d (Eq. neqd), or for
+                // q > 1/2 under treatment bit 8 held at its x_f value
+                const bool hold = ph.neq_split && q > A(0.5);
+                const A fneq = (hold ? A(1) : tq) * (fdf - eq_i<DEV, A>(d, drf, rf, uf[0], uf[1], uf[2])) +
+                               (hold ? A(0) : oq) *
+                                   (fdff - eq_i<DEV, A>(d, drff, rff, uff[0], uff[1], uff[2]));
                 // density at x_d (Eq. rhod)
                 A drd, rd;
                 if (q <= A(0.5)) {

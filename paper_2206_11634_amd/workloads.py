@@ -514,6 +514,43 @@ def config_c5(seed: int = 5, n: int = 128):
     return lat, ps, meta
 
 
+def square_metaball(d_eq: float = 14.65, rs: float = 0.1) -> Shape:
+    """Flat metaball whose four control points form a square with equal
+    weights (K = 0.6 on a unit square, for which the internal body's bounding
+    box has a thickness-to-length ratio of 0.845; the paper's shape has
+    0.84375), scaled to the volume-equivalent diameter d_eq.  The body frame's
+    third axis is the square's normal."""
+    pts = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 1, 0], [1.0, 1, 0]])
+    return metaball_shape(pts, np.full(4, 0.6), rs, d_eq=d_eq, samples_per_unit=3.0)
+
+
+def config_dkt(shape: str = "metaball", tau: float | None = None):
+    """Two bodies settling one above the other in a closed 150x150x250 box,
+    the setting of the paper's two-metaball example (Sec. 4): flat square
+    metaballs of the volume of the paper's printed particle (1648 lu^3,
+    d_eq = 14.65) or volume-equivalent spheres, centres at heights 220 and
+    205 with the lower one 2 lu off the centreline, the squares horizontal;
+    density ratio 1200/927; nu = 7.55e-5 m^2/s at dx = 1 mm, dt = 0.2 ms
+    (tau = 0.5453); gravity 9.8 m/s^2 = 3.92e-4 lu/step^2; 10 DEM substeps
+    per lattice step (dt_DEM = 2e-6 s would be 100).
+
+    The flat faces start 2.3 lu apart, two fluid nodes across.  There, at
+    this tau, the VIBB non-equilibrium extrapolation for q > 1/2 grows
+    without bound within ~80 steps (FP64 as FP32), so the metaball case
+    carries treatment bit 8, which holds that part at its x_f value; the
+    spheres run with the reconstruction as printed."""
+    if tau is None:
+        tau = 0.5 + 3.0 * 7.55e-5 * 2e-4 / 1e-6
+    lat = LatticeSpec(150, 150, 250, (0, 0, 0), tau=tau)
+    sh = square_metaball() if shape == "metaball" else sphere_shape(14.65, 0.1)
+    ps = make_particles([sh, sh], [[75.0, 75.0, 220.0], [77.0, 75.0, 205.0]],
+                        [[1.0, 0, 0, 0], [1.0, 0, 0, 0]], 1200.0 / 927.0)
+    meta = dict(name=f"dkt_{shape}_150x150x250", steps=7000, storage="f32",
+                rho_r=1200.0 / 927.0, gravity=(0.0, 0.0, -3.92e-4), n_sub=10,
+                treatments=11 if shape == "metaball" else 3)
+    return lat, ps, meta
+
+
 def tiny_case(seed: int, dims=(16, 14, 12), periodic=(1, 0, 1), n_particles=3,
               diameter_range=(3.0, 6.0), tau=0.7, u0=(0.0, 0.0, 0.0),
               speed=0.0, spin=0.0, body_force=(0.0, 0.0, 0.0), allow_near=True):
@@ -567,6 +604,8 @@ WORKLOADS = {
     "c3": config_c3,
     "c4": config_c4,
     "c5": config_c5,
+    "dkt_metaball": lambda: config_dkt("metaball"),
+    "dkt_sphere": lambda: config_dkt("sphere"),
 }
 
 

@@ -76,7 +76,7 @@ def test_init_rejects_unknown_treatment_bits(lib):
     bufs = B.LbmBuffers()
     ctx = ctypes.c_void_p()
     cfg = _cfg()
-    cfg.treatments = 8
+    cfg.treatments = 16
     assert lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)) == B.LBM_EINVAL
     assert b"treatment" in lib.lbm_last_error(None)
 

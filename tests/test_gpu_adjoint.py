@@ -8,6 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2206_11634_amd import adjoint as AD
+from paper_2206_11634_amd import binding as B
 from paper_2206_11634_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -74,6 +75,14 @@ def _check(prob, fd_prob, fn, rtol):
 
 def test_fp64_adjoint_matches_finite_differences():
     prob = _problem("f64")
+    _check(prob, prob, _gpu_J, 2e-6)
+
+
+def test_fp64_adjoint_with_neq_split_matches_finite_differences():
+    """Treatment bit 8 changes the VIBB reconstruction for q > 1/2; its
+    transpose in the link adjoint follows."""
+    prob = dataclasses.replace(_problem("f64"),
+                               treatments=B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_NEQ_SPLIT)
     _check(prob, prob, _gpu_J, 2e-6)
 
 

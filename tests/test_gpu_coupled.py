@@ -1,0 +1,98 @@
+"""The coupled loop with free particle motion (classify -> step -> forces ->
+DEM, the loop the benchmark times), and the two-body settling workloads of the
+paper's Sec. 4 (drafting, kissing and tumbling, DKT): two flat square
+metaballs and two volume-equivalent spheres in a closed 150x150x250 box.
+
+The FP64 GPU loop is compared with the oracle's own coupled loop (each side
+feeds its own forces to its own DEM; no value crosses between them).  The
+FP32 DKT runs are physics regressions with properties of the known dynamics."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2206_11634_amd import binding as B
+from paper_2206_11634_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape", ["metaball", "sphere"])
+def test_coupled_loop_fp64_matches_oracle(shape):
+    """30 coupled steps of the settling pair at full size (150x150x250, two
+    bodies, 10 DEM substeps per step, the workload's treatments): forces every
+    step within 1e-9 of the largest, poses and velocities at the end within
+    1e-10."""
+    lat, ps, meta = W.config_dkt(shape)
+    kw = W.dem_defaults(ps, gravity=meta["gravity"])
+    steps, n_sub, treat = 30, meta["n_sub"], meta["treatments"]
+    print(f"coupled fp64 {meta['name']} treat {treat}", flush=True)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64", treatments=treat)
+    parts = B.DeviceParticles(ps)
+    ora, dem = O.Oracle(lat, treat=treat), O.OracleDEM(ps, lat)
+    P = ps.copy()
+    Fg, Fo = [], []
+    gpu.classify(parts)
+    for n in range(steps):
+        ora.classify(P)
+        F, T = ora.step(P)
+        Fo.append(np.concatenate([F, T], 1))
+        dem.step(P, F, T, O.DemParams(**kw), n_sub, 1.0 / n_sub)
+        gpu.step(parts)
+        Fh, Th = gpu.forces()
+        Fg.append(np.concatenate([Fh.cpu().numpy(), Th.cpu().numpy()], 1))
+        gpu.dem(parts, n_sub, 1.0 / n_sub, B.DemParams.make(**kw))
+        gpu.classify(parts)
+    G = parts.to_host(ps)
+    gpu.close()
+    Fg, Fo = np.array(Fg), np.array(Fo)
+    assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max()
+    for k in ("pos", "vel", "omega", "quat"):
+        assert np.abs(getattr(G, k) - getattr(P, k)).max() <= 1e-10, k
+    assert np.abs(P.vel[:, 2]).max() > 1e-3   # the pair has started to fall
+
+
+def _settle(shape, steps, every=50):
+    lat, ps, meta = W.config_dkt(shape)
+    print(f"settle fp32 {meta['name']} treat {meta['treatments']} steps {steps}", flush=True)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32", treatments=meta["treatments"])
+    parts = B.DeviceParticles(ps)
+    prm = B.DemParams.make(**W.dem_defaults(ps, gravity=meta["gravity"]))
+    gpu.classify(parts)
+    hist = []
+    for n in range(1, steps + 1):
+        gpu.step(parts)
+        gpu.forces()
+        gpu.dem(parts, meta["n_sub"], 1.0 / meta["n_sub"], prm)
+        gpu.classify(parts)
+        if n % every == 0:
+            P = parts.to_host(ps)
+            hist.append(np.concatenate([P.pos.ravel(), P.vel.ravel()]))
+    gpu.close()
+    h = np.array(hist)
+    return h[:, 0:6].reshape(-1, 2, 3), h[:, 6:12].reshape(-1, 2, 3)
+
+
+def test_dkt_spheres_draft_kiss_and_tumble():
+    """Volume-equivalent spheres at the paper's parameters: the trailing
+    sphere (starting 15 lu above) falls faster in the leader's wake, closes to
+    near contact, and the pair tumbles (the trailing sphere ends below)."""
+    pos, vel = _settle("sphere", 6000)
+    assert np.all(np.isfinite(pos)) and np.all(np.isfinite(vel))
+    d = np.linalg.norm(pos[:, 0] - pos[:, 1], axis=1)
+    assert (vel[:, 0, 2] < 1.05 * vel[:, 1, 2]).any()          # drafting
+    assert d.min() < 14.65 + 1.5                                # kissing
+    assert pos[-1, 0, 2] < pos[-1, 1, 2]                        # tumbling
+    assert vel[-1, :, 2].max() < -0.02                          # both still settling
+
+
+def test_dkt_metaballs_draft_kiss_and_tumble():
+    """The paper's flat square metaballs at its tau (0.5453, with treatment
+    bit 8): drafting, a close approach, the trailing body passing below, both
+    still settling after 6000 steps (1.2 s)."""
+    pos, vel = _settle("metaball", 6000)
+    assert np.all(np.isfinite(pos)) and np.all(np.isfinite(vel))
+    d = np.linalg.norm(pos[:, 0] - pos[:, 1], axis=1)
+    assert (vel[:, 0, 2] < 1.05 * vel[:, 1, 2]).any()
+    assert d.min() < 16.0
+    assert pos[-1, 0, 2] < pos[-1, 1, 2]
+    assert vel[-1, :, 2].max() < -0.02

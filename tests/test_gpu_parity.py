@@ -114,7 +114,8 @@ def test_ragged_multi_tile_lattice_with_walls_and_missing_points():
 
 
 @pytest.mark.parametrize("treat", [B.TREAT_VIBB, B.TREAT_MISSING, 0,
-                                   B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_EXACT_Q])
+                                   B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_EXACT_Q,
+                                   B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_NEQ_SPLIT])
 def test_treatment_switches(treat):
     lat, ps = W.tiny_case(5, dims=(28, 26, 18), periodic=(1, 1, 0), n_particles=3,
                           diameter_range=(5.0, 7.0), speed=0.06, spin=0.006, u0=(0.01, 0.0, 0.0))
@@ -189,5 +190,34 @@ def test_dem_parity_with_contacts():
     gpu.close()
     assert np.abs(dem.fc).max() > 0 or np.abs(P.vel - ps.vel).max() > 1e-3
     for k in ("pos", "vel", "omega", "quat", "world_pts"):
+        a, b = getattr(G, k), getattr(P, k)
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
+
+
+@pytest.mark.parametrize("ang", [0.0, 0.6])
+def test_dem_parity_tilted_flat_pair(ang):
+    """Flat square metaballs meeting face to face and at an angle (the
+    stationary point of M_A + M_B enters one internal body before contact):
+    1500 DEM steps through approach, contact and rebound."""
+    lat = W.LatticeSpec(150, 150, 250, (0, 0, 0))
+    sh = W.square_metaball()
+    ps = W.make_particles([sh, sh], [[75.0, 75.0, 120.0], [79.0, 75.0, 104.5]],
+                          [[1.0, 0, 0, 0], [np.cos(ang / 2), 0, np.sin(ang / 2), 0]], 1.3,
+                          vel=np.array([[0, 0, -0.005], [0, 0, 0]]))
+    kw = W.dem_defaults(ps)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    parts = B.DeviceParticles(ps)
+    dem = O.OracleDEM(ps, lat)
+    P = ps.copy()
+    Fh = np.zeros((2, 3))
+    touched = False
+    for n in range(1500):
+        gpu.dem(parts, 10, 0.1, B.DemParams.make(**kw))
+        dem.step(P, Fh, Fh, O.DemParams(**kw), 10, 0.1)
+        touched |= bool(np.abs(dem.fc).max() > 0)
+    G = parts.to_host(ps)
+    gpu.close()
+    assert touched
+    for k in ("pos", "vel", "omega", "quat"):
         a, b = getattr(G, k), getattr(P, k)
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k

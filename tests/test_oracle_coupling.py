@@ -56,6 +56,68 @@ def test_vibb_matches_geometric_interpolation():
         assert abs(got - expect) < 1e-14, (d, q)
 
 
+def test_vibb_neq_split_is_zeroth_order_beyond_x_f():
+    """With treatment bit 8 the departure point's non-equilibrium part for
+    x_d beyond x_f (q > 1/2) is held at its x_f value, as rho_d already is;
+    for q <= 1/2 nothing changes, and the value no longer depends on f at x_ff."""
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        d = int(rng.integers(1, 19))
+        db = d + 1 if d % 2 == 1 else d - 1
+        q = float(rng.uniform(0.01, 1.0))
+        rho_f, rho_ff = rng.uniform(0.95, 1.05, 2)
+        u_f, u_ff, uw = (rng.uniform(-0.05, 0.05, 3) for _ in range(3))
+        fd_f = _feq(d, rho_f, u_f) * (1 + 0.01 * rng.standard_normal())
+        fd_ff = _feq(d, rho_ff, u_ff) * (1 + 0.01 * rng.standard_normal())
+        lit = O.vibb(d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw)
+        got = O.vibb(d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw, treat=O.TREAT_NEQ_SPLIT)
+        if q <= 0.5:
+            assert got == lit
+            continue
+        xd = 2 * q - 1
+        ustar = np.array([np.interp(xd, [0, q], [u_f[a], uw[a]]) for a in range(3)])
+        u2 = np.array([np.interp(xd, [-1, q], [u_ff[a], uw[a]]) for a in range(3)])
+        expect = (_feq(d, rho_f, ustar / 3 + 2 * u2 / 3) + fd_f - _feq(d, rho_f, u_f)
+                  + 6 * W19[d] * rho_f * (E19[db] @ uw))
+        assert abs(got - expect) < 1e-14, (d, q)
+        moved = O.vibb(d, q, fd_f, rho_f, u_f, 2 * fd_ff, rho_ff, u_ff, uw,
+                       treat=O.TREAT_NEQ_SPLIT)
+        assert moved == got
+
+
+def _flat_pair_gap(treat, steps):
+    """Two square metaballs (d_eq 14.65, faces horizontal, half-thickness
+    6.35) 15 lu apart settle side by side in a closed 48x48x80 box at
+    tau = 0.5453: about two fluid nodes separate the parallel faces."""
+    lat = W.LatticeSpec(48, 48, 80, (0, 0, 0), tau=0.5453)
+    sh = W.square_metaball()
+    ps = W.make_particles([sh, sh], [[24.0, 24.0, 55.0], [26.0, 24.0, 40.0]],
+                          [[1.0, 0, 0, 0]] * 2, 1200 / 927)
+    kw = W.dem_defaults(ps, gravity=(0, 0, -3.92e-4))
+    o, dem = O.Oracle(lat, treat=treat), O.OracleDEM(ps, lat)
+    umax = 0.0
+    for _ in range(steps):
+        o.classify(ps)
+        F, T = o.step(ps)
+        dem.step(ps, F, T, O.DemParams(**kw), 10, 0.1)
+        rho, u = o.moments()
+        umax = float(np.abs(u[o.owner == 0]).max())
+        if not np.isfinite(umax) or umax > 0.1:
+            break
+    return umax
+
+
+def test_neq_extrapolation_in_a_two_node_gap():
+    """Eq. (neqd) as printed extrapolates for q > 1/2 with weights up to 2 and
+    -1; between the two flat faces at tau near 1/2 that grows without bound
+    within 80 steps (the bodies have fallen 0.2 lu).  Holding the
+    non-equilibrium part at x_f (treatment bit 8) keeps the same flow bounded
+    by the settling speed."""
+    base = O.TREAT_VIBB | O.TREAT_MISSING
+    assert _flat_pair_gap(base, 90) > 0.1
+    assert _flat_pair_gap(base | O.TREAT_NEQ_SPLIT, 150) < 0.01
+
+
 def test_comoving_particles_leave_uniform_flow_exact():
     """Uniform flow f = feq(1, U) with particles translating at U: VIBB, the
     moving-wall bounce-back and both refilling rules return feq(1, U), so the

@@ -148,3 +148,68 @@ def test_metaball_pair_contact_is_symmetric():
         assert np.abs(P).max() < 1e-12
         touched |= bool(np.abs(dem.fc).max() > 0)
     assert touched
+
+
+def test_unequal_spheres_overlap_follows_the_projection_through_internal_contact():
+    """Two sphero-spheres of internal radii a = 4 and b = 2 (K = a^2, b^2).  On
+    the centre line the stationary point of M_A + M_B sits where
+    K_A / rho_A^3 = K_B / rho_B^3, and the projection of Eq. k0 moves it by
+    (1 - K/rho^2) rho^3 / (2K) towards each centre, so the overlap is
+    R_sA + R_sB - s_A - s_B in closed form.  The stationary point enters the
+    larger internal sphere (rho_A < a) before the internal spheres touch;
+    the force must follow the closed form there too (the signed separation)
+    and grow monotonically as the centres approach."""
+    lat = W.LatticeSpec(64, 64, 64, (1, 1, 1))
+    rs = 0.25
+    a, b = 4.0, 2.0
+    shs = [W.sphere_shape(2 * (a + rs), rs), W.sphere_shape(2 * (b + rs), rs)]
+    kn = 2.0
+    prm = O.DemParams(kn=kn, eta_n=0.0, kt=1.0, eta_t=0.0, mu_s=0.3, newton_iter=60)
+    r = (a * a / (b * b)) ** (1.0 / 3.0)
+    seen_inside, last = False, 0.0
+    for d in np.linspace(a + b + 0.45, a + b - 0.2, 14):
+        ps = W.make_particles(shs, [[30.0, 32.0, 32.0], [30.0 + d, 32.0, 32.0]],
+                              [[1, 0, 0, 0], [1, 0, 0, 0]], 1.5)
+        dem = _dem(ps, lat)
+        z = np.zeros((2, 3))
+        dem.step(ps, z, z, prm, n_sub=1, dt=1e-9)
+        rho_a = d * r / (1 + r)
+        rho_b = d - rho_a
+        s_a = (1 - a * a / rho_a ** 2) * rho_a ** 3 / (2 * a * a)
+        s_b = (1 - b * b / rho_b ** 2) * rho_b ** 3 / (2 * b * b)
+        delta = 2 * rs - s_a - s_b
+        seen_inside |= rho_a < a
+        f = -dem.fc[0, 0]
+        assert abs(dem.fc[0, 1]) < 1e-12 and abs(dem.fc[0, 2]) < 1e-12
+        if delta <= 0:
+            assert f == 0.0, d
+            continue
+        assert abs(f - kn * delta) < 1e-9 * kn, (d, f, kn * delta)
+        assert f > last
+        last = f
+    assert seen_inside and last > 0
+
+
+def test_tilted_flat_metaballs_collide_and_separate():
+    """Two flat square metaballs, the lower tilted 0.6 rad and 4 lu off axis,
+    approach at 0.005 lu/step.  Their gap is a wedge; the stationary point
+    of M_A + M_B enters one internal body before the faces touch.  The
+    contact is found, momentum is conserved, and the bodies separate."""
+    lat = W.LatticeSpec(150, 150, 250, (0, 0, 0))
+    sh = W.square_metaball()
+    ang = 0.6
+    ps = W.make_particles([sh, sh], [[75.0, 75.0, 120.0], [79.0, 75.0, 104.5]],
+                          [[1.0, 0, 0, 0], [np.cos(ang / 2), 0, np.sin(ang / 2), 0]], 1.3,
+                          vel=np.array([[0, 0, -0.005], [0, 0, 0]]))
+    kw = W.dem_defaults(ps)
+    dem = _dem(ps, lat)
+    p0 = (ps.mass[:, None] * ps.vel).sum(0)
+    z = np.zeros((2, 3))
+    touched = 0
+    for _ in range(1500):
+        dem.step(ps, z, z, O.DemParams(**kw), 10, 0.1)
+        touched += bool(np.abs(dem.fc).max() > 0)
+        assert np.abs((ps.mass[:, None] * ps.vel).sum(0) - p0).max() < 1e-12
+    assert touched > 10
+    assert ps.vel[0, 2] > ps.vel[1, 2]           # moving apart along the line of approach
+    assert ps.pos[0, 2] - ps.pos[1, 2] > 12.0    # flat faces never passed into each other
