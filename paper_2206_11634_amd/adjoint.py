@@ -11,6 +11,13 @@ gradient with respect to v, the fluid body force F and the relaxation time
 tau comes from the library's adjoint, run backwards window by window with
 checkpoints every `window` steps and recomputation inside each window.
 
+With geometry=True the adjoint also returns dJ/dx_p of every pose of the
+trajectory (the link set, owners and refill sets held fixed; q, the wall
+points and the lever arms move with the body), from which follow the
+derivatives with respect to the initial positions (the sum over poses) and
+the full derivative with respect to a velocity that drives both the poses
+and the wall velocities (dJ/dv plus the sum of k times the pose gradient).
+
 `DragFunction` wraps this as a torch.autograd.Function of (v, F, tau).
 """
 from __future__ import annotations
@@ -94,39 +101,57 @@ def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
     return J, run
 
 
-def backward(run: _Run, stats: dict | None = None):
+def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     """(dJ/dv [n][3], dJ/dF [3], dJ/dtau) by the adjoint, window by window from
-    the last checkpoint to the first, recomputing each window's steps.  With
-    a dict for stats, the library's per-phase timers are read into it."""
+    the last checkpoint to the first, recomputing each window's steps; with
+    geometry, also dJ/dx_p of every pose [T + 1][n][3].  With a dict for
+    stats, the library's per-phase timers are read into it."""
     prob, gpu = run.prob, run.gpu
     torch = gpu.torch
     if stats is not None:
         gpu.profile(True)
     lam = gpu.adjoint_field()
-    g = torch.zeros(4 + 3 * prob.ps.n, dtype=torch.float64, device=gpu.device)
+    n = prob.ps.n
+    g = torch.zeros(4 + 3 * n, dtype=torch.float64, device=gpu.device)
+    gx = (torch.zeros((prob.steps + 1, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
+          if geometry else None)
     for w0 in sorted(run.ckpt, reverse=True):
         w1 = min(w0 + prob.window, prob.steps)
         gpu.restore(run.ckpt[w0])
         gpu.classify(run.parts(w0))   # reproduces the geometry at w0, refills nothing
         gpu.tape_begin(w1 - w0)
-        for n in range(w0, w1):
-            gpu.step(run.parts(n))
-            gpu.classify(run.parts(n + 1))
-        gpu.adjoint(run.parts(w1), prob.weights, lam, g)
+        for k in range(w0, w1):
+            gpu.step(run.parts(k))
+            gpu.classify(run.parts(k + 1))
+        # poses w0 .. w1 of this window: a contiguous view of gx
+        gpu.adjoint(run.parts(w1), prob.weights, lam, g,
+                    None if gx is None else gx[w0:w1 + 1])
     out = g.cpu().numpy()
     if stats is not None:
         stats.update(gpu.profile_read())
         gpu.profile(False)
     gpu.close()
-    return out[4:].reshape(prob.ps.n, 3), out[:3].copy(), float(out[3])
+    res = (out[4:].reshape(n, 3), out[:3].copy(), float(out[3]))
+    if geometry:
+        res = res + (gx[:, :n].cpu().numpy(),)
+    return res
 
 
-def evaluate(prob: Problem, vel, body_force, tau, grad: bool = False):
-    """J, and with grad=True also (dJ/dv [n][3], dJ/dF [3], dJ/dtau)."""
+def evaluate(prob: Problem, vel, body_force, tau, grad: bool = False, geometry: bool = False):
+    """J, and with grad=True also (dJ/dv [n][3], dJ/dF [3], dJ/dtau), and with
+    geometry=True also dJ/dx_p of every pose [T + 1][n][3]."""
     J, run = forward(prob, vel, body_force, tau, keep=grad)
     if not grad:
         return J
-    return (J,) + backward(run)
+    return (J,) + backward(run, geometry=geometry)
+
+
+def trajectory_gradients(prob: Problem, gx: np.ndarray, dv: np.ndarray):
+    """For the prescribed trajectory x_p(k) = x_p(0) + v0 k: dJ/dx_p(0) (the
+    sum of the pose gradients) and the full dJ/dv0 when v0 drives both the
+    poses and the wall velocities (dJ/dv + sum_k k dJ/dx_p(k))."""
+    k = np.arange(gx.shape[0], dtype=float)[:, None, None]
+    return gx.sum(0), dv + (k * gx).sum(0)
 
 
 def _make_function():

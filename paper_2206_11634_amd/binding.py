@@ -121,7 +121,7 @@ def load(path: Path | None = None):
         "lbm_checkpoint_save": [_P, _P],
         "lbm_checkpoint_load": [_P, _P],
         "lbm_tape_begin": [_P, ctypes.c_int],
-        "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P],
+        "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -430,10 +430,13 @@ class Lattice:
         es = 8 if self.storage == "f64" else 4
         return self.torch.zeros(self.sizes.adjoint_bytes // es, dtype=dt, device=self.device)
 
-    def adjoint(self, parts: "DeviceParticles", weights: np.ndarray, lam, grad):
+    def adjoint(self, parts: "DeviceParticles", weights: np.ndarray, lam, grad, gpos=None):
+        """gpos: None, or a zeroed device FP64 tensor [(T + 1), n, 3] that
+        receives dJ/dx_p of each taped step's pose (and of parts)."""
         w = np.ascontiguousarray(weights, np.float64).reshape(-1)
         _check(load().lbm_adjoint(self.ctx, ctypes.byref(parts.struct),
-                                  w.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(grad)),
+                                  w.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(grad),
+                                  None if gpos is None else _ptr(gpos)),
                self.ctx)
 
     def close(self):

@@ -108,30 +108,75 @@ __device__ __forceinline__ T eq_t(int d, const int e[3], const T& rho, const T u
 
 // The reconstructed population of a link from its inputs: the formulas of
 // the forward link kernel (VIBB, Eqs. eqneq, neqd, rhod, u*_d, u**_d, u_d; or
-// halfway bounce-back), written for a generic scalar.
+// halfway bounce-back), written for a generic scalar; q is a scalar of the
+// same kind so that its derivative can be carried too.
+template <class A>
+__device__ __forceinline__ A val(const A& x)
+{
+    return x;
+}
+template <class A, int N>
+__device__ __forceinline__ A val(const Dual<A, N>& x)
+{
+    return x.v;
+}
+
 template <bool DEV, class A, class T>
-__device__ T link_value(int kind, int d, const int e[3], A q, const T& fdf, const T& rf,
+__device__ T link_value(int kind, int d, const int e[3], const T& q, const T& fdf, const T& rf,
                         const T* uf, const T& fdff, const T& rff, const T* uff, const T* uw,
                         bool neq_split)
 {
     const T ebu = T(A(-e[0])) * uw[0] + T(A(-e[1])) * uw[1] + T(A(-e[2])) * uw[2];
     const T mw = T(A(6) * W<A>(d)) * rf * ebu;
     if (kind != LBM_LINK_VIBB) return fdf + mw;
-    const A tq = A(2) * q, oq = A(1) - A(2) * q;
-    const bool hold = neq_split && q > A(0.5);
-    const T fneq = T(hold ? A(1) : tq) * (fdf - eq_t<DEV, A>(d, e, rf, uf)) +
-                   T(hold ? A(0) : oq) * (fdff - eq_t<DEV, A>(d, e, rff, uff));
-    const T rd = (q <= A(0.5)) ? T(tq) * rf + T(oq) * rff : rf;
+    const A qv = val(q);
+    const T one = T(A(1));
+    const T tq = T(A(2)) * q, oq = one - tq;
+    const bool hold = neq_split && qv > A(0.5);
+    const T fneq = (hold ? one : tq) * (fdf - eq_t<DEV, A>(d, e, rf, uf)) +
+                   (hold ? T(A(0)) : oq) * (fdff - eq_t<DEV, A>(d, e, rff, uff));
+    const T rd = (qv <= A(0.5)) ? tq * rf + oq * rff : rf;
+    const T c1 = (one - q) / q, c2 = (tq - one) / q;
+    const T c3 = (one - q) / (one + q), c4 = tq / (one + q);
     T ud[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const T us = (q <= A(0.5)) ? T(tq) * uf[a] + T(oq) * uff[a]
-                                   : T((A(1) - q) / q) * uf[a] + T((tq - A(1)) / q) * uw[a];
-        const T uss = T((A(1) - q) / (A(1) + q)) * uff[a] + T(tq / (A(1) + q)) * uw[a];
+        const T us = (qv <= A(0.5)) ? tq * uf[a] + oq * uff[a] : c1 * uf[a] + c2 * uw[a];
+        const T uss = c3 * uff[a] + c4 * uw[a];
         ud[a] = us / T(A(3)) + T(A(2)) * uss / T(A(3));
     }
     return eq_t<DEV, A>(d, e, rd, ud) + fneq + mw;
 }
+
+// Metaball sum of one particle and its gradient at X (world coordinates of
+// the image nearest the particle).
+__device__ __forceinline__ void metaball_grad(const double* pts, const double* K, int i0, int i1,
+                                              const double X[3], double& M, double gM[3])
+{
+    M = 0.0;
+    gM[0] = gM[1] = gM[2] = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const double r[3] = {X[0] - pts[3 * i], X[1] - pts[3 * i + 1], X[2] - pts[3 * i + 2]};
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double t = K[i] / r2;
+        M += t;
+        const double s = -2.0 * t / r2;
+        gM[0] += s * r[0];
+        gM[1] += s * r[1];
+        gM[2] += s * r[2];
+    }
+}
+
+// Pose data of one taped step for the geometry terms of the adjoint.
+struct GeoArgs {
+    const double* wpts = nullptr;   // world control points of the step's pose
+    const double* K = nullptr;
+    const double* c0 = nullptr;
+    const int32_t* off = nullptr;
+    double* g_links = nullptr;      // [np][3] dJ/dx_p of the pose the links used
+    double* g_refill = nullptr;     // [np][3] dJ/dx_p of the pose the refill used
+    int exact_q = 0;
+};
 
 __device__ __forceinline__ void dir_of(int d, int e[3])
 {
@@ -313,7 +358,7 @@ __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __r
                                                     typename St<S>::A* __restrict__ lam0,
                                                     const double* pos1, const double* vel1,
                                                     const double* om1, Geom g, Phys ph,
-                                                    double* grad)
+                                                    double* grad, double* gpos)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
@@ -385,6 +430,13 @@ __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __r
         }
         for (int k = 0; k < 3; ++k)
             if (dv[k] != 0.0) atomicAdd(grad + 4 + 3 * p + k, dv[k]);
+        if (gpos) {
+            // u_new = v + omega x (x - x_p): dJ/dx_p = -(dJ/du_new) x omega
+            const double gx[3] = {-(dv[1] * wp[2] - dv[2] * wp[1]), -(dv[2] * wp[0] - dv[0] * wp[2]),
+                                  -(dv[0] * wp[1] - dv[1] * wp[0])};
+            for (int k = 0; k < 3; ++k)
+                if (gx[k] != 0.0) atomicAdd(gpos + 3 * p + k, gx[k]);
+        }
         // entries read through the streaming rule of direction j (x - e_j fluid
         // at n): f_j(x - e_j) also fed the bounce-back of opp(j) when x + e_j
         // was not fluid
@@ -408,23 +460,30 @@ __device__ __forceinline__ void atomic_add_a(A* p, A v)
     if (v != A(0)) atomicAdd(p, v);
 }
 
-template <int S>
+// With GEO, also dJ/dx_p of the pose the links were built from, with the
+// link set held fixed: through q (Eq. appq, or Eq. calq by the implicit
+// function theorem), which moves the VIBB weights and the wall point
+// x_w = x_n + q e, and through the lever arm r = x_w - x_p of the torque
+// weight and of u_w = v + omega x r.
+template <int S, bool GEO>
 __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __restrict__ f,
                                                    const LinkRec* __restrict__ links,
                                                    const uint32_t* __restrict__ cursor,
                                                    int64_t cap, const double* pos,
                                                    const double* vel, const double* om,
                                                    typename St<S>::A* lam0, const double* wts,
-                                                   Geom g, Phys ph, double* grad)
+                                                   Geom g, Phys ph, double* grad, GeoArgs ga)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
-    using D13 = Dual<A, 13>;
+    constexpr int N = GEO ? 14 : 13;  // tangents: 13 link inputs (+ q)
+    using DN = Dual<A, N>;
     const int p = blockIdx.y;
     const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
     if (blockIdx.x * 256u >= cnt) return;
     const uint32_t l = blockIdx.x * 256u + threadIdx.x;
-    double acc[6] = {0, 0, 0, 0, 0, 0};  // dJ/dF (3), dJ/dv_p (3)
+    // dJ/dF (3), dJ/dv_p (3), dJ/dx_p (3, GEO)
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (l < cnt) {
         const LinkRec r = links[(int64_t)p * cap + l];
         const int d = r.d, db = opp(d);
@@ -434,13 +493,13 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
         const int cs[3] = {(int)(r.node % nx), (int)((r.node / nx) % ny), (int)(r.node / (nx * ny))};
         int cn[3] = {cs[0] - e[0], cs[1] - e[1], cs[2] - e[2]};
         wrap3(cn, g);
-        double rr[3], uw[3], Wv[3];
+        double rr[3], uw[3], Wv[3], Xn[3];
         const double* xp = pos + 3 * p;
         const double* wp = om + 3 * p;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double Xn = image_coord(cn[a], g.n[a], g.per[a], xp[a]);
-            rr[a] = Xn + r.q * (double)e[a] - xp[a];
+            Xn[a] = image_coord(cn[a], g.n[a], g.per[a], xp[a]);
+            rr[a] = Xn[a] + r.q * (double)e[a] - xp[a];
         }
         uw[0] = vel[3 * p] + (wp[1] * rr[2] - wp[2] * rr[1]);
         uw[1] = vel[3 * p + 1] + (wp[2] * rr[0] - wp[0] * rr[2]);
@@ -451,6 +510,9 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
         Wv[0] = wF[0] + (wT[1] * rr[2] - wT[2] * rr[1]);
         Wv[1] = wF[1] + (wT[2] * rr[0] - wT[0] * rr[2]);
         Wv[2] = wF[2] + (wT[0] * rr[1] - wT[1] * rr[0]);
+        // geometry terms: t = the link's momentum-exchange vector, G = dJ/du_w
+        // of the link (all paths), dq = dJ/dq through the reconstruction
+        double tv[3] = {0, 0, 0}, G[3] = {0, 0, 0}, dq = 0.0;
         if (r.kind == LBM_LINK_MISSING) {
             // J = [(e_d - u_w) feq_d(rho0, u_w) - (e_db - u_w) feq_db(rho0, u_w)] . W
             using D3 = Dual<double, 3>;
@@ -461,9 +523,13 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
             const D3 fi = eq_t<false, double>(db, eb, r0, u3);
             D3 J = D3(0.0);
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                J = J + D3(Wv[a]) * ((D3((double)e[a]) - u3[a]) * fo - (D3((double)eb[a]) - u3[a]) * fi);
+            for (int a = 0; a < 3; ++a) {
+                const D3 ta = (D3((double)e[a]) - u3[a]) * fo - (D3((double)eb[a]) - u3[a]) * fi;
+                J = J + D3(Wv[a]) * ta;
+                tv[a] = ta.v;
+            }
             acc[3] = J.d[0], acc[4] = J.d[1], acc[5] = J.d[2];
+            G[0] = J.d[0], G[1] = J.d[1], G[2] = J.d[2];
         } else {
             A F[3];
             if constexpr (DEV) {
@@ -493,14 +559,19 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
                 for (int i = 0; i < kQ; ++i) fdff = (i == d) ? v[i] : fdff;
             }
             // value and gradient of the reconstructed population
-            D13 x_fdf = var<A, 13>(fdf, 0), x_rf = var<A, 13>(rf, 1);
-            D13 x_uf[3] = {var<A, 13>(uf[0], 2), var<A, 13>(uf[1], 3), var<A, 13>(uf[2], 4)};
-            D13 x_fdff = var<A, 13>(fdff, 5), x_rff = var<A, 13>(rff, 6);
-            D13 x_uff[3] = {var<A, 13>(uff[0], 7), var<A, 13>(uff[1], 8), var<A, 13>(uff[2], 9)};
-            D13 x_uw[3] = {var<A, 13>(A(uw[0]), 10), var<A, 13>(A(uw[1]), 11),
-                           var<A, 13>(A(uw[2]), 12)};
-            const D13 unk = link_value<DEV, A>(r.kind, d, e, A(r.q), x_fdf, x_rf, x_uf, x_fdff,
-                                               x_rff, x_uff, x_uw, ph.neq_split != 0);
+            DN x_fdf = var<A, N>(fdf, 0), x_rf = var<A, N>(rf, 1);
+            DN x_uf[3] = {var<A, N>(uf[0], 2), var<A, N>(uf[1], 3), var<A, N>(uf[2], 4)};
+            DN x_fdff = var<A, N>(fdff, 5), x_rff = var<A, N>(rff, 6);
+            DN x_uff[3] = {var<A, N>(uff[0], 7), var<A, N>(uff[1], 8), var<A, N>(uff[2], 9)};
+            DN x_uw[3] = {var<A, N>(A(uw[0]), 10), var<A, N>(A(uw[1]), 11),
+                          var<A, N>(A(uw[2]), 12)};
+            DN x_q;
+            if constexpr (GEO)
+                x_q = var<A, N>(A(r.q), 13);
+            else
+                x_q = DN(A(r.q));
+            const DN unk = link_value<DEV, A>(r.kind, d, e, x_q, x_fdf, x_rf, x_uf, x_fdff,
+                                              x_rff, x_uff, x_uw, ph.neq_split != 0);
             // momentum exchange of this link: [(e_d - u_w) out - (e_db - u_w) in] . W
             double out = (double)fdf, in = (double)unk.v;
             if constexpr (DEV) {
@@ -513,6 +584,8 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
                 d_out += ((double)e[a] - uw[a]) * Wv[a];
                 d_in += ((double)e[a] + uw[a]) * Wv[a];
                 acc[3 + a] += -(out - in) * Wv[a];
+                tv[a] = ((double)e[a] - uw[a]) * out + ((double)e[a] + uw[a]) * in;
+                G[a] = -(out - in) * Wv[a];
             }
             // adjoint of the reconstructed value: the fluid node that pulled
             // the ghost slot, plus the objective
@@ -521,9 +594,9 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
             A* ghost = lam0 + (int64_t)db * g.stride + r.node;
             const A lu = *ghost + A(d_in);
             *ghost = A(0);
-            A gk[13];
+            A gk[N];
 #pragma unroll
-            for (int k = 0; k < 13; ++k) gk[k] = lu * unk.d[k];
+            for (int k = 0; k < N; ++k) gk[k] = lu * unk.d[k];
             atomic_add_a(lam0 + (int64_t)d * g.stride + xf, gk[0] + A(d_out));
             const A irf = A(1) / rf;
 #pragma unroll
@@ -547,14 +620,54 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
                 for (int a = 0; a < 3; ++a) acc[a] += -(double)(gk[7 + a] * A(0.5) * irff);
             }
 #pragma unroll
-            for (int a = 0; a < 3; ++a) acc[3 + a] += (double)gk[10 + a];
+            for (int a = 0; a < 3; ++a) {
+                acc[3 + a] += (double)gk[10 + a];
+                G[a] += (double)gk[10 + a];
+            }
+            if constexpr (GEO) dq = (double)gk[13];
             (void)drf;
             (void)drff;
         }
+        if constexpr (GEO) {
+            // dJ/dr: torque weight (wT x r).t and u_w = v + omega x r
+            double Jr[3];
+            Jr[0] = (tv[1] * wT[2] - tv[2] * wT[1]) + (G[1] * wp[2] - G[2] * wp[1]);
+            Jr[1] = (tv[2] * wT[0] - tv[0] * wT[2]) + (G[2] * wp[0] - G[0] * wp[2]);
+            Jr[2] = (tv[0] * wT[1] - tv[1] * wT[0]) + (G[0] * wp[1] - G[1] * wp[0]);
+            dq += Jr[0] * e[0] + Jr[1] * e[1] + Jr[2] * e[2];
+            // dq/dx_p: translating the body by dx moves M(X) by -grad M(X).dx
+            const int i0 = ga.off[p], i1 = ga.off[p + 1];
+            const double c0 = ga.c0[p];
+            double qx[3];
+            if (ga.exact_q) {
+                const double Xw[3] = {Xn[0] + r.q * e[0], Xn[1] + r.q * e[1], Xn[2] + r.q * e[2]};
+                double M, gM[3];
+                metaball_grad(ga.wpts, ga.K, i0, i1, Xw, M, gM);
+                const double ge = gM[0] * e[0] + gM[1] * e[1] + gM[2] * e[2];
+                for (int a = 0; a < 3; ++a) qx[a] = gM[a] / ge;
+            } else {
+                const double Xs[3] = {Xn[0] + e[0], Xn[1] + e[1], Xn[2] + e[2]};
+                double Mn, Ms, gn[3], gs[3];
+                metaball_grad(ga.wpts, ga.K, i0, i1, Xn, Mn, gn);
+                metaball_grad(ga.wpts, ga.K, i0, i1, Xs, Ms, gs);
+                const double den = (Ms - Mn) * (Ms - Mn);
+                const double an = (c0 - Ms) / den, as = (Mn - c0) / den;
+                for (int a = 0; a < 3; ++a) qx[a] = -(an * gn[a] + as * gs[a]);
+            }
+            for (int a = 0; a < 3; ++a) acc[6 + a] = dq * qx[a] - Jr[a];
+        }
     }
-    double* outs[6] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
-                       grad + 6 + 3 * p};
-    block_add<6>(acc, outs);
+    if constexpr (GEO) {
+        double* outs[9] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
+                           grad + 6 + 3 * p, ga.g_links + 3 * p, ga.g_links + 3 * p + 1,
+                           ga.g_links + 3 * p + 2};
+        block_add<9>(acc, outs);
+    } else {
+        double a6[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5]};
+        double* outs[6] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
+                           grad + 6 + 3 * p};
+        block_add<6>(a6, outs);
+    }
 }
 
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
@@ -563,7 +676,7 @@ template <int S>
 struct RunAdj {
     static hipError_t run(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1, const double* pos1,
                           const double* vel1, const double* om1, const void* lam1,
-                          void* lam0, const double* wts, double* grad)
+                          void* lam0, const double* wts, double* grad, const GeoArgs& ga)
     {
         using T = typename St<S>::T;
         using A = typename St<S>::A;
@@ -572,13 +685,20 @@ struct RunAdj {
                            own1, (const A*)lam1, (A*)lam0, c->geom, c->phys, grad);
         hipLaunchKernelGGL(k_adj_refill<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f,
                            ts.own, own1, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom,
-                           c->phys, grad);
+                           c->phys, grad, ga.g_refill);
         if (c->cfg.n_particles > 0 && ts.link_max > 0) {
-            dim3 grid(blocks_for(ts.link_max), c->cfg.n_particles);
-            hipLaunchKernelGGL(k_adj_links<S>, grid, dim3(256), 0, c->stream, (const T*)ts.f,
-                               ts.links, ts.cursor, ts.link_cap, ts.part, ts.part + 3 * c->cfg.n_particles,
-                               ts.part + 6 * c->cfg.n_particles, (A*)lam0, wts,
-                               c->geom, c->phys, grad);
+            const int np = c->cfg.n_particles;
+            dim3 grid(blocks_for(ts.link_max), np);
+            if (ga.g_links)
+                hipLaunchKernelGGL((k_adj_links<S, true>), grid, dim3(256), 0, c->stream,
+                                   (const T*)ts.f, ts.links, ts.cursor, ts.link_cap, ts.part,
+                                   ts.part + 3 * np, ts.part + 6 * np, (A*)lam0, wts, c->geom,
+                                   c->phys, grad, ga);
+            else
+                hipLaunchKernelGGL((k_adj_links<S, false>), grid, dim3(256), 0, c->stream,
+                                   (const T*)ts.f, ts.links, ts.cursor, ts.link_cap, ts.part,
+                                   ts.part + 3 * np, ts.part + 6 * np, (A*)lam0, wts, c->geom,
+                                   c->phys, grad, ga);
         }
         return hipGetLastError();
     }
@@ -589,15 +709,27 @@ struct RunAdj {
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
                                const void* lam1, void* lam0, const double* wts,
-                               double* grad)
+                               double* grad, const lbm_particles* P, double* gpos0,
+                               double* gpos1)
 {
+    GeoArgs ga;
+    if (gpos0) {
+        const int np = c->cfg.n_particles;
+        ga.wpts = ts.part + 9 * np;
+        ga.K = P->K;
+        ga.c0 = P->c0;
+        ga.off = P->ctrl_off;
+        ga.g_links = gpos0;
+        ga.g_refill = gpos1;
+        ga.exact_q = (c->cfg.treatments & LBM_TREAT_EXACT_Q) ? 1 : 0;
+    }
     switch (c->cfg.storage) {
     case LBM_STORE_F64:
-        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad);
+        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga);
     case LBM_STORE_F32:
-        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad);
+        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga);
     case LBM_STORE_F16:
-        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad);
+        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga);
     default: return hipErrorInvalidValue;
     }
 }

@@ -176,6 +176,8 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
                                  hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(t.part + 6 * np, P->omega, sizeof(double) * 3 * np,
                                  hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.part + 9 * np, P->world_pts, sizeof(double) * 3 * c->cfg.n_ctrl,
+                                 hipMemcpyDeviceToDevice, c->stream));
     }
     c->tape_len += 1;
     return LBM_OK;
@@ -662,7 +664,8 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
             hipError_t e = hipMalloc(&t.f, c->sizes.population_bytes);
             if (e == hipSuccess) e = alloc(&t.own, c->sizes.owner_bytes / sizeof(uint32_t));
             if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
-            if (e == hipSuccess) e = alloc(&t.part, (size_t)9 * std::max(np, 1));
+            if (e == hipSuccess)
+                e = alloc(&t.part, (size_t)9 * std::max(np, 1) + (size_t)3 * c->cfg.n_ctrl);
             if (e != hipSuccess) {
                 free_tape(c);
                 return fail(c, LBM_ENOMEM, "tape allocation failed");
@@ -676,7 +679,7 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
 }
 
 int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void* lam_dev,
-                double* grad_dev)
+                double* grad_dev, double* gpos_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
@@ -702,9 +705,11 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         const double* pos1 = last ? P->pos : c->tape[s + 1].part;
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
+        double* g0 = (gpos_dev && np > 0) ? gpos_dev + (size_t)3 * np * s : nullptr;
+        double* g1 = g0 ? g0 + 3 * np : nullptr;
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
         HIPCHK(c, launch_adjoint_step(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
-                                      c->adj_wts, grad_dev));
+                                      c->adj_wts, grad_dev, P, g0, g1));
         in = 1 - in;
     }
     if (in != 0)

@@ -76,7 +76,7 @@ struct TapeStep {
     int64_t link_alloc = 0;      // records allocated
     uint32_t* cursor = nullptr;  // [np * kCursorPad]
     int64_t link_max = 0;
-    double* part = nullptr;      // [9 np]: pos, vel, omega
+    double* part = nullptr;      // [9 np + 3 n_ctrl]: pos, vel, omega, world control points
 };
 
 // Lattice geometry passed by value to kernels.
@@ -215,7 +215,8 @@ hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t
 // Launchers (lbm_adjoint.hip)
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
-                               const void* lam1, void* lam0, const double* wts, double* grad);
+                               const void* lam1, void* lam0, const double* wts, double* grad,
+                               const lbm_particles* P, double* gpos0, double* gpos1);
 
 // Launchers (lbm_dem.hip)
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);

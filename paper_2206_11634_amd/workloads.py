@@ -30,6 +30,7 @@ __all__ = [
     "LatticeSpec", "ParticleSet", "quat_to_matrix", "random_quaternion",
     "sphere_shape", "metaball_shape", "make_particles", "prescribed_state",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5",
+    "square_metaball", "config_dkt", "config_floor_pair",
     "tiny_case", "WORKLOADS",
 ]
 
@@ -551,6 +552,29 @@ def config_dkt(shape: str = "metaball", tau: float | None = None):
     return lat, ps, meta
 
 
+def config_floor_pair(rho_r: float = 3.0, gap: float = 3.0, tau: float = 0.5453):
+    """Two equal spheres (d = 14.65) side by side, `gap` lu apart, released
+    0.7 lu above the floor of a closed 48x40x40 box, under relative gravity:
+    the setting of the paper's two-sphere test of the near-contact treatments
+    (Sec. 3.3), shortened to the phase it is about, the bodies at rest on the
+    floor.  A body resting on the floor covers force points below the wall
+    plane; with treatment 2 they count with the reference density and the
+    resting body feels no net fluid force, without it the fluid pushes it
+    into the wall with the reference pressure on the covered patch.  A
+    density ratio of 3 keeps the bodies in DEM contact with the floor;
+    lighter ones hover one node row above it, where the row's momentum along
+    the wall normal flips sign every step without damping and the coupling
+    feeds it.  Gaps of one node row between the two spheres behave alike."""
+    lat = LatticeSpec(48, 40, 40, (0, 0, 0), tau=tau)
+    sh = sphere_shape(14.65, 0.1)
+    x0 = 24.0 - (14.65 + gap) / 2
+    ps = make_particles([sh, sh], [[x0, 20.2, 8.0], [x0 + 14.65 + gap, 19.9, 8.0]],
+                        [[1.0, 0, 0, 0], [1.0, 0, 0, 0]], rho_r)
+    meta = dict(name="floor_pair_48x40x40", steps=1500, storage="f64", rho_r=rho_r,
+                gravity=(0.0, 0.0, -3.92e-4), n_sub=10, treatments=3)
+    return lat, ps, meta
+
+
 def tiny_case(seed: int, dims=(16, 14, 12), periodic=(1, 0, 1), n_particles=3,
               diameter_range=(3.0, 6.0), tau=0.7, u0=(0.0, 0.0, 0.0),
               speed=0.0, spin=0.0, body_force=(0.0, 0.0, 0.0), allow_near=True):
@@ -606,6 +630,7 @@ WORKLOADS = {
     "c5": config_c5,
     "dkt_metaball": lambda: config_dkt("metaball"),
     "dkt_sphere": lambda: config_dkt("sphere"),
+    "floor_pair": config_floor_pair,
 }
 
 

@@ -141,3 +141,85 @@ def test_autograd_function_returns_the_adjoint_gradient():
     np.testing.assert_allclose(v.grad.numpy(), 2 * ref[1], rtol=1e-10, atol=1e-14)
     np.testing.assert_allclose(F.grad.numpy(), 2 * ref[2], rtol=1e-10)
     assert abs(float(tau.grad) - 2 * ref[3]) <= 1e-7 * abs(ref[3])
+
+
+def _shifted(prob, dx=None, dv=None):
+    ps = prob.ps.copy()
+    if dx is not None:
+        ps.pos = ps.pos + dx
+    if dv is not None:
+        ps.vel = ps.vel + dv
+    ps.refresh_world()
+    return dataclasses.replace(prob, ps=ps)
+
+
+def _geometry_problem(omega):
+    prob = _problem("f64", steps=24, window=10)
+    ps = prob.ps.copy()
+    ps.omega = np.array([[0.0, 0.0, omega], [0.0, 0.0, 0.0]])
+    return dataclasses.replace(prob, ps=ps)
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.004])
+def test_fp64_geometry_adjoint_matches_moving_geometry_differences(omega):
+    """dJ/dx_p(0) (sum of the pose gradients) against central differences
+    that translate the whole trajectory, and the full dJ/dv0 (wall velocity
+    and poses together) against differences of v0; both replay the moved
+    geometry.  Steps are few and h small so that no owner changes."""
+    prob = _geometry_problem(omega)
+    v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
+    J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
+    gx0, dv0 = AD.trajectory_gradients(prob, gx, dv)
+    scale = max(np.abs(gx0).max(), 1e-12)
+    h = 1e-6
+    for p in range(2):
+        for a in range(3):
+            e = np.zeros((2, 3))
+            e[p, a] = h
+            Jp = AD.evaluate(_shifted(prob, dx=e), v, F, tau)
+            Jm = AD.evaluate(_shifted(prob, dx=-e), v, F, tau)
+            fd = (Jp - Jm) / (2 * h)
+            assert abs(gx0[p, a] - fd) <= 2e-5 * scale, (p, a, gx0[p, a], fd)
+    scale = max(np.abs(dv0).max(), 1e-12)
+    for p in range(2):
+        for a in range(3):
+            e = np.zeros((2, 3))
+            e[p, a] = h
+            Pp, Pm = _shifted(prob, dv=e), _shifted(prob, dv=-e)
+            fd = (AD.evaluate(Pp, v + e, F, tau) - AD.evaluate(Pm, v - e, F, tau)) / (2 * h)
+            assert abs(dv0[p, a] - fd) <= 2e-5 * scale, (p, a, dv0[p, a], fd)
+    assert np.abs(gx0).max() > 0
+
+
+def test_fp64_geometry_adjoint_matches_oracle_differences():
+    """The reference: central differences of the FP64 oracle's J with the
+    whole trajectory translated, its own geometry rebuilt."""
+    prob = _geometry_problem(0.004)
+    prob = dataclasses.replace(prob, steps=16)
+    v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
+    J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
+    gx0, _ = AD.trajectory_gradients(prob, gx, dv)
+    scale = max(np.abs(gx0).max(), 1e-12)
+    h = 1e-6
+    for p, a in [(0, 0), (0, 2), (1, 1)]:
+        e = np.zeros((2, 3))
+        e[p, a] = h
+        fd = (_oracle_J(_shifted(prob, dx=e), v, F, tau) -
+              _oracle_J(_shifted(prob, dx=-e), v, F, tau)) / (2 * h)
+        assert abs(gx0[p, a] - fd) <= 5e-5 * scale, (p, a, gx0[p, a], fd)
+
+
+def test_fp64_geometry_adjoint_with_exact_q():
+    prob = dataclasses.replace(_geometry_problem(0.0),
+                               treatments=B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_EXACT_Q)
+    v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
+    J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
+    gx0, _ = AD.trajectory_gradients(prob, gx, dv)
+    scale = max(np.abs(gx0).max(), 1e-12)
+    h = 1e-6
+    for p, a in [(0, 0), (0, 1), (1, 2)]:
+        e = np.zeros((2, 3))
+        e[p, a] = h
+        fd = (AD.evaluate(_shifted(prob, dx=e), v, F, tau) -
+              AD.evaluate(_shifted(prob, dx=-e), v, F, tau)) / (2 * h)
+        assert abs(gx0[p, a] - fd) <= 2e-5 * scale, (p, a, gx0[p, a], fd)

@@ -96,3 +96,37 @@ def test_dkt_metaballs_draft_kiss_and_tumble():
     assert d.min() < 16.0
     assert pos[-1, 0, 2] < pos[-1, 1, 2]
     assert vel[-1, :, 2].max() < -0.02
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_resting_pair_feels_no_fluid_force_with_missing_point_treatment(storage):
+    """Two heavy spheres resting on the floor (Sec. 3.3's two-sphere test,
+    after they land): with treatment 2 the mean fluid force over steps
+    1000-1500 is a small fraction of the submerged weight W and the floor
+    contact carries W; without it the covered force points leave the
+    reference pressure on the rest of the surface unbalanced and the fluid
+    pushes each body into the floor with several W."""
+    res = {}
+    for treat in (3, 1):
+        lat, ps, meta = W.config_floor_pair()
+        print(f"floor pair {storage} treat {treat}", flush=True)
+        gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat)
+        parts = B.DeviceParticles(ps)
+        prm = B.DemParams.make(**W.dem_defaults(ps, gravity=meta["gravity"]))
+        gpu.classify(parts)
+        Fz, V = [], []
+        for n in range(1, 1501):
+            gpu.step(parts)
+            Fh, _ = gpu.forces()
+            gpu.dem(parts, meta["n_sub"], 1.0 / meta["n_sub"], prm)
+            gpu.classify(parts)
+            if n > 1000 and n % 10 == 0:
+                Fz.append(Fh[:, 2].cpu().numpy())
+                V.append(np.linalg.norm(parts.to_host(ps).vel, axis=1))
+        gpu.close()
+        res[treat] = np.array(Fz).mean(0), np.array(V).max()
+    Wsub = (ps.mass - ps.volume) * 3.92e-4
+    print({k: (v[0] / Wsub, v[1]) for k, v in res.items()})
+    assert np.all(np.abs(res[3][0]) < 0.3 * Wsub)
+    assert np.all(res[1][0] < -3.0 * Wsub)
+    assert res[3][1] < 1e-3
