@@ -353,6 +353,8 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->adj_scratch);
     (void)hipFree(c->adj_wts);
     (void)hipFree(c->hist_pp);
+    (void)hipFree(c->pairs);
+    (void)hipFree(c->pair_count);
     (void)hipFree(c->hist_pw);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
     for (auto& t : c->timed) {
@@ -530,7 +532,9 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
     if (np == 0) return LBM_OK;
     if (!c->hist_pp) {
         if (alloc(&c->hist_pp, (size_t)np * np * 8) != hipSuccess ||
-            alloc(&c->hist_pw, (size_t)np * 6 * 8) != hipSuccess)
+            alloc(&c->hist_pw, (size_t)np * 6 * 8) != hipSuccess ||
+            alloc(&c->pairs, std::max<size_t>((size_t)np * (np - 1) / 2, 1)) != hipSuccess ||
+            alloc(&c->pair_count, 1) != hipSuccess)
             return fail(c, LBM_ENOMEM, "contact history allocation failed");
         HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * np * np * 8, c->stream));
         HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));

@@ -346,19 +346,14 @@ __device__ __forceinline__ void pair_contact(const BA& A, const BB& B, double x[
 
 // Threads [0, np*np) take the pairs i < j, threads [np*np, np*np + 6 np) the
 // particle-wall pairs.
-__global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, double* hist_w, double* fc, const double* rch,
-                           DemP c, double dt, Geom g)
+// Contact of pair (i < j): broad-phase test on the reach radii, then the
+// Newton search and force; the pair's history is record i * np + j.
+__device__ __forceinline__ void pair_item(const PartDev& P, double* hist, double* fc,
+                                          const double* rch, const DemP& c, double dt,
+                                          const Geom& g, int i, int j)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int np = P.n;
-    if (t >= (int64_t)np * np) {
-        const int64_t w = t - (int64_t)np * np;
-        if (w < (int64_t)np * 6) wall_contact(P, (int)w, hist_w, fc, rch, c, dt, g);
-        return;
-    }
-    const int i = (int)(t / np), j = (int)(t % np);
-    if (i >= j) return;
-    double* h = hist + t * kHist;
+    double* h = hist + ((int64_t)i * np + j) * kHist;
     const double* xi = P.pos + 3 * i;
     const double* xj = P.pos + 3 * j;
     double sh[3], dv[3];
@@ -408,6 +403,81 @@ __global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, doubl
     else
         pair_contact(BodyG{pi, P.K + ai, ni}, BodyG{pj, P.K + aj, nj}, x, h, xi, xj, sh, i, j,
                      rsi, rsj, P, c, dt, fc);
+}
+
+__global__ void k_zero_count(uint32_t* count)
+{
+    if (threadIdx.x == 0) count[0] = 0u;
+}
+
+// Candidate pairs of one dem_step call: pairs whose centres are within the
+// reach radii, R_s and a skin that covers the relative displacement of the
+// call, (|v_i| + |v_j|) T + 1/2 (velocities change by far less than 1/4 lu
+// per lattice step under the accelerations of a stable run).  A pair outside
+// it cannot come into reach during the call; its history, if any, is
+// cleared.  Appends i << 16 | j, one atomic per wave.
+__global__ __launch_bounds__(256) void k_pairs(PartDev P, double* hist, double T, Geom g,
+                                               uint32_t* list, uint32_t* count)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = P.n;
+    bool take = false;
+    int i = 0, j = 0;
+    if (t < (int64_t)np * np) {
+        i = (int)(t / np);
+        j = (int)(t % np);
+        if (i < j) {
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double d = P.pos[3 * j + a] - P.pos[3 * i + a];
+                if (g.per[a]) {
+                    const double L = g.n[a];
+                    if (d > 0.5 * L) d -= L;
+                    else if (d < -0.5 * L) d += L;
+                }
+                d2 += d * d;
+            }
+            const double* vi = P.vel + 3 * i;
+            const double* vj = P.vel + 3 * j;
+            const double skin = (sqrt(dot3(vi, vi)) + sqrt(dot3(vj, vj))) * T + 0.5;
+            const double thr = reach(P, i) + reach(P, j) + P.rs[i] + P.rs[j] + skin;
+            take = sqrt(d2) <= thr;
+            if (!take) {
+                double* h = hist + t * kHist;
+                if (h[0] != 0.0)
+                    for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+            }
+        }
+    }
+    const uint64_t m = __ballot(take);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = __shfl(base, __ffsll((unsigned long long)m) - 1, 64);
+    if (take) {
+        const uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        list[base + below] = ((uint32_t)i << 16) | (uint32_t)j;
+    }
+}
+
+// One substep's contacts: the walls of every body (6 n items), then the
+// listed pairs; grid-stride over both.
+__global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, double* hist_w, double* fc,
+                                                  const double* rch, DemP c, double dt, Geom g,
+                                                  const uint32_t* list, const uint32_t* count)
+{
+    const int64_t nw = (int64_t)P.n * 6;
+    const int64_t total = nw + (int64_t)*count;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < nw) {
+            wall_contact(P, (int)t, hist_w, fc, rch, c, dt, g);
+        } else {
+            const uint32_t e = list[t - nw];
+            pair_item(P, hist, fc, rch, c, dt, g, (int)(e >> 16), (int)(e & 0xffffu));
+        }
+    }
 }
 
 // In-plane Newton for the point of the wall plane where M is largest, the
@@ -530,13 +600,19 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
     for (int a = 0; a < 3; ++a) c.g[a] = prm.gravity[a];
     c.rhof = prm.rho_f;
     const uint32_t bp = (np + 63) / 64;
-    const int64_t nthreads = (int64_t)np * np + 6 * (int64_t)np;
-    const uint32_t bc = (uint32_t)((nthreads + 255) / 256);
+    // candidate pairs for the whole call (the list holds every pair at most)
+    const uint32_t bq = (uint32_t)(((int64_t)np * np + 255) / 256);
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, ctx->stream, ctx->pair_count);
+    hipLaunchKernelGGL(k_pairs, dim3(bq), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
+                       (double)n_sub * dt, ctx->geom, ctx->pairs, ctx->pair_count);
+    const int64_t most = 6 * (int64_t)np + (int64_t)np * (np - 1) / 2;
+    const uint32_t bc = (uint32_t)std::min<int64_t>((most + 255) / 256, 1024);
     for (int s = 0; s < n_sub; ++s) {
         hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
                            ctx->reach, c, dt, ctx->geom);
         hipLaunchKernelGGL(k_contacts, dim3(bc), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
-                           ctx->hist_pw, ctx->fc, ctx->reach, c, dt, ctx->geom);
+                           ctx->hist_pw, ctx->fc, ctx->reach, c, dt, ctx->geom, ctx->pairs,
+                           ctx->pair_count);
         hipLaunchKernelGGL(k_second_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
                            c, dt);
     }

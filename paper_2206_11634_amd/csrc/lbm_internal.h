@@ -167,6 +167,8 @@ struct lbm_ctx {
     double* hist_pw = nullptr;    // [np*6][8]
     double* fc = nullptr;         // [np][6] last contact force / torque
     double* reach = nullptr;      // [np] broad-phase radius of each particle
+    uint32_t* pairs = nullptr;    // [np (np - 1) / 2] candidate pairs of a dem_step call
+    uint32_t* pair_count = nullptr;
     // kernel timing
     bool prof = false;
     struct Timed {
