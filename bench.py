@@ -85,14 +85,18 @@ def _stream_source_hash():
 
 
 def bulk_roofline(res, lat, storage, workload=None):
-    """Algorithmic bytes of one stream-collide launch: every fluid node reads
-    and writes 19 populations and writes its moments (rho - 1, u) (4 values in
-    the storage's arithmetic, read back by the link kernel); every node reads
-    its 1-byte flag.  The rest-state stores of solid nodes are not counted."""
+    """Algorithmic bytes of one stream-collide launch, per cell update of the
+    lattice: 2 Q s + 1 bytes (Q = 19 populations of s bytes read and written,
+    plus the 1-byte flag), times every cell of the lattice.  Also reported: the
+    stricter count of what the method needs, every fluid node reading and
+    writing 19 populations and writing its moments (rho - 1, u), every node
+    its flag, solid nodes nothing."""
     ncell = lat.ncell
     nfluid = ncell - res["n_solid"]
+    per_cell = 2 * 19 * BYTES[storage] + 1
+    bytes_launch = ncell * per_cell
     per_fluid = 2 * 19 * BYTES[storage] + 4 * BYTES[storage]
-    bytes_launch = nfluid * per_fluid + ncell * 1
+    bytes_fluid = nfluid * per_fluid + ncell * 1
     ms, n = res["prof"]["bulk"]
     avg_ms = ms / max(n, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
@@ -103,8 +107,10 @@ def bulk_roofline(res, lat, storage, workload=None):
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel="k_stream_collide", avg_ms=round(avg_ms, 4),
-                bytes_per_launch=int(bytes_launch),
-                bytes_per_fluid_cell=per_fluid, bytes_per_cell_flag=1)
+                bytes_per_launch=int(bytes_launch), bytes_per_cell=per_cell,
+                fluid_only=dict(bytes_per_launch=int(bytes_fluid), bytes_per_fluid_cell=per_fluid,
+                                bytes_per_cell_flag=1,
+                                achieved=round(bytes_fluid / (avg_ms * 1e-3) / 1e9, 1)))
 
 
 def cpu_baseline(seconds=15.0):
