@@ -287,15 +287,16 @@ int lbm_tape_begin(lbm_ctx* ctx, int max_steps);
  *            step (zeros for J above), on return dJ/df at the first taped step;
  *   grad_dev device FP64 [4 + 3 n], accumulated into: dJ/dF (3), dJ/dtau,
  *            dJ/dv_p (3 per particle);
- *   gpos_dev NULL, or device FP64 [(T + 1) n 3] for T taped steps, accumulated
- *            into: entry k is dJ/dx_p for a translation of particle p's pose
- *            P_k (the pose the k-th taped step's links were built from, and
- *            whose classification refilled the nodes that step found new;
- *            P_T is P), with the owners, links and refill sets held fixed:
- *            through q (Eq. appq, or Eq. calq when LBM_TREAT_EXACT_Q), the
- *            wall point x_w = x_n + q e_d, the lever arm x_w - x_p of the
- *            torque and of u_w = v + omega x (x_w - x_p), and the refill's
- *            u = v + omega x (x - x_p).  The orientation is held fixed.
+ *   gpos_dev NULL, or device FP64 [(T + 1) n 6] for T taped steps, accumulated
+ *            into: entry k holds, for particle p's pose P_k (the pose the
+ *            k-th taped step's links were built from, and whose
+ *            classification refilled the nodes that step found new; P_T is
+ *            P), dJ/dx_p for a translation and dJ/dtheta_p for a small
+ *            world-frame rotation about x_p, with the owners, links and
+ *            refill sets held fixed: through q (Eq. appq, or Eq. calq when
+ *            LBM_TREAT_EXACT_Q), the wall point x_w = x_n + q e_d, the lever
+ *            arm x_w - x_p of the torque and of u_w = v + omega x (x_w - x_p),
+ *            and the refill's u = v + omega x (x - x_p).
  * Synchronises.  ESTATE when nothing was taped. */
 int lbm_adjoint(lbm_ctx* ctx, const lbm_particles* P, const double* weights, void* lam_dev,
                 double* grad_dev, double* gpos_dev);

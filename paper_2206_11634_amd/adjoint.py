@@ -11,12 +11,13 @@ gradient with respect to v, the fluid body force F and the relaxation time
 tau comes from the library's adjoint, run backwards window by window with
 checkpoints every `window` steps and recomputation inside each window.
 
-With geometry=True the adjoint also returns dJ/dx_p of every pose of the
-trajectory (the link set, owners and refill sets held fixed; q, the wall
-points and the lever arms move with the body), from which follow the
-derivatives with respect to the initial positions (the sum over poses) and
-the full derivative with respect to a velocity that drives both the poses
-and the wall velocities (dJ/dv plus the sum of k times the pose gradient).
+With geometry=True the adjoint also returns, for every pose of the
+trajectory, dJ/dx_p (translation) and dJ/dtheta_p (small world-frame
+rotation about x_p), with the link set, owners and refill sets held fixed
+(q, the wall points and the lever arms move with the body).  From them follow
+the derivatives with respect to the initial pose and the full derivative
+with respect to a velocity that drives both the poses and the wall
+velocities (`trajectory_gradients`).
 
 `DragFunction` wraps this as a torch.autograd.Function of (v, F, tau).
 """
@@ -104,8 +105,8 @@ def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
 def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     """(dJ/dv [n][3], dJ/dF [3], dJ/dtau) by the adjoint, window by window from
     the last checkpoint to the first, recomputing each window's steps; with
-    geometry, also dJ/dx_p of every pose [T + 1][n][3].  With a dict for
-    stats, the library's per-phase timers are read into it."""
+    geometry, also (dJ/dx_p, dJ/dtheta_p) of every pose [T + 1][n][6].  With
+    a dict for stats, the library's per-phase timers are read into it."""
     prob, gpu = run.prob, run.gpu
     torch = gpu.torch
     if stats is not None:
@@ -113,7 +114,7 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     lam = gpu.adjoint_field()
     n = prob.ps.n
     g = torch.zeros(4 + 3 * n, dtype=torch.float64, device=gpu.device)
-    gx = (torch.zeros((prob.steps + 1, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
+    gx = (torch.zeros((prob.steps + 1, max(n, 1), 6), dtype=torch.float64, device=gpu.device)
           if geometry else None)
     for w0 in sorted(run.ckpt, reverse=True):
         w1 = min(w0 + prob.window, prob.steps)
@@ -139,7 +140,7 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
 
 def evaluate(prob: Problem, vel, body_force, tau, grad: bool = False, geometry: bool = False):
     """J, and with grad=True also (dJ/dv [n][3], dJ/dF [3], dJ/dtau), and with
-    geometry=True also dJ/dx_p of every pose [T + 1][n][3]."""
+    geometry=True also (dJ/dx_p, dJ/dtheta_p) of every pose [T + 1][n][6]."""
     J, run = forward(prob, vel, body_force, tau, keep=grad)
     if not grad:
         return J
@@ -147,11 +148,28 @@ def evaluate(prob: Problem, vel, body_force, tau, grad: bool = False, geometry: 
 
 
 def trajectory_gradients(prob: Problem, gx: np.ndarray, dv: np.ndarray):
-    """For the prescribed trajectory x_p(k) = x_p(0) + v0 k: dJ/dx_p(0) (the
-    sum of the pose gradients) and the full dJ/dv0 when v0 drives both the
-    poses and the wall velocities (dJ/dv + sum_k k dJ/dx_p(k))."""
-    k = np.arange(gx.shape[0], dtype=float)[:, None, None]
-    return gx.sum(0), dv + (k * gx).sum(0)
+    """For the prescribed trajectory x_p(k) = x_p(0) + v0 k,
+    q_p(k) = exp(omega k / 2) q_p(0):
+      dJ/dx_p(0)     = sum_k dJ/dx_p(k);
+      dJ/dv0         = dJ/dv + sum_k k dJ/dx_p(k), v0 driving both the poses
+                       and the wall velocities;
+      dJ/dtheta_p(0) = sum_k R_k^T dJ/dtheta_p(k) for a small world-frame
+                       rotation of the initial orientation, which reaches
+                       pose k rotated by R_k = R(exp(omega k / 2))."""
+    T1, n = gx.shape[0], gx.shape[1]
+    k = np.arange(T1, dtype=float)[:, None, None]
+    gt0 = np.zeros((n, 3))
+    for p in range(n):
+        w = prob.ps.omega[p]
+        wn = float(np.linalg.norm(w))
+        for j in range(T1):
+            if wn > 0:
+                a = 0.5 * wn * j
+                R = W.quat_to_matrix(np.concatenate([[np.cos(a)], np.sin(a) * w / wn]))
+            else:
+                R = np.eye(3)
+            gt0[p] += R.T @ gx[j, p, 3:]
+    return gx[:, :, :3].sum(0), dv + (k * gx[:, :, :3]).sum(0), gt0
 
 
 def _make_function():

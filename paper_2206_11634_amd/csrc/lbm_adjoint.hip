@@ -148,13 +148,17 @@ __device__ T link_value(int kind, int d, const int e[3], const T& q, const T& fd
     return eq_t<DEV, A>(d, e, rd, ud) + fneq + mw;
 }
 
-// Metaball sum of one particle and its gradient at X (world coordinates of
-// the image nearest the particle).
+// Metaball sum of one particle at X (world coordinates of the image nearest
+// the particle), its gradient in X, and its derivative for a small rotation
+// of the body about its centre xp: each point x_i moves by dtheta x (x_i - xp),
+// so dM/dtheta = sum_i (x_i - xp) x dm_i/dx_i with dm_i/dx_i = -grad_X m_i.
 __device__ __forceinline__ void metaball_grad(const double* pts, const double* K, int i0, int i1,
-                                              const double X[3], double& M, double gM[3])
+                                              const double X[3], const double xp[3], double& M,
+                                              double gM[3], double gR[3])
 {
     M = 0.0;
     gM[0] = gM[1] = gM[2] = 0.0;
+    gR[0] = gR[1] = gR[2] = 0.0;
     for (int i = i0; i < i1; ++i) {
         const double r[3] = {X[0] - pts[3 * i], X[1] - pts[3 * i + 1], X[2] - pts[3 * i + 2]};
         const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -164,6 +168,11 @@ __device__ __forceinline__ void metaball_grad(const double* pts, const double* K
         gM[0] += s * r[0];
         gM[1] += s * r[1];
         gM[2] += s * r[2];
+        const double b[3] = {pts[3 * i] - xp[0], pts[3 * i + 1] - xp[1], pts[3 * i + 2] - xp[2]};
+        // (x_i - xp) x (-s r)
+        gR[0] -= s * (b[1] * r[2] - b[2] * r[1]);
+        gR[1] -= s * (b[2] * r[0] - b[0] * r[2]);
+        gR[2] -= s * (b[0] * r[1] - b[1] * r[0]);
     }
 }
 
@@ -173,8 +182,8 @@ struct GeoArgs {
     const double* K = nullptr;
     const double* c0 = nullptr;
     const int32_t* off = nullptr;
-    double* g_links = nullptr;      // [np][3] dJ/dx_p of the pose the links used
-    double* g_refill = nullptr;     // [np][3] dJ/dx_p of the pose the refill used
+    double* g_links = nullptr;      // [np][6] dJ/d(x_p, theta_p) of the pose the links used
+    double* g_refill = nullptr;     // [np][6] the same for the pose the refill used
     int exact_q = 0;
 };
 
@@ -435,7 +444,7 @@ __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __r
             const double gx[3] = {-(dv[1] * wp[2] - dv[2] * wp[1]), -(dv[2] * wp[0] - dv[0] * wp[2]),
                                   -(dv[0] * wp[1] - dv[1] * wp[0])};
             for (int k = 0; k < 3; ++k)
-                if (gx[k] != 0.0) atomicAdd(gpos + 3 * p + k, gx[k]);
+                if (gx[k] != 0.0) atomicAdd(gpos + 6 * p + k, gx[k]);
         }
         // entries read through the streaming rule of direction j (x - e_j fluid
         // at n): f_j(x - e_j) also fed the bounce-back of opp(j) when x + e_j
@@ -482,8 +491,8 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
     const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
     if (blockIdx.x * 256u >= cnt) return;
     const uint32_t l = blockIdx.x * 256u + threadIdx.x;
-    // dJ/dF (3), dJ/dv_p (3), dJ/dx_p (3, GEO)
-    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // dJ/dF (3), dJ/dv_p (3), dJ/dx_p (3, GEO), dJ/dtheta_p (3, GEO)
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (l < cnt) {
         const LinkRec r = links[(int64_t)p * cap + l];
         const int d = r.d, db = opp(d);
@@ -635,33 +644,43 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
             Jr[1] = (tv[2] * wT[0] - tv[0] * wT[2]) + (G[2] * wp[0] - G[0] * wp[2]);
             Jr[2] = (tv[0] * wT[1] - tv[1] * wT[0]) + (G[0] * wp[1] - G[1] * wp[0]);
             dq += Jr[0] * e[0] + Jr[1] * e[1] + Jr[2] * e[2];
-            // dq/dx_p: translating the body by dx moves M(X) by -grad M(X).dx
+            // dq/dx_p and dq/dtheta_p: translating the body by dx moves M(X)
+            // by -grad M(X).dx; a small rotation moves it by dM/dtheta
             const int i0 = ga.off[p], i1 = ga.off[p + 1];
             const double c0 = ga.c0[p];
-            double qx[3];
+            double qx[3], qt[3];
             if (ga.exact_q) {
                 const double Xw[3] = {Xn[0] + r.q * e[0], Xn[1] + r.q * e[1], Xn[2] + r.q * e[2]};
-                double M, gM[3];
-                metaball_grad(ga.wpts, ga.K, i0, i1, Xw, M, gM);
+                double M, gM[3], gR[3];
+                metaball_grad(ga.wpts, ga.K, i0, i1, Xw, xp, M, gM, gR);
                 const double ge = gM[0] * e[0] + gM[1] * e[1] + gM[2] * e[2];
-                for (int a = 0; a < 3; ++a) qx[a] = gM[a] / ge;
+                for (int a = 0; a < 3; ++a) {
+                    qx[a] = gM[a] / ge;
+                    qt[a] = -gR[a] / ge;
+                }
             } else {
                 const double Xs[3] = {Xn[0] + e[0], Xn[1] + e[1], Xn[2] + e[2]};
-                double Mn, Ms, gn[3], gs[3];
-                metaball_grad(ga.wpts, ga.K, i0, i1, Xn, Mn, gn);
-                metaball_grad(ga.wpts, ga.K, i0, i1, Xs, Ms, gs);
+                double Mn, Ms, gn[3], gs[3], rn[3], rs[3];
+                metaball_grad(ga.wpts, ga.K, i0, i1, Xn, xp, Mn, gn, rn);
+                metaball_grad(ga.wpts, ga.K, i0, i1, Xs, xp, Ms, gs, rs);
                 const double den = (Ms - Mn) * (Ms - Mn);
                 const double an = (c0 - Ms) / den, as = (Mn - c0) / den;
-                for (int a = 0; a < 3; ++a) qx[a] = -(an * gn[a] + as * gs[a]);
+                for (int a = 0; a < 3; ++a) {
+                    qx[a] = -(an * gn[a] + as * gs[a]);
+                    qt[a] = an * rn[a] + as * rs[a];
+                }
             }
-            for (int a = 0; a < 3; ++a) acc[6 + a] = dq * qx[a] - Jr[a];
+            for (int a = 0; a < 3; ++a) {
+                acc[6 + a] = dq * qx[a] - Jr[a];
+                acc[9 + a] = dq * qt[a];
+            }
         }
     }
     if constexpr (GEO) {
-        double* outs[9] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
-                           grad + 6 + 3 * p, ga.g_links + 3 * p, ga.g_links + 3 * p + 1,
-                           ga.g_links + 3 * p + 2};
-        block_add<9>(acc, outs);
+        double* gl = ga.g_links + 6 * p;
+        double* outs[12] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
+                            grad + 6 + 3 * p, gl, gl + 1, gl + 2, gl + 3, gl + 4, gl + 5};
+        block_add<12>(acc, outs);
     } else {
         double a6[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5]};
         double* outs[6] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,

@@ -709,8 +709,8 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         const double* pos1 = last ? P->pos : c->tape[s + 1].part;
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
-        double* g0 = (gpos_dev && np > 0) ? gpos_dev + (size_t)3 * np * s : nullptr;
-        double* g1 = g0 ? g0 + 3 * np : nullptr;
+        double* g0 = (gpos_dev && np > 0) ? gpos_dev + (size_t)6 * np * s : nullptr;
+        double* g1 = g0 ? g0 + 6 * np : nullptr;
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
         HIPCHK(c, launch_adjoint_step(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
                                       c->adj_wts, grad_dev, P, g0, g1));

@@ -169,7 +169,7 @@ def test_fp64_geometry_adjoint_matches_moving_geometry_differences(omega):
     prob = _geometry_problem(omega)
     v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
     J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
-    gx0, dv0 = AD.trajectory_gradients(prob, gx, dv)
+    gx0, dv0, _ = AD.trajectory_gradients(prob, gx, dv)
     scale = max(np.abs(gx0).max(), 1e-12)
     h = 1e-6
     for p in range(2):
@@ -198,7 +198,7 @@ def test_fp64_geometry_adjoint_matches_oracle_differences():
     prob = dataclasses.replace(prob, steps=16)
     v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
     J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
-    gx0, _ = AD.trajectory_gradients(prob, gx, dv)
+    gx0, _, _ = AD.trajectory_gradients(prob, gx, dv)
     scale = max(np.abs(gx0).max(), 1e-12)
     h = 1e-6
     for p, a in [(0, 0), (0, 2), (1, 1)]:
@@ -214,7 +214,7 @@ def test_fp64_geometry_adjoint_with_exact_q():
                                treatments=B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_EXACT_Q)
     v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
     J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
-    gx0, _ = AD.trajectory_gradients(prob, gx, dv)
+    gx0, _, _ = AD.trajectory_gradients(prob, gx, dv)
     scale = max(np.abs(gx0).max(), 1e-12)
     h = 1e-6
     for p, a in [(0, 0), (0, 1), (1, 2)]:
@@ -223,3 +223,31 @@ def test_fp64_geometry_adjoint_with_exact_q():
         fd = (AD.evaluate(_shifted(prob, dx=e), v, F, tau) -
               AD.evaluate(_shifted(prob, dx=-e), v, F, tau)) / (2 * h)
         assert abs(gx0[p, a] - fd) <= 2e-5 * scale, (p, a, gx0[p, a], fd)
+
+
+def _rotated(prob, p, axis, ang):
+    ps = prob.ps.copy()
+    ax = np.zeros(3)
+    ax[axis] = 1.0
+    dq = np.concatenate([[np.cos(0.5 * ang)], np.sin(0.5 * ang) * ax])
+    ps.quat[p] = W.quat_mul(dq, ps.quat[p])
+    ps.refresh_world()
+    return dataclasses.replace(prob, ps=ps)
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.004])
+def test_fp64_rotation_adjoint_matches_moving_geometry_differences(omega):
+    """dJ/dtheta of the initial orientation (summed over the poses, each
+    rotated by the trajectory's own rotation) against central differences
+    that rotate the initial quaternion and rebuild the geometry."""
+    prob = _geometry_problem(omega)
+    v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
+    J, dv, dF, dtau, gx = AD.evaluate(prob, v, F, tau, grad=True, geometry=True)
+    _, _, gt0 = AD.trajectory_gradients(prob, gx, dv)
+    scale = max(np.abs(gt0[0]).max(), 1e-12)
+    h = 1e-6
+    for a in range(3):
+        fd = (AD.evaluate(_rotated(prob, 0, a, h), v, F, tau) -
+              AD.evaluate(_rotated(prob, 0, a, -h), v, F, tau)) / (2 * h)
+        assert abs(gt0[0, a] - fd) <= 2e-5 * scale, (a, gt0[0, a], fd)
+    assert np.abs(gt0[0]).max() > 0
