@@ -34,12 +34,13 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=3):
+def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=3, lattice=19):
     import torch
     from paper_2206_11634_amd import binding as B
     from paper_2206_11634_amd import workloads as W
 
-    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treatments)
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treatments,
+                                  lattice=lattice)
     parts = B.DeviceParticles(ps)
     prm = B.DemParams.make(**W.dem_defaults(ps, gravity=meta["gravity"]))
     n_sub = int(meta.get("n_sub", 10))
@@ -84,7 +85,7 @@ def _stream_source_hash():
     return h.hexdigest()[:16]
 
 
-def bulk_roofline(res, lat, storage, workload=None):
+def bulk_roofline(res, lat, storage, workload=None, Q=19):
     """Algorithmic bytes of one stream-collide launch, per cell update of the
     lattice: 2 Q s + 1 bytes (Q = 19 populations of s bytes read and written,
     plus the 1-byte flag), times every cell of the lattice.  Also reported: the
@@ -93,15 +94,15 @@ def bulk_roofline(res, lat, storage, workload=None):
     its flag, solid nodes nothing."""
     ncell = lat.ncell
     nfluid = ncell - res["n_solid"]
-    per_cell = 2 * 19 * BYTES[storage] + 1
+    per_cell = 2 * Q * BYTES[storage] + 1
     bytes_launch = ncell * per_cell
-    per_fluid = 2 * 19 * BYTES[storage] + 4 * BYTES[storage]
+    per_fluid = 2 * Q * BYTES[storage] + 4 * BYTES[storage]
     bytes_fluid = nfluid * per_fluid + ncell * 1
     ms, n = res["prof"]["bulk"]
     avg_ms = ms / max(n, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
-    rec = MEASURED_TRAFFIC.get((workload, storage))
+    rec = MEASURED_TRAFFIC.get((workload, storage)) if Q == 19 else None
     if rec and rec["source_sha256_16"] == _stream_source_hash():
         traffic = int(rec["read"] + rec["written"])
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -276,8 +277,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
-    ap.add_argument("--variants", default="f16,f64",
-                    help="other storages timed on the same workload (comma list, or none)")
+    ap.add_argument("--variants", default="f16,f64,q15",
+                    help="other storages timed on the same workload, and q15 for the "
+                         "paper's D3Q15 lattice in the main storage (comma list, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drag", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -298,10 +300,15 @@ def main():
     main_res = run_storage(lat, ps, meta, args.storage, args.steps, args.warmup)
     print(f"[bench] {args.storage}: {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr,
           flush=True)
-    variants = {}
+    variants, lattices = {}, {}
     for v in [s for s in args.variants.split(",") if s and s != "none" and s != args.storage]:
-        r = run_storage(lat, ps, meta, v, max(3, min(args.steps, 10)), 2)
-        variants[v] = r
+        if v == "q15":
+            r = run_storage(lat, ps, meta, args.storage, max(3, min(args.steps, 10)), 2,
+                            lattice=15)
+            lattices[f"d3q15_{args.storage}"] = r
+        else:
+            r = run_storage(lat, ps, meta, v, max(3, min(args.steps, 10)), 2)
+            variants[v] = r
         print(f"[bench] {v}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     ncell = lat.ncell
@@ -344,6 +351,15 @@ def main():
             mlups=round(ncell / (r["ms_per_step"] * 1e-3) / 1e6, 1),
             ms_per_step=round(r["ms_per_step"], 4),
             roofline_frac=bulk_roofline(r, lat, v)["frac"])
+    for v, r in lattices.items():
+        rl = bulk_roofline(r, lat, args.storage, Q=15)
+        line.setdefault("lattice_variants", {})[v] = dict(
+            mlups=round(ncell / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+            ms_per_step=round(r["ms_per_step"], 4),
+            phase_ms_per_launch={k: round(t[0] / max(t[1], 1), 4)
+                                 for k, t in r["prof"].items() if t[1]},
+            links=r["n_links"], roofline_achieved=rl["achieved"], roofline_frac=rl["frac"],
+            bytes_per_cell=rl["bytes_per_cell"])
     if "f64" in variants:
         line["speedup_vs_plain_f64"] = round(variants["f64"]["ms_per_step"] /
                                              main_res["ms_per_step"], 3)

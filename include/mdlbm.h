@@ -6,11 +6,13 @@
  * Conventions shared by every entry point
  * ----------------------------------------
  *  * Lattice units: dx = dt = 1, c_s^2 = 1/3, nu = (tau - 1/2)/3 (Sec. 2.2).
- *  * Lattice D3Q19, directions numbered
+ *  * Lattice D3Q19 (default), directions numbered
  *      0:(0,0,0) 1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1)
  *      6:(0,0,-1) 7:(+1,+1,0) 8:(-1,-1,0) 9:(+1,-1,0) 10:(-1,+1,0)
  *      11:(+1,0,+1) 12:(-1,0,-1) 13:(+1,0,-1) 14:(-1,0,+1) 15:(0,+1,+1)
  *      16:(0,-1,-1) 17:(0,+1,-1) 18:(0,-1,+1);  opposite of odd i is i + 1.
+ *    Or D3Q15, the paper's (lbm_config.lattice), numbered in lbm_lattice;
+ *    Q below is the number of directions of the configured lattice.
  *  * Node (i,j,k) sits at coordinates (i,j,k); cell index i + nx*(j + ny*k).
  *    A non-periodic axis ends in no-slip walls half a cell outside the first
  *    and last node (static halfway bounce-back).
@@ -92,7 +94,16 @@ typedef struct {
     void* stream;          /* hipStream_t, NULL for the null stream */
     int32_t classify_mode; /* lbm_classify_mode; the same owners, links and refill
                               sets either way, only the work differs */
+    int32_t lattice;       /* lbm_lattice; 0 selects D3Q19 */
 } lbm_config;
+
+typedef enum {
+    LBM_LATTICE_D3Q19 = 19, /* rest, 6 axes, 12 face diagonals; w = 1/3, 1/18, 1/36 */
+    LBM_LATTICE_D3Q15 = 15  /* the paper's lattice (Sec. 2.2): rest, 6 axes, 8 cube
+                               diagonals; w = 2/9, 1/9, 1/72.  Directions 7..14 are
+                               (1,1,1), (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1),
+                               (-1,1,-1), (-1,1,1), (1,-1,-1) */
+} lbm_lattice;
 
 typedef enum {
     LBM_CLASSIFY_AUTO = 0,  /* lattice sweep when the particles' bounding balls

@@ -39,8 +39,9 @@ class Problem:
     window: int = 100
     storage: str = "f32"
     weights: np.ndarray = None  # [n][6]: (wF, wT) per particle per step
-    f0: np.ndarray = None       # [19][ncell] initial populations
+    f0: np.ndarray = None       # [Q][ncell] initial populations
     treatments: int = B.TREAT_VIBB | B.TREAT_MISSING
+    lattice: int = 19           # 19 (D3Q19) or 15 (D3Q15)
 
     def __post_init__(self):
         if self.weights is None:
@@ -58,7 +59,7 @@ class Problem:
 
     def initial(self) -> np.ndarray:
         if self.f0 is None:
-            g = B.Lattice.for_particles(self.lat, self.ps, storage="f64")
+            g = B.Lattice.for_particles(self.lat, self.ps, storage="f64", lattice=self.lattice)
             self.f0 = g.populations()
             g.close()
         return self.f0
@@ -71,7 +72,7 @@ class _Run:
         lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
                                   tau=float(tau))
         self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage,
-                                           treatments=prob.treatments)
+                                           treatments=prob.treatments, lattice=prob.lattice)
         # every state on the device: poses of the nominal trajectory, velocity v
         self.traj = B.DeviceTrajectory(prob.states(), vel=self.vel)
 

@@ -34,7 +34,8 @@ class LbmConfig(ctypes.Structure):
                 ("body_force", ctypes.c_double * 3), ("storage", ctypes.c_int32),
                 ("treatments", ctypes.c_int32), ("n_particles", ctypes.c_int32),
                 ("n_ctrl", ctypes.c_int32), ("box_half", ctypes.c_int32),
-                ("h16_scale", ctypes.c_double), ("stream", _P), ("classify_mode", ctypes.c_int32)]
+                ("h16_scale", ctypes.c_double), ("stream", _P), ("classify_mode", ctypes.c_int32),
+                ("lattice", ctypes.c_int32)]
 
 
 class LbmSizes(ctypes.Structure):
@@ -278,7 +279,8 @@ class Lattice:
 
     def __init__(self, lat, n_particles=0, n_ctrl=0, box_half=2, storage="f32",
                  treatments=TREAT_VIBB | TREAT_MISSING, h16_scale=0.0, device="cuda",
-                 classify="auto"):
+                 classify="auto", lattice=19):
+        """lattice: 19 (D3Q19) or 15 (D3Q15, the paper's Sec. 2.2)."""
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -297,6 +299,8 @@ class Lattice:
         cfg.box_half = int(box_half)
         cfg.h16_scale = float(h16_scale)
         cfg.classify_mode = CLASSIFY[classify]
+        cfg.lattice = int(lattice)
+        self.Q = 15 if int(lattice) == 15 else 19
         with torch.cuda.device(self.device):
             cfg.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         self.cfg = cfg
@@ -357,9 +361,9 @@ class Lattice:
         return out.cpu().numpy()
 
     def populations(self, nodes=None) -> np.ndarray:
-        """FP64 populations [19][ncell]; with nodes (indices), only those
+        """FP64 populations [Q][ncell]; with nodes (indices), only those
         columns are copied to the host."""
-        out = self.torch.empty((Q, self.ncell), dtype=self.torch.float64, device=self.device)
+        out = self.torch.empty((self.Q, self.ncell), dtype=self.torch.float64, device=self.device)
         _check(load().lbm_get_populations(self.ctx, _ptr(out)), self.ctx)
         if nodes is not None:
             idx = self.torch.as_tensor(np.asarray(nodes, np.int64), device=self.device)
@@ -431,8 +435,9 @@ class Lattice:
         return self.torch.zeros(self.sizes.adjoint_bytes // es, dtype=dt, device=self.device)
 
     def adjoint(self, parts: "DeviceParticles", weights: np.ndarray, lam, grad, gpos=None):
-        """gpos: None, or a zeroed device FP64 tensor [(T + 1), n, 3] that
-        receives dJ/dx_p of each taped step's pose (and of parts)."""
+        """gpos: None, or a zeroed device FP64 tensor [(T + 1), n, 6] that
+        receives (dJ/dx_p, dJ/dtheta_p) of each taped step's pose (and of
+        parts)."""
         w = np.ascontiguousarray(weights, np.float64).reshape(-1)
         _check(load().lbm_adjoint(self.ctx, ctypes.byref(parts.struct),
                                   w.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(grad),

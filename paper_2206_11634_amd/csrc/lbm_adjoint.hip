@@ -27,6 +27,7 @@
 // Arithmetic is that of the storage (double for FP64, float otherwise);
 // parameter gradients are summed in FP64.
 #include "lbm_internal.h"
+#include "lbm_stencil.h"
 #include "lbm_kernels.h"
 
 namespace mdlbm {
@@ -189,12 +190,9 @@ struct GeoArgs {
 
 __device__ __forceinline__ void dir_of(int d, int e[3])
 {
-    e[0] = (d == 1 || d == 7 || d == 9 || d == 11 || d == 13) ? 1
-         : (d == 2 || d == 8 || d == 10 || d == 12 || d == 14) ? -1 : 0;
-    e[1] = (d == 3 || d == 7 || d == 10 || d == 15 || d == 17) ? 1
-         : (d == 4 || d == 8 || d == 9 || d == 16 || d == 18) ? -1 : 0;
-    e[2] = (d == 5 || d == 11 || d == 14 || d == 15 || d == 18) ? 1
-         : (d == 6 || d == 12 || d == 13 || d == 16 || d == 17) ? -1 : 0;
+    e[0] = cx(d);
+    e[1] = cy(d);
+    e[2] = cz(d);
 }
 
 // Sum n doubles over the block and add them to out[] (one atomic each).
@@ -725,6 +723,8 @@ struct RunAdj {
 
 }  // namespace
 
+namespace MDLBM_QNS {
+
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
                                const void* lam1, void* lam0, const double* wts,
@@ -753,4 +753,5 @@ hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* o
     }
 }
 
+}  // namespace MDLBM_QNS
 }  // namespace mdlbm

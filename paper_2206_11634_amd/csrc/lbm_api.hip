@@ -183,13 +183,24 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
     return LBM_OK;
 }
 
+// Number of lattice velocities of the configured lattice (0 selects D3Q19).
+int lattice_q(const lbm_config* cfg)
+{
+    return cfg->lattice == LBM_LATTICE_D3Q15 ? 15 : 19;
+}
+
 }  // namespace
+
+// The launcher of the configured lattice.
+#define LQ(c, fn) ((c)->cfg.lattice == LBM_LATTICE_D3Q15 ? q15::fn : q19::fn)
 
 extern "C" {
 
 int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
 {
     if (!cfg || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    if (cfg->lattice != 0 && cfg->lattice != LBM_LATTICE_D3Q19 && cfg->lattice != LBM_LATTICE_D3Q15)
+        return fail(nullptr, LBM_EINVAL, "unknown lattice");
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
         return fail(nullptr, LBM_EINVAL, "lattice dimensions must be >= 1");
     const int64_t ncell = (int64_t)cfg->nx * cfg->ny * cfg->nz;
@@ -198,12 +209,12 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
     if (!es) return fail(nullptr, LBM_EINVAL, "unknown storage");
     out->ncell = ncell;
     out->cell_stride = (ncell + 63) / 64 * 64;
-    out->population_bytes = (size_t)kQ * (size_t)out->cell_stride * es;
+    out->population_bytes = (size_t)lattice_q(cfg) * (size_t)out->cell_stride * es;
     out->owner_bytes = (size_t)ncell * sizeof(uint32_t);
     out->flag_bytes = (size_t)ncell;
     out->moment_bytes = (size_t)ncell * 4 * es;
     out->checkpoint_bytes = out->population_bytes + out->moment_bytes;
-    out->adjoint_bytes = (size_t)kQ * (size_t)out->cell_stride * (es == 8 ? 8 : 4);
+    out->adjoint_bytes = (size_t)lattice_q(cfg) * (size_t)out->cell_stride * (es == 8 ? 8 : 4);
     return LBM_OK;
 }
 
@@ -309,7 +320,7 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         lbm_destroy(c);
         return fail(nullptr, LBM_ENOMEM, msg);
     }
-    e = launch_init_equilibrium(c, c->f[0]);
+    e = LQ(c, launch_init_equilibrium)(c, c->f[0]);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[0], 0xFF, sz.owner_bytes, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[1], 0xFF, sz.owner_bytes, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sz.flag_bytes, c->stream);
@@ -390,7 +401,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
         HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
         HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
         HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
-        HIPCHK(c, launch_boxes(c, Pd, slot));
+        HIPCHK(c, LQ(c, launch_boxes)(c, Pd, slot));
         // check the boxes before touching the owner planes or the flags
         HIPCHK(c, hipMemcpyAsync(c->host_stage, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                  c->stream));
@@ -399,12 +410,12 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[0]));
         {
             PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
-            if (k >= 2) HIPCHK(c, launch_clear_boxes(c, own_new, slot_prev2, np));
-            HIPCHK(c, launch_mark(c, own_new, Pd, slot));
+            if (k >= 2) HIPCHK(c, LQ(c, launch_clear_boxes)(c, own_new, slot_prev2, np));
+            HIPCHK(c, LQ(c, launch_mark)(c, own_new, Pd, slot));
             // the lattice sweep also runs on a first classification (own_prev
             // is all fluid then): in dense mode it writes every flag
-            if (k >= 1 || c->dense) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
-            HIPCHK(c, launch_links(c, own_new, Pd, slot));
+            if (k >= 1 || c->dense) HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
+            HIPCHK(c, LQ(c, launch_links)(c, own_new, Pd, slot));
         }
         uint32_t* link_counts = c->host_stage + 2;
         uint32_t* cand_counts = c->host_stage + 2 + (size_t)kCursorPad * np;
@@ -443,7 +454,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 if (alloc(&c->cand, (size_t)np * c->cand_cap) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "candidate list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
-                HIPCHK(c, launch_mark(c, own_new, Pd, slot));  // same owners, full list
+                HIPCHK(c, LQ(c, launch_mark)(c, own_new, Pd, slot));  // same owners, full list
             }
             if (grow_links) {
                 HIPCHK(c, hipFree(c->links));
@@ -454,7 +465,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             }
             if (grow_cand || grow_links) {
                 HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
-                HIPCHK(c, launch_links(c, own_new, Pd, slot));
+                HIPCHK(c, LQ(c, launch_links)(c, own_new, Pd, slot));
             }
             if (grow_refill) {
                 HIPCHK(c, hipFree(c->refill));
@@ -463,14 +474,14 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 if (alloc(&c->refill, (size_t)c->refill_cap) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "refill list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
-                if (k >= 1) HIPCHK(c, launch_finish(c, own_prev, own_new, slot_prev, np));
+                if (k >= 1) HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
             }
         }
         if (c->refill_total > 0) {
             // populations of the time level the previous classification describes
             const void* src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
             PhaseTimer tm(c, LBM_PHASE_REFILL);
-            HIPCHK(c, launch_refill(c, src, c->f[c->cur], own_prev, Pd));
+            HIPCHK(c, LQ(c, launch_refill)(c, src, c->f[c->cur], own_prev, Pd));
         }
     } else {
         c->link_max = c->link_total = c->refill_total = 0;
@@ -495,8 +506,8 @@ int lbm_step(lbm_ctx* c, const lbm_particles* P)
     const int np = c->cfg.n_particles;
     {
         PhaseTimer tm(c, LBM_PHASE_BOUNDARY);
-        HIPCHK(c, launch_zero_f64(c, c->FT, 6 * (int64_t)np));
-        if (np > 0 && c->n_classify > 0) HIPCHK(c, launch_boundary(c, c->f[c->cur], to_dev(P)));
+        HIPCHK(c, LQ(c, launch_zero_f64)(c, c->FT, 6 * (int64_t)np));
+        if (np > 0 && c->n_classify > 0) HIPCHK(c, LQ(c, launch_boundary)(c, c->f[c->cur], to_dev(P)));
     }
     if (c->taping && c->tape_len < c->tape_steps) {
         int rc2 = record_tape_step(c, P);
@@ -504,7 +515,7 @@ int lbm_step(lbm_ctx* c, const lbm_particles* P)
     }
     {
         PhaseTimer tm(c, LBM_PHASE_BULK);
-        HIPCHK(c, launch_stream_collide(c, c->f[c->cur], c->f[1 - c->cur]));
+        HIPCHK(c, LQ(c, launch_stream_collide)(c, c->f[c->cur], c->f[1 - c->cur]));
     }
     c->cur = 1 - c->cur;
     c->stepped_since_classify = true;
@@ -515,7 +526,7 @@ int lbm_particle_forces(const lbm_ctx* c, double* F_dev, double* T_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     if (!F_dev || !T_dev) return fail(const_cast<lbm_ctx*>(c), LBM_EINVAL, "null output");
-    HIPCHK(const_cast<lbm_ctx*>(c), launch_split_forces(c, F_dev, T_dev));
+    HIPCHK(const_cast<lbm_ctx*>(c), LQ(c, launch_split_forces)(c, F_dev, T_dev));
     return LBM_OK;
 }
 
@@ -565,7 +576,7 @@ int lbm_get_links(const lbm_ctx* cc, int64_t cap, int32_t* node_dev, int8_t* d_d
     HIPCHK(c, alloc(&off_dev, np));
     HIPCHK(c, hipMemcpyAsync(off_dev, off.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice,
                              c->stream));
-    HIPCHK(c, launch_link_export(c, node_dev, d_dev, kind_dev, part_dev, q_dev, off_dev));
+    HIPCHK(c, LQ(c, launch_link_export)(c, node_dev, d_dev, kind_dev, part_dev, q_dev, off_dev));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipFree(off_dev));
     return LBM_OK;
@@ -593,7 +604,7 @@ int lbm_get_owner(const lbm_ctx* cc, int32_t* owner_dev)
 {
     lbm_ctx* c = const_cast<lbm_ctx*>(cc);
     if (!c || !owner_dev) return fail(c, LBM_EINVAL, "null argument");
-    HIPCHK(c, launch_owner_export(c, c->own[c->own_cur], owner_dev));
+    HIPCHK(c, LQ(c, launch_owner_export)(c, c->own[c->own_cur], owner_dev));
     return LBM_OK;
 }
 
@@ -601,14 +612,14 @@ int lbm_get_populations(const lbm_ctx* cc, double* f_dev)
 {
     lbm_ctx* c = const_cast<lbm_ctx*>(cc);
     if (!c || !f_dev) return fail(c, LBM_EINVAL, "null argument");
-    HIPCHK(c, launch_get_populations(c, c->f[c->cur], f_dev));
+    HIPCHK(c, LQ(c, launch_get_populations)(c, c->f[c->cur], f_dev));
     return LBM_OK;
 }
 
 int lbm_set_populations(lbm_ctx* c, const double* f_dev)
 {
     if (!c || !f_dev) return fail(c, LBM_EINVAL, "null argument");
-    HIPCHK(c, launch_set_populations(c, c->f[c->cur], f_dev));
+    HIPCHK(c, LQ(c, launch_set_populations)(c, c->f[c->cur], f_dev));
     return LBM_OK;
 }
 
@@ -712,7 +723,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         double* g0 = (gpos_dev && np > 0) ? gpos_dev + (size_t)6 * np * s : nullptr;
         double* g1 = g0 ? g0 + 6 * np : nullptr;
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
-        HIPCHK(c, launch_adjoint_step(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
+        HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
                                       c->adj_wts, grad_dev, P, g0, g1));
         in = 1 - in;
     }

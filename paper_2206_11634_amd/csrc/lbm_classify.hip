@@ -19,27 +19,12 @@
 #include <algorithm>
 
 #include "lbm_internal.h"
+#include "lbm_stencil.h"
 
 namespace mdlbm {
 namespace {
 
 constexpr int kMaxCtrl = 64;
-
-__device__ __forceinline__ int ex_d(int d)
-{
-    return (d == 1 || d == 7 || d == 9 || d == 11 || d == 13) ? 1
-         : (d == 2 || d == 8 || d == 10 || d == 12 || d == 14) ? -1 : 0;
-}
-__device__ __forceinline__ int ey_d(int d)
-{
-    return (d == 3 || d == 7 || d == 10 || d == 15 || d == 17) ? 1
-         : (d == 4 || d == 8 || d == 9 || d == 16 || d == 18) ? -1 : 0;
-}
-__device__ __forceinline__ int ez_d(int d)
-{
-    return (d == 5 || d == 11 || d == 14 || d == 15 || d == 18) ? 1
-         : (d == 6 || d == 12 || d == 13 || d == 16 || d == 17) ? -1 : 0;
-}
 
 // Control points (x, y, z, K) of particle p staged in LDS.
 __device__ __forceinline__ int stage_ctrl(const PartDev& P, int p, double* sp)
@@ -294,12 +279,13 @@ __global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball
 // the estimate decides what the FP64 sum decides; nodes in the band, or
 // within g of a control point, or of a box with h > 127, take the FP64 sum.
 //
-// Candidates for links.  M_p at any D3Q19 neighbour (|e| <= sqrt 2) is at
-// least sum_i K_i / (r_i + sqrt 2)^2.  A solid node where the FP32 value of
-// this bound clears c0 by the same margin (its relative error stays below
-// 3.5e-5 for h <= 127: the r_i + 1.4143 terms are never small) has M_p >= c0
-// at every neighbour, hence no link of any kind, and is left off p's
-// candidate list.  Every other solid node of p goes on the list.
+// Candidates for links.  M_p at any lattice neighbour (|e| <= E: sqrt 2 for
+// D3Q19, sqrt 3 for D3Q15) is at least sum_i K_i / (r_i + E)^2.  A solid
+// node where the FP32 value of this bound (E rounded up) clears c0 by the
+// same margin (its relative error stays below 3.5e-5 for h <= 127: the
+// r_i + E terms are never small) has M_p >= c0 at every neighbour, hence no
+// link of any kind, and is left off p's candidate list.  Every other solid
+// node of p goes on the list.
 constexpr int kRows = 2 * kMaxBoxHalf + 1;
 constexpr uint32_t kCandBuf = 2048;
 
@@ -439,7 +425,7 @@ __global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ba
                             const float4 q = sf[i];
                             const float dx = X - q.x, dy = Y - q.y;
                             const float r2 = fmaf(dx, dx, fmaf(dy, dy, q.z));
-                            const float t = __builtin_amdgcn_sqrtf(r2) + 1.4143f;
+                            const float t = __builtin_amdgcn_sqrtf(r2) + kMaxSpeedUp;
                             lb = fmaf(q.w, __builtin_amdgcn_rcpf(t * t), lb);
                         }
                         interior = lb >= c0hi;
@@ -609,13 +595,13 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const dou
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
                     int cn[3];
-                    const bool ok = neighbour(c, ex_d(d), ey_d(d), ez_d(d), g, cn);
+                    const bool ok = neighbour(c, cx(d), cy(d), cz(d), g, cn);
                     const uint32_t on = ok ? own[node_idx(cn, g)] : kFluid;
                     if (ok && on == (uint32_t)p) continue;
                     if (ok && on == kFluid) {
                         mask |= 1u << d;
                     } else if (treat & LBM_TREAT_MISSING) {
-                        const double Mn = metaball(sp, n, X - ex_d(d), Y - ey_d(d), Z - ez_d(d));
+                        const double Mn = metaball(sp, n, X - cx(d), Y - cy(d), Z - cz(d));
                         if (Mn < c0) mask |= 1u << d;
                     }
                 }
@@ -654,7 +640,7 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const dou
             const double sX = __shfl(X, src, 64), sY = __shfl(Y, src, 64), sZ = __shfl(Z, src, 64);
             const double sMs = __shfl(Ms, src, 64);
             if (j < total) {
-                const int ex = ex_d(d), ey = ey_d(d), ez = ez_d(d);
+                const int ex = cx(d), ey = cy(d), ez = cz(d);
                 const double Mn = metaball(sp, n, sX - ex, sY - ey, sZ - ez);
                 int cn[3];
                 const bool ok = neighbour(sc, ex, ey, ez, g, cn);
@@ -754,6 +740,8 @@ inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
 
 }  // namespace
 
+namespace MDLBM_QNS {
+
 hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot)
 {
     const int np = c->cfg.n_particles;
@@ -830,4 +818,5 @@ hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t
     return hipGetLastError();
 }
 
+}  // namespace MDLBM_QNS
 }  // namespace mdlbm

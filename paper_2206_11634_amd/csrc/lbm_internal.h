@@ -13,36 +13,6 @@
 
 namespace mdlbm {
 
-// ---------------------------------------------------------------------------
-// D3Q19 in the exported numbering (opposite of odd i is i + 1).
-// ---------------------------------------------------------------------------
-constexpr int kQ = 19;
-
-__host__ __device__ constexpr int cx(int i)
-{
-    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
-         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
-}
-__host__ __device__ constexpr int cy(int i)
-{
-    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
-         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
-}
-__host__ __device__ constexpr int cz(int i)
-{
-    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
-         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
-}
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr double wgt(int i)
-{
-    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
-}
-__host__ __device__ constexpr float wgtf(int i)
-{
-    return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
-}
-
 // Owner plane value of a fluid node (a solid node holds its particle index).
 // Largest per-particle box half-width h (the classification kernels keep a
 // table of the 2h + 1 rows of one box plane in LDS).
@@ -192,33 +162,13 @@ struct lbm_ctx {
 
 namespace mdlbm {
 
-// Launchers (lbm_stream.hip)
-hipError_t launch_init_equilibrium(lbm_ctx* c, void* f);
-hipError_t launch_stream_collide(lbm_ctx* c, const void* src, void* dst);
-hipError_t launch_boundary(lbm_ctx* c, void* f, const PartDev& P);
-hipError_t launch_refill(lbm_ctx* c, const void* fprev, void* fcur, const uint32_t* own_prev,
-                         const PartDev& P);
-hipError_t launch_get_populations(lbm_ctx* c, const void* f, double* out);
-hipError_t launch_set_populations(lbm_ctx* c, void* f, const double* in);
-hipError_t launch_zero_f64(lbm_ctx* c, double* p, int64_t n);
-hipError_t launch_split_forces(const lbm_ctx* c, double* F, double* T);
-
-// Launchers (lbm_classify.hip)
-hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot);
-hipError_t launch_clear_boxes(lbm_ctx* c, uint32_t* own, int slot, int np);
-hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot);
-hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* own_new, int slot,
-                         int np_prev);
-hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int slot);
-hipError_t launch_owner_export(const lbm_ctx* c, const uint32_t* own, int32_t* out);
-hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t* kind,
-                              int32_t* part, double* q, const int64_t* offsets_dev);
-
-// Launchers (lbm_adjoint.hip)
-hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
-                               const double* pos1, const double* vel1, const double* om1,
-                               const void* lam1, void* lam0, const double* wts, double* grad,
-                               const lbm_particles* P, double* gpos0, double* gpos1);
+// Launchers of the lattice kernels, one set per lattice (D3Q19, D3Q15).
+namespace q19 {
+#include "lbm_launchers.inc"
+}
+namespace q15 {
+#include "lbm_launchers.inc"
+}
 
 // Launchers (lbm_dem.hip)
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "lbm_internal.h"
+#include "lbm_stencil.h"
 
 namespace mdlbm {
 

@@ -18,6 +18,7 @@
 // the reconstructed population f_i(x_f, t+1) of the one fluid node
 // x_f = x_s + e_i that pulls from it, so the bulk kernel needs no link lookup.
 #include "lbm_internal.h"
+#include "lbm_stencil.h"
 #include "lbm_kernels.h"
 
 namespace mdlbm {
@@ -113,14 +114,7 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
     if (l < cnt) {
         const LinkRec r = links[(int64_t)p * cap + l];
         const int d = r.d, db = opp(d);
-        int e[3];
-        // runtime direction: decode from the numbering
-        e[0] = (d == 1 || d == 7 || d == 9 || d == 11 || d == 13) ? 1
-             : (d == 2 || d == 8 || d == 10 || d == 12 || d == 14) ? -1 : 0;
-        e[1] = (d == 3 || d == 7 || d == 10 || d == 15 || d == 17) ? 1
-             : (d == 4 || d == 8 || d == 9 || d == 16 || d == 18) ? -1 : 0;
-        e[2] = (d == 5 || d == 11 || d == 14 || d == 15 || d == 18) ? 1
-             : (d == 6 || d == 12 || d == 13 || d == 16 || d == 17) ? -1 : 0;
+        const int e[3] = {cx(d), cy(d), cz(d)};
         const uint32_t nx = g.n[0], ny = g.n[1];
         const int cs[3] = {(int)(r.node % nx), (int)((r.node / nx) % ny), (int)(r.node / (nx * ny))};
         int cn[3] = {cs[0] - e[0], cs[1] - e[1], cs[2] - e[2]};
@@ -455,6 +449,8 @@ struct RunSet {
 
 }  // namespace
 
+namespace MDLBM_QNS {
+
 hipError_t launch_init_equilibrium(lbm_ctx* c, void* f)
 {
     return dispatch<RunInit>(c->cfg.storage, c, f);
@@ -494,4 +490,5 @@ hipError_t launch_split_forces(const lbm_ctx* c, double* F, double* T)
     return hipGetLastError();
 }
 
+}  // namespace MDLBM_QNS
 }  // namespace mdlbm

@@ -81,6 +81,22 @@ def test_init_rejects_unknown_treatment_bits(lib):
     assert b"treatment" in lib.lbm_last_error(None)
 
 
+def test_query_sizes_follow_the_lattice(lib):
+    for lattice, q in ((0, 19), (19, 19), (15, 15)):
+        cfg = _cfg()
+        cfg.lattice = lattice
+        s = B.lbm_query_sizes(cfg)
+        es = 4
+        assert s.population_bytes == q * s.cell_stride * es
+        assert s.adjoint_bytes == q * s.cell_stride * 4
+    cfg = _cfg()
+    cfg.lattice = 27
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_query_sizes(cfg)
+    assert e.value.code == B.LBM_EINVAL
+    assert b"lattice" in lib.lbm_last_error(None)
+
+
 def test_query_sizes_rejects_bad_input(lib):
     with pytest.raises(B.LbmError) as e:
         B.lbm_query_sizes(_cfg(dims=(0, 4, 4)))

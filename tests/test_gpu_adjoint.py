@@ -251,3 +251,12 @@ def test_fp64_rotation_adjoint_matches_moving_geometry_differences(omega):
               AD.evaluate(_rotated(prob, 0, a, -h), v, F, tau)) / (2 * h)
         assert abs(gt0[0, a] - fd) <= 2e-5 * scale, (a, gt0[0, a], fd)
     assert np.abs(gt0[0]).max() > 0
+
+
+def test_d3q15_fp64_adjoint_matches_finite_differences():
+    """The adjoint kernels built for the paper's D3Q15 lattice."""
+    prob = _problem("f64", steps=30, window=12, n=26)
+    w15 = np.array([2 / 9] + [1 / 9] * 6 + [1 / 72] * 8)
+    f0 = np.repeat(w15[:, None], prob.lat.ncell, axis=1)
+    prob = dataclasses.replace(prob, lattice=15, f0=f0)
+    _check(prob, prob, _gpu_J, 2e-6)

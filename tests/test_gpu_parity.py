@@ -38,10 +38,12 @@ def _compare_geometry(gpu, ora, tag):
         assert np.array_equal(parts, ora.owner_prev[nodes] - 1)
 
 
-def _run(lat, ps, storage, steps, treat=3, check_geometry=True, tag="", classify="auto"):
-    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat, classify=classify)
+def _run(lat, ps, storage, steps, treat=3, check_geometry=True, tag="", classify="auto",
+         lattice=19):
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat, classify=classify,
+                                  lattice=lattice)
     parts = B.DeviceParticles(ps)
-    ora = O.Oracle(lat, treat=treat)
+    ora = O.Oracle(lat, Q=lattice, treat=treat)
     Fo_all, Fg_all, To_all, Tg_all = [], [], [], []
     refilled = 0
     for n in range(steps):
@@ -124,14 +126,15 @@ def test_treatment_switches(treat):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_poiseuille_channel_without_particles(storage):
+@pytest.mark.parametrize("lattice", [19, 15])
+def test_poiseuille_channel_without_particles(storage, lattice):
     tau = 0.5 + np.sqrt(3.0) / 4.0
     H, g = 12, 1e-6
     lat = W.LatticeSpec(5, H, 3, (1, 0, 1), tau=tau, body_force=(g, 0, 0))
     ps = W.make_particles([], np.zeros((0, 3)), np.zeros((0, 4)), 1.0)
-    gpu = B.Lattice(lat, storage=storage)
+    gpu = B.Lattice(lat, storage=storage, lattice=lattice)
     parts = B.DeviceParticles(ps)
-    ora = O.Oracle(lat)
+    ora = O.Oracle(lat, Q=lattice)
     ora.classify(ps)
     gpu.classify(parts)
     for _ in range(300):
@@ -221,3 +224,40 @@ def test_dem_parity_tilted_flat_pair(ang):
     for k in ("pos", "vel", "omega", "quat"):
         a, b = getattr(G, k), getattr(P, k)
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
+
+
+# ---------------------------------------------------------------------------
+# D3Q15, the paper's lattice (Sec. 2.2): the same kernels built for 15
+# directions, against the oracle's D3Q15 stencil
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("classify", ["balls", "sweep"])
+@pytest.mark.parametrize("case", GEOM_CASES[:3], ids=lambda c: f"seed{c['seed']}")
+def test_d3q15_geometry_and_plain_fp64_step_parity(case, classify):
+    lat, ps = W.tiny_case(case["seed"], dims=case["dims"], periodic=case["periodic"],
+                          n_particles=case["n_particles"], diameter_range=(4.0, 7.0),
+                          speed=0.06, spin=0.006, u0=(0.02, -0.01, 0.005))
+    r = _run(lat, ps, "f64", 8, tag=f"q15 seed{case['seed']} {classify}", classify=classify,
+             lattice=15)
+    assert r["refilled"] > 0
+    assert r["pop_err"] < POP_TOL["f64"], r
+    assert r["F"] < FORCE_TOL["f64"] and r["T"] < FORCE_TOL["f64"], r
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_d3q15_deviation_storage_parity(storage):
+    lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
+                          diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
+                          u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
+    r = _run(lat, ps, storage, 8, tag=f"q15 {storage}", lattice=15)
+    assert r["pop_err"] < POP_TOL[storage], r
+    assert r["F"] < FORCE_TOL[storage] and r["T"] < FORCE_TOL[storage], r
+
+
+@pytest.mark.parametrize("treat", [B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_EXACT_Q,
+                                   B.TREAT_MISSING, B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_NEQ_SPLIT])
+def test_d3q15_treatment_switches(treat):
+    lat, ps = W.tiny_case(5, dims=(28, 26, 18), periodic=(1, 1, 0), n_particles=3,
+                          diameter_range=(5.0, 7.0), speed=0.06, spin=0.006, u0=(0.01, 0.0, 0.0))
+    r = _run(lat, ps, "f64", 4, treat=treat, tag=f"q15 treat{treat}", lattice=15)
+    assert r["pop_err"] < POP_TOL["f64"] and r["F"] < FORCE_TOL["f64"], r
