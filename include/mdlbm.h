@@ -312,6 +312,32 @@ int lbm_tape_begin(lbm_ctx* ctx, int max_steps);
 int lbm_adjoint(lbm_ctx* ctx, const lbm_particles* P, const double* weights, void* lam_dev,
                 double* grad_dev, double* gpos_dev);
 
+/* The adjoint of a run in which the particles move freely: each taped step
+ * was followed by dem_step(ctx, P, n_sub, dt, prm) and then
+ * lbm_classify_nodes, so the state s_{k+1} = (x, q, v, omega) that the next
+ * step used came from s_k and the step's F^h, T^h through the DEM.  Running
+ * backwards, each step (1) adds the refill's wall-velocity terms to the
+ * adjoint of s_{k+1}, (2) applies the transposed Jacobian of the dem_step
+ * call (forward-mode dual numbers over x, a small world-frame rotation
+ * theta, v, omega, F^h and T^h, through the same substeps), giving the
+ * adjoint of s_k and dJ/dF^h_k, dJ/dT^h_k, (3) runs the step's node and link
+ * adjoint with objective weights (wF, wT) + (dJ/dF^h_k, dJ/dT^h_k), adding
+ * the link terms of s_k (pose through q and the lever arms, v and omega
+ * through u_w).  Contact forces are not differentiated (free motion).
+ *   P         the state after the last taped step's dem_step (the one the
+ *             last classification used);
+ *   weights   host [n][6]: (wF, wT) per particle, the same for every step;
+ *   prm, n_sub, dt  the dem_step arguments of the run;
+ *   lam_dev   as for lbm_adjoint;
+ *   grad_dev  device FP64 [4], accumulated into: dJ/dF (3), dJ/dtau;
+ *   sigma_dev device FP64 [n][12]: on entry the adjoint of P (zeros for J
+ *             above), on return the adjoint of the state the first taped
+ *             step used, ordered (x, theta, v, omega).
+ * Synchronises.  ESTATE when nothing was taped. */
+int lbm_adjoint_coupled(lbm_ctx* ctx, const lbm_particles* P, const double* weights,
+                        const dem_params* prm, int n_sub, double dt, void* lam_dev,
+                        double* grad_dev, double* sigma_dev);
+
 /* ---- kernel timing (hipEvent pairs around each launch group) ------------ */
 
 typedef enum {

@@ -173,6 +173,124 @@ def trajectory_gradients(prob: Problem, gx: np.ndarray, dv: np.ndarray):
     return gx[:, :, :3].sum(0), dv + (k * gx[:, :, :3]).sum(0), gt0
 
 
+# ---------------------------------------------------------------------------
+# free motion: the particles follow the DEM under the step's forces
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class FreeProblem:
+    """J(s_0) = sum over steps k < T of wF . F^h(k) + wT . T^h(k) for a run in
+    which, after every lattice step, dem_step advances the particles (n_sub
+    substeps of 1/n_sub) under F^h, T^h and relative gravity.  The gradient
+    is with respect to the initial state s_0 = (x, theta, v, omega) of every
+    particle (theta a small world-frame rotation of the initial orientation),
+    the fluid body force and tau.  Contact forces, if any occur, are not
+    differentiated."""
+    lat: W.LatticeSpec
+    ps: W.ParticleSet
+    steps: int
+    window: int = 100
+    storage: str = "f32"
+    weights: np.ndarray = None
+    f0: np.ndarray = None
+    treatments: int = B.TREAT_VIBB | B.TREAT_MISSING
+    lattice: int = 19
+    gravity: tuple = (0.0, 0.0, 0.0)
+    n_sub: int = 10
+
+    def __post_init__(self):
+        if self.weights is None:
+            w = np.zeros((self.ps.n, 6))
+            w[0, 0] = 1.0 / self.steps
+            self.weights = w
+
+    def dem(self):
+        return B.DemParams.make(**W.dem_defaults(self.ps, gravity=self.gravity))
+
+
+class _FreeRun:
+    def __init__(self, prob: FreeProblem, body_force, tau):
+        self.prob = prob
+        lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
+                                  tau=float(tau))
+        self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage,
+                                           treatments=prob.treatments, lattice=prob.lattice)
+        self.parts = B.DeviceParticles(prob.ps)
+        self.prm = prob.dem()
+        self.dt = 1.0 / prob.n_sub
+
+    def state(self):
+        return {k: self.parts.t[k].clone() for k in ("pos", "quat", "vel", "omega", "world_pts")}
+
+    def load(self, st):
+        for k, v in st.items():
+            self.parts.t[k].copy_(v)
+
+    def advance(self):
+        self.gpu.dem(self.parts, self.prob.n_sub, self.dt, self.prm)
+        self.gpu.classify(self.parts)
+
+
+def forward_free(prob: FreeProblem, body_force, tau, keep: bool = False):
+    """J of the free-motion run, and the run (with checkpoints of the lattice
+    and of the particle state at every window start) if keep."""
+    run = _FreeRun(prob, body_force, tau)
+    gpu, T, n = run.gpu, prob.steps, prob.ps.n
+    torch = gpu.torch
+    if prob.f0 is not None:
+        gpu.set_populations(prob.f0)
+    run.ckpt = {}
+    hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
+    gpu.classify(run.parts)
+    for k in range(T):
+        if keep and k % prob.window == 0:
+            run.ckpt[k] = (gpu.checkpoint(), run.state())
+        gpu.step(run.parts)
+        gpu.forces(hist[k, 0], hist[k, 1])
+        run.advance()
+    w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
+    J = float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
+    if not keep:
+        gpu.close()
+        return J, None
+    run.final = run.state()
+    return J, run
+
+
+def backward_free(run: _FreeRun):
+    """(dJ/ds_0 [n][12] ordered x, theta, v, omega; dJ/dF [3]; dJ/dtau) by the
+    coupled adjoint, window by window from the last checkpoint."""
+    prob, gpu = run.prob, run.gpu
+    torch = gpu.torch
+    n = prob.ps.n
+    lam = gpu.adjoint_field()
+    g = torch.zeros(4, dtype=torch.float64, device=gpu.device)
+    sig = torch.zeros((max(n, 1), 12), dtype=torch.float64, device=gpu.device)
+    for w0 in sorted(run.ckpt, reverse=True):
+        w1 = min(w0 + prob.window, prob.steps)
+        ck, st = run.ckpt[w0]
+        gpu.restore(ck)
+        run.load(st)
+        gpu.classify(run.parts)   # reproduces the geometry at w0, refills nothing
+        gpu.tape_begin(w1 - w0)
+        for k in range(w0, w1):
+            gpu.step(run.parts)
+            run.advance()
+        gpu.adjoint_coupled(run.parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig)
+    out = g.cpu().numpy()
+    s0 = sig[:n].cpu().numpy()
+    gpu.close()
+    return s0, out[:3].copy(), float(out[3])
+
+
+def evaluate_free(prob: FreeProblem, body_force, tau, grad: bool = False):
+    """J, and with grad=True also (dJ/ds_0 [n][12], dJ/dF [3], dJ/dtau)."""
+    J, run = forward_free(prob, body_force, tau, keep=grad)
+    if not grad:
+        return J
+    return (J,) + backward_free(run)
+
+
 def _make_function():
     import torch
 

@@ -85,7 +85,7 @@ EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_
            "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
-           "lbm_tape_begin", "lbm_adjoint"]
+           "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled"]
 
 _lib = None
 
@@ -123,6 +123,8 @@ def load(path: Path | None = None):
         "lbm_checkpoint_load": [_P, _P],
         "lbm_tape_begin": [_P, ctypes.c_int],
         "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P, _P],
+        "lbm_adjoint_coupled": [_P, ctypes.POINTER(LbmParticles), _P, ctypes.POINTER(DemParams),
+                                ctypes.c_int, ctypes.c_double, _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -443,6 +445,16 @@ class Lattice:
                                   w.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(grad),
                                   None if gpos is None else _ptr(gpos)),
                self.ctx)
+
+    def adjoint_coupled(self, parts: "DeviceParticles", weights: np.ndarray, prm: DemParams,
+                        n_sub: int, dt: float, lam, grad, sigma):
+        """Free-motion adjoint over the taped steps (each followed by dem with
+        these arguments); sigma: device FP64 [n, 12], in/out."""
+        w = np.ascontiguousarray(weights, np.float64).reshape(-1)
+        _check(load().lbm_adjoint_coupled(self.ctx, ctypes.byref(parts.struct),
+                                          w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm),
+                                          int(n_sub), float(dt), _ptr(lam), _ptr(grad),
+                                          _ptr(sigma)), self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -28,6 +28,7 @@ LIB = PKG / "libmdlbm.so"
 SOURCES = [
     ("lbm_api.hip", "lbm_api", []),
     ("lbm_dem.hip", "lbm_dem", []),
+    ("lbm_dem_adjoint.hip", "lbm_dem_adjoint", []),
 ] + [
     (src, f"{src[:-4]}_q{q}", [f"-DMDLBM_Q={q}", *extra])
     for q in (19, 15)

@@ -177,15 +177,25 @@ __device__ __forceinline__ void metaball_grad(const double* pts, const double* K
     }
 }
 
-// Pose data of one taped step for the geometry terms of the adjoint.
+// Pose data of one taped step for the geometry terms of the adjoint, and
+// where the per-particle derivatives go.  Prescribed trajectories: the pose
+// gradients of each step (stride 6: x, theta) and one dJ/dv for all steps
+// (stride 3); free motion: the state adjoints of the steps (stride 12: x,
+// theta, v, omega).
 struct GeoArgs {
     const double* wpts = nullptr;   // world control points of the step's pose
     const double* K = nullptr;
     const double* c0 = nullptr;
     const int32_t* off = nullptr;
-    double* g_links = nullptr;      // [np][6] dJ/d(x_p, theta_p) of the pose the links used
-    double* g_refill = nullptr;     // [np][6] the same for the pose the refill used
     int exact_q = 0;
+    double* g_links = nullptr;      // dJ/d(x_p, theta_p) of the pose the links used
+    double* g_refill = nullptr;     // dJ/dx_p of the pose the refill used
+    int gstride = 6;
+    double* v_links = nullptr;      // dJ/dv_p seen by the links (null: grad + 4)
+    double* v_refill = nullptr;     // dJ/dv_p seen by the refill (null: grad + 4)
+    int vstride = 3;
+    double* w_links = nullptr;      // dJ/domega_p seen by the links (null: not kept)
+    double* w_refill = nullptr;     // dJ/domega_p seen by the refill (null: not kept)
 };
 
 __device__ __forceinline__ void dir_of(int d, int e[3])
@@ -335,14 +345,21 @@ __global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __res
             }
             co = adj_collide<DEV, A>(lam, pre, ph, acc);
         }
+        // a node refilled between n and n + 1 leaves the entries it read from
+        // nodes fluid at n to k_adj_refill, so the two kernels write
+        // disjoint entries and may run in either order
+        const bool refilled = own0[cell] != kFluid && own1[cell] == kFluid;
 #pragma unroll
         for (int j = 0; j < kQ; ++j) {
             const A v = live ? co(j, lam[j]) : A(0);
             const int sx = 1 - cx(j), sy = 1 - cy(j), sz = 1 - cz(j);  // x - e_j
-            if (vx[sx] && vy[sy] && vz[sz])
-                lam0[(int64_t)j * g.stride + ox[sx] + oy[sy] + oz[sz]] = v;
-            else  // x pulled f_j through a wall: its own f_opp(j)
+            if (vx[sx] && vy[sy] && vz[sz]) {
+                const uint32_t y = ox[sx] + oy[sy] + oz[sz];
+                if (!(refilled && j > 0 && own0[y] == kFluid))
+                    lam0[(int64_t)j * g.stride + y] = v;
+            } else {  // x pulled f_j through a wall: its own f_opp(j)
                 lam0[(int64_t)opp(j) * g.stride + cell] = v;
+            }
         }
     }
     double* outs[4] = {grad + 0, grad + 1, grad + 2, grad + 3};
@@ -365,7 +382,7 @@ __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __r
                                                     typename St<S>::A* __restrict__ lam0,
                                                     const double* pos1, const double* vel1,
                                                     const double* om1, Geom g, Phys ph,
-                                                    double* grad, double* gpos)
+                                                    double* grad, GeoArgs ga)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
@@ -435,14 +452,22 @@ __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __r
                 }
             }
         }
+        double* vout = ga.v_refill ? ga.v_refill + (int64_t)ga.vstride * p : grad + 4 + 3 * p;
         for (int k = 0; k < 3; ++k)
-            if (dv[k] != 0.0) atomicAdd(grad + 4 + 3 * p + k, dv[k]);
-        if (gpos) {
+            if (dv[k] != 0.0) atomicAdd(vout + k, dv[k]);
+        if (ga.g_refill) {
             // u_new = v + omega x (x - x_p): dJ/dx_p = -(dJ/du_new) x omega
             const double gx[3] = {-(dv[1] * wp[2] - dv[2] * wp[1]), -(dv[2] * wp[0] - dv[0] * wp[2]),
                                   -(dv[0] * wp[1] - dv[1] * wp[0])};
             for (int k = 0; k < 3; ++k)
-                if (gx[k] != 0.0) atomicAdd(gpos + 6 * p + k, gx[k]);
+                if (gx[k] != 0.0) atomicAdd(ga.g_refill + (int64_t)ga.gstride * p + k, gx[k]);
+        }
+        if (ga.w_refill) {
+            // dJ/domega = (x - x_p) x dJ/du_new
+            const double gw[3] = {rr[1] * dv[2] - rr[2] * dv[1], rr[2] * dv[0] - rr[0] * dv[2],
+                                  rr[0] * dv[1] - rr[1] * dv[0]};
+            for (int k = 0; k < 3; ++k)
+                if (gw[k] != 0.0) atomicAdd(ga.w_refill + (int64_t)ga.vstride * p + k, gw[k]);
         }
         // entries read through the streaming rule of direction j (x - e_j fluid
         // at n): f_j(x - e_j) also fed the bounce-back of opp(j) when x + e_j
@@ -489,8 +514,9 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
     const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
     if (blockIdx.x * 256u >= cnt) return;
     const uint32_t l = blockIdx.x * 256u + threadIdx.x;
-    // dJ/dF (3), dJ/dv_p (3), dJ/dx_p (3, GEO), dJ/dtheta_p (3, GEO)
-    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // dJ/dF (3), dJ/dv_p (3), dJ/dx_p (3, GEO), dJ/dtheta_p (3, GEO),
+    // dJ/domega_p (3, GEO)
+    double acc[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (l < cnt) {
         const LinkRec r = links[(int64_t)p * cap + l];
         const int d = r.d, db = opp(d);
@@ -672,13 +698,27 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
                 acc[6 + a] = dq * qx[a] - Jr[a];
                 acc[9 + a] = dq * qt[a];
             }
+            // u_w = v + omega x r: dJ/domega = r x G
+            acc[12] = rr[1] * G[2] - rr[2] * G[1];
+            acc[13] = rr[2] * G[0] - rr[0] * G[2];
+            acc[14] = rr[0] * G[1] - rr[1] * G[0];
         }
     }
     if constexpr (GEO) {
-        double* gl = ga.g_links + 6 * p;
-        double* outs[12] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
-                            grad + 6 + 3 * p, gl, gl + 1, gl + 2, gl + 3, gl + 4, gl + 5};
-        block_add<12>(acc, outs);
+        double* gl = ga.g_links + (int64_t)ga.gstride * p;
+        double* vl = ga.v_links ? ga.v_links + (int64_t)ga.vstride * p : grad + 4 + 3 * p;
+        if (ga.w_links) {
+            double* wl = ga.w_links + (int64_t)ga.vstride * p;
+            double* outs[15] = {grad + 0, grad + 1, grad + 2, vl, vl + 1, vl + 2, gl, gl + 1, gl + 2,
+                                gl + 3, gl + 4, gl + 5, wl, wl + 1, wl + 2};
+            block_add<15>(acc, outs);
+        } else {
+            double a12[12];
+            for (int k = 0; k < 12; ++k) a12[k] = acc[k];
+            double* outs[12] = {grad + 0, grad + 1, grad + 2, vl, vl + 1, vl + 2, gl, gl + 1, gl + 2,
+                                gl + 3, gl + 4, gl + 5};
+            block_add<12>(a12, outs);
+        }
     } else {
         double a6[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5]};
         double* outs[6] = {grad + 0, grad + 1, grad + 2, grad + 4 + 3 * p, grad + 5 + 3 * p,
@@ -693,16 +733,19 @@ template <int S>
 struct RunAdj {
     static hipError_t run(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1, const double* pos1,
                           const double* vel1, const double* om1, const void* lam1,
-                          void* lam0, const double* wts, double* grad, const GeoArgs& ga)
+                          void* lam0, const double* wts, double* grad, const GeoArgs& ga,
+                          int parts)
     {
         using T = typename St<S>::T;
         using A = typename St<S>::A;
         const uint32_t nb = blocks_for(c->geom.ncell);
+        if (parts & kAdjRefill)
+            hipLaunchKernelGGL(k_adj_refill<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f,
+                               ts.own, own1, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom,
+                               c->phys, grad, ga);
+        if (!(parts & kAdjMain)) return hipGetLastError();
         hipLaunchKernelGGL(k_adj_node<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f, ts.own,
                            own1, (const A*)lam1, (A*)lam0, c->geom, c->phys, grad);
-        hipLaunchKernelGGL(k_adj_refill<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f,
-                           ts.own, own1, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom,
-                           c->phys, grad, ga.g_refill);
         if (c->cfg.n_particles > 0 && ts.link_max > 0) {
             const int np = c->cfg.n_particles;
             dim3 grid(blocks_for(ts.link_max), np);
@@ -728,27 +771,33 @@ namespace MDLBM_QNS {
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
                                const void* lam1, void* lam0, const double* wts,
-                               double* grad, const lbm_particles* P, double* gpos0,
-                               double* gpos1)
+                               double* grad, const lbm_particles* P, const AdjOut& out, int parts)
 {
     GeoArgs ga;
-    if (gpos0) {
-        const int np = c->cfg.n_particles;
-        ga.wpts = ts.part + 9 * np;
-        ga.K = P->K;
-        ga.c0 = P->c0;
-        ga.off = P->ctrl_off;
-        ga.g_links = gpos0;
-        ga.g_refill = gpos1;
-        ga.exact_q = (c->cfg.treatments & LBM_TREAT_EXACT_Q) ? 1 : 0;
-    }
+    const int np = c->cfg.n_particles;
+    ga.wpts = ts.part + 9 * np;
+    ga.K = P->K;
+    ga.c0 = P->c0;
+    ga.off = P->ctrl_off;
+    ga.exact_q = (c->cfg.treatments & LBM_TREAT_EXACT_Q) ? 1 : 0;
+    ga.g_links = out.g_links;
+    ga.g_refill = out.g_refill;
+    ga.gstride = out.gstride;
+    ga.v_links = out.v_links;
+    ga.v_refill = out.v_refill;
+    ga.w_links = out.w_links;
+    ga.w_refill = out.w_refill;
+    ga.vstride = out.vstride;
     switch (c->cfg.storage) {
     case LBM_STORE_F64:
-        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga);
+        return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga,
+                                          parts);
     case LBM_STORE_F32:
-        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga);
+        return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga,
+                                          parts);
     case LBM_STORE_F16:
-        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga);
+        return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga,
+                                          parts);
     default: return hipErrorInvalidValue;
     }
 }

@@ -178,6 +178,11 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
                                  hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(t.part + 9 * np, P->world_pts, sizeof(double) * 3 * c->cfg.n_ctrl,
                                  hipMemcpyDeviceToDevice, c->stream));
+        double* tq = t.part + 9 * np + 3 * c->cfg.n_ctrl;
+        HIPCHK(c, hipMemcpyAsync(tq, P->quat, sizeof(double) * 4 * np, hipMemcpyDeviceToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(tq + 4 * np, c->FT, sizeof(double) * 6 * np,
+                                 hipMemcpyDeviceToDevice, c->stream));
     }
     c->tape_len += 1;
     return LBM_OK;
@@ -363,6 +368,7 @@ int lbm_destroy(lbm_ctx* c)
     }
     (void)hipFree(c->adj_scratch);
     (void)hipFree(c->adj_wts);
+    (void)hipFree(c->adj_sig);
     (void)hipFree(c->hist_pp);
     (void)hipFree(c->pairs);
     (void)hipFree(c->pair_count);
@@ -680,7 +686,7 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
             if (e == hipSuccess) e = alloc(&t.own, c->sizes.owner_bytes / sizeof(uint32_t));
             if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
             if (e == hipSuccess)
-                e = alloc(&t.part, (size_t)9 * std::max(np, 1) + (size_t)3 * c->cfg.n_ctrl);
+                e = alloc(&t.part, (size_t)19 * std::max(np, 1) + (size_t)3 * c->cfg.n_ctrl);
             if (e != hipSuccess) {
                 free_tape(c);
                 return fail(c, LBM_ENOMEM, "tape allocation failed");
@@ -720,16 +726,94 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         const double* pos1 = last ? P->pos : c->tape[s + 1].part;
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
-        double* g0 = (gpos_dev && np > 0) ? gpos_dev + (size_t)6 * np * s : nullptr;
-        double* g1 = g0 ? g0 + 6 * np : nullptr;
+        AdjOut out;
+        if (gpos_dev && np > 0) {
+            out.g_links = gpos_dev + (size_t)6 * np * s;
+            out.g_refill = out.g_links + 6 * np;
+        }
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
         HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
-                                      c->adj_wts, grad_dev, P, g0, g1));
+                                             c->adj_wts, grad_dev, P, out,
+                                             kAdjRefill | kAdjMain));
         in = 1 - in;
     }
     if (in != 0)
         HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
                                  c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->tape_len = 0;
+    c->taping = false;
+    return LBM_OK;
+}
+
+int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weights,
+                        const dem_params* prm, int n_sub, double dt, void* lam_dev,
+                        double* grad_dev, double* sigma_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (!lam_dev || !grad_dev || !prm) return fail(c, LBM_EINVAL, "null argument");
+    if (n_sub < 1 || !(dt > 0.0)) return fail(c, LBM_EINVAL, "n_sub must be >= 1 and dt > 0");
+    if (c->tape_len == 0) return fail(c, LBM_ESTATE, "nothing was taped");
+    int rc = check_particles(c, P, true);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    if (np > 0 && (!weights || !sigma_dev)) return fail(c, LBM_EINVAL, "null objective weights or state adjoint");
+    if (!c->adj_scratch && hipMalloc(&c->adj_scratch, c->sizes.adjoint_bytes) != hipSuccess)
+        return fail(c, LBM_ENOMEM, "adjoint scratch allocation failed");
+    const size_t nps = (size_t)std::max(np, 1);
+    if (!c->adj_wts && alloc(&c->adj_wts, 6 * nps) != hipSuccess)
+        return fail(c, LBM_ENOMEM, "adjoint weight allocation failed");
+    if (!c->adj_sig && alloc(&c->adj_sig, 2 * 12 * nps + 6 * nps) != hipSuccess)
+        return fail(c, LBM_ENOMEM, "state adjoint allocation failed");
+    double* sig[2] = {c->adj_sig, c->adj_sig + 12 * nps};
+    double* wJ = c->adj_sig + 24 * nps;
+    if (np > 0) {
+        HIPCHK(c, hipMemcpyAsync(wJ, weights, sizeof(double) * 6 * np, hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(sig[0], sigma_dev, sizeof(double) * 12 * np,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+    void* bufs[2] = {lam_dev, c->adj_scratch};
+    int in = 0, si = 0;
+    for (int s = c->tape_len - 1; s >= 0; --s) {
+        const TapeStep& ts = c->tape[s];
+        const bool last = s + 1 >= c->tape_len;
+        const uint32_t* own1 = last ? c->own[c->own_cur] : c->tape[s + 1].own;
+        const double* pos1 = last ? P->pos : c->tape[s + 1].part;
+        const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
+        const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
+        double* s1 = sig[si];      // adjoint of the state after this step's dem_step
+        double* s0 = sig[1 - si];  // adjoint of the state this step used
+        PhaseTimer tm(c, LBM_PHASE_ADJOINT);
+        // 1. nodes refilled by the classification of the next state: their
+        //    wall velocities belong to s1
+        AdjOut ro;
+        ro.g_refill = s1;
+        ro.v_refill = s1 + 6;
+        ro.w_refill = s1 + 9;
+        ro.gstride = ro.vstride = 12;
+        HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
+                                             c->adj_wts, grad_dev, P, ro, kAdjRefill));
+        // 2. the DEM call: s1 -> s0, and this step's force weights
+        HIPCHK(c, launch_dem_adjoint(c, ts, P, *prm, n_sub, dt, s1, s0, wJ, c->adj_wts));
+        // 3. nodes and links of this step under those weights, into s0
+        AdjOut lo;
+        lo.g_links = s0;
+        lo.v_links = s0 + 6;
+        lo.w_links = s0 + 9;
+        lo.gstride = lo.vstride = 12;
+        HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
+                                             c->adj_wts, grad_dev, P, lo, kAdjMain));
+        in = 1 - in;
+        si = 1 - si;
+    }
+    if (in != 0)
+        HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    if (np > 0)
+        HIPCHK(c, hipMemcpyAsync(sigma_dev, sig[si], sizeof(double) * 12 * np,
+                                 hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->tape_len = 0;
     c->taping = false;

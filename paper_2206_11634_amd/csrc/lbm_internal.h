@@ -46,7 +46,8 @@ struct TapeStep {
     int64_t link_alloc = 0;      // records allocated
     uint32_t* cursor = nullptr;  // [np * kCursorPad]
     int64_t link_max = 0;
-    double* part = nullptr;      // [9 np + 3 n_ctrl]: pos, vel, omega, world control points
+    double* part = nullptr;      // [19 np + 3 n_ctrl]: pos, vel, omega, world control
+                                 // points, quaternion (4 np), F^h and T^h (6 np)
 };
 
 // Lattice geometry passed by value to kernels.
@@ -157,10 +158,27 @@ struct lbm_ctx {
     bool taping = false;
     void* adj_scratch = nullptr;  // the second adjoint field of the ping-pong
     double* adj_wts = nullptr;
+    double* adj_sig = nullptr;    // free-motion state adjoints [2][np][12] + weights [np][6]
     std::string last_error;
 };
 
 namespace mdlbm {
+
+// Where an adjoint step puts its per-particle derivatives (all optional):
+// pose gradients (x, theta) of the links' pose and dJ/dx of the refill's
+// pose, with stride gstride; dJ/dv and dJ/domega seen by the links and by the
+// refill, with stride vstride (dJ/dv defaults to grad + 4 + 3 p).
+struct AdjOut {
+    double* g_links = nullptr;
+    double* g_refill = nullptr;
+    int gstride = 6;
+    double* v_links = nullptr;
+    double* v_refill = nullptr;
+    double* w_links = nullptr;
+    double* w_refill = nullptr;
+    int vstride = 3;
+};
+constexpr int kAdjRefill = 1, kAdjMain = 2;
 
 // Launchers of the lattice kernels, one set per lattice (D3Q19, D3Q15).
 namespace q19 {
@@ -170,7 +188,10 @@ namespace q15 {
 #include "lbm_launchers.inc"
 }
 
-// Launchers (lbm_dem.hip)
+// Launchers (lbm_dem.hip, lbm_dem_adjoint.hip)
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);
+hipError_t launch_dem_adjoint(lbm_ctx* c, const TapeStep& ts, const lbm_particles* P,
+                              const dem_params& prm, int n_sub, double dt, const double* sig1,
+                              double* sig0, const double* wJ, double* wts);
 
 }  // namespace mdlbm

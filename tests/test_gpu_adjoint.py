@@ -260,3 +260,102 @@ def test_d3q15_fp64_adjoint_matches_finite_differences():
     f0 = np.repeat(w15[:, None], prob.lat.ncell, axis=1)
     prob = dataclasses.replace(prob, lattice=15, f0=f0)
     _check(prob, prob, _gpu_J, 2e-6)
+
+
+# ---------------------------------------------------------------------------
+# free motion: the adjoint through dem_step
+# ---------------------------------------------------------------------------
+
+def _free_problem(steps=20, window=8):
+    rng = np.random.default_rng(77)
+    n = 30
+    lat = W.LatticeSpec(n, n - 2, n, (1, 0, 1), tau=0.7, body_force=(1e-5, 0.0, 0.0))
+    pts = np.array([[0.0, 0, 0], [1.0, 0, 0], [2.0, 0, 0], [1.0, 0.6, 0]])
+    sh = W.metaball_shape(pts, rng.uniform(0.5, 1.5, 4) * 0.12, 0.1, length=8.0,
+                          axis=np.array([1.0, 0, 0]), samples_per_unit=4.0)
+    sh2 = W.sphere_shape(6.0, 0.1)
+    ps = W.make_particles([sh, sh2], [[n / 2, (n - 2) / 2, n / 2], [n / 2 + 1.0, 7.0, n / 2 + 9.5]],
+                          [W.random_quaternion(rng), [1, 0, 0, 0]], 1.5,
+                          vel=np.array([[0.03, 0.004, -0.005], [0.02, 0.0, 0.01]]),
+                          omega=np.array([[0.002, -0.001, 0.003], [0.0, 0.001, 0.0]]))
+    w = np.zeros((2, 6))
+    w[0, 0] = 1.0 / steps
+    w[0, 4] = 0.5 / steps
+    w[1, 1] = 0.3 / steps
+    wq = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    f0 = np.repeat(wq[:, None], lat.ncell, axis=1)
+    return AD.FreeProblem(lat=lat, ps=ps, steps=steps, window=window, storage="f64", weights=w,
+                          f0=f0, gravity=(0.0, -2e-4, 0.0))
+
+
+def _free_shift(prob, p, block, a, h):
+    ps = prob.ps.copy()
+    if block == 0:
+        ps.pos[p, a] += h
+    elif block == 1:
+        ax = np.zeros(3)
+        ax[a] = 1.0
+        dq = np.concatenate([[np.cos(0.5 * h)], np.sin(0.5 * h) * ax])
+        ps.quat[p] = W.quat_mul(dq, ps.quat[p])
+    elif block == 2:
+        ps.vel[p, a] += h
+    else:
+        ps.omega[p, a] += h
+    ps.refresh_world()
+    return dataclasses.replace(prob, ps=ps)
+
+
+def test_fp64_free_motion_adjoint_matches_finite_differences():
+    """dJ/d(x, theta, v, omega) of both initial states, dJ/dF and dJ/dtau of
+    a 20-step run in which the DEM moves the bodies under the step's forces
+    and gravity (windows of 8), against central differences of the same
+    free-motion forward pass, each block within 2e-5 of its largest entry."""
+    prob = _free_problem()
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
+    h = 1e-6
+    for block in range(4):
+        scale = max(np.abs(s0[:, 3 * block:3 * block + 3]).max(), 1e-12)
+        for p in range(2):
+            for a in range(3):
+                fd = (AD.evaluate_free(_free_shift(prob, p, block, a, h), F, tau) -
+                      AD.evaluate_free(_free_shift(prob, p, block, a, -h), F, tau)) / (2 * h)
+                got = s0[p, 3 * block + a]
+                assert abs(got - fd) <= 2e-5 * scale, (block, p, a, got, fd)
+    e = np.array([1e-6, 0.0, 0.0])
+    fd = (AD.evaluate_free(prob, F + e, tau) - AD.evaluate_free(prob, F - e, tau)) / 2e-6
+    assert abs(dF[0] - fd) <= 2e-5 * abs(fd), (dF[0], fd)
+    fd = (AD.evaluate_free(prob, F, tau + 1e-6) - AD.evaluate_free(prob, F, tau - 1e-6)) / 2e-6
+    assert abs(dtau - fd) <= 2e-5 * abs(fd), (dtau, fd)
+    assert np.abs(s0).max() > 0
+
+
+def _oracle_free_J(prob, F, tau):
+    lat = dataclasses.replace(prob.lat, body_force=tuple(F), tau=tau)
+    o = O.Oracle(lat)
+    o.f[...] = prob.f0
+    P = prob.ps.copy()
+    dem = O.OracleDEM(P, lat)
+    prm = O.DemParams(**W.dem_defaults(prob.ps, gravity=prob.gravity))
+    J = 0.0
+    for _ in range(prob.steps):
+        o.classify(P)
+        Fh, Th = o.step(P)
+        J += float((prob.weights[:, :3] * Fh).sum() + (prob.weights[:, 3:] * Th).sum())
+        dem.step(P, Fh, Th, prm, prob.n_sub, 1.0 / prob.n_sub)
+    return J
+
+
+def test_fp64_free_motion_adjoint_matches_oracle_differences():
+    """The reference: central differences of the oracle's own coupled loop
+    (FP64 lattice update and DEM on the CPU)."""
+    prob = _free_problem(steps=12, window=5)
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
+    assert abs(J - _oracle_free_J(prob, F, tau)) <= 1e-9 * abs(J)
+    h = 1e-6
+    for block, p, a in [(0, 0, 0), (1, 0, 2), (2, 0, 1), (3, 0, 2), (2, 1, 0), (0, 1, 1)]:
+        scale = max(np.abs(s0[:, 3 * block:3 * block + 3]).max(), 1e-12)
+        fd = (_oracle_free_J(_free_shift(prob, p, block, a, h), F, tau) -
+              _oracle_free_J(_free_shift(prob, p, block, a, -h), F, tau)) / (2 * h)
+        assert abs(s0[p, 3 * block + a] - fd) <= 5e-5 * scale, (block, p, a, s0[p, 3 * block + a], fd)

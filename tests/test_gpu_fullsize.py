@@ -46,11 +46,13 @@ def test_c2_full_size_fp32():
     assert r["pop_err"] <= POP_TOL["f32"] and r["F"] <= FORCE_TOL["f32"] and r["T"] <= FORCE_TOL["f32"], r
 
 
-@pytest.mark.parametrize("storage,classify", [("f32", "auto"), ("f16", "sweep")])
-def test_c3_full_size(storage, classify):
+@pytest.mark.parametrize("storage,classify,lattice", [("f32", "auto", 19), ("f16", "sweep", 19),
+                                                      ("f32", "auto", 15)])
+def test_c3_full_size(storage, classify, lattice):
     lat, ps, meta = W.config_c3()
     ps = _moving(ps, 13, 0.02, 0.002)
-    r = _run(lat, ps, storage, 3, tag=f"c3 {storage} {classify}", classify=classify)
+    r = _run(lat, ps, storage, 3, tag=f"c3 {storage} {classify} q{lattice}", classify=classify,
+             lattice=lattice)
     assert r["refilled"] > 0
     assert r["pop_err"] <= POP_TOL[storage], r
     assert r["F"] <= FORCE_TOL[storage] and r["T"] <= FORCE_TOL[storage], r
