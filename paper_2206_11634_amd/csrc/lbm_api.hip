@@ -407,13 +407,10 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
         HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
         HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
         HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
+        // the boxes' check is read back with the list counts below; the
+        // kernels that write the owner planes, flags and lists do nothing
+        // when it failed, so the context keeps its current geometry
         HIPCHK(c, LQ(c, launch_boxes)(c, Pd, slot));
-        // check the boxes before touching the owner planes or the flags
-        HIPCHK(c, hipMemcpyAsync(c->host_stage, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                 c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->host_stage[0])
-            return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[0]));
         {
             PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
             if (k >= 2) HIPCHK(c, LQ(c, launch_clear_boxes)(c, own_new, slot_prev2, np));
@@ -428,11 +425,15 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
         for (int attempt = 0;; ++attempt) {
             HIPCHK(c, hipMemcpyAsync(c->host_stage, c->refill_cursor, sizeof(uint32_t),
                                      hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->host_stage + 1, c->err, sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipMemcpyAsync(link_counts, c->link_cursor, cur_bytes, hipMemcpyDeviceToHost,
                                      c->stream));
             HIPCHK(c, hipMemcpyAsync(cand_counts, c->cand_cursor, cur_bytes, hipMemcpyDeviceToHost,
                                      c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->host_stage[1])
+                return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[1]));
             int64_t lmax = 0, ltot = 0, cmax = 0, ctot = 0;
             for (int p = 0; p < np; ++p) {
                 const int64_t v = link_counts[(size_t)p * kCursorPad];

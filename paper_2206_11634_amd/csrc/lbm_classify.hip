@@ -248,8 +248,10 @@ __global__ __launch_bounds__(64) void k_boxes(PartDev P, int h, double* ball, ui
     }
 }
 
-__global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball, int h, Geom g)
+__global__ __launch_bounds__(256) void k_clear(const uint32_t* __restrict__ err, uint32_t* own,
+                                               const double* ball, int h, Geom g)
 {
+    if (*err) return;  // the boxes failed their check: leave every plane as it is
     const int p = blockIdx.y;
     walk_ball_plane(ball + 4 * p, h, [&](const int* ii, bool act) {
         int c[3];
@@ -289,10 +291,11 @@ __global__ __launch_bounds__(256) void k_clear(uint32_t* own, const double* ball
 constexpr int kRows = 2 * kMaxBoxHalf + 1;
 constexpr uint32_t kCandBuf = 2048;
 
-__global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ball, int h, PartDev P,
+__global__ __launch_bounds__(256, 8) void k_mark(const uint32_t* __restrict__ err, uint32_t* own, const double* ball, int h, PartDev P,
                                               Geom g, uint8_t* flag, int store_flag, uint32_t* cand,
                                               int64_t cap, uint32_t* cursors)
 {
+    if (*err) return;  // the boxes failed their check: leave every plane as it is
     __shared__ double sp[4 * kMaxCtrl];
     __shared__ float4 sf[kMaxCtrl];
     __shared__ int rlo[kRows];
@@ -462,10 +465,11 @@ __global__ __launch_bounds__(256, 8) void k_mark(uint32_t* own, const double* ba
 
 // Over the previous balls: flags of the new classification and the nodes that
 // particle p covered before and that are fluid now.
-__global__ __launch_bounds__(256) void k_finish(const uint32_t* own_prev, const uint32_t* own_new,
+__global__ __launch_bounds__(256) void k_finish(const uint32_t* __restrict__ err, const uint32_t* own_prev, const uint32_t* own_new,
                                                 const double* ball, int h, Geom g, uint8_t* flag,
                                                 RefillRec* rec, int64_t cap, uint32_t* cursor)
 {
+    if (*err) return;  // the boxes failed their check: leave every plane as it is
     const int p = blockIdx.y;
     walk_ball_plane(ball + 4 * p, h, [&](const int* ii, bool act) {
         int c[3];
@@ -550,12 +554,13 @@ __device__ __forceinline__ int select_bit(uint64_t m, uint32_t k)
 // wave then enumerates its links in that order and gives one link to each
 // lane (candidate data by lane shuffles), so the FP64 work of q runs on full
 // waves.  A grid of a few workgroups per particle strides over the list.
-__global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const double* ball, PartDev P,
+__global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ err, const uint32_t* own, const double* ball, PartDev P,
                                                Geom g, const uint32_t* cand, int64_t cand_cap,
                                                const uint32_t* cand_cursors, LinkRec* links,
                                                int64_t cap, uint32_t* cursors, int treat,
                                                uint32_t gx)
 {
+    if (*err) return;  // the boxes failed their check: leave every plane as it is
     __shared__ double sp[4 * kMaxCtrl];
     uint32_t bx, by;
     if (!xcd_tile(gx, (uint32_t)P.n, bx, by)) return;  // uniform over the block
@@ -675,10 +680,11 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* own, const dou
 // The same as k_finish over the whole lattice (four consecutive nodes per
 // thread, 16-byte owner loads), used when the balls cover most of the lattice
 // and a coalesced sweep is cheaper.
-__global__ __launch_bounds__(256) void k_finish_all(const uint32_t* own_prev,
+__global__ __launch_bounds__(256) void k_finish_all(const uint32_t* __restrict__ err, const uint32_t* own_prev,
                                                     const uint32_t* own_new, Geom g, uint8_t* flag,
                                                     RefillRec* rec, int64_t cap, uint32_t* cursor)
 {
+    if (*err) return;  // the boxes failed their check: leave every plane as it is
     const uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u;
     uint32_t on[4] = {kFluid, kFluid, kFluid, kFluid}, op[4] = {kFluid, kFluid, kFluid, kFluid};
     if (base + 3u < g.ncell) {
@@ -756,7 +762,7 @@ hipError_t launch_clear_boxes(lbm_ctx* c, uint32_t* own, int slot, int np)
 {
     if (np == 0) return hipSuccess;
     if (c->dense) return hipMemsetAsync(own, 0xFF, sizeof(uint32_t) * (size_t)c->geom.ncell, c->stream);
-    hipLaunchKernelGGL(k_clear, dim3(c->box.S, np), dim3(256), 0, c->stream, own,
+    hipLaunchKernelGGL(k_clear, dim3(c->box.S, np), dim3(256), 0, c->stream, c->err, own,
                        c->ball_hist + (int64_t)slot * 4 * np, c->box.h, c->geom);
     return hipGetLastError();
 }
@@ -766,7 +772,7 @@ hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot)
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
     // in dense mode the lattice sweep of k_finish_all writes every flag
-    hipLaunchKernelGGL(k_mark, dim3(c->box.S, np), dim3(256), 0, c->stream, own,
+    hipLaunchKernelGGL(k_mark, dim3(c->box.S, np), dim3(256), 0, c->stream, c->err, own,
                        c->ball_hist + (int64_t)slot * 4 * np, c->box.h, P, c->geom, c->flag,
                        c->dense ? 0 : 1, c->cand, c->cand_cap, c->cand_cursor);
     return hipGetLastError();
@@ -778,11 +784,11 @@ hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* o
     if (np_prev == 0) return hipSuccess;
     if (c->dense) {
         hipLaunchKernelGGL(k_finish_all, dim3(blocks_for((c->geom.ncell + 3) / 4)), dim3(256), 0,
-                           c->stream, own_prev, own_new, c->geom, c->flag, c->refill,
+                           c->stream, c->err, own_prev, own_new, c->geom, c->flag, c->refill,
                            c->refill_cap, c->refill_cursor);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_finish, dim3(c->box.S, np_prev), dim3(256), 0, c->stream, own_prev,
+    hipLaunchKernelGGL(k_finish, dim3(c->box.S, np_prev), dim3(256), 0, c->stream, c->err, own_prev,
                        own_new, c->ball_hist + (int64_t)slot * 4 * np_prev, c->box.h, c->geom,
                        c->flag, c->refill, c->refill_cap, c->refill_cursor);
     return hipGetLastError();
@@ -794,7 +800,7 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
     if (np == 0) return hipSuccess;
     const uint32_t per = (uint32_t)std::min<int64_t>(16, (c->cand_cap + 255) / 256);
     const uint32_t nb = (per * (uint32_t)np + 7u) & ~7u;
-    hipLaunchKernelGGL(k_links, dim3(nb), dim3(256), 0, c->stream, own,
+    hipLaunchKernelGGL(k_links, dim3(nb), dim3(256), 0, c->stream, c->err, own,
                        c->ball_hist + (int64_t)slot * 4 * np, P, c->geom, c->cand, c->cand_cap,
                        c->cand_cursor, c->links, c->link_cap, c->link_cursor, c->cfg.treatments,
                        per);

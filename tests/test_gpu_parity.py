@@ -261,3 +261,32 @@ def test_d3q15_treatment_switches(treat):
                           diameter_range=(5.0, 7.0), speed=0.06, spin=0.006, u0=(0.01, 0.0, 0.0))
     r = _run(lat, ps, "f64", 4, treat=treat, tag=f"q15 treat{treat}", lattice=15)
     assert r["pop_err"] < POP_TOL["f64"] and r["F"] < FORCE_TOL["f64"], r
+
+
+def test_classify_rejects_bad_particles_and_keeps_the_geometry():
+    """A particle state that fails the boxes' check (a centre outside [0, n)
+    on a periodic axis) is reported as EINVAL by lbm_classify_nodes, whose
+    kernels then leave the owner planes, flags and lists alone; a valid
+    classification afterwards gives the oracle's geometry."""
+    lat, ps = W.tiny_case(1, dims=(28, 20, 26), periodic=(1, 0, 1), n_particles=3,
+                          diameter_range=(4.0, 7.0), speed=0.06, spin=0.006)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    parts = B.DeviceParticles(ps)
+    gpu.classify(parts)
+    own0 = gpu.owner()
+    bad = ps.copy()
+    bad.pos[0, 0] = -5.0
+    bad.refresh_world()
+    parts.set_state(bad)
+    with pytest.raises(B.LbmError) as e:
+        gpu.classify(parts)
+    assert e.value.code == B.LBM_EINVAL
+    assert np.array_equal(gpu.owner(), own0)
+    P1 = W.prescribed_state(ps, lat, 1.0)
+    parts.set_state(P1)
+    gpu.classify(parts)
+    ora = O.Oracle(lat, fields=False)
+    ora.classify(ps)
+    ora.classify(P1)
+    _compare_geometry(gpu, ora, "after a rejected state")
+    gpu.close()
