@@ -267,6 +267,47 @@ def adjoint_bench(fd_check=True):
                  tau=(dtau, fd("tau", 1e-4)))
         out["fd_rel_err"] = {k: float(abs(a - b) / abs(b)) for k, (a, b) in g.items()}
         out["fd_reference"] = "central differences of the FP64-storage forward pass"
+    out["free_motion"] = free_adjoint_bench(lat, ps, meta, fd_check)
+    return out
+
+
+def free_adjoint_bench(lat, ps, meta, fd_check=True):
+    """The same channel with the particle moving freely (dem_step after every
+    step, 10 substeps): forward and adjoint (through the DEM) steps per second
+    and dJ/dv0_x against central differences of the FP64 free-motion pass."""
+    import dataclasses
+    import torch
+    from paper_2206_11634_amd import adjoint as AD
+
+    T, K = meta["steps"], meta["checkpoint"]
+    prob = AD.FreeProblem(lat=lat, ps=ps, steps=T, window=K, storage=meta["storage"])
+    F, tau = np.array(lat.body_force), lat.tau
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, run = AD.forward_free(prob, F, tau, keep=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s0, dF, dtau = AD.backward_free(run)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = dict(steps=T, checkpoint=K, J=J, forward_steps_per_s=round(T / (t1 - t0), 1),
+               adjoint_steps_per_s=round(T / (t2 - t1), 1),
+               grad=dict(dJ_dx0=s0[0, 0:3].tolist(), dJ_dtheta0=s0[0, 3:6].tolist(),
+                         dJ_dv0=s0[0, 6:9].tolist(), dJ_domega0=s0[0, 9:12].tolist(),
+                         dJ_dF=dF.tolist(), dJ_dtau=dtau))
+    print(f"[bench] free-motion adjoint: forward {t1 - t0:.2f} s, backward {t2 - t1:.2f} s",
+          file=sys.stderr, flush=True)
+    if fd_check:
+        ref = dataclasses.replace(prob, storage="f64")
+
+        def at(d):
+            p2 = ps.copy()
+            p2.vel = p2.vel.copy()
+            p2.vel[0, 0] += d
+            return AD.evaluate_free(dataclasses.replace(ref, ps=p2), F, tau)
+        h = 1e-4
+        fd = (at(h) - at(-h)) / (2 * h)
+        out["fd_rel_err_v0x"] = float(abs(s0[0, 6] - fd) / abs(fd))
     return out
 
 

@@ -7,10 +7,11 @@
 // (explicit Euler half step of Euler's equations in the body frame), the
 // drift x += dt v and rotation q <- exp(omega dt / 2) q, and a second half
 // kick whose rotational part takes four fixed-point sweeps in the new frame.
-// The kernel runs those substeps in forward-mode dual numbers over the 18
-// inputs (x, theta, v, omega, F, T), theta being a small world-frame rotation
-// of the pose (q -> exp(theta / 2) q), and applies the transposed Jacobian to
-// the adjoint of the state after the call:
+// The kernel runs those substeps in forward-mode dual numbers, one thread per
+// particle and input: each of the 18 inputs (x, theta, v, omega, F, T), theta
+// being a small world-frame rotation of the pose (q -> exp(theta / 2) q),
+// gives one column of the Jacobian, and its product with the adjoint of the
+// state after the call is that input's adjoint:
 //   sigma(s_k) = (d s_{k+1} / d s_k)^T sigma(s_{k+1}),
 //   dJ/d(F, T)_k = (d s_{k+1} / d(F, T)_k)^T sigma(s_{k+1}),
 // with sigma ordered (x, theta, v, omega).  The second line becomes the
@@ -23,7 +24,8 @@
 namespace mdlbm {
 namespace {
 
-constexpr int NT = 18;  // tangents: x 0-2, theta 3-5, v 6-8, omega 9-11, F 12-14, T 15-17
+constexpr int NIN = 18;  // inputs: x 0-2, theta 3-5, v 6-8, omega 9-11, F 12-14, T 15-17
+constexpr int NT = 1;    // one tangent per thread
 
 struct D {
     double v;
@@ -35,10 +37,11 @@ struct D {
         for (int k = 0; k < NT; ++k) d[k] = 0.0;
     }
 };
-__device__ __forceinline__ D var(double x, int k)
+// x, with tangent 1 when it is the thread's input k
+__device__ __forceinline__ D var(double x, int k, int seed)
 {
     D r(x);
-    r.d[k] = 1.0;
+    r.d[0] = (k == seed) ? 1.0 : 0.0;
     return r;
 }
 __device__ __forceinline__ D operator+(const D& a, const D& b)
@@ -157,15 +160,16 @@ __global__ __launch_bounds__(64) void k_dem_adjoint(int np, const double* mass, 
                                                     int n_sub, double dt, const double* sig1,
                                                     double* sig0, const double* wJ, double* wts)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= np * NIN) return;
+    const int p = t / NIN, seed = t % NIN;
     D x[3], v[3], w[3], F[3], T[3], q[4];
     for (int a = 0; a < 3; ++a) {
-        x[a] = var(pos[3 * p + a], a);
-        v[a] = var(vel[3 * p + a], 6 + a);
-        w[a] = var(om[3 * p + a], 9 + a);
-        F[a] = var(FT[6 * p + a], 12 + a);
-        T[a] = var(FT[6 * p + 3 + a], 15 + a);
+        x[a] = var(pos[3 * p + a], a, seed);
+        v[a] = var(vel[3 * p + a], 6 + a, seed);
+        w[a] = var(om[3 * p + a], 9 + a, seed);
+        F[a] = var(FT[6 * p + a], 12 + a, seed);
+        T[a] = var(FT[6 * p + 3 + a], 15 + a, seed);
     }
     // q(theta) = exp(theta / 2) q: dq/dtheta_a = (0, e_a)/2 (x) q
     for (int c = 0; c < 4; ++c) q[c] = D(quat[4 * p + c]);
@@ -178,7 +182,8 @@ __global__ __launch_bounds__(64) void k_dem_adjoint(int np, const double* mass, 
                                  u[0] * qq[1] + u[1] * qq[0] + u[2] * qq[3] - u[3] * qq[2],
                                  u[0] * qq[2] - u[1] * qq[3] + u[2] * qq[0] + u[3] * qq[1],
                                  u[0] * qq[3] + u[1] * qq[2] - u[2] * qq[1] + u[3] * qq[0]};
-            for (int c = 0; c < 4; ++c) q[c].d[3 + a] = 0.5 * r[c];
+            if (seed == 3 + a)
+                for (int c = 0; c < 4; ++c) q[c].d[0] = 0.5 * r[c];
         }
     }
     const double m = mass[p];
@@ -212,30 +217,29 @@ __global__ __launch_bounds__(64) void k_dem_adjoint(int np, const double* mass, 
         for (int a = 0; a < 3; ++a) v[a] = v[a] + (h / m) * (F[a] + D(mrel * gv[a]));
         spin_kick(q, w, T, I, h, 4);
     }
-    // Jacobian rows of the output state in (x, theta, v, omega): the rotation
-    // tangent is 2 vec(dq (x) conj(q))
-    double J[12][NT];
-    for (int k = 0; k < NT; ++k) {
-        for (int a = 0; a < 3; ++a) {
-            J[a][k] = x[a].d[k];
-            J[6 + a][k] = v[a].d[k];
-            J[9 + a][k] = w[a].d[k];
-        }
-        const double dw = q[0].d[k], dx = q[1].d[k], dy = q[2].d[k], dz = q[3].d[k];
+    // this input's column of the Jacobian of the output state in (x, theta,
+    // v, omega), the rotation tangent being 2 vec(dq (x) conj(q)), times the
+    // adjoint of the output
+    double col[12];
+    for (int a = 0; a < 3; ++a) {
+        col[a] = x[a].d[0];
+        col[6 + a] = v[a].d[0];
+        col[9 + a] = w[a].d[0];
+    }
+    {
+        const double dw = q[0].d[0], dx = q[1].d[0], dy = q[2].d[0], dz = q[3].d[0];
         const double cw = q[0].v, cx_ = -q[1].v, cy_ = -q[2].v, cz_ = -q[3].v;
-        J[3][k] = 2.0 * (dw * cx_ + dx * cw + dy * cz_ - dz * cy_);
-        J[4][k] = 2.0 * (dw * cy_ - dx * cz_ + dy * cw + dz * cx_);
-        J[5][k] = 2.0 * (dw * cz_ + dx * cy_ - dy * cx_ + dz * cw);
+        col[3] = 2.0 * (dw * cx_ + dx * cw + dy * cz_ - dz * cy_);
+        col[4] = 2.0 * (dw * cy_ - dx * cz_ + dy * cw + dz * cx_);
+        col[5] = 2.0 * (dw * cz_ + dx * cy_ - dy * cx_ + dz * cw);
     }
     const double* s1 = sig1 + 12 * p;
-    for (int k = 0; k < NT; ++k) {
-        double acc = 0.0;
-        for (int i = 0; i < 12; ++i) acc += J[i][k] * s1[i];
-        if (k < 12)
-            sig0[12 * p + k] = acc;
-        else
-            wts[6 * p + (k - 12)] = wJ[6 * p + (k - 12)] + acc;
-    }
+    double acc = 0.0;
+    for (int i = 0; i < 12; ++i) acc += col[i] * s1[i];
+    if (seed < 12)
+        sig0[12 * p + seed] = acc;
+    else
+        wts[6 * p + (seed - 12)] = wJ[6 * p + (seed - 12)] + acc;
 }
 
 }  // namespace
@@ -249,7 +253,7 @@ hipError_t launch_dem_adjoint(lbm_ctx* c, const TapeStep& ts, const lbm_particle
     const double* st = ts.part;
     const double* quat = st + 9 * np + 3 * c->cfg.n_ctrl;
     const double* FT = quat + 4 * np;
-    hipLaunchKernelGGL(k_dem_adjoint, dim3((np + 63) / 64), dim3(64), 0, c->stream, np, P->mass,
+    hipLaunchKernelGGL(k_dem_adjoint, dim3((np * NIN + 63) / 64), dim3(64), 0, c->stream, np, P->mass,
                        P->volume, P->inertia, st, st + 3 * np, st + 6 * np, quat, FT,
                        prm.gravity[0], prm.gravity[1], prm.gravity[2], prm.rho_f, n_sub, dt,
                        sig1, sig0, wJ, wts);
