@@ -27,7 +27,7 @@ METRIC = "MLUPS + % HBM roofline (FP32/FP16-store vs plain), drag err; adjoint s
 # WRITE_SIZE passes (scaled by a copy kernel of known size; see profiles/),
 # valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
-    ("c4_sediment_512cube_1000p", "f32"): dict(source_sha256_16="e9dd3f3ae8ab7d4c",
+    ("c4_sediment_512cube_1000p", "f32"): dict(source_sha256_16="0c8038dcce0fd0e7",
                                               read=10.331e9, written=12.348e9),
 }
 HBM_PEAK_GBS = 8000.0
@@ -76,12 +76,27 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=
 
 
 def _stream_source_hash():
-    """Hash of the sources the stream-collide kernel is compiled from."""
+    """Hash of the source the stream-collide kernel is compiled from: the
+    kernel's own text, the storage traits and stencil headers, and the Geom
+    and Phys records it takes."""
     import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2206_11634_amd", "csrc")
+
+    def read(name):
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+            return fh.read()
+
+    stream = read("lbm_stream.hip")
+    k = re.search(r"template <int S>\n__global__[^\n]*k_stream_collide\(.*?\n}\n", stream, re.S)
+    internal = read("lbm_internal.h")
+    parts = [k.group(0) if k else stream, read("lbm_kernels.h"), read("lbm_stencil.h")]
+    for name in ("Geom", "Phys"):
+        m = re.search(r"struct " + name + r" \{.*?\n\};", internal, re.S)
+        parts.append(m.group(0) if m else internal)
     h = hashlib.sha256()
-    for name in ("lbm_stream.hip", "lbm_kernels.h", "lbm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2206_11634_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    for part in parts:
+        h.update(part.encode())
     return h.hexdigest()[:16]
 
 

@@ -208,7 +208,9 @@ const char* lbm_last_error(const lbm_ctx* ctx);
  * Coordinates on a periodic axis are taken at the image nearest x_p.
  * Synchronises the stream to report counts (out may be NULL).  EINVAL when a
  * particle's body reaches beyond box_half, K <= 0, or x_p lies outside
- * [0, n) on a periodic axis; the previous classification then stays in force. */
+ * [0, n) on a periodic axis; the previous classification then stays in force.
+ * ENUMERIC when a step since the previous classification produced a
+ * non-finite force or torque; the context is then failed. */
 int lbm_classify_nodes(lbm_ctx* ctx, const lbm_particles* P, lbm_counts* out);
 
 /* One lattice step n -> n+1 on the links of the last classification:
@@ -217,7 +219,9 @@ int lbm_classify_nodes(lbm_ctx* ctx, const lbm_particles* P, lbm_counts* out);
  * particle (Eq. mem, and Eqs. fh_s_issue / th_s_issue for missing points),
  * then fused pull-streaming and BGK collision (Eq. lbm_collide, with Guo
  * forcing for body_force) of every fluid node.  Wall velocities come from
- * P->vel, P->omega and P->pos.  Asynchronous. */
+ * P->vel, P->omega and P->pos.  Asynchronous.  A step whose force or torque
+ * sums are not finite (a run that has gone unstable) is reported by the next
+ * lbm_classify_nodes as ENUMERIC, which leaves the context failed. */
 int lbm_step(lbm_ctx* ctx, const lbm_particles* P);
 
 /* Copy the force F^h and torque T^h (FP64, [n][3] each, device pointers) of

@@ -20,7 +20,7 @@ int fail(lbm_ctx* c, int code, const std::string& msg)
 {
     if (c) {
         c->last_error = msg;
-        if (code == LBM_EDEVICE) c->failed = true;
+        if (code == LBM_EDEVICE || code == LBM_ENUMERIC) c->failed = true;
     } else {
         g_init_error = msg;
     }
@@ -316,9 +316,11 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->fc, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->reach, (size_t)std::max(np, 1));
+    if (e == hipSuccess) e = alloc(&c->numeric, 1);
+    if (e == hipSuccess) e = hipMemsetAsync(c->numeric, 0, sizeof(uint32_t), c->stream);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&c->host_stage,
-                          sizeof(uint32_t) * (2 + 2 * (size_t)kCursorPad * std::max(np, 1)),
+                          sizeof(uint32_t) * (kStageHead + 2 * (size_t)kCursorPad * std::max(np, 1)),
                           hipHostMallocDefault);
     if (e != hipSuccess) {
         std::string msg = std::string("scratch allocation failed: ") + hipGetErrorString(e);
@@ -359,6 +361,7 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->FT);
     (void)hipFree(c->fc);
     (void)hipFree(c->reach);
+    (void)hipFree(c->numeric);
     for (auto& t : c->tape) {
         (void)hipFree(t.f);
         (void)hipFree(t.own);
@@ -420,18 +423,24 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             if (k >= 1 || c->dense) HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
             HIPCHK(c, LQ(c, launch_links)(c, own_new, Pd, slot));
         }
-        uint32_t* link_counts = c->host_stage + 2;
-        uint32_t* cand_counts = c->host_stage + 2 + (size_t)kCursorPad * np;
+        uint32_t* link_counts = c->host_stage + kStageHead;
+        uint32_t* cand_counts = c->host_stage + kStageHead + (size_t)kCursorPad * np;
         for (int attempt = 0;; ++attempt) {
             HIPCHK(c, hipMemcpyAsync(c->host_stage, c->refill_cursor, sizeof(uint32_t),
                                      hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->host_stage + 1, c->err, sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->host_stage + 2, c->numeric, sizeof(uint32_t),
                                      hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipMemcpyAsync(link_counts, c->link_cursor, cur_bytes, hipMemcpyDeviceToHost,
                                      c->stream));
             HIPCHK(c, hipMemcpyAsync(cand_counts, c->cand_cursor, cur_bytes, hipMemcpyDeviceToHost,
                                      c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->host_stage[2])
+                return fail(c, LBM_ENUMERIC,
+                            "lbm_classify_nodes: a step since the previous classification "
+                            "produced a non-finite hydrodynamic force or torque");
             if (c->host_stage[1])
                 return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[1]));
             int64_t lmax = 0, ltot = 0, cmax = 0, ctot = 0;
@@ -577,7 +586,7 @@ int lbm_get_links(const lbm_ctx* cc, int64_t cap, int32_t* node_dev, int8_t* d_d
     int64_t acc = 0;
     for (int p = 0; p < np; ++p) {
         off[p] = acc;
-        acc += c->host_stage[2 + (size_t)p * kCursorPad];
+        acc += c->host_stage[kStageHead + (size_t)p * kCursorPad];
     }
     int64_t* off_dev = nullptr;
     HIPCHK(c, alloc(&off_dev, np));

@@ -18,6 +18,9 @@ namespace mdlbm {
 // table of the 2h + 1 rows of one box plane in LDS).
 constexpr int kMaxBoxHalf = 511;
 constexpr uint32_t kFluid = 0xFFFFFFFFu;
+// Pinned host staging: refill count, box check, non-finite flag, pad, then
+// the link and candidate counts of every particle.
+constexpr int kStageHead = 4;
 
 // ---------------------------------------------------------------------------
 // Records
@@ -138,6 +141,7 @@ struct lbm_ctx {
     double* hist_pw = nullptr;    // [np*6][8]
     double* fc = nullptr;         // [np][6] last contact force / torque
     double* reach = nullptr;      // [np] broad-phase radius of each particle
+    uint32_t* numeric = nullptr;  // set by a step whose force or torque sums are not finite
     uint32_t* pairs = nullptr;    // [np (np - 1) / 2] candidate pairs of a dem_step call
     uint32_t* pair_count = nullptr;
     // kernel timing

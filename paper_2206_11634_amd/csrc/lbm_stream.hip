@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
                                                   const LinkRec* __restrict__ links,
                                                   const uint32_t* __restrict__ cursor, int64_t cap,
                                                   PartDev P, double* __restrict__ FT, Geom g,
-                                                  Phys ph)
+                                                  Phys ph, uint32_t* __restrict__ numeric)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
@@ -219,6 +219,7 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
         const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
                          (red[2][threadIdx.x] + red[3][threadIdx.x]);
         atomicAdd(FT + 6 * p + threadIdx.x, s);
+        if (!isfinite(s)) atomicOr(numeric, 1u);  // reported by the next classification
     }
 }
 
@@ -408,7 +409,7 @@ struct RunBC {
         dim3 grid(blocks_for(c->link_max), c->cfg.n_particles);
         hipLaunchKernelGGL(k_boundary<S>, grid, dim3(256), 0, c->stream, (typename St<S>::T*)f,
                            (const typename St<S>::M*)c->mom, c->links, c->link_cursor, c->link_cap,
-                           P, c->FT, c->geom, c->phys);
+                           P, c->FT, c->geom, c->phys, c->numeric);
         return hipGetLastError();
     }
 };

@@ -290,3 +290,32 @@ def test_classify_rejects_bad_particles_and_keeps_the_geometry():
     ora.classify(P1)
     _compare_geometry(gpu, ora, "after a rejected state")
     gpu.close()
+
+
+def test_non_finite_forces_are_reported_and_fail_the_context():
+    """A population set to NaN next to a body (forced from the host) makes the
+    step's momentum-exchange sums non-finite; the next classification reports
+    ENUMERIC and every later call ESTATE."""
+    lat, ps = W.tiny_case(2, dims=(27, 26, 28), periodic=(1, 1, 1), n_particles=3,
+                          diameter_range=(4.0, 7.0))
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    gpu.classify(parts)
+    gpu.step(parts)
+    gpu.classify(parts)
+    L = gpu.links()
+    f = gpu.populations()
+    d, node = int(L["d"][0]), int(L["node"][0])
+    e = np.array(O.stencil(19)[0][d])
+    x = np.array([node % lat.nx, (node // lat.nx) % lat.ny, node // (lat.nx * lat.ny)]) - e
+    x %= np.array(lat.dims)
+    f[d, x[0] + lat.nx * (x[1] + lat.ny * x[2])] = np.nan
+    gpu.set_populations(f)
+    gpu.step(parts)
+    with pytest.raises(B.LbmError) as err:
+        gpu.classify(parts)
+    assert err.value.code == B.LBM_ENUMERIC
+    with pytest.raises(B.LbmError) as err:
+        gpu.step(parts)
+    assert err.value.code == B.LBM_ESTATE
+    gpu.close()
