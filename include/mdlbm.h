@@ -258,6 +258,12 @@ int lbm_get_owner(const lbm_ctx* ctx, int32_t* owner_dev);
  * ncell (x fastest) into f_dev.  Asynchronous. */
 int lbm_get_populations(const lbm_ctx* ctx, double* f_dev);
 
+/* Density and velocity of every node in FP64: rho_dev [ncell], u_dev
+ * [ncell][3], from the moment plane that every collision writes (rho of the
+ * node and u = (sum f e + F/2) / rho of its last collision, or of the
+ * initial equilibrium; solid nodes hold rho = 1, u = 0).  Asynchronous. */
+int lbm_get_moments(const lbm_ctx* ctx, double* rho_dev, double* u_dev);
+
 /* Overwrite the current populations from FP64 f_i planes (rounded to the
  * storage format).  Asynchronous. */
 int lbm_set_populations(lbm_ctx* ctx, const double* f_dev);

@@ -85,7 +85,7 @@ EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_
            "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
-           "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled"]
+           "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled", "lbm_get_moments"]
 
 _lib = None
 
@@ -122,6 +122,7 @@ def load(path: Path | None = None):
         "lbm_checkpoint_save": [_P, _P],
         "lbm_checkpoint_load": [_P, _P],
         "lbm_tape_begin": [_P, ctypes.c_int],
+        "lbm_get_moments": [_P, _P, _P],
         "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P, _P],
         "lbm_adjoint_coupled": [_P, ctypes.POINTER(LbmParticles), _P, ctypes.POINTER(DemParams),
                                 ctypes.c_int, ctypes.c_double, _P, _P, _P],
@@ -371,6 +372,13 @@ class Lattice:
             idx = self.torch.as_tensor(np.asarray(nodes, np.int64), device=self.device)
             out = out[:, idx]
         return out.cpu().numpy()
+
+    def moments(self):
+        """(rho [ncell], u [ncell][3]) in FP64 from the last collision."""
+        rho = self.torch.empty(self.ncell, dtype=self.torch.float64, device=self.device)
+        u = self.torch.empty((self.ncell, 3), dtype=self.torch.float64, device=self.device)
+        _check(load().lbm_get_moments(self.ctx, _ptr(rho), _ptr(u)), self.ctx)
+        return rho.cpu().numpy(), u.cpu().numpy()
 
     def set_populations(self, f: np.ndarray):
         t = self.torch.as_tensor(np.ascontiguousarray(f, np.float64), device=self.device)

@@ -632,6 +632,15 @@ int lbm_get_populations(const lbm_ctx* cc, double* f_dev)
     return LBM_OK;
 }
 
+int lbm_get_moments(const lbm_ctx* cc, double* rho_dev, double* u_dev)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "null output");
+    HIPCHK(c, LQ(c, launch_get_moments)(c, rho_dev, u_dev));
+    return LBM_OK;
+}
+
 int lbm_set_populations(lbm_ctx* c, const double* f_dev)
 {
     if (!c || !f_dev) return fail(c, LBM_EINVAL, "null argument");

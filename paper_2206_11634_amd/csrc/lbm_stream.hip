@@ -438,6 +438,33 @@ struct RunGet {
     }
 };
 
+// Density and velocity of every node from the moment plane, in FP64.
+template <int S>
+__global__ __launch_bounds__(256) void k_get_moments(const typename St<S>::M* __restrict__ mom,
+                                                     double* __restrict__ rho,
+                                                     double* __restrict__ u, Geom g, Phys ph)
+{
+    using A = typename St<S>::A;
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= g.ncell) return;
+    A d, ux, uy, uz;
+    St<S>::ld_mom(mom + cell, ph.inv_scale, d, ux, uy, uz);
+    rho[cell] = 1.0 + (double)d;
+    u[3 * (int64_t)cell] = (double)ux;
+    u[3 * (int64_t)cell + 1] = (double)uy;
+    u[3 * (int64_t)cell + 2] = (double)uz;
+}
+
+template <int S>
+struct RunMoments {
+    static hipError_t run(lbm_ctx* c, double* rho, double* u)
+    {
+        hipLaunchKernelGGL(k_get_moments<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0,
+                           c->stream, (const typename St<S>::M*)c->mom, rho, u, c->geom, c->phys);
+        return hipGetLastError();
+    }
+};
+
 template <int S>
 struct RunSet {
     static hipError_t run(lbm_ctx* c, void* f, const double* in)
@@ -476,6 +503,10 @@ hipError_t launch_get_populations(lbm_ctx* c, const void* f, double* out)
 hipError_t launch_set_populations(lbm_ctx* c, void* f, const double* in)
 {
     return dispatch<RunSet>(c->cfg.storage, c, f, in);
+}
+hipError_t launch_get_moments(lbm_ctx* c, double* rho, double* u)
+{
+    return dispatch<RunMoments>(c->cfg.storage, c, rho, u);
 }
 hipError_t launch_zero_f64(lbm_ctx* c, double* p, int64_t n)
 {

@@ -319,3 +319,30 @@ def test_non_finite_forces_are_reported_and_fail_the_context():
         gpu.step(parts)
     assert err.value.code == B.LBM_ESTATE
     gpu.close()
+
+
+@pytest.mark.parametrize("storage,lattice", [("f64", 19), ("f32", 19), ("f16", 19), ("f64", 15)])
+def test_moments_export_matches_oracle(storage, lattice):
+    """lbm_get_moments: rho and u = (sum f e + F/2)/rho of every fluid node
+    against the oracle's moments of its populations, after moving steps with
+    refills and a body force."""
+    lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
+                          diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
+                          u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, lattice=lattice)
+    parts = B.DeviceParticles(ps)
+    ora = O.Oracle(lat, Q=lattice)
+    for n in range(6):
+        P = W.prescribed_state(ps, lat, float(n))
+        parts.set_state(P)
+        gpu.classify(parts)
+        ora.classify(P)
+        gpu.step(parts)
+        ora.step(P)
+    rho_g, u_g = gpu.moments()
+    rho_o, u_o = ora.moments()
+    fl = ora.owner == 0
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16": 2e-4}[storage]
+    assert np.abs(rho_g[fl] - rho_o[fl]).max() < tol
+    assert np.abs(u_g[fl] - u_o[fl]).max() < tol
+    gpu.close()
