@@ -93,6 +93,97 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename St<S>::T*
     St<S>::st_mom(mom + cell, drho, ux, uy, uz, ph.scale);
 }
 
+// FP16 storage: two x-neighbouring nodes per thread, so that the stores and
+// the pulls along directions with e_x = 0 move 4 bytes per lane (half2)
+// instead of 2.  Pulls with e_x != 0 start at an odd node and are loaded per
+// node.  The arithmetic per node is that of k_stream_collide, bit for bit.
+// Requires an even nx (pairs never straddle a row).
+struct alignas(16) Mom16x2 {
+    Mom16 a, b;
+};
+
+__global__ __launch_bounds__(256) void k_stream_collide_h2(const __half* __restrict__ src,
+                                                           __half* __restrict__ dst,
+                                                           Mom16* __restrict__ mom,
+                                                           const uint8_t* __restrict__ flag,
+                                                           Geom g, Phys ph)
+{
+    using St16 = St<LBM_STORE_F16>;
+    const uint32_t pair = xcd_block() * 256u + threadIdx.x;
+    const uint32_t cell = 2u * pair;
+    if (cell >= g.ncell) return;
+    const uint16_t fl = *reinterpret_cast<const uint16_t*>(flag + cell);
+    const bool solid0 = (fl & 0xFFu) != 0, solid1 = (fl >> 8) != 0;
+    if (solid0 && solid1) {
+        const __half2 z = __floats2half2_rn(0.0f, 0.0f);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            *reinterpret_cast<__half2*>(dst + (int64_t)i * g.stride + cell) = z;
+        Mom16x2 m;
+        m.a.a = m.a.b = m.b.a = m.b.b = z;
+        *reinterpret_cast<Mom16x2*>(mom + cell) = m;
+        return;
+    }
+    const uint32_t nx = g.n[0], ny = g.n[1];
+    const uint32_t x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
+    uint32_t ox0[3], ox1[3], oy[3], oz[3];
+    bool vx0[3], vx1[3], vy[3], vz[3];
+    axis3(x, nx, g.per[0], 1u, ox0, vx0);
+    axis3(x + 1u, nx, g.per[0], 1u, ox1, vx1);
+    axis3(y, ny, g.per[1], nx, oy, vy);
+    axis3(z, g.n[2], g.per[2], nx * ny, oz, vz);
+    float f0[kQ], f1[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int sy = 1 - cy(i), sz = 1 - cz(i);
+        if (cx(i) == 0) {
+            // both sources in one aligned pair: x and x + 1 of the source row,
+            // or, beyond a wall, the nodes' own opposite populations
+            const bool ok = vy[sy] && vz[sz];
+            const uint32_t s = ok ? ox0[1] + oy[sy] + oz[sz] : cell;
+            const int64_t plane = ok ? i : opp(i);
+            const float2 v = __half22float2(
+                *reinterpret_cast<const __half2*>(src + plane * g.stride + s));
+            f0[i] = v.x * ph.inv_scale;
+            f1[i] = v.y * ph.inv_scale;
+        } else {
+            const int sx = 1 - cx(i);
+            const bool ok0 = vx0[sx] && vy[sy] && vz[sz];
+            const bool ok1 = vx1[sx] && vy[sy] && vz[sz];
+            const uint32_t s0 = ok0 ? ox0[sx] + oy[sy] + oz[sz] : cell;
+            const uint32_t s1 = ok1 ? ox1[sx] + oy[sy] + oz[sz] : cell + 1u;
+            f0[i] = St16::ld(src + (int64_t)(ok0 ? i : opp(i)) * g.stride + s0, ph.inv_scale);
+            f1[i] = St16::ld(src + (int64_t)(ok1 ? i : opp(i)) * g.stride + s1, ph.inv_scale);
+        }
+    }
+    const float F[3] = {ph.Ff[0], ph.Ff[1], ph.Ff[2]};
+    float d0, ux0, uy0, uz0, d1, ux1, uy1, uz1;
+    collide<true, float>(f0, ph.omegaf, F, d0, ux0, uy0, uz0);
+    collide<true, float>(f1, ph.omegaf, F, d1, ux1, uy1, uz1);
+    if (solid0) {
+        // rest state, as k_stream_collide stores at solid nodes
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) f0[i] = 0.0f;
+        d0 = ux0 = uy0 = uz0 = 0.0f;
+    }
+    if (solid1) {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) f1[i] = 0.0f;
+        d1 = ux1 = uy1 = uz1 = 0.0f;
+    }
+    const float sc = ph.scale;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+        *reinterpret_cast<__half2*>(dst + (int64_t)i * g.stride + cell) =
+            __floats2half2_rn(f0[i] * sc, f1[i] * sc);
+    Mom16x2 m;
+    m.a.a = __floats2half2_rn(d0 * sc, ux0 * sc);
+    m.a.b = __floats2half2_rn(uy0 * sc, uz0 * sc);
+    m.b.a = __floats2half2_rn(d1 * sc, ux1 * sc);
+    m.b.b = __floats2half2_rn(uy1 * sc, uz1 * sc);
+    *reinterpret_cast<Mom16x2*>(mom + cell) = m;
+}
+
 // ---------------------------------------------------------------------------
 // Links: one thread per link record of one particle (blockIdx.y).
 // ---------------------------------------------------------------------------
@@ -392,6 +483,16 @@ template <int S>
 struct RunSC {
     static hipError_t run(lbm_ctx* c, const void* src, void* dst)
     {
+        if constexpr (S == LBM_STORE_F16) {
+            if (c->geom.n[0] % 2 == 0) {
+                uint32_t nb = blocks_for(c->geom.ncell / 2);
+                nb = (nb + 7u) & ~7u;
+                hipLaunchKernelGGL(k_stream_collide_h2, dim3(nb), dim3(256), 0, c->stream,
+                                   (const __half*)src, (__half*)dst, (Mom16*)c->mom, c->flag,
+                                   c->geom, c->phys);
+                return hipGetLastError();
+            }
+        }
         uint32_t nb = blocks_for(c->geom.ncell);
         nb = (nb + 7u) & ~7u;  // whole rounds over the 8 XCDs
         hipLaunchKernelGGL(k_stream_collide<S>, dim3(nb), dim3(256), 0, c->stream,

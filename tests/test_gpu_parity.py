@@ -346,3 +346,16 @@ def test_moments_export_matches_oracle(storage, lattice):
     assert np.abs(rho_g[fl] - rho_o[fl]).max() < tol
     assert np.abs(u_g[fl] - u_o[fl]).max() < tol
     gpu.close()
+
+
+@pytest.mark.parametrize("dims", [(28, 22, 27), (27, 22, 26)], ids=["even_nx", "odd_nx"])
+def test_fp16_pair_and_single_node_bulk_paths(dims):
+    """FP16 storage runs the bulk pass two nodes per thread when nx is even
+    and one node per thread otherwise; both against the oracle, with walls on
+    y and z so that pairs pull through walls too."""
+    lat, ps = W.tiny_case(9, dims=dims, periodic=(1, 0, 0), n_particles=3,
+                          diameter_range=(5.0, 7.0), speed=0.05, spin=0.005,
+                          u0=(0.02, 0.01, 0.0), body_force=(1e-5, 0.0, 0.0))
+    r = _run(lat, ps, "f16", 8, tag=f"f16 {dims}")
+    assert r["pop_err"] < POP_TOL["f16"], r
+    assert r["F"] < FORCE_TOL["f16"] and r["T"] < FORCE_TOL["f16"], r
