@@ -333,6 +333,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--lattice", type=int, default=19, choices=[19, 15],
+                    help="lattice of the timed line: D3Q19, or the paper's D3Q15")
     ap.add_argument("--variants", default="f16,f64,q15",
                     help="other storages timed on the same workload, and q15 for the "
                          "paper's D3Q15 lattice in the main storage (comma list, or none)")
@@ -353,11 +355,14 @@ def main():
     lat, ps, meta = W.WORKLOADS[args.workload]()
     print(f"[bench] workload {meta['name']}: {lat.nx}x{lat.ny}x{lat.nz}, {ps.n} particles",
           file=sys.stderr, flush=True)
-    main_res = run_storage(lat, ps, meta, args.storage, args.steps, args.warmup)
+    main_res = run_storage(lat, ps, meta, args.storage, args.steps, args.warmup,
+                           lattice=args.lattice)
     print(f"[bench] {args.storage}: {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr,
           flush=True)
     variants, lattices = {}, {}
     for v in [s for s in args.variants.split(",") if s and s != "none" and s != args.storage]:
+        if v == "q15" and args.lattice == 15:
+            continue
         if v == "q15":
             r = run_storage(lat, ps, meta, args.storage, max(3, min(args.steps, 10)), 2,
                             lattice=15)
@@ -390,6 +395,7 @@ def main():
             "periodic": list(lat.periodic),
             "particles": ps.n,
             "storage": args.storage,
+            "stencil": f"D3Q{args.lattice}",
             "tau": lat.tau,
             "dem_substeps": meta.get("n_sub", 10),
             "step": "classify + step + forces + dem",
@@ -400,7 +406,7 @@ def main():
         "link_candidates": main_res["n_cand"],
         "solid_fraction": round(main_res["n_solid"] / ncell, 4),
         "refills_last_step": main_res["n_refill"],
-        "roofline": bulk_roofline(main_res, lat, args.storage, meta["name"]),
+        "roofline": bulk_roofline(main_res, lat, args.storage, meta["name"], Q=args.lattice),
     }
     for v, r in variants.items():
         line.setdefault("storage_variants", {})[v] = dict(
