@@ -359,3 +359,58 @@ def test_fp16_pair_and_single_node_bulk_paths(dims):
     r = _run(lat, ps, "f16", 8, tag=f"f16 {dims}")
     assert r["pop_err"] < POP_TOL["f16"], r
     assert r["F"] < FORCE_TOL["f16"] and r["T"] < FORCE_TOL["f16"], r
+
+
+# ---------------------------------------------------------------------------
+# limits: a body larger than the FP32 estimate covers, the most control points
+# a body may have, one more than that
+# ---------------------------------------------------------------------------
+
+def test_large_body_geometry_takes_the_fp64_path():
+    """A sphere of radius 130 (node box half-width 133 > 127, where the
+    classification's FP32 estimate is not trusted and every node takes the
+    FP64 sum) in a 272^3 periodic box: owners, links and q bit-exact."""
+    lat = W.LatticeSpec(272, 272, 272, (1, 1, 1), tau=0.7)
+    ps = W.make_particles([W.sphere_shape(260.0, 0.1)], [[136.3, 135.8, 136.1]],
+                          [[1.0, 0, 0, 0]], 1.5, vel=[[0.01, 0.0, 0.0]])
+    assert ps.box_half() > 127
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    ora = O.Oracle(lat, fields=False)
+    for n in range(2):
+        P = W.prescribed_state(ps, lat, float(n))
+        parts.set_state(P)
+        gpu.classify(parts)
+        ora.classify(P)
+        _compare_geometry(gpu, ora, f"r130 step {n}")
+    gpu.close()
+
+
+def _cluster_shape(rng, n_pts, length):
+    pts = rng.normal(size=(n_pts, 3)) * 0.6
+    return W.metaball_shape(pts, rng.uniform(0.5, 1.5, n_pts) * 0.05, 0.1, length=length,
+                            axis=np.array([1.0, 0.0, 0.0]), samples_per_unit=1.0)
+
+
+def test_sixty_four_control_points_parity():
+    rng = np.random.default_rng(64)
+    sh = _cluster_shape(rng, 64, 10.0)
+    lat = W.LatticeSpec(30, 28, 26, (1, 0, 1), tau=0.7, u0=(0.02, 0.0, 0.0))
+    ps = W.make_particles([sh], [[15.2, 13.9, 13.1]], [W.random_quaternion(rng)], 1.5,
+                          vel=[[0.03, 0.01, 0.0]], omega=[[0.0, 0.01, 0.005]])
+    r = _run(lat, ps, "f64", 5, tag="64 points")
+    assert r["pop_err"] < POP_TOL["f64"] and r["F"] < FORCE_TOL["f64"], r
+
+
+def test_more_than_sixty_four_control_points_is_rejected():
+    rng = np.random.default_rng(65)
+    sh = _cluster_shape(rng, 65, 10.0)
+    lat = W.LatticeSpec(40, 40, 40, (0, 0, 0), tau=0.7)
+    ps = W.make_particles([sh], [[20.2, 19.9, 20.1]], [[1.0, 0, 0, 0]], 1.5)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    with pytest.raises(B.LbmError) as e:
+        gpu.classify(parts)
+    assert e.value.code == B.LBM_EINVAL
+    assert b"more than 64" in B.load().lbm_last_error(gpu.ctx)
+    gpu.close()
