@@ -125,6 +125,8 @@ typedef struct {
     size_t checkpoint_bytes;   /* bytes of one raw checkpoint (populations + moments) */
     size_t adjoint_bytes;      /* bytes of one adjoint field: Q planes of cell_stride
                                   values in the storage's arithmetic (double or float) */
+    size_t dem_checkpoint_bytes; /* bytes of the DEM's own state: contact histories
+                                    and the last contact forces */
 } lbm_sizes;
 
 typedef struct {
@@ -289,6 +291,17 @@ int lbm_checkpoint_save(const lbm_ctx* ctx, void* dst_dev);
  * classification history: the next lbm_classify_nodes refills nothing, so
  * classifying the checkpoint's particle state reproduces its geometry. */
 int lbm_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
+
+/* Copy the DEM state the library keeps between dem_step calls (the contact
+ * histories of every particle pair and particle-wall pair: tangential
+ * springs and warm starts of the contact-point search, and the contact
+ * forces of the last substep) into dst_dev (dem_checkpoint_bytes); zeros
+ * before the first dem_step.  Together with lbm_checkpoint_save and the
+ * caller's particle arrays this resumes a run exactly. */
+int lbm_dem_checkpoint_save(const lbm_ctx* ctx, void* dst_dev);
+
+/* Restore the DEM state saved by lbm_dem_checkpoint_save. */
+int lbm_dem_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
 
 /* Record the next max_steps calls of lbm_step (populations after the link
  * reconstruction, owners, links, particle pose and velocities) for

@@ -42,7 +42,8 @@ class LbmSizes(ctypes.Structure):
     _fields_ = [("ncell", ctypes.c_int64), ("cell_stride", ctypes.c_int64),
                 ("population_bytes", ctypes.c_size_t), ("owner_bytes", ctypes.c_size_t),
                 ("flag_bytes", ctypes.c_size_t), ("moment_bytes", ctypes.c_size_t),
-                ("checkpoint_bytes", ctypes.c_size_t), ("adjoint_bytes", ctypes.c_size_t)]
+                ("checkpoint_bytes", ctypes.c_size_t), ("adjoint_bytes", ctypes.c_size_t),
+                ("dem_checkpoint_bytes", ctypes.c_size_t)]
 
 
 class LbmBuffers(ctypes.Structure):
@@ -85,7 +86,8 @@ EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_
            "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
-           "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled", "lbm_get_moments"]
+           "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled", "lbm_get_moments",
+           "lbm_dem_checkpoint_save", "lbm_dem_checkpoint_load"]
 
 _lib = None
 
@@ -123,6 +125,8 @@ def load(path: Path | None = None):
         "lbm_checkpoint_load": [_P, _P],
         "lbm_tape_begin": [_P, ctypes.c_int],
         "lbm_get_moments": [_P, _P, _P],
+        "lbm_dem_checkpoint_save": [_P, _P],
+        "lbm_dem_checkpoint_load": [_P, _P],
         "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P, _P],
         "lbm_adjoint_coupled": [_P, ctypes.POINTER(LbmParticles), _P, ctypes.POINTER(DemParams),
                                 ctypes.c_int, ctypes.c_double, _P, _P, _P],
@@ -434,6 +438,15 @@ class Lattice:
 
     def restore(self, t):
         _check(load().lbm_checkpoint_load(self.ctx, _ptr(t)), self.ctx)
+
+    def dem_checkpoint(self):
+        t = self.torch.empty(max(self.sizes.dem_checkpoint_bytes, 1), dtype=self.torch.uint8,
+                             device=self.device)
+        _check(load().lbm_dem_checkpoint_save(self.ctx, _ptr(t)), self.ctx)
+        return t
+
+    def dem_restore(self, t):
+        _check(load().lbm_dem_checkpoint_load(self.ctx, _ptr(t)), self.ctx)
 
     def tape_begin(self, steps: int):
         _check(load().lbm_tape_begin(self.ctx, int(steps)), self.ctx)

@@ -188,6 +188,21 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
     return LBM_OK;
 }
 
+// Contact histories and the pair list, allocated on first use.
+int dem_alloc(lbm_ctx* c)
+{
+    const int np = c->cfg.n_particles;
+    if (c->hist_pp) return LBM_OK;
+    if (alloc(&c->hist_pp, (size_t)np * np * 8) != hipSuccess ||
+        alloc(&c->hist_pw, (size_t)np * 6 * 8) != hipSuccess ||
+        alloc(&c->pairs, std::max<size_t>((size_t)np * (np - 1) / 2, 1)) != hipSuccess ||
+        alloc(&c->pair_count, 1) != hipSuccess)
+        return fail(c, LBM_ENOMEM, "contact history allocation failed");
+    HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * np * np * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));
+    return LBM_OK;
+}
+
 // Number of lattice velocities of the configured lattice (0 selects D3Q19).
 int lattice_q(const lbm_config* cfg)
 {
@@ -220,6 +235,10 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
     out->moment_bytes = (size_t)ncell * 4 * es;
     out->checkpoint_bytes = out->population_bytes + out->moment_bytes;
     out->adjoint_bytes = (size_t)lattice_q(cfg) * (size_t)out->cell_stride * (es == 8 ? 8 : 4);
+    {
+        const size_t np = (size_t)std::max(cfg->n_particles, 0);
+        out->dem_checkpoint_bytes = sizeof(double) * (np * np * 8 + np * 6 * 8 + np * 6);
+    }
     return LBM_OK;
 }
 
@@ -557,15 +576,8 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
     if (rc) return rc;
     const int np = c->cfg.n_particles;
     if (np == 0) return LBM_OK;
-    if (!c->hist_pp) {
-        if (alloc(&c->hist_pp, (size_t)np * np * 8) != hipSuccess ||
-            alloc(&c->hist_pw, (size_t)np * 6 * 8) != hipSuccess ||
-            alloc(&c->pairs, std::max<size_t>((size_t)np * (np - 1) / 2, 1)) != hipSuccess ||
-            alloc(&c->pair_count, 1) != hipSuccess)
-            return fail(c, LBM_ENOMEM, "contact history allocation failed");
-        HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * np * np * 8, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));
-    }
+    rc = dem_alloc(c);
+    if (rc) return rc;
     PhaseTimer tm(c, LBM_PHASE_DEM);
     HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm));
     return LBM_OK;
@@ -681,6 +693,42 @@ int lbm_checkpoint_load(lbm_ctx* c, const void* src_dev)
     c->own_cur = 0;
     c->stepped_since_classify = false;
     c->link_max = c->link_total = c->refill_total = c->cand_total = 0;
+    return LBM_OK;
+}
+
+int lbm_dem_checkpoint_save(const lbm_ctx* cc, void* dst_dev)
+{
+    lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+    if (!c || !dst_dev) return fail(c, LBM_EINVAL, "null argument");
+    const size_t np = (size_t)c->cfg.n_particles;
+    if (np == 0) return LBM_OK;
+    char* d = (char*)dst_dev;
+    const size_t b_pp = sizeof(double) * np * np * 8, b_pw = sizeof(double) * np * 6 * 8;
+    if (!c->hist_pp) {
+        HIPCHK(c, hipMemsetAsync(d, 0, b_pp + b_pw, c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(d, c->hist_pp, b_pp, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(d + b_pp, c->hist_pw, b_pw, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(d + b_pp + b_pw, c->fc, sizeof(double) * np * 6,
+                             hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+int lbm_dem_checkpoint_load(lbm_ctx* c, const void* src_dev)
+{
+    if (!c || !src_dev) return fail(c, LBM_EINVAL, "null argument");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    const size_t np = (size_t)c->cfg.n_particles;
+    if (np == 0) return LBM_OK;
+    int rc = dem_alloc(c);
+    if (rc) return rc;
+    const char* d = (const char*)src_dev;
+    const size_t b_pp = sizeof(double) * np * np * 8, b_pw = sizeof(double) * np * 6 * 8;
+    HIPCHK(c, hipMemcpyAsync(c->hist_pp, d, b_pp, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hist_pw, d + b_pp, b_pw, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->fc, d + b_pp + b_pw, sizeof(double) * np * 6,
+                             hipMemcpyDeviceToDevice, c->stream));
     return LBM_OK;
 }
 

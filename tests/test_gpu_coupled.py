@@ -130,3 +130,46 @@ def test_resting_pair_feels_no_fluid_force_with_missing_point_treatment(storage)
     assert np.all(np.abs(res[3][0]) < 0.3 * Wsub)
     assert np.all(res[1][0] < -3.0 * Wsub)
     assert res[3][1] < 1e-3
+
+
+def test_checkpoint_resumes_a_run_with_contacts():
+    """Lattice checkpoint + particle arrays + the DEM's own state (contact
+    histories, last contact forces) taken in the middle of a sphere-sphere
+    contact resume the coupled run to the same trajectory; without the DEM
+    state the tangential springs start again from zero and it departs."""
+    lat = W.LatticeSpec(48, 32, 32, (1, 1, 1), tau=0.7)
+    sh = W.sphere_shape(10.0, 0.1)
+    ps = W.make_particles([sh, sh], [[18.0, 16.0, 16.0], [27.95, 17.0, 16.0]],
+                          [[1.0, 0, 0, 0]] * 2, 1.5,
+                          vel=np.array([[0.03, 0.006, 0.0], [-0.03, -0.006, 0.0]]))
+    prm = B.DemParams.make(**W.dem_defaults(ps))
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    parts = B.DeviceParticles(ps)
+
+    def run(k0, k1):
+        for _ in range(k0, k1):
+            gpu.step(parts)
+            gpu.forces()
+            gpu.dem(parts, 10, 0.1, prm)
+            gpu.classify(parts)
+
+    gpu.classify(parts)
+    run(0, 6)
+    ck, ps6, dem6 = gpu.checkpoint(), parts.to_host(ps), gpu.dem_checkpoint()
+    assert gpu.torch.count_nonzero(dem6).item() > 0      # a contact is on
+    run(6, 30)
+    A = parts.to_host(ps)
+    for with_dem in (True, False):
+        gpu.restore(ck)
+        parts.set_state(ps6)
+        gpu.dem_restore(dem6 if with_dem else gpu.torch.zeros_like(dem6))
+        gpu.classify(parts)
+        run(6, 30)
+        R = parts.to_host(ps)
+        dev = max(np.abs(R.pos - A.pos).max(), np.abs(R.vel - A.vel).max(),
+                  np.abs(R.omega - A.omega).max())
+        if with_dem:
+            assert dev <= 1e-12, dev
+        else:
+            assert dev > 1e-9, dev
+    gpu.close()
