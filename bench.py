@@ -341,6 +341,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drag", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-fd", action="store_true",
+                    help="skip the finite-difference checks of the adjoint gradients")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -430,7 +432,7 @@ def main():
     if not args.no_drag:
         line["exact_q"] = exact_q_effect(lat, ps, meta)
     if not args.no_adjoint:
-        line["adjoint"] = adjoint_bench()
+        line["adjoint"] = adjoint_bench(fd_check=not args.no_fd)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

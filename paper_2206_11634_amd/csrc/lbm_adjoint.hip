@@ -14,10 +14,11 @@
 //                  populations), accumulate dJ/dtau, dJ/dF; then (every node)
 //                  push Lambda to the entries of lambda(n) that x read: entry
 //                  (j, x - e_j), of which x is the only writer (x itself for
-//                  entries read through a wall);
-//     k_adj_refill the same for the nodes refilled between n and n+1, whose
-//                  pre-collision populations come from the refill rules; also
-//                  dJ/dv of the wall velocity in those rules;
+//                  entries read through a wall); and list the nodes refilled
+//                  between n and n+1;
+//     k_adj_refill the same for the listed nodes, whose pre-collision
+//                  populations come from the refill rules; also dJ/dv of the
+//                  wall velocity in those rules;
 //  2. k_adj_links  per link: adjoint of its reconstructed population (Lambda
 //                  of the fluid node that pulled the ghost slot, left in
 //                  lambda(n) at the solid node, plus the objective), transposed
@@ -26,6 +27,8 @@
 //                  exchange and missing-point objective terms; dJ/dv, dJ/dF.
 // Arithmetic is that of the storage (double for FP64, float otherwise);
 // parameter gradients are summed in FP64.
+#include <algorithm>
+
 #include "lbm_internal.h"
 #include "lbm_stencil.h"
 #include "lbm_kernels.h"
@@ -310,17 +313,20 @@ __device__ __forceinline__ AdjCoef<A> adj_collide(const A lam[kQ], const A pre[k
 // kernel takes and clears), and zero otherwise; k_adj_refill then rewrites the
 // entries its refilled nodes read.
 template <int S>
-__global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __restrict__ f,
+// (three workgroups per CU: 168 registers, no spills; measured 9% faster
+// than the compiler's unbounded choice of 174, which allows two)
+__global__ __launch_bounds__(256, 3) void k_adj_node(const typename St<S>::T* __restrict__ f,
                                                   const uint32_t* __restrict__ own0,
                                                   const uint32_t* __restrict__ own1,
                                                   const typename St<S>::A* __restrict__ lam1,
                                                   typename St<S>::A* __restrict__ lam0, Geom g,
-                                                  Phys ph, double* grad)
+                                                  Phys ph, double* grad, AdjList list)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // dJ/dF (3), dJ/dtau
+    bool refilled = false;
     if (cell < g.ncell) {
         const uint32_t nx = g.n[0], ny = g.n[1];
         const uint32_t x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
@@ -347,8 +353,8 @@ __global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __res
         }
         // a node refilled between n and n + 1 leaves the entries it read from
         // nodes fluid at n to k_adj_refill, so the two kernels write
-        // disjoint entries and may run in either order
-        const bool refilled = own0[cell] != kFluid && own1[cell] == kFluid;
+        // disjoint entries
+        refilled = own0[cell] != kFluid && own1[cell] == kFluid;
 #pragma unroll
         for (int j = 0; j < kQ; ++j) {
             const A v = live ? co(j, lam[j]) : A(0);
@@ -361,6 +367,17 @@ __global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __res
                 lam0[(int64_t)opp(j) * g.stride + cell] = v;
             }
         }
+    }
+    // list the refilled nodes for k_adj_refill (one atomic per wave); the
+    // count may pass the capacity, which the host checks after the adjoint
+    const uint64_t m = __ballot(refilled);
+    if (m) {  // uniform over the wave
+        const int lane = threadIdx.x & 63;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(list.count, (uint32_t)__popcll(m));
+        base = __shfl(base, 0, 64);
+        const uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (refilled && idx < list.cap) list.node[idx] = cell;
     }
     double* outs[4] = {grad + 0, grad + 1, grad + 2, grad + 3};
     block_add<4>(acc, outs);
@@ -377,19 +394,19 @@ __global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __res
 template <int S>
 __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __restrict__ f,
                                                     const uint32_t* __restrict__ own0,
-                                                    const uint32_t* __restrict__ own1,
                                                     const typename St<S>::A* __restrict__ lam1,
                                                     typename St<S>::A* __restrict__ lam0,
                                                     const double* pos1, const double* vel1,
                                                     const double* om1, Geom g, Phys ph,
-                                                    double* grad, GeoArgs ga)
+                                                    double* grad, GeoArgs ga, AdjList list)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
-    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const uint32_t o0 = cell < g.ncell ? own0[cell] : kFluid;
-    if (o0 != kFluid && own1[cell] == kFluid) {
+    const uint32_t cnt = min(*list.count, list.cap);
+    for (uint32_t l = blockIdx.x * 256u + threadIdx.x; l < cnt; l += gridDim.x * 256u) {
+        const uint32_t cell = list.node[l];
+        const uint32_t o0 = own0[cell];
         const uint32_t nx = g.n[0], ny = g.n[1];
         const int c[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / (nx * ny))};
         const int p = (int)o0;
@@ -734,19 +751,22 @@ struct RunAdj {
     static hipError_t run(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1, const double* pos1,
                           const double* vel1, const double* om1, const void* lam1,
                           void* lam0, const double* wts, double* grad, const GeoArgs& ga,
-                          int parts)
+                          const AdjList& list, int parts)
     {
         using T = typename St<S>::T;
         using A = typename St<S>::A;
-        const uint32_t nb = blocks_for(c->geom.ncell);
-        if (parts & kAdjRefill)
+        if (parts & kAdjNode)
+            hipLaunchKernelGGL(k_adj_node<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0,
+                               c->stream, (const T*)ts.f, ts.own, own1, (const A*)lam1, (A*)lam0,
+                               c->geom, c->phys, grad, list);
+        if (parts & kAdjRefill) {
+            // a grid that one round of resident workgroups covers
+            const uint32_t nb = std::min<uint32_t>(blocks_for(list.cap), 512u);
             hipLaunchKernelGGL(k_adj_refill<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f,
-                               ts.own, own1, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom,
-                               c->phys, grad, ga);
-        if (!(parts & kAdjMain)) return hipGetLastError();
-        hipLaunchKernelGGL(k_adj_node<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f, ts.own,
-                           own1, (const A*)lam1, (A*)lam0, c->geom, c->phys, grad);
-        if (c->cfg.n_particles > 0 && ts.link_max > 0) {
+                               ts.own, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom, c->phys,
+                               grad, ga, list);
+        }
+        if ((parts & kAdjLinks) && c->cfg.n_particles > 0 && ts.link_max > 0) {
             const int np = c->cfg.n_particles;
             dim3 grid(blocks_for(ts.link_max), np);
             if (ga.g_links)
@@ -764,14 +784,48 @@ struct RunAdj {
     }
 };
 
+// The small arrays of one taped step in one launch: the first word of every
+// link cursor line, and the particle state (position, velocity, angular
+// velocity, world control points, quaternion, F^h and T^h of the step).
+__global__ void k_tape_small(uint32_t* __restrict__ tcur, const uint32_t* __restrict__ cur,
+                             double* __restrict__ part, const double* __restrict__ pos,
+                             const double* __restrict__ vel, const double* __restrict__ om,
+                             const double* __restrict__ wpts, const double* __restrict__ quat,
+                             const double* __restrict__ FT, int np, int nctrl)
+{
+    const int i = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (i < np) tcur[(int64_t)i * kCursorPad] = cur[(int64_t)i * kCursorPad];
+    if (i < 3 * np) {
+        part[i] = pos[i];
+        part[3 * np + i] = vel[i];
+        part[6 * np + i] = om[i];
+    }
+    if (i < 3 * nctrl) part[9 * np + i] = wpts[i];
+    double* tq = part + 9 * np + 3 * nctrl;
+    if (quat && i < 4 * np) tq[i] = quat[i];
+    if (i < 6 * np) tq[4 * np + i] = FT[i];
+}
+
 }  // namespace
 
 namespace MDLBM_QNS {
 
+hipError_t launch_tape_small(lbm_ctx* c, TapeStep& t, const lbm_particles* P)
+{
+    const int np = c->cfg.n_particles, nctrl = c->cfg.n_ctrl;
+    if (np == 0) return hipSuccess;
+    const int64_t n = std::max<int64_t>(6 * (int64_t)np, 3 * (int64_t)nctrl);
+    hipLaunchKernelGGL(k_tape_small, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       t.cursor, c->link_cursor, t.part, P->pos, P->vel, P->omega, P->world_pts,
+                       P->quat, c->FT, np, nctrl);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* own1,
                                const double* pos1, const double* vel1, const double* om1,
                                const void* lam1, void* lam0, const double* wts,
-                               double* grad, const lbm_particles* P, const AdjOut& out, int parts)
+                               double* grad, const lbm_particles* P, const AdjOut& out,
+                               const AdjList& list, int parts)
 {
     GeoArgs ga;
     const int np = c->cfg.n_particles;
@@ -791,13 +845,13 @@ hipError_t launch_adjoint_step(lbm_ctx* c, const TapeStep& ts, const uint32_t* o
     switch (c->cfg.storage) {
     case LBM_STORE_F64:
         return RunAdj<LBM_STORE_F64>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga,
-                                          parts);
+                                          list, parts);
     case LBM_STORE_F32:
         return RunAdj<LBM_STORE_F32>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga,
-                                          parts);
+                                          list, parts);
     case LBM_STORE_F16:
         return RunAdj<LBM_STORE_F16>::run(c, ts, own1, pos1, vel1, om1, lam1, lam0, wts, grad, ga,
-                                          parts);
+                                          list, parts);
     default: return hipErrorInvalidValue;
     }
 }

@@ -144,6 +144,9 @@ void free_tape(lbm_ctx* c)
     c->taping = false;
 }
 
+// The launcher of the configured lattice.
+#define LQ(c, fn) ((c)->cfg.lattice == LBM_LATTICE_D3Q15 ? q15::fn : q19::fn)
+
 // Record the step about to stream: populations with the reconstructed ghost
 // slots, the owners of the last classification, its links, the particles.
 int record_tape_step(lbm_ctx* c, const lbm_particles* P)
@@ -168,21 +171,7 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
         if (c->link_max > 0)
             HIPCHK(c, hipMemcpyAsync(t.links, c->links, sizeof(LinkRec) * (size_t)need,
                                      hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.cursor, c->link_cursor, sizeof(uint32_t) * kCursorPad * (size_t)np,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.part, P->pos, sizeof(double) * 3 * np, hipMemcpyDeviceToDevice,
-                                 c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.part + 3 * np, P->vel, sizeof(double) * 3 * np,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.part + 6 * np, P->omega, sizeof(double) * 3 * np,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.part + 9 * np, P->world_pts, sizeof(double) * 3 * c->cfg.n_ctrl,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        double* tq = t.part + 9 * np + 3 * c->cfg.n_ctrl;
-        HIPCHK(c, hipMemcpyAsync(tq, P->quat, sizeof(double) * 4 * np, hipMemcpyDeviceToDevice,
-                                 c->stream));
-        HIPCHK(c, hipMemcpyAsync(tq + 4 * np, c->FT, sizeof(double) * 6 * np,
-                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, LQ(c, launch_tape_small)(c, t, P));
     }
     c->tape_len += 1;
     return LBM_OK;
@@ -210,9 +199,6 @@ int lattice_q(const lbm_config* cfg)
 }
 
 }  // namespace
-
-// The launcher of the configured lattice.
-#define LQ(c, fn) ((c)->cfg.lattice == LBM_LATTICE_D3Q15 ? q15::fn : q19::fn)
 
 extern "C" {
 
@@ -325,21 +311,26 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     c->refill_cap = std::max<int64_t>(1 << 16, (int64_t)np * S2);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = alloc(&c->ball_hist, (size_t)3 * 4 * std::max(np, 1));
-    if (e == hipSuccess) e = alloc(&c->link_cursor, (size_t)kCursorPad * std::max(np, 1));
-    if (e == hipSuccess) e = alloc(&c->cand_cursor, (size_t)kCursorPad * std::max(np, 1));
+    const size_t np1 = (size_t)std::max(np, 1);
+    if (e == hipSuccess) e = alloc(&c->ctr, (size_t)kStageHead + 2 * (size_t)kCursorPad * np1);
+    if (e == hipSuccess) {
+        c->refill_cursor = c->ctr + kCtrRefill;
+        c->err = c->ctr + kCtrErr;
+        c->numeric = c->ctr + kCtrNumeric;
+        c->link_cursor = c->ctr + kStageHead;
+        c->cand_cursor = c->ctr + kStageHead + (size_t)kCursorPad * np1;
+        e = hipMemsetAsync(c->ctr, 0, sizeof(uint32_t) * (kStageHead + 2 * kCursorPad * np1),
+                           c->stream);
+    }
     if (e == hipSuccess && np) e = alloc(&c->cand, (size_t)np * c->cand_cap);
     if (e == hipSuccess && np) e = alloc(&c->links, (size_t)np * c->link_cap);
     if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
-    if (e == hipSuccess) e = alloc(&c->refill_cursor, 1);
-    if (e == hipSuccess) e = alloc(&c->err, 1);
     if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->fc, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->reach, (size_t)std::max(np, 1));
-    if (e == hipSuccess) e = alloc(&c->numeric, 1);
-    if (e == hipSuccess) e = hipMemsetAsync(c->numeric, 0, sizeof(uint32_t), c->stream);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&c->host_stage,
-                          sizeof(uint32_t) * (kStageHead + 2 * (size_t)kCursorPad * std::max(np, 1)),
+                          sizeof(uint32_t) * (kStageHead + 2 * (size_t)kCursorPad * np1),
                           hipHostMallocDefault);
     if (e != hipSuccess) {
         std::string msg = std::string("scratch allocation failed: ") + hipGetErrorString(e);
@@ -350,8 +341,6 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (e == hipSuccess) e = hipMemsetAsync(c->own[0], 0xFF, sz.owner_bytes, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[1], 0xFF, sz.owner_bytes, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sz.flag_bytes, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->link_cursor, 0, sizeof(uint32_t) * kCursorPad * std::max(np, 1), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->FT, 0, sizeof(double) * 6 * std::max(np, 1), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->fc, 0, sizeof(double) * 6 * std::max(np, 1), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -372,15 +361,11 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->ball_hist);
     (void)hipFree(c->links);
     (void)hipFree(c->cand);
-    (void)hipFree(c->cand_cursor);
-    (void)hipFree(c->link_cursor);
     (void)hipFree(c->refill);
-    (void)hipFree(c->refill_cursor);
-    (void)hipFree(c->err);
+    (void)hipFree(c->ctr);
     (void)hipFree(c->FT);
     (void)hipFree(c->fc);
     (void)hipFree(c->reach);
-    (void)hipFree(c->numeric);
     for (auto& t : c->tape) {
         (void)hipFree(t.f);
         (void)hipFree(t.own);
@@ -391,6 +376,8 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->adj_scratch);
     (void)hipFree(c->adj_wts);
     (void)hipFree(c->adj_sig);
+    (void)hipFree(c->adj_list);
+    (void)hipFree(c->adj_count);
     (void)hipFree(c->hist_pp);
     (void)hipFree(c->pairs);
     (void)hipFree(c->pair_count);
@@ -425,10 +412,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
     const size_t cur_bytes = sizeof(uint32_t) * kCursorPad * std::max(np, 1);
 
     if (np > 0) {
-        HIPCHK(c, hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->stream));
-        HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
+        HIPCHK(c, LQ(c, launch_reset_counters)(c));
         // the boxes' check is read back with the list counts below; the
         // kernels that write the owner planes, flags and lists do nothing
         // when it failed, so the context keeps its current geometry
@@ -442,26 +426,29 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             if (k >= 1 || c->dense) HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
             HIPCHK(c, LQ(c, launch_links)(c, own_new, Pd, slot));
         }
+        // populations of the time level the previous classification describes
+        const void* refill_src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
+        if (k >= 1) {
+            // the kernel reads the list's length on the device; should the
+            // list overflow, it runs again below over the grown list
+            PhaseTimer tm(c, LBM_PHASE_REFILL);
+            HIPCHK(c, LQ(c, launch_refill)(c, refill_src, c->f[c->cur], own_prev, Pd));
+        }
         uint32_t* link_counts = c->host_stage + kStageHead;
         uint32_t* cand_counts = c->host_stage + kStageHead + (size_t)kCursorPad * np;
         for (int attempt = 0;; ++attempt) {
-            HIPCHK(c, hipMemcpyAsync(c->host_stage, c->refill_cursor, sizeof(uint32_t),
+            // one copy of the whole counter block
+            HIPCHK(c, hipMemcpyAsync(c->host_stage, c->ctr,
+                                     sizeof(uint32_t) * kStageHead + 2 * cur_bytes,
                                      hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipMemcpyAsync(c->host_stage + 1, c->err, sizeof(uint32_t),
-                                     hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipMemcpyAsync(c->host_stage + 2, c->numeric, sizeof(uint32_t),
-                                     hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipMemcpyAsync(link_counts, c->link_cursor, cur_bytes, hipMemcpyDeviceToHost,
-                                     c->stream));
-            HIPCHK(c, hipMemcpyAsync(cand_counts, c->cand_cursor, cur_bytes, hipMemcpyDeviceToHost,
-                                     c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            if (c->host_stage[2])
+            if (c->host_stage[kCtrNumeric])
                 return fail(c, LBM_ENUMERIC,
                             "lbm_classify_nodes: a step since the previous classification "
                             "produced a non-finite hydrodynamic force or torque");
-            if (c->host_stage[1])
-                return fail(c, LBM_EINVAL, "lbm_classify_nodes: " + err_text(c->host_stage[1]));
+            if (c->host_stage[kCtrErr])
+                return fail(c, LBM_EINVAL,
+                            "lbm_classify_nodes: " + err_text(c->host_stage[kCtrErr]));
             int64_t lmax = 0, ltot = 0, cmax = 0, ctot = 0;
             for (int p = 0; p < np; ++p) {
                 const int64_t v = link_counts[(size_t)p * kCursorPad];
@@ -470,7 +457,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 cmax = std::max<int64_t>(cmax, cand_counts[(size_t)p * kCursorPad]);
                 ctot += cand_counts[(size_t)p * kCursorPad];
             }
-            const int64_t nref = c->host_stage[0];
+            const int64_t nref = c->host_stage[kCtrRefill];
             const bool grow_cand = cmax > c->cand_cap;
             const bool grow_links = lmax > c->link_cap;
             const bool grow_refill = nref > c->refill_cap;
@@ -509,14 +496,12 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 if (alloc(&c->refill, (size_t)c->refill_cap) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "refill list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
-                if (k >= 1) HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
+                if (k >= 1) {
+                    HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
+                    PhaseTimer tm(c, LBM_PHASE_REFILL);
+                    HIPCHK(c, LQ(c, launch_refill)(c, refill_src, c->f[c->cur], own_prev, Pd));
+                }
             }
-        }
-        if (c->refill_total > 0) {
-            // populations of the time level the previous classification describes
-            const void* src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
-            PhaseTimer tm(c, LBM_PHASE_REFILL);
-            HIPCHK(c, LQ(c, launch_refill)(c, src, c->f[c->cur], own_prev, Pd));
         }
     } else {
         c->link_max = c->link_total = c->refill_total = 0;
@@ -766,6 +751,54 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
     return LBM_OK;
 }
 
+namespace {
+
+// The refilled-node list of the adjoint (as long as the refill list of the
+// classifications, whose counts bound it) and one count per taped step,
+// zeroed.
+int adj_lists(lbm_ctx* c)
+{
+    if (c->adj_list_cap < c->refill_cap) {
+        HIPCHK(c, hipFree(c->adj_list));
+        c->adj_list = nullptr;
+        if (alloc(&c->adj_list, (size_t)c->refill_cap) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "adjoint refill list allocation failed");
+        c->adj_list_cap = c->refill_cap;
+    }
+    if (c->adj_count_cap < c->tape_len) {
+        HIPCHK(c, hipFree(c->adj_count));
+        c->adj_count = nullptr;
+        if (alloc(&c->adj_count, (size_t)c->tape_len) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "adjoint count allocation failed");
+        c->adj_count_cap = c->tape_len;
+    }
+    HIPCHK(c, hipMemsetAsync(c->adj_count, 0, sizeof(uint32_t) * c->tape_len, c->stream));
+    return LBM_OK;
+}
+
+AdjList adj_list_of(const lbm_ctx* c, int s)
+{
+    AdjList l;
+    l.node = c->adj_list;
+    l.count = c->adj_count + s;
+    l.cap = (uint32_t)c->adj_list_cap;
+    return l;
+}
+
+// After the adjoint's synchronisation: every step's refilled nodes fitted.
+int adj_lists_check(lbm_ctx* c)
+{
+    std::vector<uint32_t> n((size_t)c->tape_len);
+    HIPCHK(c, hipMemcpy(n.data(), c->adj_count, sizeof(uint32_t) * n.size(), hipMemcpyDeviceToHost));
+    for (uint32_t v : n)
+        if (v > c->adj_list_cap)
+            return fail(c, LBM_ECAPACITY,
+                        "adjoint: more refilled nodes in one step than the refill capacity");
+    return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void* lam_dev,
                 double* grad_dev, double* gpos_dev)
 {
@@ -784,6 +817,8 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
     if (np > 0)
         HIPCHK(c, hipMemcpyAsync(c->adj_wts, weights, sizeof(double) * 6 * np,
                                  hipMemcpyHostToDevice, c->stream));
+    rc = adj_lists(c);
+    if (rc) return rc;
     void* bufs[2] = {lam_dev, c->adj_scratch};
     int in = 0;
     for (int s = c->tape_len - 1; s >= 0; --s) {
@@ -800,17 +835,18 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         }
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
         HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
-                                             c->adj_wts, grad_dev, P, out,
-                                             kAdjRefill | kAdjMain));
+                                             c->adj_wts, grad_dev, P, out, adj_list_of(c, s),
+                                             kAdjNode | kAdjRefill | kAdjLinks));
         in = 1 - in;
     }
     if (in != 0)
         HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    rc = adj_lists_check(c);
     c->tape_len = 0;
     c->taping = false;
-    return LBM_OK;
+    return rc;
 }
 
 int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weights,
@@ -841,6 +877,8 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
         HIPCHK(c, hipMemcpyAsync(sig[0], sigma_dev, sizeof(double) * 12 * np,
                                  hipMemcpyDeviceToDevice, c->stream));
     }
+    rc = adj_lists(c);
+    if (rc) return rc;
     void* bufs[2] = {lam_dev, c->adj_scratch};
     int in = 0, si = 0;
     for (int s = c->tape_len - 1; s >= 0; --s) {
@@ -853,25 +891,27 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
         double* s1 = sig[si];      // adjoint of the state after this step's dem_step
         double* s0 = sig[1 - si];  // adjoint of the state this step used
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
-        // 1. nodes refilled by the classification of the next state: their
-        //    wall velocities belong to s1
+        // 1. nodes, and the nodes refilled by the classification of the next
+        //    state: their wall velocities belong to s1
         AdjOut ro;
         ro.g_refill = s1;
         ro.v_refill = s1 + 6;
         ro.w_refill = s1 + 9;
         ro.gstride = ro.vstride = 12;
         HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
-                                             c->adj_wts, grad_dev, P, ro, kAdjRefill));
+                                             c->adj_wts, grad_dev, P, ro, adj_list_of(c, s),
+                                             kAdjNode | kAdjRefill));
         // 2. the DEM call: s1 -> s0, and this step's force weights
         HIPCHK(c, launch_dem_adjoint(c, ts, P, *prm, n_sub, dt, s1, s0, wJ, c->adj_wts));
-        // 3. nodes and links of this step under those weights, into s0
+        // 3. links of this step under those weights, into s0
         AdjOut lo;
         lo.g_links = s0;
         lo.v_links = s0 + 6;
         lo.w_links = s0 + 9;
         lo.gstride = lo.vstride = 12;
         HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
-                                             c->adj_wts, grad_dev, P, lo, kAdjMain));
+                                             c->adj_wts, grad_dev, P, lo, adj_list_of(c, s),
+                                             kAdjLinks));
         in = 1 - in;
         si = 1 - si;
     }
@@ -882,9 +922,10 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
         HIPCHK(c, hipMemcpyAsync(sigma_dev, sig[si], sizeof(double) * 12 * np,
                                  hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    rc = adj_lists_check(c);
     c->tape_len = 0;
     c->taping = false;
-    return LBM_OK;
+    return rc;
 }
 
 static int profile_collect(lbm_ctx* c)

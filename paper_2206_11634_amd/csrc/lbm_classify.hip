@@ -717,6 +717,19 @@ __global__ __launch_bounds__(256) void k_finish_all(const uint32_t* __restrict__
         }
 }
 
+// Zero the counters a classification fills: the refill count, the box check
+// and the first word of every link and candidate cursor line (the
+// non-finite force flag is left for the classification to report).
+__global__ void k_reset_counters(uint32_t* ctr, int np)
+{
+    const int i = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (i == 0) {
+        ctr[kCtrRefill] = 0;
+        ctr[kCtrErr] = 0;
+    }
+    if (i < 2 * np) ctr[kStageHead + (int64_t)i * kCursorPad] = 0;
+}
+
 __global__ void k_owner_export(const uint32_t* own, int32_t* out, uint32_t ncell)
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
@@ -804,6 +817,14 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
                        c->ball_hist + (int64_t)slot * 4 * np, P, c->geom, c->cand, c->cand_cap,
                        c->cand_cursor, c->links, c->link_cap, c->link_cursor, c->cfg.treatments,
                        per);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(lbm_ctx* c)
+{
+    const int np = c->cfg.n_particles;
+    hipLaunchKernelGGL(k_reset_counters, dim3(blocks_for(2 * (int64_t)std::max(np, 1))), dim3(256), 0,
+                       c->stream, c->ctr, np);
     return hipGetLastError();
 }
 

@@ -18,9 +18,14 @@ namespace mdlbm {
 // table of the 2h + 1 rows of one box plane in LDS).
 constexpr int kMaxBoxHalf = 511;
 constexpr uint32_t kFluid = 0xFFFFFFFFu;
-// Pinned host staging: refill count, box check, non-finite flag, pad, then
-// the link and candidate counts of every particle.
-constexpr int kStageHead = 4;
+// Counters of one classification, in one device block mirrored by one pinned
+// host block so that a single copy reads them all: the refill count, the box
+// check, the non-finite force flag (one 128-byte line), then one line per
+// particle for its link count and one per particle for its candidate count.
+constexpr int kCtrRefill = 0;
+constexpr int kCtrErr = 1;
+constexpr int kCtrNumeric = 2;
+constexpr int kStageHead = 32;  // = kCursorPad: the counts start on the second line
 
 // ---------------------------------------------------------------------------
 // Records
@@ -96,6 +101,7 @@ struct BoxSpec {
 };
 
 constexpr int kCursorPad = 32;  // one 128-byte line per per-particle counter
+static_assert(kStageHead == kCursorPad, "counter block: one head line, then the cursors");
 
 }  // namespace mdlbm
 
@@ -134,6 +140,8 @@ struct lbm_ctx {
     uint32_t* refill_cursor = nullptr;
     int64_t refill_total = 0;
     uint32_t* err = nullptr;      // error bits written by kernels
+    uint32_t* ctr = nullptr;      // the counter block: refill_cursor, err, numeric,
+                                  // link_cursor and cand_cursor point into it
     double* FT = nullptr;         // [np][6] force, torque of the last step
     uint32_t* host_stage = nullptr; // pinned staging for counters
     // DEM
@@ -163,6 +171,10 @@ struct lbm_ctx {
     void* adj_scratch = nullptr;  // the second adjoint field of the ping-pong
     double* adj_wts = nullptr;
     double* adj_sig = nullptr;    // free-motion state adjoints [2][np][12] + weights [np][6]
+    uint32_t* adj_list = nullptr;  // refilled nodes of the adjoint step being taken
+    int64_t adj_list_cap = 0;
+    uint32_t* adj_count = nullptr; // [tape steps] their number, per step
+    int64_t adj_count_cap = 0;
     std::string last_error;
 };
 
@@ -182,7 +194,16 @@ struct AdjOut {
     double* w_refill = nullptr;
     int vstride = 3;
 };
-constexpr int kAdjRefill = 1, kAdjMain = 2;
+// Parts of one adjoint step, run in the order node, refill, links: the node
+// kernel lists the nodes refilled between n and n + 1 for the refill kernel,
+// and leaves the ghost-slot adjoints the link kernel takes.
+constexpr int kAdjRefill = 1, kAdjLinks = 2, kAdjNode = 4;
+// The list of refilled nodes of one adjoint step, and its length.
+struct AdjList {
+    uint32_t* node = nullptr;
+    uint32_t* count = nullptr;
+    uint32_t cap = 0;
+};
 
 // Launchers of the lattice kernels, one set per lattice (D3Q19, D3Q15).
 namespace q19 {

@@ -17,6 +17,8 @@
 // them is a contraction, so there is no MFMA here.  A solid node's plane-i slot serves as the "ghost" that holds
 // the reconstructed population f_i(x_f, t+1) of the one fluid node
 // x_f = x_s + e_i that pulls from it, so the bulk kernel needs no link lookup.
+#include <algorithm>
+
 #include "lbm_internal.h"
 #include "lbm_stencil.h"
 #include "lbm_kernels.h"
@@ -327,20 +329,23 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
 
 // ---------------------------------------------------------------------------
 // Refill: one thread per node uncovered since the previous classification.
+// The count is read on the device (the list's cursor, at most cap), so the
+// launch needs no read-back; a grid of at most a few thousand workgroups
+// strides over the list.  Each node reads only the previous populations and
+// owners and writes only its own populations and moments, so running the
+// kernel again over a longer list (after the list has grown) gives the same
+// values at the nodes of the first run.
 // ---------------------------------------------------------------------------
 template <int S>
-__global__ __launch_bounds__(256) void k_refill(const typename St<S>::T* __restrict__ prev,
-                                                typename St<S>::T* __restrict__ cur,
-                                                typename St<S>::M* __restrict__ mom,
-                                                const RefillRec* __restrict__ rec, uint32_t cnt,
-                                                const uint32_t* __restrict__ own_prev, PartDev P,
-                                                Geom g, Phys ph)
+__device__ __forceinline__ void refill_node(const typename St<S>::T* __restrict__ prev,
+                                            typename St<S>::T* __restrict__ cur,
+                                            typename St<S>::M* __restrict__ mom,
+                                            const RefillRec r,
+                                            const uint32_t* __restrict__ own_prev,
+                                            const PartDev& P, const Geom& g, const Phys& ph)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
-    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
-    if (l >= cnt) return;
-    const RefillRec r = rec[l];
     const int p = r.part;
     const uint32_t nx = g.n[0], ny = g.n[1];
     const int c[3] = {(int)(r.node % nx), (int)((r.node / nx) % ny), (int)(r.node / (nx * ny))};
@@ -390,6 +395,22 @@ __global__ __launch_bounds__(256) void k_refill(const typename St<S>::T* __restr
 #pragma unroll
     for (int i = 0; i < kQ; ++i) St<S>::st(cur + (int64_t)i * g.stride + r.node, v[i], ph.scale);
     St<S>::st_mom(mom + r.node, drho, ux, uy, uz, ph.scale);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_refill(const typename St<S>::T* __restrict__ prev,
+                                                typename St<S>::T* __restrict__ cur,
+                                                typename St<S>::M* __restrict__ mom,
+                                                const RefillRec* __restrict__ rec,
+                                                const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                const uint32_t* __restrict__ err,
+                                                const uint32_t* __restrict__ own_prev, PartDev P,
+                                                Geom g, Phys ph)
+{
+    if (*err) return;  // the classification's box check failed: nothing was listed
+    const uint32_t cnt = min(*cursor, cap);
+    for (uint32_t l = blockIdx.x * 256u + threadIdx.x; l < cnt; l += gridDim.x * 256u)
+        refill_node<S>(prev, cur, mom, rec[l], own_prev, P, g, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -533,11 +554,11 @@ struct RunRefill {
     static hipError_t run(lbm_ctx* c, const void* fprev, void* fcur, const uint32_t* own_prev,
                           const PartDev& P)
     {
-        if (c->refill_total == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_refill<S>, dim3(blocks_for(c->refill_total)), dim3(256), 0, c->stream,
+        const uint32_t nb = std::min<uint32_t>(blocks_for(c->refill_cap), 2048u);
+        hipLaunchKernelGGL(k_refill<S>, dim3(nb), dim3(256), 0, c->stream,
                            (const typename St<S>::T*)fprev, (typename St<S>::T*)fcur,
-                           (typename St<S>::M*)c->mom, c->refill,
-                           (uint32_t)c->refill_total, own_prev, P, c->geom, c->phys);
+                           (typename St<S>::M*)c->mom, c->refill, c->refill_cursor,
+                           (uint32_t)c->refill_cap, c->err, own_prev, P, c->geom, c->phys);
         return hipGetLastError();
     }
 };
