@@ -319,3 +319,47 @@ def __getattr__(name):
     if name == "DragFunction":
         return _make_function()
     raise AttributeError(name)
+
+
+def main(argv=None):
+    """Forward and adjoint of the 128^3 channel with one metaball at a
+    prescribed velocity (FP32 storage, 2000 steps, checkpoints every 100):
+    steps per second of each pass and the gradient, as one JSON line."""
+    import argparse
+    import json
+    import sys
+    import time
+
+    import torch
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--steps", type=int, default=None, help="steps (default: the workload's 2000)")
+    ap.add_argument("--repeat", type=int, default=1, help="forward + adjoint passes to time")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("the adjoint runs on a ROCm GPU", file=sys.stderr)
+        return 2
+    lat, ps, meta = W.config_c5()
+    T = args.steps or meta["steps"]
+    prob = Problem(lat=lat, ps=ps, steps=T, window=meta["checkpoint"], storage=meta["storage"])
+    v, F, tau = ps.vel.copy(), np.array(lat.body_force), lat.tau
+    prob.initial()
+    for _ in range(args.repeat):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, run = forward(prob, v, F, tau, keep=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dv, dF, dtau = backward(run)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(json.dumps(dict(workload=meta["name"], steps=T, J=J,
+                              forward_steps_per_s=round(T / (t1 - t0), 1),
+                              adjoint_steps_per_s=round(T / (t2 - t1), 1),
+                              dJ_dU=dv[0].tolist(), dJ_dF=dF.tolist(), dJ_dtau=dtau)),
+              flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

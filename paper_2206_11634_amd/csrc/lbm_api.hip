@@ -147,14 +147,48 @@ void free_tape(lbm_ctx* c)
 // The launcher of the configured lattice.
 #define LQ(c, fn) ((c)->cfg.lattice == LBM_LATTICE_D3Q15 ? q15::fn : q19::fn)
 
-// Record the step about to stream: populations with the reconstructed ghost
-// slots, the owners of the last classification, its links, the particles.
+// Record the step about to stream: the owners of the last classification, its
+// links, the particles (the populations with the reconstructed ghost slots
+// are the step's own source buffer, the tape slot).
+//
+// Population buffers while taping.  Step s of a window streams from tape
+// slot s into slot s + 1 (its first step copies the current populations into
+// slot 0 once), and the last step of the window into a caller buffer, so the
+// tape holds every step's populations without a copy per step.  The previous
+// level, which a following classification refills from, may then be a tape
+// slot; settle_buffers moves both levels back to the caller's buffers before
+// the tape is reused or released.
+bool caller_buffer(const lbm_ctx* c, const void* p)
+{
+    return p == c->fu[0] || p == c->fu[1];
+}
+
+int settle_buffers(lbm_ctx* c)
+{
+    void*& cur = c->f[c->cur];
+    void*& prev = c->f[1 - c->cur];
+    if (!caller_buffer(c, cur)) {
+        void* dst = (prev == c->fu[0]) ? c->fu[1] : c->fu[0];
+        HIPCHK(c, hipMemcpyAsync(dst, cur, c->sizes.population_bytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
+        cur = dst;
+    }
+    if (!caller_buffer(c, prev) || prev == cur) {
+        void* dst = (cur == c->fu[0]) ? c->fu[1] : c->fu[0];
+        // the previous level matters only to a refill still to come
+        if (c->stepped_since_classify && prev != cur)
+            HIPCHK(c, hipMemcpyAsync(dst, prev, c->sizes.population_bytes,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        prev = dst;
+    }
+    return LBM_OK;
+}
+
 int record_tape_step(lbm_ctx* c, const lbm_particles* P)
 {
     const int np = c->cfg.n_particles;
     TapeStep& t = c->tape[c->tape_len];
-    HIPCHK(c, hipMemcpyAsync(t.f, c->f[c->cur], c->sizes.population_bytes, hipMemcpyDeviceToDevice,
-                             c->stream));
+    // the populations are already in t.f: lbm_step streams into the slots
     HIPCHK(c, hipMemcpyAsync(t.own, c->own[c->own_cur], c->sizes.owner_bytes,
                              hipMemcpyDeviceToDevice, c->stream));
     if (np > 0) {
@@ -288,7 +322,7 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     c->box.vol = c->box.S * c->box.S * c->box.S;
     c->box.tiles = (c->box.vol + 255) / 256;
     for (int i = 0; i < 2; ++i) {
-        c->f[i] = bufs->f_dev[i];
+        c->f[i] = c->fu[i] = bufs->f_dev[i];
         c->own[i] = bufs->owner_dev[i];
     }
     c->flag = bufs->flag_dev;
@@ -524,19 +558,31 @@ int lbm_step(lbm_ctx* c, const lbm_particles* P)
     int rc = check_particles(c, P, false);
     if (rc) return rc;
     const int np = c->cfg.n_particles;
+    const int s = c->tape_len;
+    const bool taped = c->taping && s < c->tape_steps;
+    if (taped && c->f[c->cur] != c->tape[s].f) {
+        // the window's first step: its populations move into slot 0
+        HIPCHK(c, hipMemcpyAsync(c->tape[s].f, c->f[c->cur], c->sizes.population_bytes,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        c->f[c->cur] = c->tape[s].f;
+    }
+    void* src = c->f[c->cur];
+    void* dst = (taped && s + 1 < c->tape_steps) ? c->tape[s + 1].f
+                                                 : (src == c->fu[0] ? c->fu[1] : c->fu[0]);
     {
         PhaseTimer tm(c, LBM_PHASE_BOUNDARY);
         HIPCHK(c, LQ(c, launch_zero_f64)(c, c->FT, 6 * (int64_t)np));
-        if (np > 0 && c->n_classify > 0) HIPCHK(c, LQ(c, launch_boundary)(c, c->f[c->cur], to_dev(P)));
+        if (np > 0 && c->n_classify > 0) HIPCHK(c, LQ(c, launch_boundary)(c, src, to_dev(P)));
     }
-    if (c->taping && c->tape_len < c->tape_steps) {
+    if (taped) {
         int rc2 = record_tape_step(c, P);
         if (rc2) return rc2;
     }
     {
         PhaseTimer tm(c, LBM_PHASE_BULK);
-        HIPCHK(c, LQ(c, launch_stream_collide)(c, c->f[c->cur], c->f[1 - c->cur]));
+        HIPCHK(c, LQ(c, launch_stream_collide)(c, src, dst));
     }
+    c->f[1 - c->cur] = dst;
     c->cur = 1 - c->cur;
     c->stepped_since_classify = true;
     return LBM_OK;
@@ -721,6 +767,8 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     if (max_steps < 0) return fail(c, LBM_EINVAL, "max_steps must be >= 0");
+    int rc = settle_buffers(c);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (max_steps == 0) {
         free_tape(c);
@@ -846,7 +894,8 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
     rc = adj_lists_check(c);
     c->tape_len = 0;
     c->taping = false;
-    return rc;
+    const int rc2 = settle_buffers(c);
+    return rc ? rc : rc2;
 }
 
 int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weights,
@@ -925,7 +974,8 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
     rc = adj_lists_check(c);
     c->tape_len = 0;
     c->taping = false;
-    return rc;
+    const int rc2 = settle_buffers(c);
+    return rc ? rc : rc2;
 }
 
 static int profile_collect(lbm_ctx* c)

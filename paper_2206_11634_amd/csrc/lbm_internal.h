@@ -112,7 +112,9 @@ struct lbm_ctx {
     mdlbm::Geom geom{};
     mdlbm::Phys phys{};
     mdlbm::BoxSpec box{};
-    void* f[2] = {nullptr, nullptr};
+    void* f[2] = {nullptr, nullptr};   // current (f[cur]) and previous populations: the
+                                       // caller's buffers, or tape slots while taping
+    void* fu[2] = {nullptr, nullptr};  // the caller's two population buffers
     uint32_t* own[2] = {nullptr, nullptr};
     uint8_t* flag = nullptr;
     void* mom = nullptr;    // per-node (rho - 1, u) of the current populations
