@@ -215,6 +215,21 @@ const char* lbm_last_error(const lbm_ctx* ctx);
  * non-finite force or torque; the context is then failed. */
 int lbm_classify_nodes(lbm_ctx* ctx, const lbm_particles* P, lbm_counts* out);
 
+/* The same classification without the read-back of its list counts, so the
+ * host does not wait for it: for replaying poses whose lists an earlier
+ * lbm_classify_nodes of this context has already sized (the recomputation
+ * of an adjoint window, a prescribed trajectory run a second time).  The
+ * counts stay on the device: the refill reads its own, and lbm_step runs its
+ * link kernel over the whole link capacity.  What lbm_classify_nodes would
+ * have reported is latched on the device instead: a rejected particle (the
+ * EINVAL cases above; the owners are then not rebuilt) or a list that
+ * outgrew its capacity (ECAPACITY; its extra entries are dropped).  The next
+ * lbm_synchronize, lbm_classify_nodes, lbm_adjoint or lbm_adjoint_coupled
+ * returns that error and leaves the context failed, since the steps run in
+ * between used incomplete geometry.  lbm_get_links and lbm_get_refill
+ * return ESTATE until the next lbm_classify_nodes.  Asynchronous. */
+int lbm_classify_nodes_async(lbm_ctx* ctx, const lbm_particles* P);
+
 /* One lattice step n -> n+1 on the links of the last classification:
  * VIBB (Eqs. eqneq, neqd, rhod, u_d) or halfway reconstruction of the unknown
  * populations, Galilean-invariant momentum exchange force and torque per
@@ -270,7 +285,9 @@ int lbm_get_moments(const lbm_ctx* ctx, double* rho_dev, double* u_dev);
  * storage format).  Asynchronous. */
 int lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
 
-/* Block until the context's stream has drained; EDEVICE on a device error. */
+/* Block until the context's stream has drained; EDEVICE on a device error,
+ * and the error latched by an lbm_classify_nodes_async since the last check
+ * (with a non-finite force of a step since, ENUMERIC), if any. */
 int lbm_synchronize(lbm_ctx* ctx);
 
 /* ---- differentiation form (not in the paper) -----------------------------

@@ -80,23 +80,53 @@ class _Run:
         return self.traj[n]
 
 
+def _again_with_read_back(fn):
+    """Run fn(sync=False) -- classifications without the host read-back --
+    and, should a list outgrow its capacity there (reported at the end of the
+    run), run fn(sync=True), whose classifications grow the lists."""
+    try:
+        return fn(sync=False)
+    except B.LbmError as e:
+        if e.code != B.LBM_ECAPACITY:
+            raise
+    return fn(sync=True)
+
+
+def _closing(gpu, body):
+    try:
+        return body()
+    except BaseException:
+        gpu.close()
+        raise
+
+
 def forward(prob: Problem, vel, body_force, tau, keep: bool = False):
     """Run the forward pass; J, and the run (with its checkpoints) if keep."""
+    return _again_with_read_back(
+        lambda sync: _forward(prob, vel, body_force, tau, keep, sync))
+
+
+def _forward(prob: Problem, vel, body_force, tau, keep: bool, sync: bool):
     run = _Run(prob, vel, body_force, tau)
     gpu, T, n = run.gpu, prob.steps, prob.ps.n
     torch = gpu.torch
-    gpu.set_populations(prob.initial())
-    run.ckpt = {}
-    hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
-    gpu.classify(run.parts(0))
-    for k in range(T):
-        if keep and k % prob.window == 0:
-            run.ckpt[k] = gpu.checkpoint()
-        gpu.step(run.parts(k))
-        gpu.forces(hist[k, 0], hist[k, 1])
-        gpu.classify(run.parts(k + 1))
-    w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
-    J = float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
+
+    def body():
+        gpu.set_populations(prob.initial())
+        run.ckpt = {}
+        hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
+        gpu.classify(run.parts(0))   # sizes the lists
+        for k in range(T):
+            if keep and k % prob.window == 0:
+                run.ckpt[k] = gpu.checkpoint()
+            gpu.step(run.parts(k))
+            gpu.forces(hist[k, 0], hist[k, 1])
+            gpu.classify(run.parts(k + 1), sync=sync)
+        gpu.sync()   # reports what the classifications latched
+        w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
+        return float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
+
+    J = _closing(gpu, body)
     if not keep:
         gpu.close()
         return J, None
@@ -120,11 +150,13 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     for w0 in sorted(run.ckpt, reverse=True):
         w1 = min(w0 + prob.window, prob.steps)
         gpu.restore(run.ckpt[w0])
-        gpu.classify(run.parts(w0))   # reproduces the geometry at w0, refills nothing
+        # the forward pass sized the lists for these poses: no read-backs
+        # (lbm_adjoint reports anything the classifications latched)
+        gpu.classify(run.parts(w0), sync=False)   # the geometry at w0, refills nothing
         gpu.tape_begin(w1 - w0)
         for k in range(w0, w1):
             gpu.step(run.parts(k))
-            gpu.classify(run.parts(k + 1))
+            gpu.classify(run.parts(k + 1), sync=False)
         # poses w0 .. w1 of this window: a contiguous view of gx
         gpu.adjoint(run.parts(w1), prob.weights, lam, g,
                     None if gx is None else gx[w0:w1 + 1])
@@ -226,30 +258,39 @@ class _FreeRun:
         for k, v in st.items():
             self.parts.t[k].copy_(v)
 
-    def advance(self):
+    def advance(self, sync: bool = True):
         self.gpu.dem(self.parts, self.prob.n_sub, self.dt, self.prm)
-        self.gpu.classify(self.parts)
+        self.gpu.classify(self.parts, sync=sync)
 
 
 def forward_free(prob: FreeProblem, body_force, tau, keep: bool = False):
     """J of the free-motion run, and the run (with checkpoints of the lattice
     and of the particle state at every window start) if keep."""
+    return _again_with_read_back(lambda sync: _forward_free(prob, body_force, tau, keep, sync))
+
+
+def _forward_free(prob: FreeProblem, body_force, tau, keep: bool, sync: bool):
     run = _FreeRun(prob, body_force, tau)
     gpu, T, n = run.gpu, prob.steps, prob.ps.n
     torch = gpu.torch
-    if prob.f0 is not None:
-        gpu.set_populations(prob.f0)
-    run.ckpt = {}
-    hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
-    gpu.classify(run.parts)
-    for k in range(T):
-        if keep and k % prob.window == 0:
-            run.ckpt[k] = (gpu.checkpoint(), run.state())
-        gpu.step(run.parts)
-        gpu.forces(hist[k, 0], hist[k, 1])
-        run.advance()
-    w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
-    J = float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
+
+    def body():
+        if prob.f0 is not None:
+            gpu.set_populations(prob.f0)
+        run.ckpt = {}
+        hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
+        gpu.classify(run.parts)   # sizes the lists
+        for k in range(T):
+            if keep and k % prob.window == 0:
+                run.ckpt[k] = (gpu.checkpoint(), run.state())
+            gpu.step(run.parts)
+            gpu.forces(hist[k, 0], hist[k, 1])
+            run.advance(sync)
+        gpu.sync()   # reports what the classifications latched
+        w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
+        return float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
+
+    J = _closing(gpu, body)
     if not keep:
         gpu.close()
         return J, None
@@ -271,11 +312,13 @@ def backward_free(run: _FreeRun):
         ck, st = run.ckpt[w0]
         gpu.restore(ck)
         run.load(st)
-        gpu.classify(run.parts)   # reproduces the geometry at w0, refills nothing
+        # replayed poses: no read-backs (lbm_adjoint_coupled reports anything
+        # the classifications latched)
+        gpu.classify(run.parts, sync=False)   # the geometry at w0, refills nothing
         gpu.tape_begin(w1 - w0)
         for k in range(w0, w1):
             gpu.step(run.parts)
-            run.advance()
+            run.advance(sync=False)
         gpu.adjoint_coupled(run.parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig)
     out = g.cpu().numpy()
     s0 = sig[:n].cpu().numpy()

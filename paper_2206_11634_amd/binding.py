@@ -83,6 +83,7 @@ CLASSIFY = {"auto": 0, "sweep": 1, "balls": 2}
 PHASES = ("bulk", "boundary", "classify", "refill", "dem", "adjoint")
 
 EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_classify_nodes",
+           "lbm_classify_nodes_async",
            "lbm_step", "lbm_particle_forces", "dem_step", "lbm_get_links", "lbm_get_refill",
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
@@ -109,6 +110,7 @@ def load(path: Path | None = None):
         "lbm_init": [ctypes.POINTER(LbmConfig), ctypes.POINTER(LbmBuffers), ctypes.POINTER(_P)],
         "lbm_destroy": [_P],
         "lbm_classify_nodes": [_P, ctypes.POINTER(LbmParticles), ctypes.POINTER(LbmCounts)],
+        "lbm_classify_nodes_async": [_P, ctypes.POINTER(LbmParticles)],
         "lbm_step": [_P, ctypes.POINTER(LbmParticles)],
         "lbm_particle_forces": [_P, _P, _P],
         "dem_step": [_P, ctypes.POINTER(LbmParticles), ctypes.c_int, ctypes.c_double,
@@ -187,6 +189,10 @@ def lbm_classify_nodes(ctx, parts: LbmParticles) -> LbmCounts:
     out = LbmCounts()
     _check(load().lbm_classify_nodes(ctx, ctypes.byref(parts), ctypes.byref(out)), ctx)
     return out
+
+
+def lbm_classify_nodes_async(ctx, parts: LbmParticles):
+    _check(load().lbm_classify_nodes_async(ctx, ctypes.byref(parts)), ctx)
 
 
 def lbm_step(ctx, parts: LbmParticles):
@@ -332,7 +338,12 @@ class Lattice:
         return cls(lat, n_particles=ps.n, n_ctrl=len(ps.K), box_half=ps.box_half(), **kw)
 
     # the five calls of the hot path
-    def classify(self, parts: DeviceParticles) -> LbmCounts:
+    def classify(self, parts: DeviceParticles, sync: bool = True) -> LbmCounts | None:
+        """With sync=False, lbm_classify_nodes_async: no counts, and errors
+        are raised by the next synchronising call."""
+        if not sync:
+            lbm_classify_nodes_async(self.ctx, parts.struct)
+            return None
         return lbm_classify_nodes(self.ctx, parts.struct)
 
     def step(self, parts: DeviceParticles):

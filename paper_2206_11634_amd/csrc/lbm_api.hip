@@ -431,6 +431,107 @@ const char* lbm_last_error(const lbm_ctx* c)
     return c ? c->last_error.c_str() : g_init_error.c_str();
 }
 
+}  // extern "C"
+
+namespace {
+
+// The buffers one classification uses: its owner planes (new and previous),
+// its slots of the ball history, and the populations its refill reads.
+struct ClassifyPlan {
+    int64_t k;
+    int slot, slot_prev, slot_prev2;
+    uint32_t* own_new;
+    const uint32_t* own_prev;
+    const void* refill_src;
+};
+
+ClassifyPlan classify_plan(const lbm_ctx* c)
+{
+    ClassifyPlan cp;
+    cp.k = c->n_classify;
+    cp.slot = (int)(cp.k % 3);
+    cp.slot_prev = (int)((cp.k + 2) % 3);
+    cp.slot_prev2 = (int)((cp.k + 1) % 3);
+    cp.own_new = c->own[cp.k % 2];
+    cp.own_prev = c->own[(cp.k + 1) % 2];
+    // populations of the time level the previous classification describes
+    cp.refill_src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
+    return cp;
+}
+
+// Enqueue a classification: counters reset, boxes, owners, flags, candidates,
+// links, then the refill, which reads its list's length on the device.
+int classify_enqueue(lbm_ctx* c, const PartDev& Pd, const ClassifyPlan& cp)
+{
+    const int np = c->cfg.n_particles;
+    HIPCHK(c, LQ(c, launch_reset_counters)(c));
+    // the boxes' check is read back with the list counts; the kernels that
+    // write the owner planes, flags and lists do nothing when it failed, so
+    // the context keeps its current geometry
+    HIPCHK(c, LQ(c, launch_boxes)(c, Pd, cp.slot));
+    {
+        PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
+        if (cp.k >= 2) HIPCHK(c, LQ(c, launch_clear_boxes)(c, cp.own_new, cp.slot_prev2, np));
+        HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot));
+        // the lattice sweep also runs on a first classification (own_prev
+        // is all fluid then): in dense mode it writes every flag
+        if (cp.k >= 1 || c->dense)
+            HIPCHK(c, LQ(c, launch_finish)(c, cp.own_prev, cp.own_new, cp.slot_prev, np));
+        HIPCHK(c, LQ(c, launch_links)(c, cp.own_new, Pd, cp.slot));
+    }
+    if (cp.k >= 1) {
+        // should the list overflow, lbm_classify_nodes runs it again over
+        // the grown list
+        PhaseTimer tm(c, LBM_PHASE_REFILL);
+        HIPCHK(c, LQ(c, launch_refill)(c, cp.refill_src, c->f[c->cur], cp.own_prev, Pd));
+    }
+    return LBM_OK;
+}
+
+void classify_commit(lbm_ctx* c, const ClassifyPlan& cp)
+{
+    c->own_cur = (int)(cp.k % 2);
+    c->n_classify = cp.k + 1;
+    c->stepped_since_classify = false;
+}
+
+// What asynchronous classifications latched, and the non-finite force flag,
+// as read back into the staging block; either leaves the context failed.
+int deferred_status(lbm_ctx* c, const char* where)
+{
+    const uint32_t def = c->host_stage[kCtrDeferred];
+    if (c->host_stage[kCtrNumeric])
+        return fail(c, LBM_ENUMERIC,
+                    std::string(where) + ": a step since the previous classification "
+                    "produced a non-finite hydrodynamic force or torque");
+    if (def) {
+        c->failed = true;
+        if (def & kDeferredOverflow)
+            return fail(c, LBM_ECAPACITY,
+                        std::string(where) + ": an asynchronous classification outgrew its "
+                        "lists (lbm_classify_nodes sizes them); results since are invalid");
+        return fail(c, LBM_EINVAL,
+                    std::string(where) + ": an asynchronous classification rejected the "
+                    "particles: " + err_text(def & 0xFFu));
+    }
+    c->deferred = false;
+    return LBM_OK;
+}
+
+// Drain the stream and report what asynchronous classifications latched.
+int check_deferred(lbm_ctx* c, const char* where)
+{
+    HIPCHK(c, hipMemcpyAsync(c->host_stage, c->ctr, sizeof(uint32_t) * kStageHead,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->deferred && !c->host_stage[kCtrNumeric]) return LBM_OK;
+    return deferred_status(c, where);
+}
+
+}  // namespace
+
+extern "C" {
+
 int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
@@ -439,35 +540,13 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
     if (rc) return rc;
     const int np = c->cfg.n_particles;
     const PartDev Pd = to_dev(P);
-    const int64_t k = c->n_classify;
-    const int slot = (int)(k % 3), slot_prev = (int)((k + 2) % 3), slot_prev2 = (int)((k + 1) % 3);
-    uint32_t* own_new = c->own[k % 2];
-    const uint32_t* own_prev = c->own[(k + 1) % 2];
+    const ClassifyPlan cp = classify_plan(c);
+    const int64_t k = cp.k;
     const size_t cur_bytes = sizeof(uint32_t) * kCursorPad * std::max(np, 1);
 
     if (np > 0) {
-        HIPCHK(c, LQ(c, launch_reset_counters)(c));
-        // the boxes' check is read back with the list counts below; the
-        // kernels that write the owner planes, flags and lists do nothing
-        // when it failed, so the context keeps its current geometry
-        HIPCHK(c, LQ(c, launch_boxes)(c, Pd, slot));
-        {
-            PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
-            if (k >= 2) HIPCHK(c, LQ(c, launch_clear_boxes)(c, own_new, slot_prev2, np));
-            HIPCHK(c, LQ(c, launch_mark)(c, own_new, Pd, slot));
-            // the lattice sweep also runs on a first classification (own_prev
-            // is all fluid then): in dense mode it writes every flag
-            if (k >= 1 || c->dense) HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
-            HIPCHK(c, LQ(c, launch_links)(c, own_new, Pd, slot));
-        }
-        // populations of the time level the previous classification describes
-        const void* refill_src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
-        if (k >= 1) {
-            // the kernel reads the list's length on the device; should the
-            // list overflow, it runs again below over the grown list
-            PhaseTimer tm(c, LBM_PHASE_REFILL);
-            HIPCHK(c, LQ(c, launch_refill)(c, refill_src, c->f[c->cur], own_prev, Pd));
-        }
+        rc = classify_enqueue(c, Pd, cp);
+        if (rc) return rc;
         uint32_t* link_counts = c->host_stage + kStageHead;
         uint32_t* cand_counts = c->host_stage + kStageHead + (size_t)kCursorPad * np;
         for (int attempt = 0;; ++attempt) {
@@ -476,10 +555,8 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                                      sizeof(uint32_t) * kStageHead + 2 * cur_bytes,
                                      hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            if (c->host_stage[kCtrNumeric])
-                return fail(c, LBM_ENUMERIC,
-                            "lbm_classify_nodes: a step since the previous classification "
-                            "produced a non-finite hydrodynamic force or torque");
+            rc = deferred_status(c, "lbm_classify_nodes");
+            if (rc) return rc;
             if (c->host_stage[kCtrErr])
                 return fail(c, LBM_EINVAL,
                             "lbm_classify_nodes: " + err_text(c->host_stage[kCtrErr]));
@@ -510,7 +587,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 if (alloc(&c->cand, (size_t)np * c->cand_cap) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "candidate list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
-                HIPCHK(c, LQ(c, launch_mark)(c, own_new, Pd, slot));  // same owners, full list
+                HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot));  // same owners, full list
             }
             if (grow_links) {
                 HIPCHK(c, hipFree(c->links));
@@ -521,7 +598,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             }
             if (grow_cand || grow_links) {
                 HIPCHK(c, hipMemsetAsync(c->link_cursor, 0, cur_bytes, c->stream));
-                HIPCHK(c, LQ(c, launch_links)(c, own_new, Pd, slot));
+                HIPCHK(c, LQ(c, launch_links)(c, cp.own_new, Pd, cp.slot));
             }
             if (grow_refill) {
                 HIPCHK(c, hipFree(c->refill));
@@ -531,23 +608,44 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                     return fail(c, LBM_ENOMEM, "refill list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
                 if (k >= 1) {
-                    HIPCHK(c, LQ(c, launch_finish)(c, own_prev, own_new, slot_prev, np));
+                    HIPCHK(c, LQ(c, launch_finish)(c, cp.own_prev, cp.own_new, cp.slot_prev, np));
                     PhaseTimer tm(c, LBM_PHASE_REFILL);
-                    HIPCHK(c, LQ(c, launch_refill)(c, refill_src, c->f[c->cur], own_prev, Pd));
+                    HIPCHK(c, LQ(c, launch_refill)(c, cp.refill_src, c->f[c->cur], cp.own_prev, Pd));
                 }
             }
         }
     } else {
         c->link_max = c->link_total = c->refill_total = 0;
     }
-    c->own_cur = (int)(k % 2);
-    c->n_classify = k + 1;
-    c->stepped_since_classify = false;
+    c->counts_known = true;
+    classify_commit(c, cp);
     if (out) {
         out->n_links = c->link_total;
         out->n_refill = c->refill_total;
         out->n_candidates = c->cand_total;
     }
+    return LBM_OK;
+}
+
+int lbm_classify_nodes_async(lbm_ctx* c, const lbm_particles* P)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    int rc = check_particles(c, P, false);
+    if (rc) return rc;
+    const ClassifyPlan cp = classify_plan(c);
+    if (c->cfg.n_particles > 0) {
+        rc = classify_enqueue(c, to_dev(P), cp);
+        if (rc) return rc;
+        HIPCHK(c, LQ(c, launch_latch_deferred)(c));
+        c->link_max = c->link_cap;  // lbm_step covers the whole capacity
+        c->deferred = true;
+    } else {
+        c->link_max = 0;
+    }
+    c->link_total = c->cand_total = c->refill_total = 0;
+    c->counts_known = false;
+    classify_commit(c, cp);
     return LBM_OK;
 }
 
@@ -619,6 +717,8 @@ int lbm_get_links(const lbm_ctx* cc, int64_t cap, int32_t* node_dev, int8_t* d_d
 {
     lbm_ctx* c = const_cast<lbm_ctx*>(cc);
     if (!c || !n_out) return fail(c, LBM_EINVAL, "null argument");
+    if (!c->counts_known)
+        return fail(c, LBM_ESTATE, "the last classification was asynchronous: no counts");
     *n_out = c->link_total;
     if (c->link_total == 0) return LBM_OK;
     if (cap < c->link_total) return fail(c, LBM_ECAPACITY, "link output too small");
@@ -646,6 +746,8 @@ int lbm_get_refill(const lbm_ctx* cc, int64_t cap, int32_t* node_dev, int32_t* p
 {
     lbm_ctx* c = const_cast<lbm_ctx*>(cc);
     if (!c || !n_out) return fail(c, LBM_EINVAL, "null argument");
+    if (!c->counts_known)
+        return fail(c, LBM_ESTATE, "the last classification was asynchronous: no counts");
     *n_out = c->refill_total;
     if (c->refill_total == 0) return LBM_OK;
     if (cap < c->refill_total) return fail(c, LBM_ECAPACITY, "refill output too small");
@@ -695,6 +797,7 @@ int lbm_synchronize(lbm_ctx* c)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->deferred && !c->failed) return check_deferred(c, "lbm_synchronize");
     return LBM_OK;
 }
 
@@ -891,7 +994,8 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
         HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    rc = adj_lists_check(c);
+    rc = c->deferred ? check_deferred(c, "lbm_adjoint") : LBM_OK;
+    if (!rc) rc = adj_lists_check(c);
     c->tape_len = 0;
     c->taping = false;
     const int rc2 = settle_buffers(c);
@@ -971,7 +1075,8 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
         HIPCHK(c, hipMemcpyAsync(sigma_dev, sig[si], sizeof(double) * 12 * np,
                                  hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    rc = adj_lists_check(c);
+    rc = c->deferred ? check_deferred(c, "lbm_adjoint") : LBM_OK;
+    if (!rc) rc = adj_lists_check(c);
     c->tape_len = 0;
     c->taping = false;
     const int rc2 = settle_buffers(c);

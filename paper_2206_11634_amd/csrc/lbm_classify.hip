@@ -730,6 +730,25 @@ __global__ void k_reset_counters(uint32_t* ctr, int np)
     if (i < 2 * np) ctr[kStageHead + (int64_t)i * kCursorPad] = 0;
 }
 
+// After an asynchronous classification: latch its box check and any list
+// overflow (a count above its capacity) into the deferred word, which no
+// classification clears.
+__global__ void k_latch_deferred(uint32_t* ctr, int np, int np1, uint32_t link_cap,
+                                 uint32_t cand_cap, uint32_t refill_cap)
+{
+    uint32_t bad = 0;
+    for (int p = (int)threadIdx.x; p < np; p += (int)blockDim.x) {
+        const uint32_t nl = ctr[kStageHead + (int64_t)p * kCursorPad];
+        const uint32_t nc = ctr[kStageHead + (int64_t)(np1 + p) * kCursorPad];
+        if (nl > link_cap || nc > cand_cap) bad = kDeferredOverflow;
+    }
+    if (threadIdx.x == 0) {
+        if (ctr[kCtrRefill] > refill_cap) bad |= kDeferredOverflow;
+        bad |= ctr[kCtrErr] & 0xFFu;
+    }
+    if (bad) atomicOr(ctr + kCtrDeferred, bad);
+}
+
 __global__ void k_owner_export(const uint32_t* own, int32_t* out, uint32_t ncell)
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
@@ -825,6 +844,15 @@ hipError_t launch_reset_counters(lbm_ctx* c)
     const int np = c->cfg.n_particles;
     hipLaunchKernelGGL(k_reset_counters, dim3(blocks_for(2 * (int64_t)std::max(np, 1))), dim3(256), 0,
                        c->stream, c->ctr, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_latch_deferred(lbm_ctx* c)
+{
+    const int np = c->cfg.n_particles;
+    hipLaunchKernelGGL(k_latch_deferred, dim3(1), dim3(256), 0, c->stream, c->ctr, np,
+                       std::max(np, 1), (uint32_t)c->link_cap, (uint32_t)c->cand_cap,
+                       (uint32_t)c->refill_cap);
     return hipGetLastError();
 }
 

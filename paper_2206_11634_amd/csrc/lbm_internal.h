@@ -25,6 +25,10 @@ constexpr uint32_t kFluid = 0xFFFFFFFFu;
 constexpr int kCtrRefill = 0;
 constexpr int kCtrErr = 1;
 constexpr int kCtrNumeric = 2;
+// Latched by asynchronous classifications: the box check's bits (low byte)
+// and kDeferredOverflow when a list outgrew its capacity.
+constexpr int kCtrDeferred = 3;
+constexpr uint32_t kDeferredOverflow = 0x100u;
 constexpr int kStageHead = 32;  // = kCursorPad: the counts start on the second line
 
 // ---------------------------------------------------------------------------
@@ -121,6 +125,8 @@ struct lbm_ctx {
     int cur = 0;            // population buffer holding the current f+
     int own_cur = 0;        // owner plane of the last classification
     int64_t n_classify = 0; // classifications done
+    bool counts_known = true;   // the last classification's list counts were read back
+    bool deferred = false;      // an asynchronous classification awaits its check
     bool stepped_since_classify = false;
     bool dense = false;     // particle balls cover most of the lattice: sweep it whole
     bool failed = false;

@@ -292,6 +292,62 @@ def test_classify_rejects_bad_particles_and_keeps_the_geometry():
     gpu.close()
 
 
+def test_async_classification_matches_the_synchronous_one():
+    """lbm_classify_nodes_async builds the same owners, links and refills as
+    lbm_classify_nodes (the step then covers the whole link capacity): over a
+    moving run the populations agree bit for bit and the forces to rounding;
+    the link list is not readable until a synchronous classification."""
+    lat, ps = W.tiny_case(3, dims=(30, 22, 26), periodic=(1, 0, 1), n_particles=3,
+                          diameter_range=(4.0, 7.0), speed=0.08, spin=0.01)
+    runs = []
+    for sync in (True, False):
+        gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+        parts = B.DeviceParticles(ps)
+        gpu.classify(parts)
+        forces = []
+        for k in range(14):
+            gpu.step(parts)
+            F, T = gpu.forces()
+            forces.append(np.concatenate([F.cpu().numpy(), T.cpu().numpy()], axis=1))
+            parts.set_state(W.prescribed_state(ps, lat, float(k + 1)))
+            gpu.classify(parts, sync=sync)
+        if not sync:
+            with pytest.raises(B.LbmError) as e:
+                gpu.links()
+            assert e.value.code == B.LBM_ESTATE
+        gpu.sync()
+        runs.append((gpu.populations(), gpu.owner(), np.array(forces)))
+        gpu.close()
+    (fa, oa, Fa), (fb, ob, Fb) = runs
+    np.testing.assert_array_equal(fa, fb)
+    np.testing.assert_array_equal(oa, ob)
+    np.testing.assert_allclose(Fb, Fa, rtol=1e-12, atol=1e-15 * np.abs(Fa).max())
+
+
+def test_async_classification_latches_a_rejected_particle():
+    """A state that fails the boxes' check under the asynchronous call is
+    reported by the next lbm_synchronize as EINVAL, and the context is failed
+    (the steps in between ran on geometry that was not rebuilt)."""
+    lat, ps = W.tiny_case(1, dims=(28, 20, 26), periodic=(1, 0, 1), n_particles=3,
+                          diameter_range=(4.0, 7.0), speed=0.06, spin=0.006)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    gpu.classify(parts)
+    gpu.step(parts)
+    bad = ps.copy()
+    bad.pos[0, 0] = -5.0
+    bad.refresh_world()
+    parts.set_state(bad)
+    gpu.classify(parts, sync=False)
+    with pytest.raises(B.LbmError) as e:
+        gpu.sync()
+    assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(B.LbmError) as e:
+        gpu.step(parts)
+    assert e.value.code == B.LBM_ESTATE
+    gpu.close()
+
+
 def test_non_finite_forces_are_reported_and_fail_the_context():
     """A population set to NaN next to a body (forced from the host) makes the
     step's momentum-exchange sums non-finite; the next classification reports
