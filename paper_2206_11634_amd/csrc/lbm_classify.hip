@@ -227,13 +227,28 @@ __global__ __launch_bounds__(64) void k_boxes(PartDev P, int h, double* ball, ui
     if (!(lim > rmax) || !(bound(lim) < c0)) {
         bad |= 4u;
     } else {
-        // bisection keeps B(hi) < c0, so hi bounds the body at every step;
-        // 40 halvings of an interval below 2 h leave it under 1e-9
+        // B decreases beyond rmax.  A 64-way search keeps B(hi) < c0, so hi
+        // bounds the body at every round: the lanes test 64 points of
+        // (lo, hi], each summing B over the control points itself, and the
+        // first that passes becomes hi; six rounds shrink an interval below
+        // 2 h under 1e-9
+        const int nn = min(n, kMaxCtrl);
         double lo = rmax, hi = lim;
-        for (int it = 0; it < 40; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (bound(mid) >= c0) lo = mid;
-            else hi = mid;
+        for (int round = 0; round < 6; ++round) {
+            const double step = (hi - lo) * (1.0 / 64.0);
+            const double d = lane == 63 ? hi : lo + step * (double)(lane + 1);
+            double B = 0.0;
+            for (int j = 0; j < nn; ++j) {
+                const double t = d - __shfl(ri, j, 64);
+                B += __shfl(Ki, j, 64) / (t * t);
+            }
+            const uint64_t pass = __ballot(B < c0);
+            if (!pass) break;  // uniform; hi keeps its bound
+            const int first = __ffsll((unsigned long long)pass) - 1;
+            const double nh = __shfl(d, first, 64);
+            const double nl = __shfl(d, first > 0 ? first - 1 : 0, 64);
+            hi = nh;
+            if (first > 0) lo = nl;
         }
         R = hi;
     }
@@ -554,11 +569,14 @@ __device__ __forceinline__ int select_bit(uint64_t m, uint32_t k)
 // wave then enumerates its links in that order and gives one link to each
 // lane (candidate data by lane shuffles), so the FP64 work of q runs on full
 // waves.  A grid of a few workgroups per particle strides over the list.
+// With few particles a wave takes cpw = 16 candidates instead of 64: about
+// one link per lane then, and four times the waves, so the serial
+// enumeration is short where the list is too small to fill the chip.
 __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ err, const uint32_t* own, const double* ball, PartDev P,
                                                Geom g, const uint32_t* cand, int64_t cand_cap,
                                                const uint32_t* cand_cursors, LinkRec* links,
                                                int64_t cap, uint32_t* cursors, int treat,
-                                               uint32_t gx)
+                                               uint32_t gx, uint32_t cpw)
 {
     if (*err) return;  // the boxes failed their check: leave every plane as it is
     __shared__ double sp[4 * kMaxCtrl];
@@ -573,12 +591,13 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
     LinkRec* out = links + (int64_t)p * cap;
     uint32_t* cursor = cursors + (int64_t)p * kCursorPad;
     const int lane = threadIdx.x & 63;
-    for (uint32_t base0 = bx * 256u; base0 < count; base0 += gx * 256u) {
-        const uint32_t k = base0 + threadIdx.x;
+    const uint32_t chunk = 4u * cpw;  // candidates of one workgroup per round
+    for (uint32_t base0 = bx * chunk; base0 < count; base0 += gx * chunk) {
+        const uint32_t k = base0 + (threadIdx.x >> 6) * cpw + (uint32_t)lane;
         uint32_t node = 0, mask = 0;
         int c[3] = {0, 0, 0};
         double X = 0.0, Y = 0.0, Z = 0.0;
-        if (k < count) {
+        if ((uint32_t)lane < cpw && k < count) {
             node = list[k];
             c[0] = (int)(node % (uint32_t)g.n[0]);
             c[1] = (int)((node / (uint32_t)g.n[0]) % (uint32_t)g.n[1]);
@@ -830,12 +849,16 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
 {
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
-    const uint32_t per = (uint32_t)std::min<int64_t>(16, (c->cand_cap + 255) / 256);
+    // few particles: 16 candidates per wave and up to 64 workgroups each
+    const uint32_t cpw = np <= 64 ? 16u : 64u;
+    const int64_t chunk = 4 * (int64_t)cpw;
+    const uint32_t per =
+        (uint32_t)std::min<int64_t>(np <= 64 ? 64 : 16, (c->cand_cap + chunk - 1) / chunk);
     const uint32_t nb = (per * (uint32_t)np + 7u) & ~7u;
     hipLaunchKernelGGL(k_links, dim3(nb), dim3(256), 0, c->stream, c->err, own,
                        c->ball_hist + (int64_t)slot * 4 * np, P, c->geom, c->cand, c->cand_cap,
                        c->cand_cursor, c->links, c->link_cap, c->link_cursor, c->cfg.treatments,
-                       per);
+                       per, cpw);
     return hipGetLastError();
 }
 
