@@ -119,3 +119,17 @@ def test_init_rejects_bad_arguments_before_touching_the_device(lib):
     cfg = _cfg(n_particles=1, box_half=6, dims=(16, 40, 40), periodic=(1, 0, 0))
     assert lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)) == B.LBM_EINVAL
     assert b"2*box_half" in lib.lbm_last_error(None)
+
+
+def test_calls_reject_a_null_context_without_touching_the_device(lib):
+    """Every call on the hot path, the asynchronous classification and the
+    synchronisation that reports its latched errors return EINVAL for a null
+    context before any device work."""
+    p = B.LbmParticles()
+    prm = B.DemParams()
+    assert lib.lbm_classify_nodes(None, ctypes.byref(p), None) == B.LBM_EINVAL
+    assert lib.lbm_classify_nodes_async(None, ctypes.byref(p)) == B.LBM_EINVAL
+    assert lib.lbm_step(None, ctypes.byref(p)) == B.LBM_EINVAL
+    assert lib.dem_step(None, ctypes.byref(p), 1, ctypes.c_double(0.1), ctypes.byref(prm)) == B.LBM_EINVAL
+    assert lib.lbm_synchronize(None) == B.LBM_EINVAL
+    assert b"null context" in lib.lbm_last_error(None)
