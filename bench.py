@@ -34,11 +34,13 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=3, lattice=19):
+def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=None, lattice=19):
     import torch
     from paper_2206_11634_amd import binding as B
     from paper_2206_11634_amd import workloads as W
 
+    if treatments is None:   # the workload's own treatment bits
+        treatments = int(meta.get("treatments", 3))
     gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treatments,
                                   lattice=lattice)
     parts = B.DeviceParticles(ps)
@@ -223,7 +225,7 @@ def exact_q_effect(lat, ps, meta, steps=200):
         drag_mean_rel_diff=float(abs(lin[tail, 2].mean() - ex[tail, 2].mean()) / abs(ex[tail, 2].mean())),
         force_series_rel_diff=float(np.abs(lin - ex).max() / np.abs(ex).max()),
         sphere_workload=f"c1 40x40x80 sphere d=10, prescribed descent 0.01 lu/step, {steps} steps, FP32")
-    r = run_storage(lat, ps, meta, "f32", 5, 1, treatments=7)
+    r = run_storage(lat, ps, meta, "f32", 5, 1, treatments=int(meta.get("treatments", 3)) | 4)
     res["ms_per_step"] = round(r["ms_per_step"], 4)
     res["classify_ms"] = round(r["prof"]["classify"][0] / max(r["prof"]["classify"][1], 1), 4)
     return res
@@ -407,6 +409,7 @@ def main():
             "storage": args.storage,
             "stencil": f"D3Q{args.lattice}",
             "tau": lat.tau,
+            "treatments": int(meta.get("treatments", 3)),
             "dem_substeps": meta.get("n_sub", 10),
             "step": "classify + step + forces + dem",
         },

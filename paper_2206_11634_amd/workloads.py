@@ -474,10 +474,85 @@ def config_c3(seed: int = 3, n_particles: int = 200, n: int = 256):
     return lat, ps, meta
 
 
+def _surface_cloud(shape: Shape, rng, n_dirs: int = 4000) -> np.ndarray:
+    """Body-frame points on the outer surface of the body: along each of
+    n_dirs random directions from the centroid, the last sample inside."""
+    dirs = rng.normal(size=(n_dirs, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    t = np.linspace(0, shape.radius * 1.05, 400)
+    inside = _field(shape.pts, shape.K, t[None, :, None] * dirs[:, None, :]) >= shape.c0
+    last = np.where(inside.any(1), (inside * np.arange(400)).max(1), 0)
+    return dirs * t[last][:, None]
+
+
+def _place_lattice(rng, shapes, grid_pos, dims, periodic, jitter, wall_gap=2.5, level=0.8,
+                   tries=400):
+    """Bodies on jittered lattice sites with random orientations, each drawn
+    again (orientation and jitter) until it keeps wall_gap from every wall
+    and does not meet a body placed before it: no surface point of one lies
+    where the other's field reaches level * c0 (a shell of roughly 10% of
+    the radius around each body)."""
+    n = len(shapes)
+    L = np.asarray(dims, float)
+    per = np.asarray([bool(v) for v in periodic])
+    clouds = {}
+    pos = np.zeros((n, 3))
+    quats = np.zeros((n, 4))
+    wpts = [None] * n
+    radii = np.array([s.radius for s in shapes])
+
+    def field_at(j, X):
+        d = X[:, None, :] - wpts[j][None, :, :]
+        return (shapes[j].K[None, :] / (d * d).sum(-1)).sum(-1)
+
+    for i in range(n):
+        sh = shapes[i]
+        if id(sh) not in clouds:
+            clouds[id(sh)] = _surface_cloud(sh, rng)
+        cloud = clouds[id(sh)]
+        for _ in range(tries):
+            q = random_quaternion(rng)
+            x = grid_pos[i] + rng.uniform(-jitter, jitter, 3)
+            R = quat_to_matrix(q[None, :])[0]
+            P = cloud @ R.T + x
+            fits = True
+            for ax in range(3):
+                if not per[ax] and (P[:, ax].min() < wall_gap - 0.5 or
+                                    P[:, ax].max() > L[ax] - 0.5 - wall_gap):
+                    fits = False
+            if not fits:
+                continue
+            W_i = sh.pts @ R.T + x
+            D = pos[:i] - x
+            D[:, per] -= L[per] * np.round(D[:, per] / L[per])
+            near = np.flatnonzero(np.linalg.norm(D, axis=1) <= sh.radius + radii[:i] + 2.0)
+            for j in near:
+                d = D[j]
+                shift = (pos[j] - x) - d          # image of j nearest x
+                Pj = clouds[id(shapes[j])] @ quat_to_matrix(quats[j][None, :])[0].T + pos[j] - shift
+                wj = wpts[j]
+                wpts[j] = wj - shift
+                hit = (field_at(j, P) >= level * shapes[j].c0).any()
+                wpts[j] = wj
+                dd = Pj[:, None, :] - W_i[None, :, :]
+                hit = hit or ((sh.K[None, :] / (dd * dd).sum(-1)).sum(-1) >= level * sh.c0).any()
+                if hit:
+                    fits = False
+                    break
+            if fits:
+                break
+        else:
+            raise RuntimeError(f"no clear placement for body {i}")
+        pos[i], quats[i] = x, q
+        wpts[i] = sh.pts @ quat_to_matrix(q[None, :])[0].T + x
+    return pos, quats
+
+
 def config_c4(seed: int = 4, n: int = 512, per_axis: int = 10, storage: str = "f32"):
     """512^3 lattice, periodic in x and y with walls in z, 1000 metaballs at
     20% solids (d_eq ~ 37) on a jittered 10x10x10 lattice, tau 0.55,
-    density ratio 1.5, sedimenting."""
+    density ratio 1.5, sedimenting.  Orientations and jitters are drawn
+    again until every body is clear of the walls and of its neighbours."""
     rng = np.random.default_rng(seed)
     lat = LatticeSpec(n, n, n, (1, 1, 0), tau=0.55)
     npart = per_axis ** 3
@@ -490,12 +565,14 @@ def config_c4(seed: int = 4, n: int = 512, per_axis: int = 10, storage: str = "f
     sp = n / per_axis
     g = (np.arange(per_axis) + 0.5) * sp
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
-    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], -1)
-    pos += rng.uniform(-0.05 * sp, 0.05 * sp, pos.shape)
-    quats = np.array([random_quaternion(rng) for _ in range(npart)])
+    grid = np.stack([X.ravel(), Y.ravel(), Z.ravel()], -1)
+    pos, quats = _place_lattice(rng, shapes, grid, lat.dims, lat.periodic, 0.05 * sp)
     ps = make_particles(shapes, pos, quats, 1.5)
+    # treatment bits 1+2+8: at tau 0.55 the extrapolated non-equilibrium part
+    # of VIBB for q > 1/2 grows without bound in narrow gaps between
+    # neighbouring bodies (plain 1+2 diverges within ~70 steps here)
     meta = dict(name=f"c4_sediment_{n}cube_{npart}p", steps=5000, storage=storage, rho_r=1.5,
-                gravity=(0.0, 0.0, -8.8e-6), n_sub=10)
+                gravity=(0.0, 0.0, -8.8e-6), n_sub=10, treatments=11)
     return lat, ps, meta
 
 
