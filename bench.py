@@ -138,7 +138,7 @@ def cpu_baseline(seconds=15.0):
     from paper_2206_11634_amd import workloads as W
 
     lat, ps, meta = W.config_c4(seed=44, n=128, per_axis=2)
-    o = O.Oracle(lat)
+    o = O.Oracle(lat, treat=int(meta.get("treatments", 3)))
     o.classify(ps)
     steps = 0
     t0 = time.perf_counter()
