@@ -27,8 +27,8 @@ METRIC = "MLUPS + % HBM roofline (FP32/FP16-store vs plain), drag err; adjoint s
 # WRITE_SIZE passes (scaled by a copy kernel of known size; see profiles/),
 # valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
-    ("c4_sediment_512cube_1000p", "f32"): dict(source_sha256_16="0c8038dcce0fd0e7",
-                                              read=10.330e9, written=12.348e9),
+    ("c4_sediment_512cube_1000p", "f32"): dict(source_sha256_16="a244481d9894da87",
+                                              read=10.327e9, written=12.348e9),
 }
 HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
@@ -79,8 +79,8 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=
 
 def _stream_source_hash():
     """Hash of the source the stream-collide kernel is compiled from: the
-    kernel's own text, the storage traits and stencil headers, and the Geom
-    and Phys records it takes."""
+    kernel's own text, its workgroup-to-node mapping, the storage traits and
+    stencil headers, and the Geom and Phys records it takes."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_2206_11634_amd", "csrc")
@@ -91,8 +91,10 @@ def _stream_source_hash():
 
     stream = read("lbm_stream.hip")
     k = re.search(r"template <int S>\n__global__[^\n]*k_stream_collide\(.*?\n}\n", stream, re.S)
+    m = re.search(r"__device__ __forceinline__ uint32_t xcd_block\(\).*?\n}\n", stream, re.S)
     internal = read("lbm_internal.h")
-    parts = [k.group(0) if k else stream, read("lbm_kernels.h"), read("lbm_stencil.h")]
+    parts = [k.group(0) if k else stream, m.group(0) if m else stream, read("lbm_kernels.h"),
+             read("lbm_stencil.h")]
     for name in ("Geom", "Phys"):
         m = re.search(r"struct " + name + r" \{.*?\n\};", internal, re.S)
         parts.append(m.group(0) if m else internal)
@@ -129,6 +131,28 @@ def bulk_roofline(res, lat, storage, workload=None, Q=19):
                 fluid_only=dict(bytes_per_launch=int(bytes_fluid), bytes_per_fluid_cell=per_fluid,
                                 bytes_per_cell_flag=1,
                                 achieved=round(bytes_fluid / (avg_ms * 1e-3) / 1e9, 1)))
+
+
+def copy_ceiling(nbytes, reps=5):
+    """Rate of a plain elementwise copy (out = in * 1) moving the same bytes
+    as one stream-collide launch's populations, read and written once, timed
+    with hipEvents: what HBM delivers to a streaming kernel on this device."""
+    import torch
+    n = int(nbytes // 4)
+    a = torch.zeros(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
 
 
 def cpu_baseline(seconds=15.0):
@@ -421,6 +445,10 @@ def main():
         "refills_last_step": main_res["n_refill"],
         "roofline": bulk_roofline(main_res, lat, args.storage, meta["name"], Q=args.lattice),
     }
+    # context for the fraction: the same bytes moved by a plain copy
+    ceil = copy_ceiling(args.lattice * lat.ncell * BYTES[args.storage])
+    line["roofline"]["copy_ceiling"] = dict(achieved=ceil, unit="GB/s",
+                                            frac_of_copy=round(line["roofline"]["achieved"] / ceil, 4))
     for v, r in variants.items():
         line.setdefault("storage_variants", {})[v] = dict(
             mlups=round(ncell / (r["ms_per_step"] * 1e-3) / 1e6, 1),
