@@ -179,6 +179,53 @@ def cpu_baseline(seconds=15.0):
                        f"(8 metaballs, 20% solids), {steps} steps in {dt:.1f} s")
 
 
+def drag_error_suspension(steps=100):
+    """Force/torque error of FP32 and FP16 storage on the 256^3 suspension (200
+    bodies) with every body on a prescribed rigid motion, against the FP64
+    storage path (which the parity tests hold to 1e-10 of the oracle): per
+    body, max over steps of |F_s - F_64| / max over steps of |F_64|; the
+    maximum and the median over the bodies."""
+    import torch
+    from paper_2206_11634_amd import binding as B
+    from paper_2206_11634_amd import workloads as W
+
+    lat, ps, meta = W.config_c3()
+    rng = np.random.default_rng(31)
+    ps = ps.copy()
+    ps.vel = rng.normal(size=(ps.n, 3)) * 0.01
+    ps.omega = rng.normal(size=(ps.n, 3)) * 0.001
+    traj = B.DeviceTrajectory([W.prescribed_state(ps, lat, float(n)) for n in range(steps + 1)])
+    series = {}
+    for storage in ("f64", "f32", "f16"):
+        gpu = B.Lattice.for_particles(lat, ps, storage=storage,
+                                      treatments=int(meta.get("treatments", 3)))
+        gpu.classify(traj[0])
+        F = torch.zeros((steps, ps.n, 6), dtype=torch.float64, device=gpu.device)
+        for k in range(steps):
+            gpu.step(traj[k])
+            f, t = gpu.forces()
+            F[k, :, :3] = f
+            F[k, :, 3:] = t
+            gpu.classify(traj[k + 1], sync=False)
+        gpu.sync()
+        series[storage] = F.cpu().numpy()
+        gpu.close()
+    ref = series["f64"]
+    out = {}
+    for storage in ("f32", "f16"):
+        d = series[storage] - ref
+        res = {}
+        for name, sl in (("force", slice(0, 3)), ("torque", slice(3, 6))):
+            num = np.linalg.norm(d[:, :, sl], axis=2).max(0)
+            den = np.linalg.norm(ref[:, :, sl], axis=2).max(0)
+            e = num / np.maximum(den, 1e-300)
+            res[name] = dict(max=float(e.max()), median=float(np.median(e)))
+        out[storage] = res
+    out["workload"] = (f"c3 256^3 periodic, 200 bodies on prescribed rigid motions, {steps} steps, "
+                       "against FP64 storage")
+    return out
+
+
 def drag_error(steps=200):
     """Force/torque error of FP32 and FP16 storage against the FP64 oracle on
     the 40x40x80 single-sphere box, the sphere moving down at 0.01 lu/step
@@ -468,6 +515,7 @@ def main():
                                              main_res["ms_per_step"], 3)
     if not args.no_drag:
         line["drag_err"] = drag_error()
+        line["drag_err_suspension"] = drag_error_suspension()
     if not args.no_drag:
         line["exact_q"] = exact_q_effect(lat, ps, meta)
     if not args.no_adjoint:
