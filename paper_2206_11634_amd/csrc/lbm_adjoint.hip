@@ -431,17 +431,20 @@ __global__ __launch_bounds__(256) void k_adj_refill(const typename St<S>::T* __r
             int cdd[3] = {c[0] + cx(i), c[1] + cy(i), c[2] + cz(i)};
             const bool iu = i > 0 && wrap3(cuu, g);
             const bool id = i > 0 && wrap3(cdd, g);
-            nu[i] = iu ? node_of(cuu, g) : kFluid;
+            // both candidate populations load beside the owners (both indices
+            // are nodes of the lattice), the owners then pick
+            const uint32_t su = iu ? node_of(cuu, g) : cell;
             const uint32_t nd = id ? node_of(cdd, g) : cell;
-            const bool up = iu && own0[nu[i]] == kFluid;
+            const A a_up = St<S>::ld(f + (int64_t)i * g.stride + su, ph.inv_scale);
+            const A a_dn = St<S>::ld(f + (int64_t)opp(i) * g.stride + nd, ph.inv_scale);
+            const bool up = iu && own0[su] == kFluid;
             const bool dn = id && own0[nd] == kFluid;
-            if (!up) nu[i] = kFluid;
+            nu[i] = up ? su : kFluid;
             const A eu = A(cx(i)) * un[0] + A(cy(i)) * un[1] + A(cz(i)) * un[2];
             if (up) {
-                pre[i] = St<S>::ld(f + (int64_t)i * g.stride + nu[i], ph.inv_scale);
+                pre[i] = a_up;
             } else if (dn) {
-                pre[i] = St<S>::ld(f + (int64_t)opp(i) * g.stride + nd, ph.inv_scale) +
-                         A(6) * W<A>(i) * r0 * eu;
+                pre[i] = a_dn + A(6) * W<A>(i) * r0 * eu;
                 rule |= 1ull << (2 * i);
             } else {
                 pre[i] = eq_i<DEV, A>(i, dr0, r0, un[0], un[1], un[2]);

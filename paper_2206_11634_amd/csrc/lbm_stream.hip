@@ -376,14 +376,17 @@ __device__ __forceinline__ void refill_node(const typename St<S>::T* __restrict_
         const bool id = i > 0 && wrap3(cd, g);
         const uint32_t nu = iu ? node_of(cu, g) : r.node;
         const uint32_t nd = id ? node_of(cd, g) : r.node;
+        // both candidate populations load beside the owners (both indices
+        // are nodes of the lattice), the owners then pick
+        const A a_up = St<S>::ld(prev + (int64_t)i * g.stride + nu, ph.inv_scale);
+        const A a_dn = St<S>::ld(prev + (int64_t)opp(i) * g.stride + nd, ph.inv_scale);
         const bool up = iu && own_prev[nu] == kFluid;
         const bool dn = id && own_prev[nd] == kFluid;
         if (up) {
-            v[i] = St<S>::ld(prev + (int64_t)i * g.stride + nu, ph.inv_scale);  // streamed
+            v[i] = a_up;  // streamed
         } else if (dn) {
             const A eu = A(cx(i)) * un[0] + A(cy(i)) * un[1] + A(cz(i)) * un[2];
-            v[i] = St<S>::ld(prev + (int64_t)opp(i) * g.stride + nd, ph.inv_scale) +
-                   A(6) * W<A>(i) * r0 * eu;  // bounce-back of the streamed opposite
+            v[i] = a_dn + A(6) * W<A>(i) * r0 * eu;  // bounce-back of the streamed opposite
         } else {
             v[i] = eq_i<DEV, A>(i, dr0, r0, un[0], un[1], un[2]);
         }
