@@ -143,6 +143,49 @@ def test_comoving_particles_leave_uniform_flow_exact():
     assert refilled > 20
 
 
+def test_comoving_pair_in_near_contact_with_moving_missing_points():
+    """Two spheres 0.4 lu apart translate together at U through a uniform
+    flow f = feq(rho0, U), rho0 = 1.03, with treatments 1 and 2 on.  Lattice
+    lines from one body run straight into the other, so each body has
+    missing force points (Eqs. fh_s_issue, th_s_issue) whose wall velocity
+    is U.  A missing point's term is the moving-wall equilibrium
+    feq(rho0, u_w) on both sides; at u_w = U it equals what a fluid link at
+    that place would give, so every lattice line through a body still
+    contributes equal and opposite terms at its two ends and F = 0 exactly
+    per body, through covering and refilling, while halfway and VIBB keep
+    the populations at feq(rho0, U)."""
+    U = np.array([0.03, -0.02, 0.015])
+    rho0 = 1.03
+    lat = W.LatticeSpec(26, 22, 20, (1, 1, 1), tau=0.7, rho0=rho0, u0=tuple(U))
+    sh_a = Shape(pts=np.zeros((1, 3)), K=np.array([9.0]), c0=1.0, rs=0.0,
+                 volume=4 / 3 * np.pi * 27, inertia_unit=np.ones(3), radius=3.0)
+    sh_b = Shape(pts=np.zeros((1, 3)), K=np.array([12.25]), c0=1.0, rs=0.0,
+                 volume=4 / 3 * np.pi * 3.5 ** 3, inertia_unit=np.ones(3), radius=3.5)
+    axis = np.array([1.0, 0.7, 0.4]) / np.linalg.norm([1.0, 0.7, 0.4])
+    ca = np.array([9.13, 8.41, 9.27])
+    ps = W.make_particles([sh_a, sh_b], [ca, ca + (3.0 + 3.5 + 0.4) * axis],
+                          [[1, 0, 0, 0]] * 2, 1.5, vel=np.array([U, U]))
+    o = O.Oracle(lat, treat=O.TREAT_VIBB | O.TREAT_MISSING)
+    P = W.prescribed_state(ps, lat, 0.0)
+    o.classify(P)
+    f0 = o.f[:, 0].copy()
+    assert abs(f0.sum() - rho0) < 1e-14
+    missing, refilled, halfway = [0, 0], 0, 0
+    for n in range(40):
+        kinds = np.bincount(o.links.kind, minlength=3)
+        halfway += kinds[O.KIND_HALFWAY]
+        for p in range(2):
+            missing[p] += int(((o.links.kind == O.KIND_MISSING) & (o.links.part == p)).sum())
+        F, T = o.step(P)
+        assert np.abs(F).max() < 1e-12, (n, F)
+        P = W.prescribed_state(ps, lat, n + 1.0)
+        o.classify(P)
+        refilled += len(o.refill_nodes)
+        fl = o.owner == 0
+        assert np.abs(o.f[:, fl] - f0[:, None]).max() < 1e-14
+    assert min(missing) > 40 and refilled > 20 and halfway > 0, (missing, refilled, halfway)
+
+
 def test_missing_force_points_restore_isotropy_near_wall_and_particle():
     """Particles at rest in fluid at rest, one 0.3 lu from a wall and the other
     0.4 lu above it: with treatment 2 every lattice line through a body enters
