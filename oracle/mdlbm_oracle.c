@@ -1217,6 +1217,15 @@ void ora_dem_step(int np, const int* off, const double* bpts, const double* K, c
     }
 }
 
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

@@ -78,6 +78,8 @@ def lib():
         L.ora_dem_step.restype = None
         L.ora_dem_step.argtypes = [ctypes.c_int] + [P] * 19 + [P, P, ctypes.c_int, ctypes.c_double]
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_set_num_threads.restype = None
+        L.ora_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -113,6 +115,12 @@ def vibb(d, q, fd_f, rho_f, u_f, fd_ff, rho_ff, u_ff, uw, Q=19, treat=0) -> floa
 
 def num_threads() -> int:
     return lib().ora_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (their results do not depend
+    on it: force sums are serial in link order)."""
+    lib().ora_set_num_threads(int(n))
 
 
 class Links:

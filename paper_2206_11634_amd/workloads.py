@@ -22,6 +22,7 @@ Conventions (lattice units, dx = dt = 1):
 from __future__ import annotations
 
 import dataclasses
+import hashlib
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -31,7 +32,7 @@ __all__ = [
     "sphere_shape", "metaball_shape", "make_particles", "prescribed_state",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5",
     "square_metaball", "config_dkt", "config_floor_pair",
-    "tiny_case", "WORKLOADS",
+    "tiny_case", "WORKLOADS", "drag_case", "DRAG_CASES", "fingerprint",
 ]
 
 
@@ -729,3 +730,104 @@ def dem_defaults(ps: ParticleSet, gravity=(0.0, 0.0, 0.0), contact_time=20.0, re
     eta = 2.0 * zeta * np.sqrt(meff * kn)
     return dict(kn=kn, eta_n=eta, kt=0.5 * kn, eta_t=0.0, mu_s=0.3, ctol=1e-3,
                 newton_tol=1e-10, newton_iter=12, gravity=tuple(gravity), rho_f=1.0)
+
+
+# ----------------------------------------------------------------------------
+# prescribed trajectories of the drag comparisons against the oracle
+# ----------------------------------------------------------------------------
+
+DRAG_CASES = ("c1", "c2", "c3", "c4")
+
+
+def drag_case(name: str):
+    """A replay run on which the force and torque of the GPU path are compared
+    with the FP64 oracle: every body moves rigidly with its (v, omega)
+    (prescribed_state), so both sides classify the same poses every step.
+    Returns (lat, ps0, steps, treatments, description).
+
+      c1  the 40x40x80 sphere moving down at 0.01 lu/step, spinning slowly;
+      c2  the 24 lu metaball in the 128x128x256 box descending at about the
+          Stokes settling speed while tumbling (2.4 rad over the run);
+      c3  the 200 bodies of the 256^3 suspension with seeded velocities;
+      c4  the 1000 bodies of the 512^3 sedimentation with seeded velocities,
+          with the workload's treatment bits; only short windows of it fit
+          the oracle (sub-boxes around sampled bodies)."""
+    if name == "c1":
+        lat, ps, meta = config_c1()
+        ps.vel[:] = [0.0, 0.0, -0.01]
+        ps.omega[:] = [0.0, 0.002, 0.0]
+        return lat, ps, 200, 3, "c1 40x40x80 sphere d=10, prescribed descent 0.01 lu/step, 200 steps"
+    if name == "c2":
+        lat, ps, meta = config_c2()
+        ps.vel[:] = [0.002, -0.001, -0.015]
+        ps.omega[:] = [0.0005, 0.001, -0.0007]
+        return (lat, ps, 2000, 3, "c2 128x128x256 metaball 24 lu long, prescribed descent "
+                "0.015 lu/step with tumbling, 2000 steps")
+    if name == "c3":
+        lat, ps, meta = config_c3()
+        rng = np.random.default_rng(31)
+        ps = ps.copy()
+        ps.vel = rng.normal(size=(ps.n, 3)) * 0.01
+        ps.omega = rng.normal(size=(ps.n, 3)) * 0.001
+        return (lat, ps, 100, int(meta.get("treatments", 3)),
+                "c3 256^3 periodic suspension, 200 bodies on prescribed rigid motions, 100 steps")
+    if name == "c4":
+        lat, ps, meta = config_c4()
+        rng = np.random.default_rng(14)
+        ps = ps.copy()
+        ps.vel = rng.normal(size=(ps.n, 3)) * 0.02
+        ps.omega = rng.normal(size=(ps.n, 3)) * 0.001
+        return (lat, ps, 3, int(meta["treatments"]),
+                "c4 512^3 sedimentation, 1000 bodies on prescribed rigid motions, treatment "
+                "bits 1+2+8; sampled bodies over 3 steps")
+    raise KeyError(name)
+
+
+def fingerprint(lat: LatticeSpec, ps: ParticleSet, steps: int, treatments: int) -> str:
+    """Short hash of a replay run's inputs, stored with reference results so
+    that a change of the inputs is noticed."""
+    h = hashlib.sha256()
+    h.update(repr((lat.dims, tuple(lat.periodic), float(lat.tau), float(lat.rho0),
+                   tuple(map(float, lat.u0)), tuple(map(float, lat.body_force)),
+                   int(steps), int(treatments))).encode())
+    for k in ("ctrl_off", "body_pts", "K", "c0", "pos", "quat", "vel", "omega"):
+        h.update(np.ascontiguousarray(getattr(ps, k)).tobytes())
+    return h.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------
+# sub-boxes of a large lattice (bounded samples and windowed comparisons)
+# ----------------------------------------------------------------------------
+
+def subset(P: ParticleSet, sel, shift) -> ParticleSet:
+    """Bodies sel of P (ascending global index), translated by the integer
+    vector shift (exact in FP64 for coordinates inside a sub-box)."""
+    segs = [np.arange(P.ctrl_off[q], P.ctrl_off[q + 1]) for q in sel]
+    ctrl = np.concatenate(segs) if segs else np.zeros(0, int)
+    off = np.zeros(len(sel) + 1, np.int32)
+    off[1:] = np.cumsum([len(s) for s in segs])
+    return ParticleSet(
+        ctrl_off=off, body_pts=P.body_pts[ctrl].copy(), K=P.K[ctrl].copy(), c0=P.c0[sel].copy(),
+        rs=P.rs[sel].copy(), volume=P.volume[sel].copy(), mass=P.mass[sel].copy(),
+        inertia=P.inertia[sel].copy(), pos=P.pos[sel] + shift, quat=P.quat[sel].copy(),
+        vel=P.vel[sel].copy(), omega=P.omega[sel].copy(), radius=P.radius[sel].copy(),
+        world_pts=P.world_pts[ctrl] + shift)
+
+
+def bodies_reaching(ps: ParticleSet, lo, hi, pad: float = 2.0):
+    """Indices of the bodies whose bounding ball (plus pad) meets [lo, hi)."""
+    return [q for q in range(ps.n)
+            if all(ps.pos[q, a] + ps.radius[q] + pad >= lo[a] and
+                   ps.pos[q, a] - ps.radius[q] - pad <= hi[a] for a in range(3))]
+
+
+def subbox(lat: LatticeSpec, ps: ParticleSet, lo, hi):
+    """The sub-lattice [lo, hi) of lat as a closed box (its faces act as
+    walls) with the bodies that reach into it, translated by -lo.  Returns
+    (sub-lattice, bodies, their global indices)."""
+    lo, hi = np.asarray(lo, int), np.asarray(hi, int)
+    wdims = hi - lo
+    wlat = LatticeSpec(*map(int, wdims), periodic=(0, 0, 0), tau=lat.tau, rho0=lat.rho0,
+                       u0=lat.u0, body_force=lat.body_force)
+    near = bodies_reaching(ps, lo, hi)
+    return wlat, subset(ps, near, -lo.astype(float)), near

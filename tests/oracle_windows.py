@@ -14,20 +14,7 @@ from oracle import oracle as O
 from paper_2206_11634_amd import workloads as W
 
 
-def subset(P, sel, shift):
-    """Bodies sel of P (ascending global index), translated by the integer
-    vector shift (exact in FP64 for coordinates inside the sub-box)."""
-    segs = [np.arange(P.ctrl_off[q], P.ctrl_off[q + 1]) for q in sel]
-    ctrl = np.concatenate(segs) if segs else np.zeros(0, int)
-    off = np.zeros(len(sel) + 1, np.int32)
-    off[1:] = np.cumsum([len(s) for s in segs])
-    out = W.ParticleSet(
-        ctrl_off=off, body_pts=P.body_pts[ctrl].copy(), K=P.K[ctrl].copy(), c0=P.c0[sel].copy(),
-        rs=P.rs[sel].copy(), volume=P.volume[sel].copy(), mass=P.mass[sel].copy(),
-        inertia=P.inertia[sel].copy(), pos=P.pos[sel] + shift, quat=P.quat[sel].copy(),
-        vel=P.vel[sel].copy(), omega=P.omega[sel].copy(), radius=P.radius[sel].copy(),
-        world_pts=P.world_pts[ctrl] + shift)
-    return out
+subset = W.subset
 
 
 def sample_bodies(lat, ps, half_extra):
@@ -62,19 +49,16 @@ def window(lat, ps, p, half_extra):
 
 
 
-def run_window(lat, ps, traj, p, steps, half_extra):
+def run_window(lat, ps, traj, p, steps, half_extra, treat=O.TREAT_VIBB | O.TREAT_MISSING):
     """Oracle over a sub-box around body p for `steps` steps of the trajectory
-    traj (list of global particle states).  Returns the force and torque of p
-    per step, the oracle, lo, the sub-box dims and its wall faces."""
+    traj (list of global particle states) with treatment bits treat.  Returns
+    the force and torque of p per step, the oracle, lo, the sub-box dims and
+    its wall faces."""
     lo, hi, real = window(lat, ps, p, half_extra)
     wdims = hi - lo
-    wlat = W.LatticeSpec(*map(int, wdims), periodic=(0, 0, 0), tau=lat.tau, rho0=lat.rho0,
-                         u0=lat.u0, body_force=lat.body_force)
-    near = [q for q in range(ps.n)
-            if all(ps.pos[q, a] + ps.radius[q] + 2 >= lo[a] and
-                   ps.pos[q, a] - ps.radius[q] - 2 <= hi[a] for a in range(3))]
+    wlat, _, near = W.subbox(lat, ps, lo, hi)
     local = near.index(p)
-    ora = O.Oracle(wlat)
+    ora = O.Oracle(wlat, treat=treat)
     Fo, To = [], []
     for t in range(steps):
         P = subset(traj[t], near, -lo.astype(float))

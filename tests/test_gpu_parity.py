@@ -94,12 +94,17 @@ def test_geometry_and_plain_fp64_step_parity(case, classify):
     assert r["F"] < FORCE_TOL["f64"] and r["T"] < FORCE_TOL["f64"], r
 
 
+TREAT_PLAIN = B.TREAT_VIBB | B.TREAT_MISSING
+TREAT_TIMED = B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_NEQ_SPLIT   # the 512^3 workload's bits
+
+
+@pytest.mark.parametrize("treat", [TREAT_PLAIN, TREAT_TIMED], ids=["bits3", "bits11"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_deviation_storage_parity(storage):
+def test_deviation_storage_parity(storage, treat):
     lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
                           diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
                           u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
-    r = _run(lat, ps, storage, 8, tag=storage)
+    r = _run(lat, ps, storage, 8, treat=treat, tag=f"{storage} treat{treat}")
     assert r["pop_err"] < POP_TOL[storage], r
     assert r["F"] < FORCE_TOL[storage] and r["T"] < FORCE_TOL[storage], r
 
@@ -197,6 +202,49 @@ def test_dem_parity_with_contacts():
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
 
 
+def test_dem_parity_sliding_and_glancing_contacts():
+    """Contacts whose tangential force reaches the Coulomb limit, under
+    gravity tilted 20 degrees against the floor: a sphere launched sliding
+    with spin on the floor (it slides, then rolls), a flat metaball resting
+    on the floor, and a sphere striking it at a glancing angle with a
+    tangential velocity; the second pair runs without tangential damping,
+    so the spring's reset length after the Coulomb limit sets the force.
+    600 DEM calls of 10 substeps, FP64 on both sides."""
+    lat = W.LatticeSpec(96, 64, 48, (1, 1, 0))
+    g, th = 1e-4, np.radians(20.0)
+    sh_s, sh_m = W.sphere_shape(10.0, 0.1), W.square_metaball(12.0, 0.2)
+    ps = W.make_particles([sh_s, sh_m, sh_s],
+                          [[20.0, 20.0, -0.5 + 5.0 - 0.01], [60.0, 30.0, 6.0],
+                           [52.0, 30.3, 15.5]],
+                          [[1.0, 0, 0, 0], [np.cos(0.05), np.sin(0.05), 0, 0], [1.0, 0, 0, 0]],
+                          np.array([2.0, 1.5, 2.0]),
+                          vel=np.array([[0.01, 0.004, 0.0], [0.0, 0.0, 0.0], [0.012, 0.003, -0.006]]),
+                          omega=np.array([[0.0, 0.0, 0.002], [0.0, 0.0, 0.0], [0.004, 0.0, -0.003]]))
+    m = ps.mass.min()
+    kn = (ps.mass[0] - ps.volume[0]) * g / 0.01
+    kw = dict(kn=kn, eta_n=1.4 * np.sqrt(m * kn), kt=kn / 2, eta_t=0.0, mu_s=0.3,
+              gravity=(g * np.sin(th), 0.0, -g * np.cos(th)), rho_f=1.0)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    parts = B.DeviceParticles(ps)
+    dem = O.OracleDEM(ps, lat)
+    P = ps.copy()
+    Fh = np.zeros((3, 3))
+    slid = rolled = False
+    for n in range(600):
+        gpu.dem(parts, 10, 0.1, B.DemParams.make(**kw))
+        dem.step(P, Fh, Fh, O.DemParams(**kw), 10, 0.1)
+        slip = P.vel[0, 0] - P.omega[0, 1] * 5.0
+        slid |= slip > 0.2 * P.vel[0, 0]
+        rolled |= slid and abs(slip) < 0.02 * abs(P.vel[0, 0])
+    G = parts.to_host(ps)
+    gpu.close()
+    assert slid and rolled
+    assert np.abs(P.vel[2] - ps.vel[2]).max() > 1e-3   # the glancing pair touched
+    for k in ("pos", "vel", "omega", "quat", "world_pts"):
+        a, b = getattr(G, k), getattr(P, k)
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
+
+
 @pytest.mark.parametrize("ang", [0.0, 0.6])
 def test_dem_parity_tilted_flat_pair(ang):
     """Flat square metaballs meeting face to face and at an angle (the
@@ -244,12 +292,13 @@ def test_d3q15_geometry_and_plain_fp64_step_parity(case, classify):
     assert r["F"] < FORCE_TOL["f64"] and r["T"] < FORCE_TOL["f64"], r
 
 
+@pytest.mark.parametrize("treat", [TREAT_PLAIN, TREAT_TIMED], ids=["bits3", "bits11"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_d3q15_deviation_storage_parity(storage):
+def test_d3q15_deviation_storage_parity(storage, treat):
     lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
                           diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
                           u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
-    r = _run(lat, ps, storage, 8, tag=f"q15 {storage}", lattice=15)
+    r = _run(lat, ps, storage, 8, treat=treat, tag=f"q15 {storage} treat{treat}", lattice=15)
     assert r["pop_err"] < POP_TOL[storage], r
     assert r["F"] < FORCE_TOL[storage] and r["T"] < FORCE_TOL[storage], r
 
