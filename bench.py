@@ -155,114 +155,124 @@ def copy_ceiling(nbytes, reps=5):
     return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
 
 
-def cpu_baseline(seconds=15.0):
-    """The FP64 oracle on a bounded sample of the same workload: the
-    sedimentation layout at 128^3 with 8 metaballs at 20% solids."""
+def cpu_baseline(seconds=12.0):
+    """The FP64 oracle on a bounded sample of the timed workload: the sub-box
+    [0, 128)^3 of the 512^3 sedimentation lattice (its z = 0 wall and the
+    bodies reaching into it; the other faces act as walls), classify + step
+    repeated for about `seconds`, on all of the host's threads and on one."""
     from oracle import oracle as O
     from paper_2206_11634_amd import workloads as W
 
-    lat, ps, meta = W.config_c4(seed=44, n=128, per_axis=2)
-    o = O.Oracle(lat, treat=int(meta.get("treatments", 3)))
-    o.classify(ps)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.step(ps)
-        o.classify(ps)
-        steps += 1
-        if time.perf_counter() - t0 > seconds and steps >= 2:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=round(lat.ncell * steps / dt / 1e6, 3), unit="MLUPS",
-                cores=O.num_threads(), kind="oracle",
-                sample=f"FP64 oracle classify+step on the 128^3 sedimentation layout "
-                       f"(8 metaballs, 20% solids), {steps} steps in {dt:.1f} s")
+    lat, ps, meta = W.config_c4()
+    wlat, sub, near = W.subbox(lat, ps, (0, 0, 0), (128, 128, 128))
+    threads = O.num_threads()
+
+    def rate(nthreads):
+        O.set_num_threads(nthreads)
+        o = O.Oracle(wlat, treat=int(meta.get("treatments", 3)))
+        o.classify(sub)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            o.step(sub)
+            o.classify(sub)
+            steps += 1
+            if time.perf_counter() - t0 > seconds and steps >= 2:
+                break
+        dt = time.perf_counter() - t0
+        return wlat.ncell * steps / dt / 1e6, steps, dt
+
+    v_all, n_all, t_all = rate(threads)
+    v_one, n_one, t_one = rate(1)
+    O.set_num_threads(threads)
+    return dict(value=round(v_all, 3), unit="MLUPS", cores=threads, kind="oracle",
+                value_1thread=round(v_one, 3),
+                sample=f"FP64 oracle classify+step on the sub-box [0,128)^3 of the 512^3 "
+                       f"sedimentation lattice ({len(near)} bodies reaching into it, "
+                       f"treatment bits {int(meta.get('treatments', 3))}): {n_all} steps in "
+                       f"{t_all:.1f} s on {threads} threads, {n_one} steps in {t_one:.1f} s "
+                       f"on 1 thread")
 
 
-def drag_error_suspension(steps=100):
-    """Force/torque error of FP32 and FP16 storage on the 256^3 suspension (200
-    bodies) with every body on a prescribed rigid motion, against the FP64
-    storage path (which the parity tests hold to 1e-10 of the oracle): per
-    body, max over steps of |F_s - F_64| / max over steps of |F_64|; the
-    maximum and the median over the bodies."""
+def _reference_series(name, lat, ps, steps, treat):
+    """The oracle's stored force and torque series of a drag case
+    (tests/golden/make_drag_reference.py), or None with the reason when it is
+    missing or was made from other inputs."""
+    from paper_2206_11634_amd import workloads as W
+    path = os.path.join(ROOT, "tests", "golden", f"drag_{name}.npz")
+    if not os.path.exists(path):
+        return None, f"no oracle reference ({path})"
+    d = np.load(path, allow_pickle=False)
+    if str(d["fingerprint"]) != W.fingerprint(lat, ps, steps, treat):
+        return None, "oracle reference made from other inputs"
+    return d, None
+
+
+def _replay(lat, ps, steps, treat, storage, bodies=None):
+    """Force and torque of the GPU path on a prescribed replay, [steps, n, 6]."""
     import torch
     from paper_2206_11634_amd import binding as B
     from paper_2206_11634_amd import workloads as W
 
-    lat, ps, meta = W.config_c3()
-    rng = np.random.default_rng(31)
-    ps = ps.copy()
-    ps.vel = rng.normal(size=(ps.n, 3)) * 0.01
-    ps.omega = rng.normal(size=(ps.n, 3)) * 0.001
     traj = B.DeviceTrajectory([W.prescribed_state(ps, lat, float(n)) for n in range(steps + 1)])
-    series = {}
-    for storage in ("f64", "f32", "f16"):
-        gpu = B.Lattice.for_particles(lat, ps, storage=storage,
-                                      treatments=int(meta.get("treatments", 3)))
-        gpu.classify(traj[0])
-        F = torch.zeros((steps, ps.n, 6), dtype=torch.float64, device=gpu.device)
-        for k in range(steps):
-            gpu.step(traj[k])
-            f, t = gpu.forces()
-            F[k, :, :3] = f
-            F[k, :, 3:] = t
-            gpu.classify(traj[k + 1], sync=False)
-        gpu.sync()
-        series[storage] = F.cpu().numpy()
-        gpu.close()
-    ref = series["f64"]
-    out = {}
-    for storage in ("f32", "f16"):
-        d = series[storage] - ref
-        res = {}
-        for name, sl in (("force", slice(0, 3)), ("torque", slice(3, 6))):
-            num = np.linalg.norm(d[:, :, sl], axis=2).max(0)
-            den = np.linalg.norm(ref[:, :, sl], axis=2).max(0)
-            e = num / np.maximum(den, 1e-300)
-            res[name] = dict(max=float(e.max()), median=float(np.median(e)))
-        out[storage] = res
-    out["workload"] = (f"c3 256^3 periodic, 200 bodies on prescribed rigid motions, {steps} steps, "
-                       "against FP64 storage")
-    return out
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat)
+    F = torch.zeros((steps, ps.n, 6), dtype=torch.float64, device=gpu.device)
+    for k in range(steps):
+        gpu.classify(traj[k])
+        gpu.step(traj[k])
+        f, t = gpu.forces()
+        F[k, :, :3] = f
+        F[k, :, 3:] = t
+    out = F.cpu().numpy()
+    gpu.close()
+    del gpu, traj
+    torch.cuda.empty_cache()
+    return out if bodies is None else out[:, bodies]
 
 
-def drag_error(steps=200):
-    """Force/torque error of FP32 and FP16 storage against the FP64 oracle on
-    the 40x40x80 single-sphere box, the sphere moving down at 0.01 lu/step
-    (prescribed) and spinning slowly."""
-    from oracle import oracle as O
-    from paper_2206_11634_amd import binding as B
+def _errors(g, F, T):
+    """Per body: max over steps of |X_gpu - X_oracle| over the largest
+    |X_oracle| of the run (vector norms), for force and torque; the largest and
+    the median over the bodies."""
+    res = {}
+    for name, sl, ref in (("force", slice(0, 3), F), ("torque", slice(3, 6), T)):
+        num = np.linalg.norm(g[:, :, sl] - ref, axis=2).max(0)
+        den = np.linalg.norm(ref, axis=2).max(0)
+        e = num / np.maximum(den, 1e-300)
+        res[name] = dict(max=float(e.max()), median=float(np.median(e)))
+    return res
+
+
+DRAG_BAR = {"f64": 1e-10, "f32": 1e-4, "f16": 2e-2}
+
+
+def drag_errors(storages=("f64", "f32", "f16")):
+    """Force and torque of each storage against the FP64 oracle on the replay
+    runs of every workload (workloads.drag_case): c1 (200 steps), c2 (2000
+    steps), c3 (200 bodies, 100 steps) on the whole lattice, c4 on sampled
+    bodies over 3 steps (the oracle's sub-box runs)."""
     from paper_2206_11634_amd import workloads as W
 
-    lat, ps, meta = W.config_c1()
-    ps.vel[:] = [0.0, 0.0, -0.01]
-    ps.omega[:] = [0.0, 0.002, 0.0]
-    ora = O.Oracle(lat)
     out = {}
-    traj = [W.prescribed_state(ps, lat, float(n)) for n in range(steps)]
-    Fo, To = [], []
-    for n in range(steps):
-        ora.classify(traj[n])
-        F, T = ora.step(traj[n])
-        Fo.append(F[0].copy())
-        To.append(T[0].copy())
-    Fo, To = np.array(Fo), np.array(To)
-    for storage in ("f32", "f16"):
-        gpu = B.Lattice.for_particles(lat, ps, storage=storage)
-        parts = B.DeviceParticles(ps)
-        Fg, Tg = [], []
-        for n in range(steps):
-            parts.set_state(traj[n])
-            gpu.classify(parts)
-            gpu.step(parts)
-            F, T = gpu.forces()
-            Fg.append(F[0].cpu().numpy().copy())
-            Tg.append(T[0].cpu().numpy().copy())
-        gpu.close()
-        eF = float(np.abs(np.array(Fg) - Fo).max() / np.abs(Fo).max())
-        eT = float(np.abs(np.array(Tg) - To).max() / np.abs(To).max())
-        out[storage] = dict(force=eF, torque=eT)
-    out["workload"] = f"c1 40x40x80 sphere d=10, prescribed descent, {steps} steps"
+    for name in W.DRAG_CASES:
+        lat, ps, steps, treat, desc = W.drag_case(name)
+        ref, why = _reference_series(name, lat, ps, steps, treat)
+        if ref is None:
+            out[name] = dict(workload=desc, skipped=why)
+            continue
+        bodies = ref["bodies"] if "bodies" in ref.files else None
+        res = dict(workload=desc, treatments=treat)
+        for storage in storages:
+            g = _replay(lat, ps, steps, treat, storage, bodies)
+            e = _errors(g, ref["F"], ref["T"])
+            e["within_bar"] = bool(max(e["force"]["max"], e["torque"]["max"]) <= DRAG_BAR[storage])
+            res[storage] = e
+        out[name] = res
+        print(f"[bench] drag {name}: " + ", ".join(
+            f"{st} {res[st]['force']['max']:.2e}" for st in storages), file=sys.stderr, flush=True)
+    out["bars"] = DRAG_BAR
+    out["measure"] = ("per body, max over steps |F_gpu - F_oracle| / max over steps |F_oracle| "
+                      "(vector norms); max and median over the bodies")
     return out
 
 
@@ -514,10 +524,13 @@ def main():
         line["speedup_vs_plain_f64"] = round(variants["f64"]["ms_per_step"] /
                                              main_res["ms_per_step"], 3)
     if not args.no_drag:
-        line["drag_err"] = drag_error()
-        line["drag_err_suspension"] = drag_error_suspension()
-    if not args.no_drag:
+        line["drag_err"] = drag_errors()
         line["exact_q"] = exact_q_effect(lat, ps, meta)
+        c4 = line["drag_err"].get("c4", {})
+        if "f64" in variants and "f32" in c4 and "f64" in c4:
+            line["speedup_vs_plain_f64_equal_accuracy"] = dict(
+                speedup=line["speedup_vs_plain_f64"],
+                f32_within_bar=c4["f32"]["within_bar"], f64_within_bar=c4["f64"]["within_bar"])
     if not args.no_adjoint:
         line["adjoint"] = adjoint_bench(fd_check=not args.no_fd)
     if not args.no_cpu_baseline:

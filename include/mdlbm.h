@@ -250,8 +250,13 @@ int lbm_particle_forces(const lbm_ctx* ctx, double* F_dev, double* T_dev);
  * relative gravity, metaball-metaball and metaball-wall contacts with a
  * linear spring-dashpot normal force and a Coulomb-limited tangential spring.
  * Updates P->pos, quat, vel, omega and world_pts in place and the contact
- * histories held by the context.  EINVAL on n_sub < 1 or dt <= 0.
- * Asynchronous. */
+ * histories held by the context (allocated by lbm_init: 32 pair records per
+ * particle, for its candidate partners of higher index, and one per wall).
+ * EINVAL on n_sub < 1 or dt <= 0.  A particle with more than 32 candidate
+ * partners in one call (centres within the bodies' reach plus the call's
+ * displacement) has the extra pairs left out; that is latched and reported
+ * as ECAPACITY, with the context failed, by the next lbm_synchronize or
+ * lbm_classify_nodes.  Allocates nothing.  Asynchronous. */
 int dem_step(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_params* prm);
 
 /* ---- inspection (tests and tools) --------------------------------------- */
@@ -285,35 +290,45 @@ int lbm_get_moments(const lbm_ctx* ctx, double* rho_dev, double* u_dev);
  * storage format).  Asynchronous. */
 int lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
 
-/* Block until the context's stream has drained; EDEVICE on a device error,
- * and the error latched by an lbm_classify_nodes_async since the last check
- * (with a non-finite force of a step since, ENUMERIC), if any. */
+/* Block until the context's stream has drained; EDEVICE on a device error;
+ * otherwise the error latched on the device since the last check, if any,
+ * which leaves the context failed: ENUMERIC for a step with a non-finite
+ * force or torque, EINVAL or ECAPACITY for an lbm_classify_nodes_async
+ * that rejected the particles or outgrew its lists, ECAPACITY for a
+ * dem_step in which a particle had more candidate partners than its
+ * contact-history records. */
 int lbm_synchronize(lbm_ctx* ctx);
 
 /* ---- differentiation form (not in the paper) -----------------------------
  *
  * The adjoint differentiates J = sum over taped steps n and particles p of
- * wF_p . F^h_p(n) + wT_p . T^h_p(n) with respect to the fluid body force F,
- * the relaxation time tau and the particle velocities v_p, holding the
- * geometry schedule (owners, links, q, refill sets) of the taped run fixed;
- * the velocities enter through the wall velocities of VIBB, halfway
- * bounce-back, refilling and the momentum exchange.  Angular velocities and
- * positions are not differentiated. */
+ * wF_p . F^h_p(n) + wT_p . T^h_p(n), holding the discrete geometry (owners,
+ * link sets, refill sets and rule choices) of the taped run fixed.
+ * lbm_adjoint (prescribed motion) gives the gradient with respect to the
+ * fluid body force F, the relaxation time tau and the particle velocities
+ * v_p, which enter through the wall velocities of VIBB, halfway bounce-back,
+ * refilling and the momentum exchange, and optionally with respect to every
+ * pose of the trajectory (translation and rotation, through q and the lever
+ * arms).  lbm_adjoint_coupled (free motion) gives it with respect to the
+ * initial position, orientation, velocity and angular velocity of every
+ * particle, through the DEM substeps, and to F and tau. */
 
 /* Copy the current populations and moments, raw, into dst_dev
- * (checkpoint_bytes). */
+ * (checkpoint_bytes).  Asynchronous. */
 int lbm_checkpoint_save(const lbm_ctx* ctx, void* dst_dev);
 
 /* Restore populations and moments from a raw checkpoint, and forget the
  * classification history: the next lbm_classify_nodes refills nothing, so
- * classifying the checkpoint's particle state reproduces its geometry. */
+ * classifying the checkpoint's particle state reproduces its geometry.
+ * Asynchronous. */
 int lbm_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
 
 /* Copy the DEM state the library keeps between dem_step calls (the contact
- * histories of every particle pair and particle-wall pair: tangential
- * springs and warm starts of the contact-point search, and the contact
- * forces of the last substep) into dst_dev (dem_checkpoint_bytes); zeros
- * before the first dem_step.  Together with lbm_checkpoint_save and the
+ * histories of the candidate particle pairs, with the partner each record
+ * belongs to, and of every particle-wall pair: tangential springs and warm
+ * starts of the contact-point search; and the contact forces of the last
+ * substep) into dst_dev (dem_checkpoint_bytes); all zero before the first
+ * dem_step, and an all-zero state loads as no contact histories.  Together with lbm_checkpoint_save and the
  * caller's particle arrays this resumes a run exactly. */
 int lbm_dem_checkpoint_save(const lbm_ctx* ctx, void* dst_dev);
 
@@ -363,7 +378,10 @@ int lbm_adjoint(lbm_ctx* ctx, const lbm_particles* P, const double* weights, voi
  * adjoint of s_k and dJ/dF^h_k, dJ/dT^h_k, (3) runs the step's node and link
  * adjoint with objective weights (wF, wT) + (dJ/dF^h_k, dJ/dT^h_k), adding
  * the link terms of s_k (pose through q and the lever arms, v and omega
- * through u_w).  Contact forces are not differentiated (free motion).
+ * through u_w).  Contact forces are not differentiated (free motion): ESTATE,
+ * with the tape consumed and nothing accumulated, when any dem_step since
+ * lbm_tape_begin evaluated a contact (particle-particle or particle-wall
+ * overlap), or a contact force of the dem_step before it carried over.
  *   P         the state after the last taped step's dem_step (the one the
  *             last classification used);
  *   weights   host [n][6]: (wF, wT) per particle, the same for every step;

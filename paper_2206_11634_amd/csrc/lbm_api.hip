@@ -211,19 +211,33 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
     return LBM_OK;
 }
 
-// Contact histories and the pair list, allocated on first use.
+// Contact histories (kPairSlots keyed records per particle for its pairs,
+// six per particle for the walls) and the pair list of a dem_step call;
+// allocated by lbm_init, so that dem_step never allocates.
 int dem_alloc(lbm_ctx* c)
 {
-    const int np = c->cfg.n_particles;
-    if (c->hist_pp) return LBM_OK;
-    if (alloc(&c->hist_pp, (size_t)np * np * 8) != hipSuccess ||
-        alloc(&c->hist_pw, (size_t)np * 6 * 8) != hipSuccess ||
-        alloc(&c->pairs, std::max<size_t>((size_t)np * (np - 1) / 2, 1)) != hipSuccess ||
+    const size_t np = (size_t)c->cfg.n_particles;
+    if (c->hist_pp || np == 0) return LBM_OK;
+    const size_t slots = np * kPairSlots;
+    if (alloc(&c->hist_pp, slots * 8) != hipSuccess || alloc(&c->hist_key, slots) != hipSuccess ||
+        alloc(&c->hist_pw, np * 6 * 8) != hipSuccess || alloc(&c->pairs, slots) != hipSuccess ||
         alloc(&c->pair_count, 1) != hipSuccess)
         return fail(c, LBM_ENOMEM, "contact history allocation failed");
-    HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * np * np * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * slots * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->hist_key, 0, sizeof(int32_t) * slots, c->stream));
     HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));
     return LBM_OK;
+}
+
+// Bytes of the DEM state saved by lbm_dem_checkpoint_save, in its order: the
+// pair histories, their partner keys, the wall histories, the contact sums.
+struct DemStateBytes {
+    size_t pp, key, pw, fc;
+};
+DemStateBytes dem_state_bytes(size_t np)
+{
+    return {sizeof(double) * np * kPairSlots * 8, sizeof(int32_t) * np * kPairSlots,
+            sizeof(double) * np * 6 * 8, sizeof(double) * np * 6};
 }
 
 // Number of lattice velocities of the configured lattice (0 selects D3Q19).
@@ -257,7 +271,8 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
     out->adjoint_bytes = (size_t)lattice_q(cfg) * (size_t)out->cell_stride * (es == 8 ? 8 : 4);
     {
         const size_t np = (size_t)std::max(cfg->n_particles, 0);
-        out->dem_checkpoint_bytes = sizeof(double) * (np * np * 8 + np * 6 * 8 + np * 6);
+        const DemStateBytes b = dem_state_bytes((size_t)np);
+        out->dem_checkpoint_bytes = b.pp + b.key + b.pw + b.fc;
     }
     return LBM_OK;
 }
@@ -371,6 +386,11 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         lbm_destroy(c);
         return fail(nullptr, LBM_ENOMEM, msg);
     }
+    if (dem_alloc(c) != LBM_OK) {
+        std::string msg = c->last_error;
+        lbm_destroy(c);
+        return fail(nullptr, LBM_ENOMEM, msg);
+    }
     e = LQ(c, launch_init_equilibrium)(c, c->f[0]);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[0], 0xFF, sz.owner_bytes, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[1], 0xFF, sz.owner_bytes, c->stream);
@@ -413,6 +433,7 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->adj_list);
     (void)hipFree(c->adj_count);
     (void)hipFree(c->hist_pp);
+    (void)hipFree(c->hist_key);
     (void)hipFree(c->pairs);
     (void)hipFree(c->pair_count);
     (void)hipFree(c->hist_pw);
@@ -506,6 +527,11 @@ int deferred_status(lbm_ctx* c, const char* where)
                     "produced a non-finite hydrodynamic force or torque");
     if (def) {
         c->failed = true;
+        if (def & kDeferredSlots)
+            return fail(c, LBM_ECAPACITY,
+                        std::string(where) + ": a particle had more than " +
+                            std::to_string(kPairSlots) + " candidate contact partners in a "
+                            "dem_step call; contacts beyond them were left out");
         if (def & kDeferredOverflow)
             return fail(c, LBM_ECAPACITY,
                         std::string(where) + ": an asynchronous classification outgrew its "
@@ -524,7 +550,8 @@ int check_deferred(lbm_ctx* c, const char* where)
     HIPCHK(c, hipMemcpyAsync(c->host_stage, c->ctr, sizeof(uint32_t) * kStageHead,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (!c->deferred && !c->host_stage[kCtrNumeric]) return LBM_OK;
+    if (!c->deferred && !c->host_stage[kCtrNumeric] && !c->host_stage[kCtrDeferred])
+        return LBM_OK;
     return deferred_status(c, where);
 }
 
@@ -705,10 +732,8 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
     if (rc) return rc;
     const int np = c->cfg.n_particles;
     if (np == 0) return LBM_OK;
-    rc = dem_alloc(c);
-    if (rc) return rc;
     PhaseTimer tm(c, LBM_PHASE_DEM);
-    HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm));
+    HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm, DemScratch{c->pairs, c->pair_count, c->reach}));
     return LBM_OK;
 }
 
@@ -797,7 +822,7 @@ int lbm_synchronize(lbm_ctx* c)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->deferred && !c->failed) return check_deferred(c, "lbm_synchronize");
+    if (!c->failed) return check_deferred(c, "lbm_synchronize");
     return LBM_OK;
 }
 
@@ -837,15 +862,13 @@ int lbm_dem_checkpoint_save(const lbm_ctx* cc, void* dst_dev)
     const size_t np = (size_t)c->cfg.n_particles;
     if (np == 0) return LBM_OK;
     char* d = (char*)dst_dev;
-    const size_t b_pp = sizeof(double) * np * np * 8, b_pw = sizeof(double) * np * 6 * 8;
-    if (!c->hist_pp) {
-        HIPCHK(c, hipMemsetAsync(d, 0, b_pp + b_pw, c->stream));
-    } else {
-        HIPCHK(c, hipMemcpyAsync(d, c->hist_pp, b_pp, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(d + b_pp, c->hist_pw, b_pw, hipMemcpyDeviceToDevice, c->stream));
-    }
-    HIPCHK(c, hipMemcpyAsync(d + b_pp + b_pw, c->fc, sizeof(double) * np * 6,
-                             hipMemcpyDeviceToDevice, c->stream));
+    const DemStateBytes b = dem_state_bytes(np);
+    HIPCHK(c, hipMemcpyAsync(d, c->hist_pp, b.pp, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + b.pp, c->hist_key, b.key, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + b.pp + b.key, c->hist_pw, b.pw, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + b.pp + b.key + b.pw, c->fc, b.fc, hipMemcpyDeviceToDevice,
+                             c->stream));
     return LBM_OK;
 }
 
@@ -855,14 +878,14 @@ int lbm_dem_checkpoint_load(lbm_ctx* c, const void* src_dev)
     if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
     const size_t np = (size_t)c->cfg.n_particles;
     if (np == 0) return LBM_OK;
-    int rc = dem_alloc(c);
-    if (rc) return rc;
     const char* d = (const char*)src_dev;
-    const size_t b_pp = sizeof(double) * np * np * 8, b_pw = sizeof(double) * np * 6 * 8;
-    HIPCHK(c, hipMemcpyAsync(c->hist_pp, d, b_pp, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->hist_pw, d + b_pp, b_pw, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->fc, d + b_pp + b_pw, sizeof(double) * np * 6,
-                             hipMemcpyDeviceToDevice, c->stream));
+    const DemStateBytes b = dem_state_bytes(np);
+    HIPCHK(c, hipMemcpyAsync(c->hist_pp, d, b.pp, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hist_key, d + b.pp, b.key, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hist_pw, d + b.pp + b.key, b.pw, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->fc, d + b.pp + b.key + b.pw, b.fc, hipMemcpyDeviceToDevice,
+                             c->stream));
     return LBM_OK;
 }
 
@@ -899,6 +922,7 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
     c->tape_len = 0;
     c->tape_steps = max_steps;
     c->taping = true;
+    HIPCHK(c, launch_contact_flag_reset(c));
     return LBM_OK;
 }
 
@@ -1015,6 +1039,21 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
     if (rc) return rc;
     const int np = c->cfg.n_particles;
     if (np > 0 && (!weights || !sigma_dev)) return fail(c, LBM_EINVAL, "null objective weights or state adjoint");
+    {
+        // the window's DEM calls must have been free motion
+        HIPCHK(c, hipMemcpyAsync(c->host_stage + kCtrContact, c->ctr + kCtrContact,
+                                 sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->host_stage[kCtrContact]) {
+            c->tape_len = 0;
+            c->taping = false;
+            const int rc2 = settle_buffers(c);
+            if (rc2) return rc2;
+            return fail(c, LBM_ESTATE,
+                        "lbm_adjoint_coupled: a contact force acted during the taped window; "
+                        "the adjoint differentiates free motion only");
+        }
+    }
     if (!c->adj_scratch && hipMalloc(&c->adj_scratch, c->sizes.adjoint_bytes) != hipSuccess)
         return fail(c, LBM_ENOMEM, "adjoint scratch allocation failed");
     const size_t nps = (size_t)std::max(np, 1);

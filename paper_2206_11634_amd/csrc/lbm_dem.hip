@@ -24,6 +24,7 @@ struct DemP {
     int niter;
     double g[3];
     double rhof;
+    uint32_t* contact_seen;  // flag set by every contact evaluation (may be null)
 };
 
 __device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3])
@@ -158,6 +159,7 @@ __device__ double reach(const PartDev& P, int p)
 __device__ void contact_force(const DemP& c, double delta, const double n[3], const double vrel[3],
                               double dt, double* h, double Fi[3])
 {
+    if (c.contact_seen) atomicOr(c.contact_seen, 1u);
     const double vn = dot3(vrel, n);
     double Fn = c.kn * delta - c.etan * vn;
     if (Fn < 0.0) Fn = 0.0;
@@ -344,16 +346,13 @@ __device__ __forceinline__ void pair_contact(const BA& A, const BB& B, double x[
     for (int a = 0; a < 3; ++a) atomicAdd(fc + 6 * j + 3 + a, -tq[a]);
 }
 
-// Threads [0, np*np) take the pairs i < j, threads [np*np, np*np + 6 np) the
-// particle-wall pairs.
 // Contact of pair (i < j): broad-phase test on the reach radii, then the
-// Newton search and force; the pair's history is record i * np + j.
+// Newton search and force; the pair's history is record `slot` of particle i.
 __device__ __forceinline__ void pair_item(const PartDev& P, double* hist, double* fc,
                                           const double* rch, const DemP& c, double dt,
-                                          const Geom& g, int i, int j)
+                                          const Geom& g, int i, int j, int slot)
 {
-    const int np = P.n;
-    double* h = hist + ((int64_t)i * np + j) * kHist;
+    double* h = hist + ((int64_t)i * kPairSlots + slot) * kHist;
     const double* xi = P.pos + 3 * i;
     const double* xj = P.pos + 3 * j;
     double sh[3], dv[3];
@@ -369,8 +368,8 @@ __device__ __forceinline__ void pair_item(const PartDev& P, double* hist, double
     }
     const double rsi = P.rs[i], rsj = P.rs[j];
     if (sqrt(dot3(dv, dv)) > rch[i] + rch[j] + rsi + rsj) {
-        // out of reach: forget the pair (most of the n^2 records are zero
-        // already, so read one double instead of writing eight)
+        // out of reach: forget the pair's contact (read one double instead of
+        // writing eight when the record is zero already)
         if (h[0] != 0.0)
             for (int k = 0; k < kHist; ++k) h[k] = 0.0;
         return;
@@ -410,43 +409,74 @@ __global__ void k_zero_count(uint32_t* count)
     if (threadIdx.x == 0) count[0] = 0u;
 }
 
-// Candidate pairs of one dem_step call: pairs whose centres are within the
-// reach radii, R_s and a skin that covers the relative displacement of the
-// call, (|v_i| + |v_j|) T + 1/2 (velocities change by far less than 1/4 lu
-// per lattice step under the accelerations of a stable run).  A pair outside
-// it cannot come into reach during the call; its history, if any, is
-// cleared.  Appends i << 16 | j, one atomic per wave.
-__global__ __launch_bounds__(256) void k_pairs(PartDev P, double* hist, double T, Geom g,
-                                               uint32_t* list, uint32_t* count)
+// Whether pair (i, j) is a candidate of a dem_step call of duration T: the
+// centres are within the reach radii, R_s and a skin that covers the
+// relative displacement of the call, (|v_i| + |v_j|) T + 1/2 (velocities
+// change by far less than 1/4 lu per lattice step under the accelerations of
+// a stable run).  A pair outside it cannot come into reach during the call.
+__device__ bool pair_candidate(const PartDev& P, int i, int j, double T, const Geom& g)
+{
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = P.pos[3 * j + a] - P.pos[3 * i + a];
+        if (g.per[a]) {
+            const double L = g.n[a];
+            if (d > 0.5 * L) d -= L;
+            else if (d < -0.5 * L) d += L;
+        }
+        d2 += d * d;
+    }
+    const double* vi = P.vel + 3 * i;
+    const double* vj = P.vel + 3 * j;
+    const double skin = (sqrt(dot3(vi, vi)) + sqrt(dot3(vj, vj))) * T + 0.5;
+    const double thr = reach(P, i) + reach(P, j) + P.rs[i] + P.rs[j] + skin;
+    return sqrt(d2) <= thr;
+}
+
+// The history records of pairs that are no longer candidates are released
+// (zeroed, slot freed): one thread per (particle, slot).  A slot's key is
+// the partner's index + 1, 0 when free, so zeroed state is empty.
+__global__ __launch_bounds__(256) void k_pair_release(PartDev P, double* hist, int32_t* key,
+                                                      double T, Geom g)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)P.n * kPairSlots) return;
+    const int j = key[t] - 1;
+    if (j < 0) return;
+    const int i = (int)(t / kPairSlots);
+    if (pair_candidate(P, i, j, T, g)) return;
+    double* h = hist + t * kHist;
+    for (int k = 0; k < kHist; ++k) h[k] = 0.0;
+    key[t] = 0;
+}
+
+// Candidate pairs of one dem_step call, one thread per (i, j): a candidate
+// pair i < j finds its history record among particle i's slots, or claims a
+// free one (released records are zero), and is appended as
+// slot << 32 | i << 16 | j, one atomic per wave.  A particle with more
+// candidate partners than slots latches kDeferredSlots (the pair is left
+// out).
+__global__ __launch_bounds__(256) void k_pairs(PartDev P, int32_t* key, double T, Geom g,
+                                               uint64_t* list, uint32_t* count, uint32_t* deferred)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int np = P.n;
     bool take = false;
-    int i = 0, j = 0;
+    int i = 0, j = 0, slot = -1;
     if (t < (int64_t)np * np) {
         i = (int)(t / np);
         j = (int)(t % np);
-        if (i < j) {
-            double d2 = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                double d = P.pos[3 * j + a] - P.pos[3 * i + a];
-                if (g.per[a]) {
-                    const double L = g.n[a];
-                    if (d > 0.5 * L) d -= L;
-                    else if (d < -0.5 * L) d += L;
-                }
-                d2 += d * d;
-            }
-            const double* vi = P.vel + 3 * i;
-            const double* vj = P.vel + 3 * j;
-            const double skin = (sqrt(dot3(vi, vi)) + sqrt(dot3(vj, vj))) * T + 0.5;
-            const double thr = reach(P, i) + reach(P, j) + P.rs[i] + P.rs[j] + skin;
-            take = sqrt(d2) <= thr;
-            if (!take) {
-                double* h = hist + t * kHist;
-                if (h[0] != 0.0)
-                    for (int k = 0; k < kHist; ++k) h[k] = 0.0;
-            }
+        take = i < j && pair_candidate(P, i, j, T, g);
+    }
+    if (take) {
+        int32_t* ki = key + (int64_t)i * kPairSlots;
+        for (int s = 0; s < kPairSlots && slot < 0; ++s)
+            if (ki[s] == j + 1) slot = s;
+        for (int s = 0; s < kPairSlots && slot < 0; ++s)
+            if (atomicCAS(ki + s, 0, j + 1) == 0) slot = s;
+        if (slot < 0) {
+            atomicOr(deferred, kDeferredSlots);
+            take = false;
         }
     }
     const uint64_t m = __ballot(take);
@@ -457,7 +487,7 @@ __global__ __launch_bounds__(256) void k_pairs(PartDev P, double* hist, double T
     base = __shfl(base, __ffsll((unsigned long long)m) - 1, 64);
     if (take) {
         const uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        list[base + below] = ((uint32_t)i << 16) | (uint32_t)j;
+        list[base + below] = ((uint64_t)slot << 32) | ((uint64_t)i << 16) | (uint64_t)j;
     }
 }
 
@@ -465,7 +495,7 @@ __global__ __launch_bounds__(256) void k_pairs(PartDev P, double* hist, double T
 // listed pairs; grid-stride over both.
 __global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, double* hist_w, double* fc,
                                                   const double* rch, DemP c, double dt, Geom g,
-                                                  const uint32_t* list, const uint32_t* count)
+                                                  const uint64_t* list, const uint32_t* count)
 {
     const int64_t nw = (int64_t)P.n * 6;
     const int64_t total = nw + (int64_t)*count;
@@ -474,8 +504,9 @@ __global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, doubl
         if (t < nw) {
             wall_contact(P, (int)t, hist_w, fc, rch, c, dt, g);
         } else {
-            const uint32_t e = list[t - nw];
-            pair_item(P, hist, fc, rch, c, dt, g, (int)(e >> 16), (int)(e & 0xffffu));
+            const uint64_t e = list[t - nw];
+            pair_item(P, hist, fc, rch, c, dt, g, (int)((e >> 16) & 0xffffu), (int)(e & 0xffffu),
+                      (int)(e >> 32));
         }
     }
 }
@@ -582,9 +613,26 @@ __global__ void k_second_half(PartDev P, const double* FTh, const double* fc, De
     half_kick(P, p, FTh, fc, c, 0.5 * dt, true);
 }
 
+// One wave: flag = whether any of the n6 contact sums is not zero.
+__global__ __launch_bounds__(64) void k_contact_flag_reset(const double* fc, int n6, uint32_t* flag)
+{
+    bool any = false;
+    for (int k = (int)threadIdx.x; k < n6; k += 64) any |= fc[k] != 0.0;
+    const bool set = __any(any);
+    if (threadIdx.x == 0) *flag = set ? 1u : 0u;
+}
+
 }  // namespace
 
-hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, const dem_params& prm)
+hipError_t launch_contact_flag_reset(lbm_ctx* ctx)
+{
+    hipLaunchKernelGGL(k_contact_flag_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->fc,
+                       6 * ctx->cfg.n_particles, ctx->ctr + kCtrContact);
+    return hipGetLastError();
+}
+
+hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, const dem_params& prm,
+                      const DemScratch& ws)
 {
     const int np = P.n;
     if (np == 0) return hipSuccess;
@@ -599,20 +647,25 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
     c.niter = prm.newton_iter;
     for (int a = 0; a < 3; ++a) c.g[a] = prm.gravity[a];
     c.rhof = prm.rho_f;
+    c.contact_seen = ctx->ctr + kCtrContact;
     const uint32_t bp = (np + 63) / 64;
-    // candidate pairs for the whole call (the list holds every pair at most)
+    // candidate pairs for the whole call: histories of pairs that dropped out
+    // are released first, so that their slots can be claimed again
+    const double T = (double)n_sub * dt;
+    const uint32_t br = (uint32_t)(((int64_t)np * kPairSlots + 255) / 256);
     const uint32_t bq = (uint32_t)(((int64_t)np * np + 255) / 256);
-    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, ctx->stream, ctx->pair_count);
-    hipLaunchKernelGGL(k_pairs, dim3(bq), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
-                       (double)n_sub * dt, ctx->geom, ctx->pairs, ctx->pair_count);
-    const int64_t most = 6 * (int64_t)np + (int64_t)np * (np - 1) / 2;
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, ctx->stream, ws.count);
+    hipLaunchKernelGGL(k_pair_release, dim3(br), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
+                       ctx->hist_key, T, ctx->geom);
+    hipLaunchKernelGGL(k_pairs, dim3(bq), dim3(256), 0, ctx->stream, P, ctx->hist_key, T,
+                       ctx->geom, ws.pairs, ws.count, ctx->ctr + kCtrDeferred);
+    const int64_t most = 6 * (int64_t)np + (int64_t)np * kPairSlots;
     const uint32_t bc = (uint32_t)std::min<int64_t>((most + 255) / 256, 1024);
     for (int s = 0; s < n_sub; ++s) {
         hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
-                           ctx->reach, c, dt, ctx->geom);
+                           ws.reach, c, dt, ctx->geom);
         hipLaunchKernelGGL(k_contacts, dim3(bc), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
-                           ctx->hist_pw, ctx->fc, ctx->reach, c, dt, ctx->geom, ctx->pairs,
-                           ctx->pair_count);
+                           ctx->hist_pw, ctx->fc, ws.reach, c, dt, ctx->geom, ws.pairs, ws.count);
         hipLaunchKernelGGL(k_second_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
                            c, dt);
     }

@@ -29,6 +29,18 @@ constexpr int kCtrNumeric = 2;
 // and kDeferredOverflow when a list outgrew its capacity.
 constexpr int kCtrDeferred = 3;
 constexpr uint32_t kDeferredOverflow = 0x100u;
+// Set by dem_step whenever a contact overlap is evaluated (and by
+// lbm_tape_begin when a contact force is carried into the window); cleared
+// by lbm_tape_begin.  The coupled adjoint differentiates free motion only
+// and refuses a window in which it is set.
+constexpr int kCtrContact = 4;
+// Latched by dem_step when a particle had more candidate contact partners
+// than its history slots (reported like the asynchronous classifications).
+constexpr uint32_t kDeferredSlots = 0x200u;
+// Pair contact histories: each particle i keeps kPairSlots records for its
+// partners j > i, keyed by j; a record lives while the pair stays a
+// broad-phase candidate.
+constexpr int kPairSlots = 32;
 constexpr int kStageHead = 32;  // = kCursorPad: the counts start on the second line
 
 // ---------------------------------------------------------------------------
@@ -153,12 +165,13 @@ struct lbm_ctx {
     double* FT = nullptr;         // [np][6] force, torque of the last step
     uint32_t* host_stage = nullptr; // pinned staging for counters
     // DEM
-    double* hist_pp = nullptr;    // [np*np][8]
+    double* hist_pp = nullptr;    // [np][kPairSlots][8] pair histories
+    int32_t* hist_key = nullptr;  // [np][kPairSlots] partner + 1 of each record, 0 free
     double* hist_pw = nullptr;    // [np*6][8]
     double* fc = nullptr;         // [np][6] last contact force / torque
     double* reach = nullptr;      // [np] broad-phase radius of each particle
     uint32_t* numeric = nullptr;  // set by a step whose force or torque sums are not finite
-    uint32_t* pairs = nullptr;    // [np (np - 1) / 2] candidate pairs of a dem_step call
+    uint64_t* pairs = nullptr;    // [np kPairSlots] candidate pairs of a dem_step call
     uint32_t* pair_count = nullptr;
     // kernel timing
     bool prof = false;
@@ -222,7 +235,18 @@ namespace q15 {
 }
 
 // Launchers (lbm_dem.hip, lbm_dem_adjoint.hip)
-hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm);
+// Work space of one dem_step call: the candidate pairs (i, j, history slot),
+// their count, and each particle's broad-phase reach.
+struct DemScratch {
+    uint64_t* pairs;
+    uint32_t* count;
+    double* reach;
+};
+hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm,
+                      const DemScratch& s);
+// Clear the contact flag of the counter block, then set it if the contact
+// force carried into the next dem_step is not zero.
+hipError_t launch_contact_flag_reset(lbm_ctx* c);
 hipError_t launch_dem_adjoint(lbm_ctx* c, const TapeStep& ts, const lbm_particles* P,
                               const dem_params& prm, int n_sub, double dt, const double* sig1,
                               double* sig0, const double* wJ, double* wts);

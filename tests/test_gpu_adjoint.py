@@ -398,3 +398,27 @@ def test_fp64_free_motion_adjoint_matches_oracle_differences():
         fd = (_oracle_free_J(_free_shift(prob, p, block, a, h), F, tau) -
               _oracle_free_J(_free_shift(prob, p, block, a, -h), F, tau)) / (2 * h)
         assert abs(s0[p, 3 * block + a] - fd) <= 5e-5 * scale, (block, p, a, s0[p, 3 * block + a], fd)
+
+
+def test_free_motion_adjoint_refuses_a_window_with_contact():
+    """Two spheres whose contact surfaces overlap by 0.05 lu (in contact
+    from the first substep on): the coupled adjoint, which differentiates
+    free motion only, returns ESTATE rather than a gradient that leaves the
+    contact force out.  The same bodies 6 lu apart are differentiated as
+    before."""
+    lat = W.LatticeSpec(32, 28, 30, (1, 0, 1), tau=0.7)
+    sh = W.sphere_shape(6.0, 0.2)
+    for gap, expect_refusal in ((-0.05, True), (6.0, False)):
+        ps = W.make_particles([sh, sh], [[12.0, 14.0, 15.0], [18.0 + gap, 14.0, 15.0]],
+                              [[1, 0, 0, 0]] * 2, 1.5,
+                              vel=np.array([[0.03, 0.0, 0.0], [-0.03, 0.0, 0.0]]))
+        prob = AD.FreeProblem(lat=lat, ps=ps, steps=12, window=6, storage="f64")
+        F, tau = np.array(lat.body_force), lat.tau
+        if expect_refusal:
+            with pytest.raises(B.LbmError) as e:
+                AD.evaluate_free(prob, F, tau, grad=True)
+            assert e.value.code == B.LBM_ESTATE
+            assert "contact" in str(e.value)
+        else:
+            J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
+            assert np.isfinite(s0).all() and np.abs(s0).max() > 0

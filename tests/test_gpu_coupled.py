@@ -132,7 +132,8 @@ def test_resting_pair_feels_no_fluid_force_with_missing_point_treatment(storage)
     assert res[3][1] < 1e-3
 
 
-def test_checkpoint_resumes_a_run_with_contacts():
+@pytest.mark.parametrize("classify", ["balls", "sweep"])
+def test_checkpoint_resumes_a_run_with_contacts(classify):
     """Lattice checkpoint + particle arrays + the DEM's own state (contact
     histories, last contact forces) taken in the middle of a sphere-sphere
     contact resume the coupled run to the same trajectory; without the DEM
@@ -143,7 +144,7 @@ def test_checkpoint_resumes_a_run_with_contacts():
                           [[1.0, 0, 0, 0]] * 2, 1.5,
                           vel=np.array([[0.03, 0.006, 0.0], [-0.03, -0.006, 0.0]]))
     prm = B.DemParams.make(**W.dem_defaults(ps))
-    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64", classify=classify)
     parts = B.DeviceParticles(ps)
 
     def run(k0, k1):

@@ -134,3 +134,55 @@ def test_c4_dem_full_size():
     for k in ("pos", "vel", "omega", "quat", "world_pts"):
         a, b = getattr(G, k), getattr(P, k)
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
+
+
+# ---------------------------------------------------------------------------
+# long replay runs against the oracle's stored series
+# (tests/golden/make_drag_reference.py writes them with the oracle alone)
+# ---------------------------------------------------------------------------
+
+def _stored_reference(name):
+    from pathlib import Path
+    lat, ps, steps, treat, desc = W.drag_case(name)
+    path = Path(__file__).resolve().parent / "golden" / f"drag_{name}.npz"
+    ref = np.load(path, allow_pickle=False)
+    assert str(ref["fingerprint"]) == W.fingerprint(lat, ps, steps, treat), \
+        "stored oracle series made from other inputs: run tests/golden/make_drag_reference.py"
+    return lat, ps, steps, treat, ref
+
+
+def _replay_forces(lat, ps, steps, treat, storage):
+    import torch
+    traj = B.DeviceTrajectory([W.prescribed_state(ps, lat, float(n)) for n in range(steps + 1)])
+    gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat)
+    out = torch.zeros((steps, ps.n, 6), dtype=torch.float64, device=gpu.device)
+    for k in range(steps):
+        gpu.classify(traj[k])
+        gpu.step(traj[k])
+        f, t = gpu.forces()
+        out[k, :, :3] = f
+        out[k, :, 3:] = t
+    res = out.cpu().numpy()
+    gpu.close()
+    return res
+
+
+def _series_error(g, ref):
+    """Per body: max over steps |X_gpu - X_oracle| / max over steps |X_oracle|."""
+    e = []
+    for sl, R in ((slice(0, 3), ref["F"]), (slice(3, 6), ref["T"])):
+        num = np.linalg.norm(g[:, :, sl] - R, axis=2).max(0)
+        den = np.linalg.norm(R, axis=2).max(0)
+        e.append(num / den)
+    return np.max(e, axis=0)
+
+
+@pytest.mark.parametrize("name,storage", [("c2", "f32"), ("c3", "f32"), ("c3", "f16")])
+def test_drag_series_against_the_oracle(name, storage):
+    """c2: the 24 lu metaball descending and tumbling for 2000 steps; c3: the
+    200-body suspension for 100 steps.  Force and torque of every body at
+    every step within the storage's drag bar of the FP64 oracle."""
+    lat, ps, steps, treat, ref = _stored_reference(name)
+    g = _replay_forces(lat, ps, steps, treat, storage)
+    err = _series_error(g, ref)
+    assert err.max() <= FORCE_TOL[storage], (name, storage, err.max(), int(err.argmax()))

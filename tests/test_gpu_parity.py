@@ -98,13 +98,18 @@ TREAT_PLAIN = B.TREAT_VIBB | B.TREAT_MISSING
 TREAT_TIMED = B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_NEQ_SPLIT   # the 512^3 workload's bits
 
 
+@pytest.mark.parametrize("classify", ["balls", "sweep"])
 @pytest.mark.parametrize("treat", [TREAT_PLAIN, TREAT_TIMED], ids=["bits3", "bits11"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_deviation_storage_parity(storage, treat):
+def test_deviation_storage_parity(storage, treat, classify):
+    """With the lattice sweep the collision writes moments only in the band
+    the next link step reads (links outside it take them from the
+    populations); with ball walks it writes them everywhere."""
     lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
                           diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
                           u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
-    r = _run(lat, ps, storage, 8, treat=treat, tag=f"{storage} treat{treat}")
+    r = _run(lat, ps, storage, 8, treat=treat, tag=f"{storage} treat{treat} {classify}",
+             classify=classify)
     assert r["pop_err"] < POP_TOL[storage], r
     assert r["F"] < FORCE_TOL[storage] and r["T"] < FORCE_TOL[storage], r
 
@@ -518,4 +523,30 @@ def test_more_than_sixty_four_control_points_is_rejected():
         gpu.classify(parts)
     assert e.value.code == B.LBM_EINVAL
     assert b"more than 64" in B.load().lbm_last_error(gpu.ctx)
+    gpu.close()
+
+
+def test_dem_more_candidate_partners_than_history_records_is_reported():
+    """A sphere ringed by 40 small spheres within the broad phase's reach
+    (centres 4.2 lu apart, reach 2.9 + 0.9 + R_s + 1/2): particle 0 has 40
+    candidate partners of higher index, more than its 32 history records.
+    dem_step leaves the extra pairs out and latches it; lbm_synchronize
+    reports ECAPACITY and the context is failed."""
+    lat = W.LatticeSpec(40, 40, 40, (1, 1, 1))
+    k = np.arange(40) + 0.5
+    th, ph = np.arccos(1 - 2 * k / 40), np.pi * (1 + 5 ** 0.5) * k
+    ring = 4.2 * np.stack([np.cos(ph) * np.sin(th), np.sin(ph) * np.sin(th), np.cos(th)], 1)
+    c = np.array([20.0, 20.0, 20.0])
+    shapes = [W.sphere_shape(6.0, 0.1)] + [W.sphere_shape(2.0, 0.1)] * 40
+    ps = W.make_particles(shapes, np.vstack([c, c + ring]), [[1.0, 0, 0, 0]] * 41, 1.5)
+    gpu = B.Lattice.for_particles(lat, ps, storage="f64")
+    parts = B.DeviceParticles(ps)
+    gpu.dem(parts, 2, 0.1, B.DemParams.make(**W.dem_defaults(ps)))
+    with pytest.raises(B.LbmError) as e:
+        gpu.sync()
+    assert e.value.code == B.LBM_ECAPACITY
+    assert "candidate contact partners" in str(e.value)
+    with pytest.raises(B.LbmError) as e:
+        gpu.dem(parts, 2, 0.1, B.DemParams.make(**W.dem_defaults(ps)))
+    assert e.value.code == B.LBM_ESTATE
     gpu.close()
