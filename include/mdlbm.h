@@ -259,6 +259,19 @@ int lbm_particle_forces(const lbm_ctx* ctx, double* F_dev, double* T_dev);
  * lbm_classify_nodes.  Allocates nothing.  Asynchronous. */
 int dem_step(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_params* prm);
 
+/* dem_step for callers that cannot allocate device memory or use memory the
+ * library allocated after lbm_init (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same substeps and results,
+ * with the call's work space (candidate pairs, their count, the bodies'
+ * reach) in a static device array instead of the context's, looked up once
+ * per device by lbm_init.  The array holds at most 1024 particles (about
+ * 270 KB per device, held until the process ends); EINVAL for a context with
+ * more.  Every call on one device shares that array and leaves its contents
+ * there: calls that overlap on one device (on different streams or
+ * contexts) race and must not be issued.  Calls no hipMalloc, hipFree or
+ * hipMemset.  Asynchronous. */
+int dem_step_noalloc(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_params* prm);
+
 /* ---- inspection (tests and tools) --------------------------------------- */
 
 /* Links of the last classification, in an unspecified order, into device

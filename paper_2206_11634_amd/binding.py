@@ -88,7 +88,7 @@ EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
            "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled", "lbm_get_moments",
-           "lbm_dem_checkpoint_save", "lbm_dem_checkpoint_load"]
+           "lbm_dem_checkpoint_save", "lbm_dem_checkpoint_load", "dem_step_noalloc"]
 
 _lib = None
 
@@ -115,6 +115,8 @@ def load(path: Path | None = None):
         "lbm_particle_forces": [_P, _P, _P],
         "dem_step": [_P, ctypes.POINTER(LbmParticles), ctypes.c_int, ctypes.c_double,
                      ctypes.POINTER(DemParams)],
+        "dem_step_noalloc": [_P, ctypes.POINTER(LbmParticles), ctypes.c_int, ctypes.c_double,
+                             ctypes.POINTER(DemParams)],
         "lbm_get_links": [_P, ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)],
         "lbm_get_refill": [_P, ctypes.c_int64, _P, _P, ctypes.POINTER(ctypes.c_int64)],
         "lbm_get_owner": [_P, _P],
@@ -206,6 +208,11 @@ def lbm_particle_forces(ctx, F, T):
 def dem_step(ctx, parts: LbmParticles, n_sub: int, dt: float, prm: DemParams):
     _check(load().dem_step(ctx, ctypes.byref(parts), int(n_sub), float(dt), ctypes.byref(prm)),
            ctx)
+
+
+def dem_step_noalloc(ctx, parts: LbmParticles, n_sub: int, dt: float, prm: DemParams):
+    _check(load().dem_step_noalloc(ctx, ctypes.byref(parts), int(n_sub), float(dt),
+                                   ctypes.byref(prm)), ctx)
 
 
 def lbm_synchronize(ctx):
@@ -360,6 +367,10 @@ class Lattice:
 
     def dem(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
         dem_step(self.ctx, parts.struct, n_sub, dt, prm)
+
+    def dem_noalloc(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
+        """dem_step_noalloc: the same substeps with the static work space."""
+        dem_step_noalloc(self.ctx, parts.struct, n_sub, dt, prm)
 
     def sync(self):
         lbm_synchronize(self.ctx)

@@ -391,6 +391,15 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         lbm_destroy(c);
         return fail(nullptr, LBM_ENOMEM, msg);
     }
+    // the device, and the address of the allocation-free DEM entry point's
+    // work space on it
+    e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = dem_noalloc_setup();
+    if (e != hipSuccess) {
+        std::string msg = std::string("device set-up failed: ") + hipGetErrorString(e);
+        lbm_destroy(c);
+        return fail(nullptr, LBM_EDEVICE, msg);
+    }
     e = LQ(c, launch_init_equilibrium)(c, c->f[0]);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[0], 0xFF, sz.owner_bytes, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->own[1], 0xFF, sz.owner_bytes, c->stream);
@@ -734,6 +743,30 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
     if (np == 0) return LBM_OK;
     PhaseTimer tm(c, LBM_PHASE_DEM);
     HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm, DemScratch{c->pairs, c->pair_count, c->reach}));
+    return LBM_OK;
+}
+
+int dem_step_noalloc(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_params* prm)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (!prm) return fail(c, LBM_EINVAL, "null DEM parameters");
+    if (n_sub < 1) return fail(c, LBM_EINVAL, "n_sub must be >= 1");
+    if (!(dt > 0.0)) return fail(c, LBM_EINVAL, "dt must be positive");
+    const int np = c->cfg.n_particles;
+    if (np > kNoAllocParticles)
+        return fail(c, LBM_EINVAL,
+                    "dem_step_noalloc: " + std::to_string(np) + " particles, more than the " +
+                        std::to_string(kNoAllocParticles) + " its static work space holds "
+                        "(use dem_step)");
+    int rc = check_particles(c, P, true);
+    if (rc) return rc;
+    if (np == 0) return LBM_OK;
+    DemScratch ws;
+    if (!dem_noalloc_scratch(c->device, &ws))
+        return fail(c, LBM_ESTATE, "dem_step_noalloc: work space of this device not set up");
+    PhaseTimer tm(c, LBM_PHASE_DEM);
+    HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm, ws));
     return LBM_OK;
 }
 

@@ -11,6 +11,8 @@
 // and one per particle-wall pair, FP64 atomics into the sums), second half
 // kick.
 // The work is latency-bound (a few thousand particles at most), not HBM-bound.
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace mdlbm {
@@ -670,6 +672,55 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
                            c, dt);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free work space of dem_step_noalloc: one static array per
+// device (module-scope device memory, loaded with the code object), laid out
+// as the pair count (first 512 bytes), the reach of up to kNoAllocParticles
+// particles, then up to kNoAllocParticles * kPairSlots pair entries.  Host
+// code never uses the array's name as an address: the device address is
+// looked up once per device and kept.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocHead = 64;  // 8-byte words before the reach
+constexpr size_t kNoAllocWords =
+    kNoAllocHead + (size_t)kNoAllocParticles + (size_t)kNoAllocParticles * kPairSlots;
+__device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t dem_noalloc_setup()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<uint64_t*>(ptr);
+    return hipSuccess;
+}
+
+bool dem_noalloc_scratch(int dev, DemScratch* out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return false;
+    uint64_t* base;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_dev[dev];
+    }
+    if (!base) return false;
+    out->count = reinterpret_cast<uint32_t*>(base);
+    out->reach = reinterpret_cast<double*>(base + kNoAllocHead);
+    out->pairs = base + kNoAllocHead + kNoAllocParticles;
+    return true;
 }
 
 }  // namespace mdlbm

@@ -125,6 +125,7 @@ static_assert(kStageHead == kCursorPad, "counter block: one head line, then the 
 struct lbm_ctx {
     lbm_config cfg{};
     hipStream_t stream = nullptr;
+    int device = 0;         // the HIP device current at lbm_init
     mdlbm::Geom geom{};
     mdlbm::Phys phys{};
     mdlbm::BoxSpec box{};
@@ -244,6 +245,14 @@ struct DemScratch {
 };
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm,
                       const DemScratch& s);
+// Most particles dem_step_noalloc takes (its static work space holds the
+// pair list of that many).
+constexpr int kNoAllocParticles = 1024;
+// Device address of the allocation-free DEM work space on the current
+// device (looked up once per device); hipSuccess or the lookup's error.
+hipError_t dem_noalloc_setup();
+// The work space of device dev, after dem_noalloc_setup ran on it.
+bool dem_noalloc_scratch(int dev, DemScratch* out);
 // Clear the contact flag of the counter block, then set it if the contact
 // force carried into the next dem_step is not zero.
 hipError_t launch_contact_flag_reset(lbm_ctx* c);
