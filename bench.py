@@ -411,9 +411,17 @@ def free_adjoint_bench(lat, ps, meta, fd_check=True):
             p2.vel = p2.vel.copy()
             p2.vel[0, 0] += d
             return AD.evaluate_free(dataclasses.replace(ref, ps=p2), F, tau)
-        h = 1e-4
-        fd = (at(h) - at(-h)) / (2 * h)
+        # steps small enough that no node changes owner between the runs (a
+        # change of v0 by h moves the body by at most ~2000 h over the run);
+        # two step sizes that agree show that none did
+        fds = {}
+        for h in (1e-8, 4e-8):
+            fds[h] = (at(h) - at(-h)) / (2 * h)
+        fd = fds[1e-8]
         out["fd_rel_err_v0x"] = float(abs(s0[0, 6] - fd) / abs(fd))
+        out["fd_v0x"] = {f"h={h:g}": float(v) for h, v in fds.items()}
+        out["fd_step_agreement"] = float(abs(fds[1e-8] - fds[4e-8]) / abs(fds[1e-8]))
+        out["fd_reference"] = "central differences of the FP64-storage free-motion pass"
     return out
 
 

@@ -127,6 +127,11 @@ typedef struct {
                                   values in the storage's arithmetic (double or float) */
     size_t dem_checkpoint_bytes; /* bytes of the DEM's own state: contact histories
                                     and the last contact forces */
+    size_t contact_adjoint_bytes; /* bytes of the adjoint of that state for
+                                     lbm_adjoint_coupled: per particle 120 doubles, the
+                                     carried contact force and torque (6), the springs
+                                     of its 32 pair records (96) and of its six wall
+                                     records (18) */
 } lbm_sizes;
 
 typedef struct {
@@ -382,19 +387,25 @@ int lbm_adjoint(lbm_ctx* ctx, const lbm_particles* P, const double* weights, voi
 
 /* The adjoint of a run in which the particles move freely: each taped step
  * was followed by dem_step(ctx, P, n_sub, dt, prm) and then
- * lbm_classify_nodes, so the state s_{k+1} = (x, q, v, omega) that the next
- * step used came from s_k and the step's F^h, T^h through the DEM.  Running
+ * lbm_classify_nodes, so the state that the next step used came from the
+ * previous one and the step's F^h, T^h through the DEM, contacts included.
+ * The DEM state is s = (x, q, v, omega) per particle, the contact force and
+ * torque carried into the next call's first half kick, and the tangential
+ * spring of every contact record (pair and particle-wall).  Running
  * backwards, each step (1) adds the refill's wall-velocity terms to the
  * adjoint of s_{k+1}, (2) applies the transposed Jacobian of the dem_step
  * call (forward-mode dual numbers over x, a small world-frame rotation
- * theta, v, omega, F^h and T^h, through the same substeps), giving the
+ * theta, v, omega, F^h, T^h, the carried contact sum and the springs,
+ * through the same substeps and contacts; the contact point's derivative by
+ * the implicit function theorem at the converged Newton point), giving the
  * adjoint of s_k and dJ/dF^h_k, dJ/dT^h_k, (3) runs the step's node and link
  * adjoint with objective weights (wF, wT) + (dJ/dF^h_k, dJ/dT^h_k), adding
  * the link terms of s_k (pose through q and the lever arms, v and omega
- * through u_w).  Contact forces are not differentiated (free motion): ESTATE,
- * with the tape consumed and nothing accumulated, when any dem_step since
- * lbm_tape_begin evaluated a contact (particle-particle or particle-wall
- * overlap), or a contact force of the dem_step before it carried over.
+ * through u_w).  Each particle's contact cluster in one call (the particles
+ * linked to it through broad-phase candidate pairs) may hold at most 8
+ * particles: ESTATE otherwise, with the tape consumed and the outputs not
+ * valid.  Discrete events (a contact starting or ending, the Coulomb limit
+ * switching) are not differentiated across.
  *   P         the state after the last taped step's dem_step (the one the
  *             last classification used);
  *   weights   host [n][6]: (wF, wT) per particle, the same for every step;
@@ -403,11 +414,15 @@ int lbm_adjoint(lbm_ctx* ctx, const lbm_particles* P, const double* weights, voi
  *   grad_dev  device FP64 [4], accumulated into: dJ/dF (3), dJ/dtau;
  *   sigma_dev device FP64 [n][12]: on entry the adjoint of P (zeros for J
  *             above), on return the adjoint of the state the first taped
- *             step used, ordered (x, theta, v, omega).
+ *             step used, ordered (x, theta, v, omega);
+ *   sigma_contact_dev  NULL (zero on entry, not returned), or device FP64
+ *             (contact_adjoint_bytes): the same for the contact state, so
+ *             that windows run from the last to the first chain their
+ *             adjoints.
  * Synchronises.  ESTATE when nothing was taped. */
 int lbm_adjoint_coupled(lbm_ctx* ctx, const lbm_particles* P, const double* weights,
                         const dem_params* prm, int n_sub, double dt, void* lam_dev,
-                        double* grad_dev, double* sigma_dev);
+                        double* grad_dev, double* sigma_dev, double* sigma_contact_dev);
 
 /* ---- kernel timing (hipEvent pairs around each launch group) ------------ */
 

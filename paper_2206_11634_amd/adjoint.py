@@ -216,8 +216,8 @@ class FreeProblem:
     substeps of 1/n_sub) under F^h, T^h and relative gravity.  The gradient
     is with respect to the initial state s_0 = (x, theta, v, omega) of every
     particle (theta a small world-frame rotation of the initial orientation),
-    the fluid body force and tau.  Contact forces, if any occur, are not
-    differentiated."""
+    the fluid body force and tau, through the DEM's contact forces as well
+    (contact clusters of at most 8 particles per dem_step call)."""
     lat: W.LatticeSpec
     ps: W.ParticleSet
     steps: int
@@ -252,11 +252,18 @@ class _FreeRun:
         self.dt = 1.0 / prob.n_sub
 
     def state(self):
-        return {k: self.parts.t[k].clone() for k in ("pos", "quat", "vel", "omega", "world_pts")}
+        """The particle arrays and the DEM's own state (contact histories and
+        the carried contact sums), which a replayed window starts from."""
+        st = {k: self.parts.t[k].clone() for k in ("pos", "quat", "vel", "omega", "world_pts")}
+        st["dem"] = self.gpu.dem_checkpoint()
+        return st
 
     def load(self, st):
         for k, v in st.items():
-            self.parts.t[k].copy_(v)
+            if k == "dem":
+                self.gpu.dem_restore(v)
+            else:
+                self.parts.t[k].copy_(v)
 
     def advance(self, sync: bool = True):
         self.gpu.dem(self.parts, self.prob.n_sub, self.dt, self.prm)
@@ -264,8 +271,9 @@ class _FreeRun:
 
 
 def forward_free(prob: FreeProblem, body_force, tau, keep: bool = False):
-    """J of the free-motion run, and the run (with checkpoints of the lattice
-    and of the particle state at every window start) if keep."""
+    """J of the free-motion run, and the run (with checkpoints of the lattice,
+    of the particle state and of the DEM state at every window start) if
+    keep."""
     return _again_with_read_back(lambda sync: _forward_free(prob, body_force, tau, keep, sync))
 
 
@@ -294,7 +302,6 @@ def _forward_free(prob: FreeProblem, body_force, tau, keep: bool, sync: bool):
     if not keep:
         gpu.close()
         return J, None
-    run.final = run.state()
     return J, run
 
 
@@ -307,6 +314,7 @@ def backward_free(run: _FreeRun):
     lam = gpu.adjoint_field()
     g = torch.zeros(4, dtype=torch.float64, device=gpu.device)
     sig = torch.zeros((max(n, 1), 12), dtype=torch.float64, device=gpu.device)
+    sigc = gpu.contact_adjoint()   # carried contact sums and springs, across windows
     for w0 in sorted(run.ckpt, reverse=True):
         w1 = min(w0 + prob.window, prob.steps)
         ck, st = run.ckpt[w0]
@@ -319,7 +327,8 @@ def backward_free(run: _FreeRun):
         for k in range(w0, w1):
             gpu.step(run.parts)
             run.advance(sync=False)
-        gpu.adjoint_coupled(run.parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig)
+        gpu.adjoint_coupled(run.parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig,
+                            sigc)
     out = g.cpu().numpy()
     s0 = sig[:n].cpu().numpy()
     gpu.close()

@@ -43,7 +43,8 @@ class LbmSizes(ctypes.Structure):
                 ("population_bytes", ctypes.c_size_t), ("owner_bytes", ctypes.c_size_t),
                 ("flag_bytes", ctypes.c_size_t), ("moment_bytes", ctypes.c_size_t),
                 ("checkpoint_bytes", ctypes.c_size_t), ("adjoint_bytes", ctypes.c_size_t),
-                ("dem_checkpoint_bytes", ctypes.c_size_t)]
+                ("dem_checkpoint_bytes", ctypes.c_size_t),
+                ("contact_adjoint_bytes", ctypes.c_size_t)]
 
 
 class LbmBuffers(ctypes.Structure):
@@ -133,7 +134,7 @@ def load(path: Path | None = None):
         "lbm_dem_checkpoint_load": [_P, _P],
         "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P, _P],
         "lbm_adjoint_coupled": [_P, ctypes.POINTER(LbmParticles), _P, ctypes.POINTER(DemParams),
-                                ctypes.c_int, ctypes.c_double, _P, _P, _P],
+                                ctypes.c_int, ctypes.c_double, _P, _P, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -490,14 +491,23 @@ class Lattice:
                self.ctx)
 
     def adjoint_coupled(self, parts: "DeviceParticles", weights: np.ndarray, prm: DemParams,
-                        n_sub: int, dt: float, lam, grad, sigma):
-        """Free-motion adjoint over the taped steps (each followed by dem with
-        these arguments); sigma: device FP64 [n, 12], in/out."""
+                        n_sub: int, dt: float, lam, grad, sigma, sigma_contact=None):
+        """Adjoint of a free-moving run over the taped steps (each followed by
+        dem with these arguments); sigma: device FP64 [n, 12], in/out;
+        sigma_contact: device FP64 [n, contact_adjoint_bytes / 8], in/out, or
+        None for zero."""
         w = np.ascontiguousarray(weights, np.float64).reshape(-1)
         _check(load().lbm_adjoint_coupled(self.ctx, ctypes.byref(parts.struct),
                                           w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(prm),
                                           int(n_sub), float(dt), _ptr(lam), _ptr(grad),
-                                          _ptr(sigma)), self.ctx)
+                                          _ptr(sigma),
+                                          None if sigma_contact is None else _ptr(sigma_contact)),
+               self.ctx)
+
+    def contact_adjoint(self):
+        """A zero contact-state adjoint for adjoint_coupled."""
+        n = max(self.sizes.contact_adjoint_bytes // 8, 1)
+        return self.torch.zeros(n, dtype=self.torch.float64, device=self.device)
 
     def close(self):
         if getattr(self, "ctx", None):

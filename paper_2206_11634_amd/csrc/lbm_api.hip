@@ -137,6 +137,8 @@ void free_tape(lbm_ctx* c)
         (void)hipFree(t.links);
         (void)hipFree(t.cursor);
         (void)hipFree(t.part);
+        (void)hipFree(t.dem);
+        (void)hipFree(t.dem_key);
     }
     c->tape.clear();
     c->tape_len = 0;
@@ -206,9 +208,27 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
             HIPCHK(c, hipMemcpyAsync(t.links, c->links, sizeof(LinkRec) * (size_t)need,
                                      hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, LQ(c, launch_tape_small)(c, t, P));
+        // the DEM state the next dem_step starts from, for the coupled adjoint
+        const size_t npp = (size_t)np * kPairSlots;
+        HIPCHK(c, hipMemcpyAsync(t.dem, c->hist_pp, sizeof(double) * npp * 8,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.dem + npp * 8, c->hist_pw, sizeof(double) * (size_t)np * 48,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.dem + npp * 8 + (size_t)np * 48, c->fc,
+                                 sizeof(double) * (size_t)np * 6, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(t.dem_key, c->hist_key, sizeof(int32_t) * npp,
+                                 hipMemcpyDeviceToDevice, c->stream));
     }
     c->tape_len += 1;
     return LBM_OK;
+}
+
+// Doubles of one taped step's DEM state: pair records, wall records, contact
+// sums.
+size_t dem_tape_doubles(int np)
+{
+    const size_t n = (size_t)std::max(np, 1);
+    return n * kPairSlots * 8 + n * 48 + n * 6;
 }
 
 // Contact histories (kPairSlots keyed records per particle for its pairs,
@@ -273,6 +293,7 @@ int lbm_query_sizes(const lbm_config* cfg, lbm_sizes* out)
         const size_t np = (size_t)std::max(cfg->n_particles, 0);
         const DemStateBytes b = dem_state_bytes((size_t)np);
         out->dem_checkpoint_bytes = b.pp + b.key + b.pw + b.fc;
+        out->contact_adjoint_bytes = sizeof(double) * np * kAdjContact;
     }
     return LBM_OK;
 }
@@ -946,6 +967,8 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
             if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
             if (e == hipSuccess)
                 e = alloc(&t.part, (size_t)19 * std::max(np, 1) + (size_t)3 * c->cfg.n_ctrl);
+            if (e == hipSuccess) e = alloc(&t.dem, dem_tape_doubles(np));
+            if (e == hipSuccess) e = alloc(&t.dem_key, (size_t)kPairSlots * std::max(np, 1));
             if (e != hipSuccess) {
                 free_tape(c);
                 return fail(c, LBM_ENOMEM, "tape allocation failed");
@@ -955,7 +978,6 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
     c->tape_len = 0;
     c->tape_steps = max_steps;
     c->taping = true;
-    HIPCHK(c, launch_contact_flag_reset(c));
     return LBM_OK;
 }
 
@@ -1061,7 +1083,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
 
 int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weights,
                         const dem_params* prm, int n_sub, double dt, void* lam_dev,
-                        double* grad_dev, double* sigma_dev)
+                        double* grad_dev, double* sigma_dev, double* sigma_contact_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
@@ -1072,35 +1094,30 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
     if (rc) return rc;
     const int np = c->cfg.n_particles;
     if (np > 0 && (!weights || !sigma_dev)) return fail(c, LBM_EINVAL, "null objective weights or state adjoint");
-    {
-        // the window's DEM calls must have been free motion
-        HIPCHK(c, hipMemcpyAsync(c->host_stage + kCtrContact, c->ctr + kCtrContact,
-                                 sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->host_stage[kCtrContact]) {
-            c->tape_len = 0;
-            c->taping = false;
-            const int rc2 = settle_buffers(c);
-            if (rc2) return rc2;
-            return fail(c, LBM_ESTATE,
-                        "lbm_adjoint_coupled: a contact force acted during the taped window; "
-                        "the adjoint differentiates free motion only");
-        }
-    }
     if (!c->adj_scratch && hipMalloc(&c->adj_scratch, c->sizes.adjoint_bytes) != hipSuccess)
         return fail(c, LBM_ENOMEM, "adjoint scratch allocation failed");
     const size_t nps = (size_t)std::max(np, 1);
     if (!c->adj_wts && alloc(&c->adj_wts, 6 * nps) != hipSuccess)
         return fail(c, LBM_ENOMEM, "adjoint weight allocation failed");
-    if (!c->adj_sig && alloc(&c->adj_sig, 2 * 12 * nps + 6 * nps) != hipSuccess)
+    // state adjoints [2][np][12], objective weights [np][6], contact-state
+    // adjoints [2][np][kAdjContact]
+    if (!c->adj_sig && alloc(&c->adj_sig, 2 * 12 * nps + 6 * nps + 2 * kAdjContact * nps) != hipSuccess)
         return fail(c, LBM_ENOMEM, "state adjoint allocation failed");
     double* sig[2] = {c->adj_sig, c->adj_sig + 12 * nps};
     double* wJ = c->adj_sig + 24 * nps;
+    double* sct[2] = {c->adj_sig + 30 * nps, c->adj_sig + 30 * nps + kAdjContact * nps};
+    uint32_t* err = c->ctr + kCtrAdjCluster;
+    HIPCHK(c, hipMemsetAsync(err, 0, sizeof(uint32_t), c->stream));
     if (np > 0) {
         HIPCHK(c, hipMemcpyAsync(wJ, weights, sizeof(double) * 6 * np, hipMemcpyHostToDevice,
                                  c->stream));
         HIPCHK(c, hipMemcpyAsync(sig[0], sigma_dev, sizeof(double) * 12 * np,
                                  hipMemcpyDeviceToDevice, c->stream));
+        if (sigma_contact_dev)
+            HIPCHK(c, hipMemcpyAsync(sct[0], sigma_contact_dev, sizeof(double) * kAdjContact * np,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        else
+            HIPCHK(c, hipMemsetAsync(sct[0], 0, sizeof(double) * kAdjContact * np, c->stream));
     }
     rc = adj_lists(c);
     if (rc) return rc;
@@ -1113,6 +1130,7 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
         const double* pos1 = last ? P->pos : c->tape[s + 1].part;
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
+        const int32_t* key1 = last ? c->hist_key : c->tape[s + 1].dem_key;
         double* s1 = sig[si];      // adjoint of the state after this step's dem_step
         double* s0 = sig[1 - si];  // adjoint of the state this step used
         PhaseTimer tm(c, LBM_PHASE_ADJOINT);
@@ -1126,8 +1144,10 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
         HIPCHK(c, LQ(c, launch_adjoint_step)(c, ts, own1, pos1, vel1, om1, bufs[in], bufs[1 - in],
                                              c->adj_wts, grad_dev, P, ro, adj_list_of(c, s),
                                              kAdjNode | kAdjRefill));
-        // 2. the DEM call: s1 -> s0, and this step's force weights
-        HIPCHK(c, launch_dem_adjoint(c, ts, P, *prm, n_sub, dt, s1, s0, wJ, c->adj_wts));
+        // 2. the DEM call: (s1, contact state after it) -> (s0, contact state
+        //    before it), and this step's force weights
+        HIPCHK(c, launch_dem_adjoint(c, ts, key1, P, *prm, n_sub, dt, s1, sct[si], s0, sct[1 - si],
+                                     wJ, c->adj_wts, err));
         // 3. links of this step under those weights, into s0
         AdjOut lo;
         lo.g_links = s0;
@@ -1143,12 +1163,23 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
     if (in != 0)
         HIPCHK(c, hipMemcpyAsync(lam_dev, bufs[in], c->sizes.adjoint_bytes, hipMemcpyDeviceToDevice,
                                  c->stream));
-    if (np > 0)
+    if (np > 0) {
         HIPCHK(c, hipMemcpyAsync(sigma_dev, sig[si], sizeof(double) * 12 * np,
                                  hipMemcpyDeviceToDevice, c->stream));
+        if (sigma_contact_dev)
+            HIPCHK(c, hipMemcpyAsync(sigma_contact_dev, sct[si], sizeof(double) * kAdjContact * np,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->host_stage + kCtrAdjCluster, err, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     rc = c->deferred ? check_deferred(c, "lbm_adjoint") : LBM_OK;
     if (!rc) rc = adj_lists_check(c);
+    if (!rc && c->host_stage[kCtrAdjCluster])
+        rc = fail(c, LBM_ESTATE,
+                  "lbm_adjoint_coupled: a contact cluster (particles linked through candidate "
+                  "pairs of one dem_step call) has more than " + std::to_string(kAdjCluster) +
+                      " particles; the results are not valid");
     c->tape_len = 0;
     c->taping = false;
     const int rc2 = settle_buffers(c);

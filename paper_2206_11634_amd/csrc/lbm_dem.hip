@@ -26,7 +26,6 @@ struct DemP {
     int niter;
     double g[3];
     double rhof;
-    uint32_t* contact_seen;  // flag set by every contact evaluation (may be null)
 };
 
 __device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3])
@@ -161,7 +160,6 @@ __device__ double reach(const PartDev& P, int p)
 __device__ void contact_force(const DemP& c, double delta, const double n[3], const double vrel[3],
                               double dt, double* h, double Fi[3])
 {
-    if (c.contact_seen) atomicOr(c.contact_seen, 1u);
     const double vn = dot3(vrel, n);
     double Fn = c.kn * delta - c.etan * vn;
     if (Fn < 0.0) Fn = 0.0;
@@ -615,23 +613,7 @@ __global__ void k_second_half(PartDev P, const double* FTh, const double* fc, De
     half_kick(P, p, FTh, fc, c, 0.5 * dt, true);
 }
 
-// One wave: flag = whether any of the n6 contact sums is not zero.
-__global__ __launch_bounds__(64) void k_contact_flag_reset(const double* fc, int n6, uint32_t* flag)
-{
-    bool any = false;
-    for (int k = (int)threadIdx.x; k < n6; k += 64) any |= fc[k] != 0.0;
-    const bool set = __any(any);
-    if (threadIdx.x == 0) *flag = set ? 1u : 0u;
-}
-
 }  // namespace
-
-hipError_t launch_contact_flag_reset(lbm_ctx* ctx)
-{
-    hipLaunchKernelGGL(k_contact_flag_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->fc,
-                       6 * ctx->cfg.n_particles, ctx->ctr + kCtrContact);
-    return hipGetLastError();
-}
 
 hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, const dem_params& prm,
                       const DemScratch& ws)
@@ -649,7 +631,6 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
     c.niter = prm.newton_iter;
     for (int a = 0; a < 3; ++a) c.g[a] = prm.gravity[a];
     c.rhof = prm.rho_f;
-    c.contact_seen = ctx->ctr + kCtrContact;
     const uint32_t bp = (np + 63) / 64;
     // candidate pairs for the whole call: histories of pairs that dropped out
     // are released first, so that their slots can be claimed again

@@ -29,11 +29,10 @@ constexpr int kCtrNumeric = 2;
 // and kDeferredOverflow when a list outgrew its capacity.
 constexpr int kCtrDeferred = 3;
 constexpr uint32_t kDeferredOverflow = 0x100u;
-// Set by dem_step whenever a contact overlap is evaluated (and by
-// lbm_tape_begin when a contact force is carried into the window); cleared
-// by lbm_tape_begin.  The coupled adjoint differentiates free motion only
-// and refuses a window in which it is set.
-constexpr int kCtrContact = 4;
+// Set by the DEM adjoint when a particle's contact cluster (the particles
+// linked to it through broad-phase candidate pairs of one dem_step call)
+// has more than kAdjCluster members.
+constexpr int kCtrAdjCluster = 4;
 // Latched by dem_step when a particle had more candidate contact partners
 // than its history slots (reported like the asynchronous classifications).
 constexpr uint32_t kDeferredSlots = 0x200u;
@@ -41,6 +40,11 @@ constexpr uint32_t kDeferredSlots = 0x200u;
 // partners j > i, keyed by j; a record lives while the pair stays a
 // broad-phase candidate.
 constexpr int kPairSlots = 32;
+// The DEM adjoint: most particles of one contact cluster, and the doubles of
+// one particle's contact-state adjoint (carried contact force and torque, the
+// springs of its kPairSlots pair records and of its six wall records).
+constexpr int kAdjCluster = 8;
+constexpr int kAdjContact = 6 + 3 * kPairSlots + 3 * 6;
 constexpr int kStageHead = 32;  // = kCursorPad: the counts start on the second line
 
 // ---------------------------------------------------------------------------
@@ -72,6 +76,10 @@ struct TapeStep {
     int64_t link_max = 0;
     double* part = nullptr;      // [19 np + 3 n_ctrl]: pos, vel, omega, world control
                                  // points, quaternion (4 np), F^h and T^h (6 np)
+    double* dem = nullptr;       // DEM state before the dem_step call that followed the
+                                 // step: pair records [np][kPairSlots][8], wall records
+                                 // [np][6][8], contact sums [np][6]
+    int32_t* dem_key = nullptr;  // [np][kPairSlots] keys of the pair records
 };
 
 // Lattice geometry passed by value to kernels.
@@ -253,11 +261,14 @@ constexpr int kNoAllocParticles = 1024;
 hipError_t dem_noalloc_setup();
 // The work space of device dev, after dem_noalloc_setup ran on it.
 bool dem_noalloc_scratch(int dev, DemScratch* out);
-// Clear the contact flag of the counter block, then set it if the contact
-// force carried into the next dem_step is not zero.
-hipError_t launch_contact_flag_reset(lbm_ctx* c);
-hipError_t launch_dem_adjoint(lbm_ctx* c, const TapeStep& ts, const lbm_particles* P,
-                              const dem_params& prm, int n_sub, double dt, const double* sig1,
-                              double* sig0, const double* wJ, double* wts);
+// The transposed Jacobian of the dem_step call that followed taped step ts
+// (key_next: the pair records' keys after it), applied to the adjoint of
+// its output state (sig1 [np][12], sc1 [np][kAdjContact]), into the adjoint
+// of its input state (sig0, sc0) and the step's force weights wts = wJ +
+// dJ/d(F^h, T^h); err latches a contact cluster beyond kAdjCluster.
+hipError_t launch_dem_adjoint(lbm_ctx* c, const TapeStep& ts, const int32_t* key_next,
+                              const lbm_particles* P, const dem_params& prm, int n_sub, double dt,
+                              const double* sig1, const double* sc1, double* sig0, double* sc0,
+                              const double* wJ, double* wts, uint32_t* err);
 
 }  // namespace mdlbm

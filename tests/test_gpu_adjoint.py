@@ -369,6 +369,30 @@ def test_fp64_free_motion_adjoint_matches_finite_differences():
     assert np.abs(s0).max() > 0
 
 
+def test_fp32_free_motion_adjoint_within_1e3_of_fp64_differences():
+    """The free-motion adjoint in FP32 storage (FP32 lattice arithmetic, FP64
+    DEM and parameter sums) against central differences of the FP64
+    free-motion pass: every component within 1e-3 of its block's largest
+    entry (the differentiation form's bar)."""
+    prob = _free_problem()
+    p32 = dataclasses.replace(prob, storage="f32")
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    J, s0, dF, dtau = AD.evaluate_free(p32, F, tau, grad=True)
+    h = 1e-6
+    for block in range(4):
+        scale = max(np.abs(s0[:, 3 * block:3 * block + 3]).max(), 1e-12)
+        for p in range(2):
+            for a in range(3):
+                fd = (AD.evaluate_free(_free_shift(prob, p, block, a, h), F, tau) -
+                      AD.evaluate_free(_free_shift(prob, p, block, a, -h), F, tau)) / (2 * h)
+                assert abs(s0[p, 3 * block + a] - fd) <= 1e-3 * scale, (block, p, a)
+    e = np.array([1e-6, 0.0, 0.0])
+    fd = (AD.evaluate_free(prob, F + e, tau) - AD.evaluate_free(prob, F - e, tau)) / 2e-6
+    assert abs(dF[0] - fd) <= 1e-3 * abs(fd), (dF[0], fd)
+    fd = (AD.evaluate_free(prob, F, tau + 1e-6) - AD.evaluate_free(prob, F, tau - 1e-6)) / 2e-6
+    assert abs(dtau - fd) <= 1e-3 * abs(fd), (dtau, fd)
+
+
 def _oracle_free_J(prob, F, tau):
     lat = dataclasses.replace(prob.lat, body_force=tuple(F), tau=tau)
     o = O.Oracle(lat)
@@ -400,25 +424,141 @@ def test_fp64_free_motion_adjoint_matches_oracle_differences():
         assert abs(s0[p, 3 * block + a] - fd) <= 5e-5 * scale, (block, p, a, s0[p, 3 * block + a], fd)
 
 
-def test_free_motion_adjoint_refuses_a_window_with_contact():
-    """Two spheres whose contact surfaces overlap by 0.05 lu (in contact
-    from the first substep on): the coupled adjoint, which differentiates
-    free motion only, returns ESTATE rather than a gradient that leaves the
-    contact force out.  The same bodies 6 lu apart are differentiated as
-    before."""
-    lat = W.LatticeSpec(32, 28, 30, (1, 0, 1), tau=0.7)
+# ---------------------------------------------------------------------------
+# free motion with contacts: the adjoint through the DEM's contact forces
+# ---------------------------------------------------------------------------
+
+# Centres sit off the lattice planes: a sphere of integer radius centred on
+# a node has nodes exactly on its surface, whose classification flips under
+# any shift, and J jumps there.
+
+def _at_rest(lat):
+    wq = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    return np.repeat(wq[:, None], lat.ncell, axis=1)
+
+
+def _pair_in_contact(steps=12, window=5):
+    """Two spheres (d = 6) whose surfaces overlap by about 0.03 lu, offset
+    sideways, spinning and closing at 0.06 lu/step: in contact through the
+    run, with the spring-dashpot normal force and the tangential spring
+    (windows of 5, so the contact state crosses two window boundaries)."""
+    lat = W.LatticeSpec(32, 28, 30, (1, 0, 1), tau=0.7, body_force=(1e-5, 0.0, 0.0))
     sh = W.sphere_shape(6.0, 0.2)
-    for gap, expect_refusal in ((-0.05, True), (6.0, False)):
-        ps = W.make_particles([sh, sh], [[12.0, 14.0, 15.0], [18.0 + gap, 14.0, 15.0]],
-                              [[1, 0, 0, 0]] * 2, 1.5,
-                              vel=np.array([[0.03, 0.0, 0.0], [-0.03, 0.0, 0.0]]))
-        prob = AD.FreeProblem(lat=lat, ps=ps, steps=12, window=6, storage="f64")
-        F, tau = np.array(lat.body_force), lat.tau
-        if expect_refusal:
-            with pytest.raises(B.LbmError) as e:
-                AD.evaluate_free(prob, F, tau, grad=True)
-            assert e.value.code == B.LBM_ESTATE
-            assert "contact" in str(e.value)
-        else:
-            J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
-            assert np.isfinite(s0).all() and np.abs(s0).max() > 0
+    ps = W.make_particles([sh, sh], [[12.13, 14.27, 15.11], [18.08, 14.67, 15.41]],
+                          [[1, 0, 0, 0]] * 2, 1.5,
+                          vel=np.array([[0.03, 0.004, -0.006], [-0.03, -0.005, 0.004]]),
+                          omega=np.array([[0.001, 0.002, -0.003], [0.0, -0.002, 0.001]]))
+    w = np.zeros((2, 6))
+    w[0, 0] = 1.0 / steps
+    w[1, 1] = 0.3 / steps
+    w[0, 5] = 0.2 / steps
+    return AD.FreeProblem(lat=lat, ps=ps, steps=steps, window=window, storage="f64", weights=w,
+                          f0=_at_rest(lat))
+
+
+def _sphere_sliding_on_the_wall(steps=12, window=5):
+    """A sphere (d = 8) pressed into the wall y = -1/2 by gravity (overlap
+    0.03 lu) and sliding along it at 0.02 lu/step: the tangential spring
+    reaches the Coulomb limit within the first step and stays there; a
+    metaball above it moves freely through the fluid."""
+    rng = np.random.default_rng(5)
+    lat = W.LatticeSpec(32, 24, 30, (1, 0, 1), tau=0.7)
+    sh = W.sphere_shape(8.0, 0.2)
+    pts = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.5, 0.8, 0]])
+    mb = W.metaball_shape(pts, np.array([0.1, 0.12, 0.08]), 0.1, length=7.0,
+                          axis=np.array([1.0, 0, 0]), samples_per_unit=4.0)
+    ps = W.make_particles([sh, mb], [[14.13, 3.47, 15.21], [16.0, 14.0, 14.0]],
+                          [[1, 0, 0, 0], W.random_quaternion(rng)], 2.0,
+                          vel=np.array([[0.02, -0.002, 0.004], [0.01, 0.003, -0.004]]),
+                          omega=np.array([[0.0, 0.001, 0.002], [0.002, 0.0, -0.001]]))
+    w = np.zeros((2, 6))
+    w[0, 0] = 1.0 / steps
+    w[0, 1] = 0.5 / steps
+    w[1, 2] = 0.4 / steps
+    w[0, 3] = 0.3 / steps
+    return AD.FreeProblem(lat=lat, ps=ps, steps=steps, window=window, storage="f64", weights=w,
+                          f0=_at_rest(lat), gravity=(0.0, -2e-4, 0.0))
+
+
+def _check_free_fd(prob, J_of, s0, rtol, comps=None):
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    h = 1e-6
+    if comps is None:
+        comps = [(b, p, a) for b in range(4) for p in range(prob.ps.n) for a in range(3)]
+    for block, p, a in comps:
+        # a sphere's rotation changes nothing: that block is zero up to the
+        # differences' rounding (|J| eps / h), measured against the others
+        scale = max(np.abs(s0[:, 3 * block:3 * block + 3]).max(), 1e-4 * np.abs(s0).max())
+        fd = (J_of(_free_shift(prob, p, block, a, h), F, tau) -
+              J_of(_free_shift(prob, p, block, a, -h), F, tau)) / (2 * h)
+        got = s0[p, 3 * block + a]
+        assert abs(got - fd) <= rtol * scale, (block, p, a, got, fd)
+
+
+def _gpu_free_J(prob, F, tau):
+    return AD.evaluate_free(prob, F, tau)
+
+
+@pytest.mark.parametrize("case", ["pair", "wall"])
+def test_fp64_contact_adjoint_matches_finite_differences(case):
+    """Runs in contact from the first substep on: every component of
+    dJ/d(x, theta, v, omega) of both initial states, and dJ/dF, dJ/dtau,
+    against central differences of the same free-motion forward pass, each
+    block within 2e-5 of its largest entry.  The contact moves the bodies
+    (their velocities change sign or stall within the run), so a gradient
+    that left the contact force out would be off by far more."""
+    prob = _pair_in_contact() if case == "pair" else _sphere_sliding_on_the_wall()
+    print(f"contact adjoint {case}", flush=True)
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
+    assert np.isfinite(s0).all() and np.abs(s0).max() > 0
+    _check_free_fd(prob, _gpu_free_J, s0, 2e-5)
+    fd = (AD.evaluate_free(prob, F, tau + 1e-6) - AD.evaluate_free(prob, F, tau - 1e-6)) / 2e-6
+    assert abs(dtau - fd) <= 2e-5 * abs(fd), (dtau, fd)
+    e = np.array([1e-6, 0.0, 0.0])
+    fd = (AD.evaluate_free(prob, F + e, tau) - AD.evaluate_free(prob, F - e, tau)) / 2e-6
+    assert abs(dF[0] - fd) <= 2e-5 * max(abs(fd), np.abs(dF).max()), (dF[0], fd)
+
+
+def test_fp64_contact_adjoint_matches_oracle_differences():
+    """The contact pair against central differences of the oracle's own
+    coupled loop (FP64 lattice update and DEM with its contact histories, on
+    the CPU)."""
+    prob = _pair_in_contact(steps=10, window=4)
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
+    assert abs(J - _oracle_free_J(prob, F, tau)) <= 1e-9 * abs(J)
+    _check_free_fd(prob, _oracle_free_J, s0, 5e-5,
+                   comps=[(0, 0, 0), (0, 1, 1), (1, 0, 2), (2, 0, 0), (2, 1, 2), (3, 1, 1)])
+
+
+def _chain(n):
+    """n spheres (d = 4) in a row along x, neighbours overlapping by 0.01
+    lu, alternately moving in +y and -y: every neighbour pair is a
+    broad-phase candidate, so the contact cluster of each is the whole row."""
+    lat = W.LatticeSpec(48, 16, 16, (1, 0, 1), tau=0.7)
+    sh = W.sphere_shape(4.0, 0.2)
+    pos = [[6.17 + 3.99 * i, 8.23, 7.91] for i in range(n)]
+    vel = np.array([[0.0, 0.004 * (-1) ** i, 0.0] for i in range(n)])
+    ps = W.make_particles([sh] * n, pos, [[1, 0, 0, 0]] * n, 1.5, vel=vel)
+    w = np.zeros((n, 6))
+    w[:, 1] = 1.0 / 6
+    return AD.FreeProblem(lat=lat, ps=ps, steps=6, window=3, storage="f64", weights=w,
+                          f0=_at_rest(lat))
+
+
+def test_contact_adjoint_at_the_largest_cluster_and_beyond():
+    """A row of 8 spheres (the largest contact cluster the adjoint
+    simulates) is differentiated (three components against central
+    differences); a row of 9 is refused with ESTATE naming the cluster
+    rather than a gradient that leaves a particle of the cluster out."""
+    prob = _chain(8)
+    F, tau = np.array(prob.lat.body_force), prob.lat.tau
+    J, s0, dF, dtau = AD.evaluate_free(prob, F, tau, grad=True)
+    assert np.isfinite(s0).all() and np.abs(s0).max() > 0
+    _check_free_fd(prob, _gpu_free_J, s0, 2e-5, comps=[(0, 0, 0), (2, 3, 1), (0, 7, 0)])
+    prob = _chain(9)
+    with pytest.raises(B.LbmError) as e:
+        AD.evaluate_free(prob, F, tau, grad=True)
+    assert e.value.code == B.LBM_ESTATE
+    assert "cluster" in str(e.value)
