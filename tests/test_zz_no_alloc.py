@@ -57,7 +57,9 @@ def _dem_state(raw, n, slots=32):
     key = np.frombuffer(b, np.int32, n * slots, o_key).reshape(n, slots)
     pw = np.frombuffer(b, np.float64, n * 6 * 8, o_pw).reshape(n, 6, 8)
     fc = np.frombuffer(b, np.float64, n * 6, o_fc).reshape(n, 6)
-    recs = {(i, int(key[i, s])): pp[i, s] for i in range(n) for s in range(slots) if key[i, s] >= 0}
+    # a key is the partner's index + 1; 0 marks a free slot
+    recs = {(i, int(key[i, s]) - 1): pp[i, s] for i in range(n) for s in range(slots)
+            if key[i, s] > 0}
     return recs, pw, fc
 
 
