@@ -262,8 +262,6 @@ __device__ __forceinline__ AdjCoef<A> adj_collide(const A lam[kQ], const A pre[k
     moments<DEV, A>(pre, A(0.5), F, drho, rho, u[0], u[1], u[2]);
     const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const A uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    A a = A(0), B[3] = {A(0), A(0), A(0)}, G[3] = {A(0), A(0), A(0)};
-    A Fd[3] = {A(0), A(0), A(0)}, dom = A(0);
     const A gf = A(1) - A(0.5) * om;
     // feq - pre - S/2 sums to zero over i, so its weight in dJ/domega may be
     // centred on the mean of lambda, which keeps the sum free of the
@@ -272,23 +270,51 @@ __device__ __forceinline__ AdjCoef<A> adj_collide(const A lam[kQ], const A pre[k
 #pragma unroll
     for (int i = 0; i < kQ; ++i) lbar += lam[i];
     lbar *= A(1.0 / kQ);
+    // weighted moments of lambda, m0 = sum w l, m1 = sum w l e, m2 = sum w l e e:
+    // the sums over i of the equilibrium's and the forcing's derivatives are
+    // polynomials in u and F with these coefficients
+    A m0 = A(0), m1[3] = {A(0), A(0), A(0)};
+    A mxx = A(0), myy = A(0), mzz = A(0), mxy = A(0), mxz = A(0), myz = A(0);
+    A dom = A(0);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const A e3[3] = {A(cx(i)), A(cy(i)), A(cz(i))};
-        const A eu = e3[0] * u[0] + e3[1] * u[1] + e3[2] * u[2];
-        const A eF = e3[0] * F[0] + e3[1] * F[1] + e3[2] * F[2];
-        const A P = A(1) + A(3) * eu + A(4.5) * eu * eu - A(1.5) * uu;
         const A wl = W<A>(i) * lam[i];
-        a += wl * P;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            B[k] += wl * rho * (A(3) * e3[k] + A(9) * eu * e3[k] - A(3) * u[k]);
-            G[k] += wl * (A(-3) * F[k] + A(9) * eF * e3[k]);
-            Fd[k] += wl * (A(3) * (e3[k] - u[k]) + A(9) * eu * e3[k]);
+        m0 += wl;
+        if (cx(i)) {
+            m1[0] += A(cx(i)) * wl;
+            mxx += wl;
         }
+        if (cy(i)) {
+            m1[1] += A(cy(i)) * wl;
+            myy += wl;
+        }
+        if (cz(i)) {
+            m1[2] += A(cz(i)) * wl;
+            mzz += wl;
+        }
+        if (cx(i) && cy(i)) mxy += A(cx(i) * cy(i)) * wl;
+        if (cx(i) && cz(i)) mxz += A(cx(i) * cz(i)) * wl;
+        if (cy(i) && cz(i)) myz += A(cy(i) * cz(i)) * wl;
+        const A eu = A(cx(i)) * u[0] + A(cy(i)) * u[1] + A(cz(i)) * u[2];
+        const A eF = A(cx(i)) * F[0] + A(cy(i)) * F[1] + A(cz(i)) * F[2];
         const A St_i = W<A>(i) * (A(3) * (eF - uF) + A(9) * eu * eF);
         const A feq = eq_i<DEV, A>(i, drho, rho, u[0], u[1], u[2]);
         dom += (lam[i] - lbar) * (feq - pre[i] - A(0.5) * St_i);
+    }
+    const A m2u[3] = {mxx * u[0] + mxy * u[1] + mxz * u[2], mxy * u[0] + myy * u[1] + myz * u[2],
+                      mxz * u[0] + myz * u[1] + mzz * u[2]};
+    const A m2F[3] = {mxx * F[0] + mxy * F[1] + mxz * F[2], mxy * F[0] + myy * F[1] + myz * F[2],
+                      mxz * F[0] + myz * F[1] + mzz * F[2]};
+    const A m1u = m1[0] * u[0] + m1[1] * u[1] + m1[2] * u[2];
+    const A um2u = u[0] * m2u[0] + u[1] * m2u[1] + u[2] * m2u[2];
+    // a = sum w l P_i with P_i = 1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u
+    const A a = m0 * (A(1) - A(1.5) * uu) + A(3) * m1u + A(4.5) * um2u;
+    A B[3], G[3], Fd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        B[k] = rho * (A(3) * m1[k] + A(9) * m2u[k] - A(3) * u[k] * m0);
+        G[k] = A(-3) * F[k] * m0 + A(9) * m2F[k];
+        Fd[k] = A(3) * m1[k] - A(3) * u[k] * m0 + A(9) * m2u[k];
     }
     AdjCoef<A> co;
     co.om = om;
@@ -313,9 +339,9 @@ __device__ __forceinline__ AdjCoef<A> adj_collide(const A lam[kQ], const A pre[k
 // kernel takes and clears), and zero otherwise; k_adj_refill then rewrites the
 // entries its refilled nodes read.
 template <int S>
-// (three workgroups per CU: 168 registers, no spills; measured 9% faster
-// than the compiler's unbounded choice of 174, which allows two)
-__global__ __launch_bounds__(256, 3) void k_adj_node(const typename St<S>::T* __restrict__ f,
+// (the moment form of the transposed collision keeps the FP32 kernel at 85
+// registers, five waves per SIMD; a bound of six spills)
+__global__ __launch_bounds__(256) void k_adj_node(const typename St<S>::T* __restrict__ f,
                                                   const uint32_t* __restrict__ own0,
                                                   const uint32_t* __restrict__ own1,
                                                   const typename St<S>::A* __restrict__ lam1,
