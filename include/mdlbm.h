@@ -353,6 +353,31 @@ int lbm_dem_checkpoint_save(const lbm_ctx* ctx, void* dst_dev);
 /* Restore the DEM state saved by lbm_dem_checkpoint_save. */
 int lbm_dem_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
 
+/* ---- geometry snapshots (differentiation form) ------------------------- */
+
+/* Bytes of one geometry snapshot for the context's current link and refill
+ * list capacities, and a tag naming those capacities (for lbm_geometry_load).
+ * A snapshot is about owner_bytes + flag_bytes + 16 B per link slot. */
+int lbm_geometry_bytes(const lbm_ctx* ctx, size_t* bytes, uint64_t* tag);
+
+/* Copy the geometry of the last classification -- owner plane, flags, link
+ * records with their counts, the nodes it refilled, the particles' bounding
+ * balls -- into dst_dev (lbm_geometry_bytes).  For runs that are replayed
+ * (the adjoint's recomputation of a window): a replayed step then loads the
+ * geometry instead of classifying the same poses again.  ESTATE before the
+ * first classification.  Asynchronous. */
+int lbm_geometry_save(lbm_ctx* ctx, void* dst_dev);
+
+/* Stand in for lbm_classify_nodes(ctx, P) at the pose P a snapshot of the
+ * same context was saved at: its owners, flags and links become the current
+ * geometry and its refilled nodes are refilled from the current populations,
+ * as that classification did (nothing after lbm_checkpoint_load, as
+ * lbm_classify_nodes).  tag: as returned by lbm_geometry_bytes when the
+ * snapshot was sized; ESTATE when the list capacities changed since.  The
+ * list counts are not read back (as lbm_classify_nodes_async).
+ * Asynchronous. */
+int lbm_geometry_load(lbm_ctx* ctx, const void* src_dev, uint64_t tag, const lbm_particles* P);
+
 /* Record the next max_steps calls of lbm_step (populations after the link
  * reconstruction, owners, links, particle pose and velocities) for
  * lbm_adjoint.  The tape's device memory (about population_bytes +

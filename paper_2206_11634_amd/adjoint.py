@@ -42,6 +42,8 @@ class Problem:
     f0: np.ndarray = None       # [Q][ncell] initial populations
     treatments: int = B.TREAT_VIBB | B.TREAT_MISSING
     lattice: int = 19           # 19 (D3Q19) or 15 (D3Q15)
+    keep_geometry: bool = True  # keep every step's geometry for the replay (about
+                                # owner_bytes + flag_bytes per step on the device)
 
     def __post_init__(self):
         if self.weights is None:
@@ -92,6 +94,23 @@ def _again_with_read_back(fn):
     return fn(sync=True)
 
 
+def _snapshot(run, k):
+    """Keep the geometry of the classification just made as that of step k."""
+    if run.prob.keep_geometry:
+        run.geo[k] = run.gpu.geometry_save()
+
+
+def _replay_classify(run, k, parts):
+    """In a replay: the forward pass's geometry of step k if it kept one that
+    fits the list capacities of now, else a classification (asynchronous:
+    the forward pass sized the lists for the same poses)."""
+    snap = run.geo.get(k)
+    if snap is not None and snap[1] == run.gpu.geometry_bytes()[1]:
+        run.gpu.geometry_load(snap, parts)
+    else:
+        run.gpu.classify(parts, sync=False)
+
+
 def _closing(gpu, body):
     try:
         return body()
@@ -113,15 +132,19 @@ def _forward(prob: Problem, vel, body_force, tau, keep: bool, sync: bool):
 
     def body():
         gpu.set_populations(prob.initial())
-        run.ckpt = {}
+        run.ckpt, run.geo = {}, {}
         hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
         gpu.classify(run.parts(0))   # sizes the lists
+        if keep:
+            _snapshot(run, 0)
         for k in range(T):
             if keep and k % prob.window == 0:
                 run.ckpt[k] = gpu.checkpoint()
             gpu.step(run.parts(k))
             gpu.forces(hist[k, 0], hist[k, 1])
             gpu.classify(run.parts(k + 1), sync=sync)
+            if keep:
+                _snapshot(run, k + 1)
         gpu.sync()   # reports what the classifications latched
         w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
         return float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
@@ -150,13 +173,13 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     for w0 in sorted(run.ckpt, reverse=True):
         w1 = min(w0 + prob.window, prob.steps)
         gpu.restore(run.ckpt[w0])
-        # the forward pass sized the lists for these poses: no read-backs
-        # (lbm_adjoint reports anything the classifications latched)
-        gpu.classify(run.parts(w0), sync=False)   # the geometry at w0, refills nothing
+        # the geometry of the forward pass, or classifications without
+        # read-backs (lbm_adjoint reports anything they latched)
+        _replay_classify(run, w0, run.parts(w0))   # the geometry at w0, refills nothing
         gpu.tape_begin(w1 - w0)
         for k in range(w0, w1):
             gpu.step(run.parts(k))
-            gpu.classify(run.parts(k + 1), sync=False)
+            _replay_classify(run, k + 1, run.parts(k + 1))
         # poses w0 .. w1 of this window: a contiguous view of gx
         gpu.adjoint(run.parts(w1), prob.weights, lam, g,
                     None if gx is None else gx[w0:w1 + 1])
@@ -229,6 +252,7 @@ class FreeProblem:
     lattice: int = 19
     gravity: tuple = (0.0, 0.0, 0.0)
     n_sub: int = 10
+    keep_geometry: bool = True
 
     def __post_init__(self):
         if self.weights is None:
@@ -265,9 +289,14 @@ class _FreeRun:
             else:
                 self.parts.t[k].copy_(v)
 
-    def advance(self, sync: bool = True):
+    def advance(self, sync: bool = True, replay_step: int | None = None):
+        """dem_step, then the classification of the new poses (in a replay,
+        step replay_step's geometry kept by the forward pass, if any)."""
         self.gpu.dem(self.parts, self.prob.n_sub, self.dt, self.prm)
-        self.gpu.classify(self.parts, sync=sync)
+        if replay_step is None:
+            self.gpu.classify(self.parts, sync=sync)
+        else:
+            _replay_classify(self, replay_step, self.parts)
 
 
 def forward_free(prob: FreeProblem, body_force, tau, keep: bool = False):
@@ -285,15 +314,19 @@ def _forward_free(prob: FreeProblem, body_force, tau, keep: bool, sync: bool):
     def body():
         if prob.f0 is not None:
             gpu.set_populations(prob.f0)
-        run.ckpt = {}
+        run.ckpt, run.geo = {}, {}
         hist = torch.zeros((T, 2, max(n, 1), 3), dtype=torch.float64, device=gpu.device)
         gpu.classify(run.parts)   # sizes the lists
+        if keep:
+            _snapshot(run, 0)
         for k in range(T):
             if keep and k % prob.window == 0:
                 run.ckpt[k] = (gpu.checkpoint(), run.state())
             gpu.step(run.parts)
             gpu.forces(hist[k, 0], hist[k, 1])
             run.advance(sync)
+            if keep:
+                _snapshot(run, k + 1)
         gpu.sync()   # reports what the classifications latched
         w = torch.as_tensor(prob.weights, dtype=torch.float64, device=gpu.device)
         return float((hist[:, 0, :n] * w[:, :3]).sum() + (hist[:, 1, :n] * w[:, 3:]).sum())
@@ -320,13 +353,13 @@ def backward_free(run: _FreeRun):
         ck, st = run.ckpt[w0]
         gpu.restore(ck)
         run.load(st)
-        # replayed poses: no read-backs (lbm_adjoint_coupled reports anything
-        # the classifications latched)
-        gpu.classify(run.parts, sync=False)   # the geometry at w0, refills nothing
+        # replayed poses: the forward pass's geometry, or classifications
+        # without read-backs (lbm_adjoint_coupled reports anything they latched)
+        _replay_classify(run, w0, run.parts)   # the geometry at w0, refills nothing
         gpu.tape_begin(w1 - w0)
         for k in range(w0, w1):
             gpu.step(run.parts)
-            run.advance(sync=False)
+            run.advance(replay_step=k + 1)
         gpu.adjoint_coupled(run.parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig,
                             sigc)
     out = g.cpu().numpy()

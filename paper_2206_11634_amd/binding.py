@@ -89,7 +89,8 @@ EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_
            "lbm_get_owner", "lbm_get_populations", "lbm_set_populations", "lbm_synchronize",
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
            "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled", "lbm_get_moments",
-           "lbm_dem_checkpoint_save", "lbm_dem_checkpoint_load", "dem_step_noalloc"]
+           "lbm_dem_checkpoint_save", "lbm_dem_checkpoint_load", "dem_step_noalloc",
+           "lbm_geometry_bytes", "lbm_geometry_save", "lbm_geometry_load"]
 
 _lib = None
 
@@ -132,6 +133,9 @@ def load(path: Path | None = None):
         "lbm_get_moments": [_P, _P, _P],
         "lbm_dem_checkpoint_save": [_P, _P],
         "lbm_dem_checkpoint_load": [_P, _P],
+        "lbm_geometry_bytes": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint64)],
+        "lbm_geometry_save": [_P, _P],
+        "lbm_geometry_load": [_P, _P, ctypes.c_uint64, ctypes.POINTER(LbmParticles)],
         "lbm_adjoint": [_P, ctypes.POINTER(LbmParticles), _P, _P, _P, _P],
         "lbm_adjoint_coupled": [_P, ctypes.POINTER(LbmParticles), _P, ctypes.POINTER(DemParams),
                                 ctypes.c_int, ctypes.c_double, _P, _P, _P, _P],
@@ -470,6 +474,27 @@ class Lattice:
 
     def dem_restore(self, t):
         _check(load().lbm_dem_checkpoint_load(self.ctx, _ptr(t)), self.ctx)
+
+    def geometry_bytes(self):
+        """(bytes, tag) of a geometry snapshot for the current list capacities."""
+        n, tag = ctypes.c_size_t(), ctypes.c_uint64()
+        _check(load().lbm_geometry_bytes(self.ctx, ctypes.byref(n), ctypes.byref(tag)), self.ctx)
+        return int(n.value), int(tag.value)
+
+    def geometry_save(self, t=None):
+        """The last classification's geometry into t (a new device buffer if
+        None); returns (t, tag)."""
+        n, tag = self.geometry_bytes()
+        if t is None:
+            t = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        _check(load().lbm_geometry_save(self.ctx, _ptr(t)), self.ctx)
+        return t, tag
+
+    def geometry_load(self, snap, parts: "DeviceParticles"):
+        """Stand in for classify(parts) with a snapshot (t, tag) taken at that pose."""
+        t, tag = snap
+        _check(load().lbm_geometry_load(self.ctx, _ptr(t), ctypes.c_uint64(tag),
+                                        ctypes.byref(parts.struct)), self.ctx)
 
     def tape_begin(self, steps: int):
         _check(load().lbm_tape_begin(self.ctx, int(steps)), self.ctx)

@@ -814,13 +814,18 @@ struct RunAdj {
 };
 
 // The small arrays of one taped step in one launch: the first word of every
-// link cursor line, and the particle state (position, velocity, angular
-// velocity, world control points, quaternion, F^h and T^h of the step).
+// link cursor line, the particle state (position, velocity, angular
+// velocity, world control points, quaternion, F^h and T^h of the step), and
+// the DEM state the next dem_step starts from (pair records, wall records,
+// carried contact sums; the pair records' keys).
 __global__ void k_tape_small(uint32_t* __restrict__ tcur, const uint32_t* __restrict__ cur,
                              double* __restrict__ part, const double* __restrict__ pos,
                              const double* __restrict__ vel, const double* __restrict__ om,
                              const double* __restrict__ wpts, const double* __restrict__ quat,
-                             const double* __restrict__ FT, int np, int nctrl)
+                             const double* __restrict__ FT, int np, int nctrl,
+                             double* __restrict__ dem, int32_t* __restrict__ dem_key,
+                             const double* __restrict__ hpp, const double* __restrict__ hpw,
+                             const double* __restrict__ fc, const int32_t* __restrict__ hkey)
 {
     const int i = (int)(blockIdx.x * 256u + threadIdx.x);
     if (i < np) tcur[(int64_t)i * kCursorPad] = cur[(int64_t)i * kCursorPad];
@@ -833,6 +838,11 @@ __global__ void k_tape_small(uint32_t* __restrict__ tcur, const uint32_t* __rest
     double* tq = part + 9 * np + 3 * nctrl;
     if (quat && i < 4 * np) tq[i] = quat[i];
     if (i < 6 * np) tq[4 * np + i] = FT[i];
+    const int npp = np * kPairSlots;
+    if (i < 8 * npp) dem[i] = hpp[i];
+    if (i < 48 * np) dem[8 * npp + i] = hpw[i];
+    if (i < 6 * np) dem[8 * npp + 48 * np + i] = fc[i];
+    if (i < npp) dem_key[i] = hkey[i];
 }
 
 }  // namespace
@@ -843,10 +853,12 @@ hipError_t launch_tape_small(lbm_ctx* c, TapeStep& t, const lbm_particles* P)
 {
     const int np = c->cfg.n_particles, nctrl = c->cfg.n_ctrl;
     if (np == 0) return hipSuccess;
-    const int64_t n = std::max<int64_t>(6 * (int64_t)np, 3 * (int64_t)nctrl);
+    const int64_t n = std::max<int64_t>({8 * (int64_t)np * kPairSlots, 48 * (int64_t)np,
+                                         3 * (int64_t)nctrl});
     hipLaunchKernelGGL(k_tape_small, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, c->stream,
                        t.cursor, c->link_cursor, t.part, P->pos, P->vel, P->omega, P->world_pts,
-                       P->quat, c->FT, np, nctrl);
+                       P->quat, c->FT, np, nctrl, t.dem, t.dem_key, c->hist_pp, c->hist_pw, c->fc,
+                       c->hist_key);
     return hipGetLastError();
 }
 

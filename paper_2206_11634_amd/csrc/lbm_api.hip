@@ -207,17 +207,9 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
         if (c->link_max > 0)
             HIPCHK(c, hipMemcpyAsync(t.links, c->links, sizeof(LinkRec) * (size_t)need,
                                      hipMemcpyDeviceToDevice, c->stream));
+        // cursors, particle state and the DEM state the next dem_step starts
+        // from (for the coupled adjoint), in one launch
         HIPCHK(c, LQ(c, launch_tape_small)(c, t, P));
-        // the DEM state the next dem_step starts from, for the coupled adjoint
-        const size_t npp = (size_t)np * kPairSlots;
-        HIPCHK(c, hipMemcpyAsync(t.dem, c->hist_pp, sizeof(double) * npp * 8,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.dem + npp * 8, c->hist_pw, sizeof(double) * (size_t)np * 48,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.dem + npp * 8 + (size_t)np * 48, c->fc,
-                                 sizeof(double) * (size_t)np * 6, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(t.dem_key, c->hist_key, sizeof(int32_t) * npp,
-                                 hipMemcpyDeviceToDevice, c->stream));
     }
     c->tape_len += 1;
     return LBM_OK;
@@ -940,6 +932,147 @@ int lbm_dem_checkpoint_load(lbm_ctx* c, const void* src_dev)
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(c->fc, d + b.pp + b.key + b.pw, b.fc, hipMemcpyDeviceToDevice,
                              c->stream));
+    return LBM_OK;
+}
+
+// Up to eight device-to-device copies (a null source: zeros) in one launch.
+struct CopySeg {
+    const uint8_t* src;
+    uint8_t* dst;
+    uint64_t bytes;
+};
+struct CopyList {
+    CopySeg s[8];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_copy_segments(CopyList L)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (int k = 0; k < L.n; ++k) {
+        const CopySeg g = L.s[k];
+        const bool v16 = ((reinterpret_cast<uintptr_t>(g.src) | reinterpret_cast<uintptr_t>(g.dst)) &
+                          15u) == 0;
+        const uint64_t n16 = v16 ? g.bytes / 16 : 0;
+        for (uint64_t i = t; i < n16; i += stride)
+            reinterpret_cast<uint4*>(g.dst)[i] =
+                g.src ? reinterpret_cast<const uint4*>(g.src)[i] : make_uint4(0, 0, 0, 0);
+        for (uint64_t i = n16 * 16 + t; i < g.bytes; i += stride) g.dst[i] = g.src ? g.src[i] : 0;
+    }
+}
+
+static hipError_t copy_segments(lbm_ctx* c, const CopyList& L)
+{
+    uint64_t most = 0;
+    for (int k = 0; k < L.n; ++k) most = std::max<uint64_t>(most, L.s[k].bytes);
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(1, (most / 16 + 255) / 256));
+    hipLaunchKernelGGL(k_copy_segments, dim3(nb), dim3(256), 0, c->stream, L);
+    return hipGetLastError();
+}
+
+// Layout of a geometry snapshot: owner plane, flags, link records, link
+// cursor lines, refill cursor line and list, bounding balls; each part on a
+// 256-byte boundary.
+struct GeometryLayout {
+    size_t own, flag, links, cursors, refill_ctr, refill, ball, total;
+};
+
+static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+static GeometryLayout geometry_layout(const lbm_ctx* c)
+{
+    const size_t np = (size_t)std::max(c->cfg.n_particles, 1);
+    GeometryLayout L;
+    L.own = 0;
+    L.flag = L.own + align256(c->sizes.owner_bytes);
+    L.links = L.flag + align256(c->sizes.flag_bytes);
+    L.cursors = L.links + align256(sizeof(LinkRec) * np * (size_t)c->link_cap);
+    L.refill_ctr = L.cursors + align256(sizeof(uint32_t) * kCursorPad * np);
+    L.refill = L.refill_ctr + 256;
+    L.ball = L.refill + align256(sizeof(RefillRec) * (size_t)c->refill_cap);
+    L.total = L.ball + align256(sizeof(double) * 4 * np);
+    return L;
+}
+
+static uint64_t geometry_tag(const lbm_ctx* c)
+{
+    return ((uint64_t)c->link_cap << 32) ^ (uint64_t)c->refill_cap;
+}
+
+int lbm_geometry_bytes(const lbm_ctx* c, size_t* bytes, uint64_t* tag)
+{
+    if (!c || !bytes || !tag) return fail(const_cast<lbm_ctx*>(c), LBM_EINVAL, "null argument");
+    *bytes = geometry_layout(c).total;
+    *tag = geometry_tag(c);
+    return LBM_OK;
+}
+
+int lbm_geometry_save(lbm_ctx* c, void* dst_dev)
+{
+    if (!c || !dst_dev) return fail(c, LBM_EINVAL, "null argument");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (c->n_classify == 0) return fail(c, LBM_ESTATE, "classify before saving the geometry");
+    const int np = c->cfg.n_particles;
+    const GeometryLayout L = geometry_layout(c);
+    uint8_t* d = (uint8_t*)dst_dev;
+    CopyList cl{};
+    auto seg = [&](const void* src, size_t off, size_t bytes) {
+        cl.s[cl.n++] = CopySeg{(const uint8_t*)src, d + off, bytes};
+    };
+    seg(c->own[c->own_cur], L.own, c->sizes.owner_bytes);
+    seg(c->flag, L.flag, c->sizes.flag_bytes);
+    if (np > 0) {
+        const int slot = (int)((c->n_classify - 1) % 3);
+        seg(c->links, L.links, sizeof(LinkRec) * np * c->link_cap);
+        seg(c->link_cursor, L.cursors, sizeof(uint32_t) * kCursorPad * np);
+        seg(c->refill_cursor, L.refill_ctr, sizeof(uint32_t));
+        seg(c->refill, L.refill, sizeof(RefillRec) * c->refill_cap);
+        seg(c->ball_hist + (int64_t)slot * 4 * np, L.ball, sizeof(double) * 4 * np);
+    }
+    HIPCHK(c, copy_segments(c, cl));
+    return LBM_OK;
+}
+
+int lbm_geometry_load(lbm_ctx* c, const void* src_dev, uint64_t tag, const lbm_particles* P)
+{
+    if (!c || !src_dev) return fail(c, LBM_EINVAL, "null argument");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (tag != geometry_tag(c))
+        return fail(c, LBM_ESTATE, "lbm_geometry_load: the link or refill list capacity changed "
+                                   "since the snapshot was sized");
+    int rc = check_particles(c, P, false);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    const GeometryLayout L = geometry_layout(c);
+    const uint8_t* d = (const uint8_t*)src_dev;
+    const ClassifyPlan cp = classify_plan(c);
+    CopyList cl{};
+    auto seg = [&](void* dst, size_t off, size_t bytes) {
+        cl.s[cl.n++] = CopySeg{d + off, (uint8_t*)dst, bytes};
+    };
+    seg(cp.own_new, L.own, c->sizes.owner_bytes);
+    seg(c->flag, L.flag, c->sizes.flag_bytes);
+    if (np > 0) {
+        seg(c->links, L.links, sizeof(LinkRec) * np * c->link_cap);
+        seg(c->link_cursor, L.cursors, sizeof(uint32_t) * kCursorPad * np);
+        seg(c->refill_cursor, L.refill_ctr, sizeof(uint32_t));
+        seg(c->refill, L.refill, sizeof(RefillRec) * c->refill_cap);
+        seg(c->ball_hist + (int64_t)cp.slot * 4 * np, L.ball, sizeof(double) * 4 * np);
+        cl.s[cl.n++] = CopySeg{nullptr, (uint8_t*)c->err, sizeof(uint32_t)};  // a valid geometry
+    }
+    HIPCHK(c, copy_segments(c, cl));
+    if (np > 0) {
+        if (cp.k >= 1) {
+            PhaseTimer tm(c, LBM_PHASE_REFILL);
+            HIPCHK(c, LQ(c, launch_refill)(c, cp.refill_src, c->f[c->cur], cp.own_prev, to_dev(P)));
+        }
+        c->link_max = c->link_cap;  // lbm_step covers the whole capacity
+    } else {
+        c->link_max = c->link_total = c->refill_total = 0;
+    }
+    c->counts_known = false;
+    classify_commit(c, cp);
     return LBM_OK;
 }
 

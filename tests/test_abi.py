@@ -133,3 +133,7 @@ def test_calls_reject_a_null_context_without_touching_the_device(lib):
     assert lib.dem_step(None, ctypes.byref(p), 1, ctypes.c_double(0.1), ctypes.byref(prm)) == B.LBM_EINVAL
     assert lib.lbm_synchronize(None) == B.LBM_EINVAL
     assert b"null context" in lib.lbm_last_error(None)
+    n, tag = ctypes.c_size_t(), ctypes.c_uint64()
+    assert lib.lbm_geometry_bytes(None, ctypes.byref(n), ctypes.byref(tag)) == B.LBM_EINVAL
+    assert lib.lbm_geometry_save(None, None) == B.LBM_EINVAL
+    assert lib.lbm_geometry_load(None, None, 0, ctypes.byref(p)) == B.LBM_EINVAL

@@ -167,6 +167,40 @@ def test_taping_windows_leave_the_run_unchanged():
         np.testing.assert_array_equal(a, b)
 
 
+def test_geometry_snapshots_replay_the_classifications():
+    """A replay whose classifications are replaced by the geometry kept from
+    the first pass (lbm_geometry_save / lbm_geometry_load: owners, flags,
+    links, refilled nodes) has bit-identical populations and owners at every
+    step, refills included; a snapshot sized for other list capacities is
+    refused with ESTATE."""
+    prob = _problem("f32", steps=24, window=6)
+    states, f0 = prob.states(), prob.initial()
+    gpu = B.Lattice.for_particles(prob.lat, prob.ps, storage="f32", treatments=prob.treatments)
+    traj = B.DeviceTrajectory(states, vel=prob.ps.vel)
+    gpu.set_populations(f0)
+    gpu.classify(traj[0])
+    ck = gpu.checkpoint()
+    snaps, pops, owners, refills = [gpu.geometry_save()], [], [], 0
+    for k in range(24):
+        gpu.step(traj[k])
+        refills += gpu.classify(traj[k + 1]).n_refill
+        snaps.append(gpu.geometry_save())
+        pops.append(gpu.populations())
+        owners.append(gpu.owner().copy())
+    assert refills > 0
+    gpu.restore(ck)
+    gpu.geometry_load(snaps[0], traj[0])
+    for k in range(24):
+        gpu.step(traj[k])
+        gpu.geometry_load(snaps[k + 1], traj[k + 1])
+        np.testing.assert_array_equal(gpu.populations(), pops[k])
+        np.testing.assert_array_equal(gpu.owner(), owners[k])
+    with pytest.raises(B.LbmError) as e:
+        gpu.geometry_load((snaps[0][0], snaps[0][1] ^ 1), traj[0])
+    assert e.value.code == B.LBM_ESTATE
+    gpu.close()
+
+
 def test_autograd_function_returns_the_adjoint_gradient():
     import torch
     prob = _problem("f64", steps=20, window=8)
