@@ -374,7 +374,10 @@ int lbm_geometry_save(lbm_ctx* ctx, void* dst_dev);
  * as that classification did (nothing after lbm_checkpoint_load, as
  * lbm_classify_nodes).  tag: as returned by lbm_geometry_bytes when the
  * snapshot was sized; ESTATE when the list capacities changed since.  The
- * list counts are not read back (as lbm_classify_nodes_async).
+ * list counts are not read back (as lbm_classify_nodes_async).  A taped
+ * step (lbm_tape_begin) whose geometry was loaded records the snapshot's
+ * owners and links by reference instead of copying them: keep the snapshot
+ * until lbm_adjoint or lbm_adjoint_coupled has consumed the tape.
  * Asynchronous. */
 int lbm_geometry_load(lbm_ctx* ctx, const void* src_dev, uint64_t tag, const lbm_particles* P);
 

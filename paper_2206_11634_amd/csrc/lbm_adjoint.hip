@@ -786,13 +786,13 @@ struct RunAdj {
         using A = typename St<S>::A;
         if (parts & kAdjNode)
             hipLaunchKernelGGL(k_adj_node<S>, dim3(blocks_for(c->geom.ncell)), dim3(256), 0,
-                               c->stream, (const T*)ts.f, ts.own, own1, (const A*)lam1, (A*)lam0,
+                               c->stream, (const T*)ts.f, ts.own_use, own1, (const A*)lam1, (A*)lam0,
                                c->geom, c->phys, grad, list);
         if (parts & kAdjRefill) {
             // a grid that one round of resident workgroups covers
             const uint32_t nb = std::min<uint32_t>(blocks_for(list.cap), 512u);
             hipLaunchKernelGGL(k_adj_refill<S>, dim3(nb), dim3(256), 0, c->stream, (const T*)ts.f,
-                               ts.own, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom, c->phys,
+                               ts.own_use, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom, c->phys,
                                grad, ga, list);
         }
         if ((parts & kAdjLinks) && c->cfg.n_particles > 0 && ts.link_max > 0) {
@@ -800,12 +800,12 @@ struct RunAdj {
             dim3 grid(blocks_for(ts.link_max), np);
             if (ga.g_links)
                 hipLaunchKernelGGL((k_adj_links<S, true>), grid, dim3(256), 0, c->stream,
-                                   (const T*)ts.f, ts.links, ts.cursor, ts.link_cap, ts.part,
+                                   (const T*)ts.f, ts.links_use, ts.cursor, ts.link_cap, ts.part,
                                    ts.part + 3 * np, ts.part + 6 * np, (A*)lam0, wts, c->geom,
                                    c->phys, grad, ga);
             else
                 hipLaunchKernelGGL((k_adj_links<S, false>), grid, dim3(256), 0, c->stream,
-                                   (const T*)ts.f, ts.links, ts.cursor, ts.link_cap, ts.part,
+                                   (const T*)ts.f, ts.links_use, ts.cursor, ts.link_cap, ts.part,
                                    ts.part + 3 * np, ts.part + 6 * np, (A*)lam0, wts, c->geom,
                                    c->phys, grad, ga);
         }

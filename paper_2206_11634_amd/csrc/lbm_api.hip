@@ -190,9 +190,21 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
 {
     const int np = c->cfg.n_particles;
     TapeStep& t = c->tape[c->tape_len];
-    // the populations are already in t.f: lbm_step streams into the slots
+    // the populations are already in t.f: lbm_step streams into the slots;
+    // owners and links: a geometry snapshot's, or copies
+    if (c->geo_own) {
+        t.own_use = c->geo_own;
+        t.links_use = c->geo_links;
+        t.link_cap = c->link_cap;
+        t.link_max = c->link_max;
+        if (np > 0) HIPCHK(c, LQ(c, launch_tape_small)(c, t, P));
+        c->tape_len += 1;
+        return LBM_OK;
+    }
     HIPCHK(c, hipMemcpyAsync(t.own, c->own[c->own_cur], c->sizes.owner_bytes,
                              hipMemcpyDeviceToDevice, c->stream));
+    t.own_use = t.own;
+    t.links_use = t.links;
     if (np > 0) {
         const int64_t need = (int64_t)np * c->link_cap;
         if (t.link_alloc < need) {
@@ -202,6 +214,7 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
                 return fail(c, LBM_ENOMEM, "tape link allocation failed");
             t.link_alloc = need;
         }
+        t.links_use = t.links;
         t.link_cap = c->link_cap;
         t.link_max = c->link_max;
         if (c->link_max > 0)
@@ -533,6 +546,8 @@ int classify_enqueue(lbm_ctx* c, const PartDev& Pd, const ClassifyPlan& cp)
 
 void classify_commit(lbm_ctx* c, const ClassifyPlan& cp)
 {
+    c->geo_own = nullptr;
+    c->geo_links = nullptr;
     c->own_cur = (int)(cp.k % 2);
     c->n_classify = cp.k + 1;
     c->stepped_since_classify = false;
@@ -897,6 +912,8 @@ int lbm_checkpoint_load(lbm_ctx* c, const void* src_dev)
     c->n_classify = 0;
     c->own_cur = 0;
     c->stepped_since_classify = false;
+    c->geo_own = nullptr;
+    c->geo_links = nullptr;
     c->link_max = c->link_total = c->refill_total = c->cand_total = 0;
     return LBM_OK;
 }
@@ -1073,6 +1090,8 @@ int lbm_geometry_load(lbm_ctx* c, const void* src_dev, uint64_t tag, const lbm_p
     }
     c->counts_known = false;
     classify_commit(c, cp);
+    c->geo_own = reinterpret_cast<const uint32_t*>(d + L.own);
+    c->geo_links = np > 0 ? reinterpret_cast<const LinkRec*>(d + L.links) : nullptr;
     return LBM_OK;
 }
 
@@ -1187,7 +1206,7 @@ int lbm_adjoint(lbm_ctx* c, const lbm_particles* P, const double* weights, void*
     for (int s = c->tape_len - 1; s >= 0; --s) {
         const TapeStep& ts = c->tape[s];
         const bool last = s + 1 >= c->tape_len;
-        const uint32_t* own1 = last ? c->own[c->own_cur] : c->tape[s + 1].own;
+        const uint32_t* own1 = last ? c->own[c->own_cur] : c->tape[s + 1].own_use;
         const double* pos1 = last ? P->pos : c->tape[s + 1].part;
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;
@@ -1259,7 +1278,7 @@ int lbm_adjoint_coupled(lbm_ctx* c, const lbm_particles* P, const double* weight
     for (int s = c->tape_len - 1; s >= 0; --s) {
         const TapeStep& ts = c->tape[s];
         const bool last = s + 1 >= c->tape_len;
-        const uint32_t* own1 = last ? c->own[c->own_cur] : c->tape[s + 1].own;
+        const uint32_t* own1 = last ? c->own[c->own_cur] : c->tape[s + 1].own_use;
         const double* pos1 = last ? P->pos : c->tape[s + 1].part;
         const double* vel1 = last ? P->vel : c->tape[s + 1].part + 3 * np;
         const double* om1 = last ? P->omega : c->tape[s + 1].part + 6 * np;

@@ -80,6 +80,10 @@ struct TapeStep {
                                  // step: pair records [np][kPairSlots][8], wall records
                                  // [np][6][8], contact sums [np][6]
     int32_t* dem_key = nullptr;  // [np][kPairSlots] keys of the pair records
+    // the owners and links the adjoint reads: own and links, or those of the
+    // geometry snapshot the step's classification was loaded from
+    const uint32_t* own_use = nullptr;
+    const LinkRec* links_use = nullptr;
 };
 
 // Lattice geometry passed by value to kernels.
@@ -149,6 +153,9 @@ struct lbm_ctx {
     bool counts_known = true;   // the last classification's list counts were read back
     bool deferred = false;      // an asynchronous classification awaits its check
     bool stepped_since_classify = false;
+    // the current geometry was loaded from this snapshot's owners and links
+    const uint32_t* geo_own = nullptr;
+    const mdlbm::LinkRec* geo_links = nullptr;
     bool dense = false;     // particle balls cover most of the lattice: sweep it whole
     bool failed = false;
 
