@@ -217,11 +217,9 @@ __device__ void half_kick(const PartDev& P, int p, const double* FTh, const doub
 
 // First half kick, drift, rotation and world control points of particle p;
 // also its broad-phase reach and the reset of its contact sums.
-__global__ void k_first_half(PartDev P, const double* FTh, double* fc, double* reach_out, DemP c,
-                             double dt, Geom g)
+__device__ void first_half(const PartDev& P, int p, const double* FTh, double* fc,
+                           double* reach_out, const DemP& c, double dt, const Geom& g)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
     half_kick(P, p, FTh, fc, c, 0.5 * dt, false);
     for (int k = 0; k < 6; ++k) fc[6 * p + k] = 0.0;
     reach_out[p] = reach(P, p);
@@ -256,6 +254,14 @@ __global__ void k_first_half(PartDev P, const double* FTh, double* fc, double* r
         for (int a = 0; a < 3; ++a)
             P.wpts[3 * (int64_t)i + a] = P.pos[3 * p + a] + (R[3 * a] * b[0] + R[3 * a + 1] * b[1] + R[3 * a + 2] * b[2]);
     }
+}
+
+__global__ void k_first_half(PartDev P, const double* FTh, double* fc, double* reach_out, DemP c,
+                             double dt, Geom g)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    first_half(P, p, FTh, fc, reach_out, c, dt, g);
 }
 
 __device__ void wall_contact(const PartDev& P, int t, double* hist, double* fc, const double* rch,
@@ -404,11 +410,6 @@ __device__ __forceinline__ void pair_item(const PartDev& P, double* hist, double
                      rsi, rsj, P, c, dt, fc);
 }
 
-__global__ void k_zero_count(uint32_t* count)
-{
-    if (threadIdx.x == 0) count[0] = 0u;
-}
-
 // Whether pair (i, j) is a candidate of a dem_step call of duration T: the
 // centres are within the reach radii, R_s and a skin that covers the
 // relative displacement of the call, (|v_i| + |v_j|) T + 1/2 (velocities
@@ -437,9 +438,10 @@ __device__ bool pair_candidate(const PartDev& P, int i, int j, double T, const G
 // (zeroed, slot freed): one thread per (particle, slot).  A slot's key is
 // the partner's index + 1, 0 when free, so zeroed state is empty.
 __global__ __launch_bounds__(256) void k_pair_release(PartDev P, double* hist, int32_t* key,
-                                                      double T, Geom g)
+                                                      double T, Geom g, uint32_t* count)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (count && t == 0) *count = 0u;  // the pair list of this call starts empty
     if (t >= (int64_t)P.n * kPairSlots) return;
     const int j = key[t] - 1;
     if (j < 0) return;
@@ -492,15 +494,14 @@ __global__ __launch_bounds__(256) void k_pairs(PartDev P, int32_t* key, double T
 }
 
 // One substep's contacts: the walls of every body (6 n items), then the
-// listed pairs; grid-stride over both.
-__global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, double* hist_w, double* fc,
-                                                  const double* rch, DemP c, double dt, Geom g,
-                                                  const uint64_t* list, const uint32_t* count)
+// listed pairs; thread t of nthreads strides over both.
+__device__ void contacts(const PartDev& P, double* hist, double* hist_w, double* fc,
+                         const double* rch, const DemP& c, double dt, const Geom& g,
+                         const uint64_t* list, const uint32_t* count, int64_t t0, int64_t nthreads)
 {
     const int64_t nw = (int64_t)P.n * 6;
     const int64_t total = nw + (int64_t)*count;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = t0; t < total; t += nthreads) {
         if (t < nw) {
             wall_contact(P, (int)t, hist_w, fc, rch, c, dt, g);
         } else {
@@ -509,6 +510,14 @@ __global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, doubl
                       (int)(e >> 32));
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_contacts(PartDev P, double* hist, double* hist_w, double* fc,
+                                                  const double* rch, DemP c, double dt, Geom g,
+                                                  const uint64_t* list, const uint32_t* count)
+{
+    contacts(P, hist, hist_w, fc, rch, c, dt, g, list, count,
+             (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 // In-plane Newton for the point of the wall plane where M is largest, the
@@ -613,6 +622,18 @@ __global__ void k_second_half(PartDev P, const double* FTh, const double* fc, De
     half_kick(P, p, FTh, fc, c, 0.5 * dt, true);
 }
 
+// The second half kick of substep s and the first half of substep s + 1 of
+// particle p in one launch: both read the contact sum of substep s, which
+// the first half then clears.
+__global__ void k_between(PartDev P, const double* FTh, double* fc, double* reach_out, DemP c,
+                          double dt, Geom g)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    half_kick(P, p, FTh, fc, c, 0.5 * dt, true);
+    first_half(P, p, FTh, fc, reach_out, c, dt, g);
+}
+
 }  // namespace
 
 hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, const dem_params& prm,
@@ -637,20 +658,25 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
     const double T = (double)n_sub * dt;
     const uint32_t br = (uint32_t)(((int64_t)np * kPairSlots + 255) / 256);
     const uint32_t bq = (uint32_t)(((int64_t)np * np + 255) / 256);
-    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, ctx->stream, ws.count);
     hipLaunchKernelGGL(k_pair_release, dim3(br), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
-                       ctx->hist_key, T, ctx->geom);
+                       ctx->hist_key, T, ctx->geom, ws.count);
     hipLaunchKernelGGL(k_pairs, dim3(bq), dim3(256), 0, ctx->stream, P, ctx->hist_key, T,
                        ctx->geom, ws.pairs, ws.count, ctx->ctr + kCtrDeferred);
     const int64_t most = 6 * (int64_t)np + (int64_t)np * kPairSlots;
     const uint32_t bc = (uint32_t)std::min<int64_t>((most + 255) / 256, 1024);
+    // first half, then per substep the contacts and the two half kicks
+    // around the substep boundary in one launch
+    hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
+                       ws.reach, c, dt, ctx->geom);
     for (int s = 0; s < n_sub; ++s) {
-        hipLaunchKernelGGL(k_first_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
-                           ws.reach, c, dt, ctx->geom);
         hipLaunchKernelGGL(k_contacts, dim3(bc), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
                            ctx->hist_pw, ctx->fc, ws.reach, c, dt, ctx->geom, ws.pairs, ws.count);
-        hipLaunchKernelGGL(k_second_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
-                           c, dt);
+        if (s + 1 < n_sub)
+            hipLaunchKernelGGL(k_between, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT, ctx->fc,
+                               ws.reach, c, dt, ctx->geom);
+        else
+            hipLaunchKernelGGL(k_second_half, dim3(bp), dim3(64), 0, ctx->stream, P, ctx->FT,
+                               ctx->fc, c, dt);
     }
     return hipGetLastError();
 }
