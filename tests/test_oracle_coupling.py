@@ -247,3 +247,53 @@ def test_rotating_sphere_stokes_torque():
     ratio = T[0, 2] / (-8 * np.pi * nu * r ** 3 * w[2])
     assert 1.0 < ratio < 1.03, ratio
     assert np.abs(T[0, :2]).max() < 1e-3 * abs(T[0, 2])
+
+
+def _light_sphere_on_the_floor(tau, steps=1500, two_step_force=False):
+    """A sphere (d = 14.65, density ratio 1.29) settling onto the floor of a
+    closed 48x40x40 box under relative gravity (the floor pair's setting with
+    one body), treatments 1 + 2, the oracle's coupled loop.  With
+    two_step_force the DEM is handed the mean of the last two steps' forces
+    (a diagnosis, not the method).  Returns the lowest height, the rise after
+    it and the largest step-to-step change of the vertical fluid force, in
+    units of the submerged weight W."""
+    lat = W.LatticeSpec(48, 40, 40, (0, 0, 0), tau=tau)
+    ps = W.make_particles([W.sphere_shape(14.65, 0.1)], [[24.0, 20.2, 8.0]], [[1.0, 0, 0, 0]],
+                          1.29)
+    o = O.Oracle(lat, treat=3)
+    dem = O.OracleDEM(ps, lat)
+    prm = O.DemParams(**W.dem_defaults(ps, gravity=(0.0, 0.0, -3.92e-4)))
+    Wsub = (ps.mass[0] - ps.volume[0]) * 3.92e-4
+    z, F, prev = [], [], None
+    for _ in range(steps):
+        o.classify(ps)
+        Fh, Th = o.step(ps)
+        Fd = Fh if (not two_step_force or prev is None) else 0.5 * (Fh + prev)
+        prev = Fh.copy()
+        dem.step(ps, Fd, Th, prm, 10, 0.1)
+        z.append(ps.pos[0, 2])
+        F.append(Fh[0, 2] / Wsub)
+    z, F = np.array(z), np.array(F)
+    k = int(np.argmin(z))
+    return z.min(), z[k:].max() - z.min(), np.abs(np.diff(F)).max()
+
+
+@pytest.mark.slow
+def test_a_light_body_hops_off_the_floor_by_a_period_two_force_mode_near_tau_one_half():
+    """What makes light bodies resting on a wall hop (a property of the
+    method, which the oracle shares with the GPU path).  At the paper's tau
+    = 0.5453 the light sphere hovers with its lowest point between the wall
+    plane and the first node row, and the momentum exchange at the gap's
+    links alternates in sign from step to step (BGK over-relaxation: the
+    non-equilibrium part flips sign with factor 1 - 1/tau = -0.83 per step)
+    with growing amplitude, fed by the body's own response; its mean lifts
+    the body about 1.5 lu.  At tau = 0.8 (factor -0.25) the alternation dies
+    out and the sphere settles into wall contact; so it does at tau = 0.5453
+    when the DEM is handed the mean of two consecutive steps' forces, which
+    cancels the period-two part."""
+    zmin, rise, jump = _light_sphere_on_the_floor(0.5453)
+    assert rise > 1.0 and jump > 20.0, (zmin, rise, jump)
+    zmin, rise, jump = _light_sphere_on_the_floor(0.8)
+    assert rise < 0.05 and jump < 1.0, (zmin, rise, jump)
+    zmin, rise, jump = _light_sphere_on_the_floor(0.5453, two_step_force=True)
+    assert rise < 0.05 and jump < 1.0, (zmin, rise, jump)
