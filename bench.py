@@ -48,22 +48,27 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=
     n_sub = int(meta.get("n_sub", 10))
     gpu.classify(parts)
 
-    def one_step():
+    def one_step(sync):
         gpu.step(parts)
         gpu.forces()
         gpu.dem(parts, n_sub, 1.0 / n_sub, prm)
-        gpu.classify(parts)
+        # timed steps classify without the host read-back of list counts
+        # (lbm_classify_nodes_async); the warm-up steps, which read them back,
+        # sized the lists, and the check after the loop reports anything the
+        # timed classifications latched
+        gpu.classify(parts, sync=sync)
 
     for _ in range(warmup):
-        one_step()
+        one_step(True)
     torch.cuda.synchronize()
     if profile:
         gpu.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        one_step()
+        one_step(False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gpu.sync()   # raises on a latched overflow, rejected particle or non-finite force
     prof = gpu.profile_read() if profile else {}
     if profile:
         gpu.profile(False)
