@@ -398,6 +398,13 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
                            c->stream);
     }
     if (e == hipSuccess && np) e = alloc(&c->cand, (size_t)np * c->cand_cap);
+    if (e == hipSuccess && np && c->dense) {
+        c->cand_prev_cap = c->cand_cap;
+        e = alloc(&c->cand_prev, (size_t)np * c->cand_prev_cap);
+        if (e == hipSuccess) e = alloc(&c->cand_prev_count, (size_t)np);
+        if (e == hipSuccess) e = alloc(&c->quat_prev, (size_t)4 * np);
+        if (e == hipSuccess) e = hipMemsetAsync(c->cand_prev_count, 0, sizeof(uint32_t) * np, c->stream);
+    }
     if (e == hipSuccess && np) e = alloc(&c->links, (size_t)np * c->link_cap);
     if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
     if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
@@ -453,6 +460,9 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->refill);
     (void)hipFree(c->ctr);
     (void)hipFree(c->FT);
+    (void)hipFree(c->cand_prev);
+    (void)hipFree(c->cand_prev_count);
+    (void)hipFree(c->quat_prev);
     (void)hipFree(c->fc);
     (void)hipFree(c->reach);
     for (auto& t : c->tape) {
@@ -499,6 +509,7 @@ struct ClassifyPlan {
     uint32_t* own_new;
     const uint32_t* own_prev;
     const void* refill_src;
+    bool inc;  // dense mode: flags and refills from the previous candidate lists
 };
 
 ClassifyPlan classify_plan(const lbm_ctx* c)
@@ -512,6 +523,7 @@ ClassifyPlan classify_plan(const lbm_ctx* c)
     cp.own_prev = c->own[(cp.k + 1) % 2];
     // populations of the time level the previous classification describes
     cp.refill_src = c->stepped_since_classify ? c->f[1 - c->cur] : c->f[c->cur];
+    cp.inc = c->dense && cp.k >= 1 && c->inc_ok && c->cfg.n_particles > 0 && c->cand_prev;
     return cp;
 }
 
@@ -520,19 +532,34 @@ ClassifyPlan classify_plan(const lbm_ctx* c)
 int classify_enqueue(lbm_ctx* c, const PartDev& Pd, const ClassifyPlan& cp)
 {
     const int np = c->cfg.n_particles;
+    if (c->dense && c->cand_prev) {
+        // this classification's candidates go into the other list (which
+        // holds those of two classifications ago, no longer needed: it is
+        // grown first if the lists grew since); the counter reset keeps the
+        // counts of the lists just set aside
+        if (c->cand_prev_cap < c->cand_cap) {
+            HIPCHK(c, hipFree(c->cand_prev));
+            c->cand_prev = nullptr;
+            c->cand_prev_cap = c->cand_cap;
+            if (alloc(&c->cand_prev, (size_t)np * c->cand_prev_cap) != hipSuccess)
+                return fail(c, LBM_ENOMEM, "candidate list allocation failed");
+        }
+        std::swap(c->cand, c->cand_prev);
+        std::swap(c->cand_cap, c->cand_prev_cap);
+    }
     HIPCHK(c, LQ(c, launch_reset_counters)(c));
     // the boxes' check is read back with the list counts; the kernels that
     // write the owner planes, flags and lists do nothing when it failed, so
     // the context keeps its current geometry
-    HIPCHK(c, LQ(c, launch_boxes)(c, Pd, cp.slot));
+    HIPCHK(c, LQ(c, launch_boxes)(c, Pd, cp.slot, cp.slot_prev, cp.inc || (c->dense && np > 0)));
     {
         PhaseTimer tm(c, LBM_PHASE_CLASSIFY);
         if (cp.k >= 2) HIPCHK(c, LQ(c, launch_clear_boxes)(c, cp.own_new, cp.slot_prev2, np));
-        HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot));
+        HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot, cp.inc));
         // the lattice sweep also runs on a first classification (own_prev
         // is all fluid then): in dense mode it writes every flag
         if (cp.k >= 1 || c->dense)
-            HIPCHK(c, LQ(c, launch_finish)(c, cp.own_prev, cp.own_new, cp.slot_prev, np));
+            HIPCHK(c, LQ(c, launch_finish)(c, cp.own_prev, cp.own_new, cp.slot_prev, np, cp.inc));
         HIPCHK(c, LQ(c, launch_links)(c, cp.own_new, Pd, cp.slot));
     }
     if (cp.k >= 1) {
@@ -546,6 +573,7 @@ int classify_enqueue(lbm_ctx* c, const PartDev& Pd, const ClassifyPlan& cp)
 
 void classify_commit(lbm_ctx* c, const ClassifyPlan& cp)
 {
+    c->inc_ok = c->dense;  // its candidate lists and orientations are kept
     c->geo_own = nullptr;
     c->geo_links = nullptr;
     c->own_cur = (int)(cp.k % 2);
@@ -651,7 +679,7 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 if (alloc(&c->cand, (size_t)np * c->cand_cap) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "candidate list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->cand_cursor, 0, cur_bytes, c->stream));
-                HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot));  // same owners, full list
+                HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot, cp.inc));  // same owners, full list
             }
             if (grow_links) {
                 HIPCHK(c, hipFree(c->links));
@@ -672,7 +700,8 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                     return fail(c, LBM_ENOMEM, "refill list allocation failed");
                 HIPCHK(c, hipMemsetAsync(c->refill_cursor, 0, sizeof(uint32_t), c->stream));
                 if (k >= 1) {
-                    HIPCHK(c, LQ(c, launch_finish)(c, cp.own_prev, cp.own_new, cp.slot_prev, np));
+                    HIPCHK(c, LQ(c, launch_finish)(c, cp.own_prev, cp.own_new, cp.slot_prev, np,
+                                                   cp.inc));
                     PhaseTimer tm(c, LBM_PHASE_REFILL);
                     HIPCHK(c, LQ(c, launch_refill)(c, cp.refill_src, c->f[c->cur], cp.own_prev, Pd));
                 }
@@ -914,6 +943,7 @@ int lbm_checkpoint_load(lbm_ctx* c, const void* src_dev)
     c->stepped_since_classify = false;
     c->geo_own = nullptr;
     c->geo_links = nullptr;
+    c->inc_ok = false;
     c->link_max = c->link_total = c->refill_total = c->cand_total = 0;
     return LBM_OK;
 }
@@ -1090,6 +1120,7 @@ int lbm_geometry_load(lbm_ctx* c, const void* src_dev, uint64_t tag, const lbm_p
     }
     c->counts_known = false;
     classify_commit(c, cp);
+    c->inc_ok = false;  // the candidate lists and orientations are not the snapshot's
     c->geo_own = reinterpret_cast<const uint32_t*>(d + L.own);
     c->geo_links = np > 0 ? reinterpret_cast<const LinkRec*>(d + L.links) : nullptr;
     return LBM_OK;

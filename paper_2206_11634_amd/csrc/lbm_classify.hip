@@ -189,7 +189,9 @@ __device__ __forceinline__ double wave_sum_d(double v)
 }
 
 // One wave per particle, a lane per control point (n <= 64).
-__global__ __launch_bounds__(64) void k_boxes(PartDev P, int h, double* ball, uint32_t* err, Geom g)
+__global__ __launch_bounds__(64) void k_boxes(PartDev P, int h, double* ball, uint32_t* err, Geom g,
+                                             const double* ball_prev, double* quat_prev,
+                                             uint32_t* inc_bad)
 {
     const int p = blockIdx.x;
     const int lane = threadIdx.x;
@@ -260,6 +262,30 @@ __global__ __launch_bounds__(64) void k_boxes(PartDev P, int h, double* ball, ui
         ball[4 * p + 2] = xp[2];
         ball[4 * p + 3] = R + 1e-6;
         if (bad) atomicOr(err, bad);
+        if (inc_bad) {
+            // how far a body point within R + 2 of the centre moved since the
+            // previous classification: the centre's displacement plus
+            // (R + 2) times the rotation angle between the two orientations
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double d = xp[a] - ball_prev[4 * p + a];
+                if (g.per[a]) {
+                    if (d > 0.5 * g.n[a]) d -= g.n[a];
+                    else if (d < -0.5 * g.n[a]) d += g.n[a];
+                }
+                d2 += d * d;
+            }
+            const double* q = P.quat + 4 * p;
+            double* qp = quat_prev + 4 * p;
+            const double dot = fabs(q[0] * qp[0] + q[1] * qp[1] + q[2] * qp[2] + q[3] * qp[3]);
+            const double ang = 2.0 * acos(fmin(1.0, dot));
+            const double D = sqrt(d2) + (R + 2.0) * ang;
+            // a solid node off the candidate list has M >= c0 wherever within
+            // the lattice's largest |e| of it; a node moved by less than that
+            // stays solid
+            if (!(D < 0.9 * (double)kMaxSpeedUp - 1e-3)) atomicOr(inc_bad, 1u);
+            for (int a = 0; a < 4; ++a) qp[a] = q[a];
+        }
     }
 }
 
@@ -701,9 +727,11 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
 // and a coalesced sweep is cheaper.
 __global__ __launch_bounds__(256) void k_finish_all(const uint32_t* __restrict__ err, const uint32_t* own_prev,
                                                     const uint32_t* own_new, Geom g, uint8_t* flag,
-                                                    RefillRec* rec, int64_t cap, uint32_t* cursor)
+                                                    RefillRec* rec, int64_t cap, uint32_t* cursor,
+                                                    const uint32_t* inc_bad)
 {
     if (*err) return;  // the boxes failed their check: leave every plane as it is
+    if (inc_bad && *inc_bad == 0u) return;  // the candidate pass did the work
     const uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u;
     uint32_t on[4] = {kFluid, kFluid, kFluid, kFluid}, op[4] = {kFluid, kFluid, kFluid, kFluid};
     if (base + 3u < g.ncell) {
@@ -736,15 +764,55 @@ __global__ __launch_bounds__(256) void k_finish_all(const uint32_t* __restrict__
         }
 }
 
+// Dense mode, bodies moved less than the guard of k_boxes: the flags of the
+// nodes that left a body and the refill list, from the previous
+// classification's candidate lists (a node solid then and fluid now was
+// within reach of the old surface, hence a candidate).  New solid nodes got
+// their flag from k_mark.  One workgroup per (chunk, particle).
+__global__ __launch_bounds__(256) void k_finish_cand(const uint32_t* __restrict__ err,
+                                                     const uint32_t* __restrict__ inc_bad,
+                                                     const uint32_t* __restrict__ own_prev,
+                                                     const uint32_t* __restrict__ own_new,
+                                                     const uint32_t* __restrict__ cand,
+                                                     int64_t cand_cap,
+                                                     const uint32_t* __restrict__ counts,
+                                                     uint8_t* flag, RefillRec* rec, int64_t cap,
+                                                     uint32_t* cursor)
+{
+    if (*err || *inc_bad) return;  // the lattice sweep does the work
+    const int p = blockIdx.y;
+    const uint32_t cnt = min((uint32_t)cand_cap, counts[p]);
+    for (uint32_t i0 = blockIdx.x * 256u; i0 < cnt; i0 += gridDim.x * 256u) {
+        const uint32_t i = i0 + threadIdx.x;
+        bool left = false;
+        uint32_t node = 0;
+        if (i < cnt) {
+            node = cand[(int64_t)p * cand_cap + i];
+            // a node in two bodies is on both lists: its owner's list takes it
+            left = own_prev[node] == (uint32_t)p && own_new[node] == kFluid;
+            if (left) flag[node] = 0;
+        }
+        uint32_t slot = wave_reserve(left ? 1u : 0u, cursor);
+        if (left && slot < cap) {
+            rec[slot].node = node;
+            rec[slot].part = (uint32_t)p;
+        }
+    }
+}
+
 // Zero the counters a classification fills: the refill count, the box check
 // and the first word of every link and candidate cursor line (the
 // non-finite force flag is left for the classification to report).
-__global__ void k_reset_counters(uint32_t* ctr, int np)
+__global__ void k_reset_counters(uint32_t* ctr, int np, uint32_t* cand_prev_count)
 {
     const int i = (int)(blockIdx.x * 256u + threadIdx.x);
+    // the candidate counts of the previous classification, kept for its lists
+    if (cand_prev_count && i >= np && i < 2 * np)
+        cand_prev_count[i - np] = ctr[kStageHead + (int64_t)i * kCursorPad];
     if (i == 0) {
         ctr[kCtrRefill] = 0;
         ctr[kCtrErr] = 0;
+        ctr[kCtrIncremental] = 0;
     }
     if (i < 2 * np) ctr[kStageHead + (int64_t)i * kCursorPad] = 0;
 }
@@ -799,12 +867,14 @@ inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + 255) / 256); }
 
 namespace MDLBM_QNS {
 
-hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot)
+hipError_t launch_boxes(lbm_ctx* c, const PartDev& P, int slot, int slot_prev, bool inc)
 {
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_boxes, dim3(np), dim3(64), 0, c->stream, P, c->box.h,
-                       c->ball_hist + (int64_t)slot * 4 * np, c->err, c->geom);
+                       c->ball_hist + (int64_t)slot * 4 * np, c->err, c->geom,
+                       c->ball_hist + (int64_t)slot_prev * 4 * np, c->quat_prev,
+                       inc ? c->ctr + kCtrIncremental : nullptr);
     return hipGetLastError();
 }
 
@@ -818,25 +888,38 @@ hipError_t launch_clear_boxes(lbm_ctx* c, uint32_t* own, int slot, int np)
     return hipGetLastError();
 }
 
-hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot)
+hipError_t launch_mark(lbm_ctx* c, uint32_t* own, const PartDev& P, int slot, bool inc)
 {
     const int np = c->cfg.n_particles;
     if (np == 0) return hipSuccess;
-    // in dense mode the lattice sweep of k_finish_all writes every flag
+    // in dense mode the lattice sweep of k_finish_all writes every flag,
+    // unless the candidate pass runs (then the solid nodes' flags come from
+    // here)
     hipLaunchKernelGGL(k_mark, dim3(c->box.S, np), dim3(256), 0, c->stream, c->err, own,
                        c->ball_hist + (int64_t)slot * 4 * np, c->box.h, P, c->geom, c->flag,
-                       c->dense ? 0 : 1, c->cand, c->cand_cap, c->cand_cursor);
+                       (c->dense && !inc) ? 0 : 1, c->cand, c->cand_cap, c->cand_cursor);
     return hipGetLastError();
 }
 
 hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* own_new, int slot,
-                         int np_prev)
+                         int np_prev, bool inc)
 {
     if (np_prev == 0) return hipSuccess;
     if (c->dense) {
+        if (inc) {
+            // the candidate pass, or, should k_boxes have found a body that
+            // moved too far, the lattice sweep (each kernel checks the word)
+            const uint32_t nb = (uint32_t)std::min<int64_t>(
+                std::max<int64_t>(1, (c->cand_prev_cap + 255) / 256), 64);
+            hipLaunchKernelGGL(k_finish_cand, dim3(nb, np_prev), dim3(256), 0, c->stream, c->err,
+                               c->ctr + kCtrIncremental, own_prev, own_new, c->cand_prev,
+                               c->cand_prev_cap, c->cand_prev_count, c->flag, c->refill,
+                               c->refill_cap, c->refill_cursor);
+        }
         hipLaunchKernelGGL(k_finish_all, dim3(blocks_for((c->geom.ncell + 3) / 4)), dim3(256), 0,
                            c->stream, c->err, own_prev, own_new, c->geom, c->flag, c->refill,
-                           c->refill_cap, c->refill_cursor);
+                           c->refill_cap, c->refill_cursor,
+                           inc ? c->ctr + kCtrIncremental : nullptr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_finish, dim3(c->box.S, np_prev), dim3(256), 0, c->stream, c->err, own_prev,
@@ -866,7 +949,7 @@ hipError_t launch_reset_counters(lbm_ctx* c)
 {
     const int np = c->cfg.n_particles;
     hipLaunchKernelGGL(k_reset_counters, dim3(blocks_for(2 * (int64_t)std::max(np, 1))), dim3(256), 0,
-                       c->stream, c->ctr, np);
+                       c->stream, c->ctr, np, c->cand_prev_count);
     return hipGetLastError();
 }
 

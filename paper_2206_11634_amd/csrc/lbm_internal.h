@@ -33,6 +33,11 @@ constexpr uint32_t kDeferredOverflow = 0x100u;
 // linked to it through broad-phase candidate pairs of one dem_step call)
 // has more than kAdjCluster members.
 constexpr int kCtrAdjCluster = 4;
+// Set by the boxes' kernel when a particle moved too far since the previous
+// classification for the candidate-list flag and refill pass (every node
+// that leaves a body was on its previous candidate list); the lattice sweep
+// then writes flags and refills instead.
+constexpr int kCtrIncremental = 5;
 // Latched by dem_step when a particle had more candidate contact partners
 // than its history slots (reported like the asynchronous classifications).
 constexpr uint32_t kDeferredSlots = 0x200u;
@@ -165,6 +170,13 @@ struct lbm_ctx {
     uint32_t* cand = nullptr;     // per particle: nodes that may carry links
     int64_t cand_cap = 0;         // per particle
     uint32_t* cand_cursor = nullptr;  // [np * kCursorPad]
+    // dense mode: the previous classification's candidate lists and counts,
+    // and the orientations it saw, for the flag and refill pass over them
+    uint32_t* cand_prev = nullptr;
+    int64_t cand_prev_cap = 0;
+    uint32_t* cand_prev_count = nullptr;  // [np]
+    double* quat_prev = nullptr;          // [np][4]
+    bool inc_ok = false;                  // the previous classification's lists are valid
     mdlbm::LinkRec* links = nullptr;
     int64_t link_cap = 0;         // per particle
     uint32_t* link_cursor = nullptr;  // [np * kCursorPad]
