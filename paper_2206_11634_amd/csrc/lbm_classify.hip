@@ -732,36 +732,40 @@ __global__ __launch_bounds__(256) void k_finish_all(const uint32_t* __restrict__
 {
     if (*err) return;  // the boxes failed their check: leave every plane as it is
     if (inc_bad && *inc_bad == 0u) return;  // the candidate pass did the work
-    const uint32_t base = (blockIdx.x * 256u + threadIdx.x) * 4u;
-    uint32_t on[4] = {kFluid, kFluid, kFluid, kFluid}, op[4] = {kFluid, kFluid, kFluid, kFluid};
-    if (base + 3u < g.ncell) {
-        const uint4 a = *reinterpret_cast<const uint4*>(own_new + base);
-        const uint4 b = *reinterpret_cast<const uint4*>(own_prev + base);
-        on[0] = a.x, on[1] = a.y, on[2] = a.z, on[3] = a.w;
-        op[0] = b.x, op[1] = b.y, op[2] = b.z, op[3] = b.w;
-        *reinterpret_cast<uchar4*>(flag + base) =
-            make_uchar4(on[0] != kFluid, on[1] != kFluid, on[2] != kFluid, on[3] != kFluid);
-    } else {
+    // grid-stride over groups of four nodes (a bounded grid: when the
+    // candidate pass did the work, its workgroups only read the word above)
+    for (uint32_t base0 = blockIdx.x * 1024u; base0 < g.ncell; base0 += gridDim.x * 1024u) {
+        const uint32_t base = base0 + threadIdx.x * 4u;
+        uint32_t on[4] = {kFluid, kFluid, kFluid, kFluid}, op[4] = {kFluid, kFluid, kFluid, kFluid};
+        if (base + 3u < g.ncell) {
+            const uint4 a = *reinterpret_cast<const uint4*>(own_new + base);
+            const uint4 b = *reinterpret_cast<const uint4*>(own_prev + base);
+            on[0] = a.x, on[1] = a.y, on[2] = a.z, on[3] = a.w;
+            op[0] = b.x, op[1] = b.y, op[2] = b.z, op[3] = b.w;
+            *reinterpret_cast<uchar4*>(flag + base) =
+                make_uchar4(on[0] != kFluid, on[1] != kFluid, on[2] != kFluid, on[3] != kFluid);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (base + k < g.ncell) {
+                    on[k] = own_new[base + k];
+                    op[k] = own_prev[base + k];
+                    flag[base + k] = on[k] != kFluid;
+                }
+        }
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cnt += (op[k] != kFluid && on[k] == kFluid) ? 1u : 0u;
+        uint32_t slot = wave_reserve(cnt, cursor);
+#pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (base + k < g.ncell) {
-                on[k] = own_new[base + k];
-                op[k] = own_prev[base + k];
-                flag[base + k] = on[k] != kFluid;
+            if (op[k] != kFluid && on[k] == kFluid) {
+                if (slot < cap) {
+                    rec[slot].node = base + k;
+                    rec[slot].part = op[k];
+                }
+                ++slot;
             }
     }
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cnt += (op[k] != kFluid && on[k] == kFluid) ? 1u : 0u;
-    uint32_t slot = wave_reserve(cnt, cursor);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (op[k] != kFluid && on[k] == kFluid) {
-            if (slot < cap) {
-                rec[slot].node = base + k;
-                rec[slot].part = op[k];
-            }
-            ++slot;
-        }
 }
 
 // Dense mode, bodies moved less than the guard of k_boxes: the flags of the
@@ -916,7 +920,9 @@ hipError_t launch_finish(lbm_ctx* c, const uint32_t* own_prev, const uint32_t* o
                                c->cand_prev_cap, c->cand_prev_count, c->flag, c->refill,
                                c->refill_cap, c->refill_cursor);
         }
-        hipLaunchKernelGGL(k_finish_all, dim3(blocks_for((c->geom.ncell + 3) / 4)), dim3(256), 0,
+        // 2048 workgroups (eight per compute unit) stride over the lattice
+        const uint32_t nb = (uint32_t)std::min<int64_t>(((int64_t)c->geom.ncell + 1023) / 1024, 2048);
+        hipLaunchKernelGGL(k_finish_all, dim3(nb), dim3(256), 0,
                            c->stream, c->err, own_prev, own_new, c->geom, c->flag, c->refill,
                            c->refill_cap, c->refill_cursor,
                            inc ? c->ctr + kCtrIncremental : nullptr);
