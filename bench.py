@@ -49,9 +49,10 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=
     gpu.classify(parts)
 
     def one_step(sync):
-        gpu.step(parts)
+        # the link pass, then the stream-collide pass with the DEM sub-cycle
+        # beside it (lbm_step_dem: the same results as lbm_step, dem_step)
+        gpu.step_dem(parts, n_sub, 1.0 / n_sub, prm)
         gpu.forces()
-        gpu.dem(parts, n_sub, 1.0 / n_sub, prm)
         # timed steps classify without the host read-back of list counts
         # (lbm_classify_nodes_async); the warm-up steps, which read them back,
         # sized the lists, and the check after the loop reports anything the
@@ -505,7 +506,7 @@ def main():
             "tau": lat.tau,
             "treatments": int(meta.get("treatments", 3)),
             "dem_substeps": meta.get("n_sub", 10),
-            "step": "classify + step + forces + dem",
+            "step": "classify + step with the dem sub-cycle beside its stream-collide pass + forces",
         },
         "fluid_mlups": round(nfluid / (main_res["ms_per_step"] * 1e-3) / 1e6, 1),
         "phase_ms_per_launch": phases,

@@ -264,6 +264,21 @@ int lbm_particle_forces(const lbm_ctx* ctx, double* F_dev, double* T_dev);
  * lbm_classify_nodes.  Allocates nothing.  Asynchronous. */
 int dem_step(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_params* prm);
 
+/* lbm_step followed by dem_step, with the DEM sub-cycle (which needs only
+ * the step's F^h and T^h, Sec. 2.3.4) running beside the stream-collide pass
+ * instead of after it: the link pass and the force sums on the context's
+ * stream, then the stream-collide pass and the n_sub DEM substeps on two
+ * streams of the library's own (default priority; the DEM's on two compute
+ * units of each XCD, the stream-collide's on the rest), and the context's
+ * stream waits for both.  The populations, forces, particle state and
+ * contact histories are those of lbm_step then dem_step.  While taping (the
+ * step's output goes to the tape), with no particles or before the first
+ * classification it runs the two calls one after the other.  The two streams
+ * and three events are made on the first call (EDEVICE if that fails) and
+ * kept until lbm_destroy.  Argument checks and errors: those of lbm_step
+ * and dem_step.  Asynchronous. */
+int lbm_step_dem(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_params* prm);
+
 /* dem_step for callers that cannot allocate device memory or use memory the
  * library allocated after lbm_init (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc): the same substeps and results,

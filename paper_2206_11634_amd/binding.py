@@ -90,7 +90,7 @@ EXPORTS = ["lbm_query_sizes", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_
            "lbm_profile_enable", "lbm_profile_read", "lbm_checkpoint_save", "lbm_checkpoint_load",
            "lbm_tape_begin", "lbm_adjoint", "lbm_adjoint_coupled", "lbm_get_moments",
            "lbm_dem_checkpoint_save", "lbm_dem_checkpoint_load", "dem_step_noalloc",
-           "lbm_geometry_bytes", "lbm_geometry_save", "lbm_geometry_load"]
+           "lbm_geometry_bytes", "lbm_geometry_save", "lbm_geometry_load", "lbm_step_dem"]
 
 _lib = None
 
@@ -119,6 +119,8 @@ def load(path: Path | None = None):
                      ctypes.POINTER(DemParams)],
         "dem_step_noalloc": [_P, ctypes.POINTER(LbmParticles), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(DemParams)],
+        "lbm_step_dem": [_P, ctypes.POINTER(LbmParticles), ctypes.c_int, ctypes.c_double,
+                         ctypes.POINTER(DemParams)],
         "lbm_get_links": [_P, ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)],
         "lbm_get_refill": [_P, ctypes.c_int64, _P, _P, ctypes.POINTER(ctypes.c_int64)],
         "lbm_get_owner": [_P, _P],
@@ -218,6 +220,11 @@ def dem_step(ctx, parts: LbmParticles, n_sub: int, dt: float, prm: DemParams):
 def dem_step_noalloc(ctx, parts: LbmParticles, n_sub: int, dt: float, prm: DemParams):
     _check(load().dem_step_noalloc(ctx, ctypes.byref(parts), int(n_sub), float(dt),
                                    ctypes.byref(prm)), ctx)
+
+
+def lbm_step_dem(ctx, parts: LbmParticles, n_sub: int, dt: float, prm: DemParams):
+    _check(load().lbm_step_dem(ctx, ctypes.byref(parts), int(n_sub), float(dt),
+                               ctypes.byref(prm)), ctx)
 
 
 def lbm_synchronize(ctx):
@@ -372,6 +379,11 @@ class Lattice:
 
     def dem(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
         dem_step(self.ctx, parts.struct, n_sub, dt, prm)
+
+    def step_dem(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
+        """lbm_step_dem: the step, with the DEM sub-cycle beside its
+        stream-collide pass."""
+        lbm_step_dem(self.ctx, parts.struct, n_sub, dt, prm)
 
     def dem_noalloc(self, parts: DeviceParticles, n_sub: int, dt: float, prm: DemParams):
         """dem_step_noalloc: the same substeps with the static work space."""

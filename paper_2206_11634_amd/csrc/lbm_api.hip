@@ -119,6 +119,48 @@ struct PhaseTimer {
     }
 };
 
+// Runs the launchers of a scope on another stream of the context.
+struct OnStream {
+    lbm_ctx* c;
+    hipStream_t saved;
+    OnStream(lbm_ctx* ctx, hipStream_t s) : c(ctx), saved(ctx->stream) { c->stream = s; }
+    ~OnStream() { c->stream = saved; }
+};
+
+// The two streams of lbm_step_dem.  The DEM kernels are latency-bound and
+// need few compute units; the stream-collide pass is bound by HBM and keeps
+// its rate on fewer.  kDemUnits units of each XCD go to the DEM: mask bit i
+// is unit i, and the bits 33x + 8m (x = 0..7, m < kDemUnits <= 4) fall on
+// XCD x whether the runtime deals the bits out to the XCDs in runs of 32 or
+// in turn.  Both streams have the default priority.
+#ifndef MDLBM_DEM_UNITS
+#define MDLBM_DEM_UNITS 2
+#endif
+constexpr int kDemUnits = MDLBM_DEM_UNITS;
+static_assert(kDemUnits >= 1 && kDemUnits <= 4, "one to four units per XCD");
+int overlap_streams(lbm_ctx* c)
+{
+    if (c->s_bulk) return LBM_OK;
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+    const int ncu = prop.multiProcessorCount;
+    if (ncu < 64) return fail(c, LBM_EDEVICE, "lbm_step_dem needs at least 64 compute units");
+    const int words = (ncu + 31) / 32;
+    std::vector<uint32_t> bulk((size_t)words, 0u), dem((size_t)words, 0u);
+    for (int i = 0; i < ncu; ++i) bulk[(size_t)(i / 32)] |= 1u << (i % 32);
+    for (int x = 0; x < 8; ++x)
+        for (int m = 0; m < kDemUnits; ++m)
+            if (const int i = 33 * x + 8 * m; i < ncu) {
+                dem[(size_t)(i / 32)] |= 1u << (i % 32);
+                bulk[(size_t)(i / 32)] &= ~(1u << (i % 32));
+            }
+    HIPCHK(c, hipExtStreamCreateWithCUMask(&c->s_bulk, (uint32_t)words, bulk.data()));
+    HIPCHK(c, hipExtStreamCreateWithCUMask(&c->s_dem, (uint32_t)words, dem.data()));
+    for (hipEvent_t* e : {&c->ev_fork, &c->ev_bulk, &c->ev_dem})
+        HIPCHK(c, hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return LBM_OK;
+}
+
 std::string err_text(uint32_t bits)
 {
     std::string s;
@@ -483,6 +525,13 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->pair_count);
     (void)hipFree(c->hist_pw);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
+    for (hipStream_t s : {c->s_bulk, c->s_dem})
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    for (hipEvent_t e : {c->ev_fork, c->ev_bulk, c->ev_dem})
+        if (e) (void)hipEventDestroy(e);
     for (auto& t : c->timed) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -800,6 +849,57 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
     if (np == 0) return LBM_OK;
     PhaseTimer tm(c, LBM_PHASE_DEM);
     HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm, DemScratch{c->pairs, c->pair_count, c->reach}));
+    return LBM_OK;
+}
+
+int lbm_step_dem(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_params* prm)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
+    if (!prm) return fail(c, LBM_EINVAL, "null DEM parameters");
+    if (n_sub < 1) return fail(c, LBM_EINVAL, "n_sub must be >= 1");
+    if (!(dt > 0.0)) return fail(c, LBM_EINVAL, "dt must be positive");
+    int rc = check_particles(c, P, true);
+    if (rc) return rc;
+    const int np = c->cfg.n_particles;
+    // a taped step (its output goes to the tape), no particles or no
+    // classification yet: the two calls one after the other
+    if (c->taping || np == 0 || c->n_classify == 0) {
+        rc = lbm_step(c, P);
+        return rc ? rc : dem_step(c, P, n_sub, dt, prm);
+    }
+    rc = overlap_streams(c);
+    if (rc) return rc;
+    void* src = c->f[c->cur];
+    void* dst = src == c->fu[0] ? c->fu[1] : c->fu[0];
+    {
+        PhaseTimer tm(c, LBM_PHASE_BOUNDARY);
+        HIPCHK(c, LQ(c, launch_zero_f64)(c, c->FT, 6 * (int64_t)np));
+        HIPCHK(c, LQ(c, launch_boundary)(c, src, to_dev(P)));
+    }
+    // both passes start after the link pass (forces complete), and the
+    // caller's stream continues after both
+    HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->s_bulk, c->ev_fork, 0));
+    HIPCHK(c, hipStreamWaitEvent(c->s_dem, c->ev_fork, 0));
+    {
+        OnStream os(c, c->s_bulk);
+        PhaseTimer tm(c, LBM_PHASE_BULK);
+        HIPCHK(c, LQ(c, launch_stream_collide)(c, src, dst));
+        HIPCHK(c, hipEventRecord(c->ev_bulk, c->s_bulk));
+    }
+    {
+        OnStream os(c, c->s_dem);
+        PhaseTimer tm(c, LBM_PHASE_DEM);
+        HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm,
+                             DemScratch{c->pairs, c->pair_count, c->reach}));
+        HIPCHK(c, hipEventRecord(c->ev_dem, c->s_dem));
+    }
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_bulk, 0));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_dem, 0));
+    c->f[1 - c->cur] = dst;
+    c->cur = 1 - c->cur;
+    c->stepped_since_classify = true;
     return LBM_OK;
 }
 

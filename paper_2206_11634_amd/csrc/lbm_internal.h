@@ -142,6 +142,10 @@ static_assert(kStageHead == kCursorPad, "counter block: one head line, then the 
 struct lbm_ctx {
     lbm_config cfg{};
     hipStream_t stream = nullptr;
+    // lbm_step_dem: the stream-collide pass and the DEM sub-cycle on two
+    // streams with disjoint compute-unit masks (made on first use)
+    hipStream_t s_bulk = nullptr, s_dem = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_bulk = nullptr, ev_dem = nullptr;
     int device = 0;         // the HIP device current at lbm_init
     mdlbm::Geom geom{};
     mdlbm::Phys phys{};

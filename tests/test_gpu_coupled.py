@@ -174,3 +174,50 @@ def test_checkpoint_resumes_a_run_with_contacts(classify):
         else:
             assert dev > 1e-9, dev
     gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_step_dem_matches_step_then_dem(storage):
+    """lbm_step_dem (the DEM sub-cycle on its own stream beside the
+    stream-collide pass) gives the trajectory of lbm_step then dem_step, over a
+    sphere-sphere contact: forces, poses, velocities, contact records and
+    populations agree to the rounding of the force sums' atomics."""
+    lat = W.LatticeSpec(48, 32, 32, (1, 1, 1), tau=0.7)
+    sh = W.sphere_shape(10.0, 0.1)
+    ps = W.make_particles([sh, sh], [[18.0, 16.0, 16.0], [27.95, 17.0, 16.0]],
+                          [[1.0, 0, 0, 0]] * 2, 1.5,
+                          vel=np.array([[0.03, 0.006, 0.0], [-0.03, -0.006, 0.0]]))
+    prm = B.DemParams.make(**W.dem_defaults(ps))
+    out = []
+    for fused in (False, True):
+        print(f"step_dem {storage} fused={fused}", flush=True)
+        gpu = B.Lattice.for_particles(lat, ps, storage=storage)
+        parts = B.DeviceParticles(ps)
+        # the first call has no classification yet: the two calls in turn
+        gpu.step_dem(parts, 10, 0.1, prm) if fused else (gpu.step(parts), gpu.dem(parts, 10, 0.1, prm))
+        gpu.classify(parts)
+        F = []
+        for _ in range(30):
+            if fused:
+                gpu.step_dem(parts, 10, 0.1, prm)
+                Fh, Th = gpu.forces()
+            else:
+                gpu.step(parts)
+                Fh, Th = gpu.forces()
+                gpu.dem(parts, 10, 0.1, prm)
+            F.append(np.concatenate([Fh.cpu().numpy(), Th.cpu().numpy()], 1))
+            gpu.classify(parts)
+        gpu.sync()
+        dem = gpu.dem_checkpoint().cpu().numpy()
+        out.append((np.array(F), parts.to_host(ps), dem[: dem.size // 8 * 8].view(np.float64),
+                    gpu.populations()))
+        gpu.close()
+    (Fa, A, Da, fa), (Fb, Bp, Db, fb) = out
+    assert np.count_nonzero(Da) > 0                      # a contact was on
+    tol = 1e-11 if storage == "f64" else 2e-5
+    assert np.abs(Fa - Fb).max() <= tol * np.abs(Fa).max()
+    for k in ("pos", "vel", "omega", "quat"):
+        assert np.abs(getattr(A, k) - getattr(Bp, k)).max() <= tol, k
+    # the records hold doubles and integer keys; compared as doubles
+    assert np.allclose(Da, Db, rtol=tol, atol=tol, equal_nan=True)
+    assert np.abs(fa - fb).max() <= tol
