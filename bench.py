@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=None, lattice=19):
+def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=None, lattice=19,
+                seq_steps=0):
     import torch
     from paper_2206_11634_amd import binding as B
     from paper_2206_11634_amd import workloads as W
@@ -73,6 +74,23 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=
     prof = gpu.profile_read() if profile else {}
     if profile:
         gpu.profile(False)
+    seq = None
+    if seq_steps:
+        # after the timed steps: lbm_step, the forces and dem_step one after
+        # the other, so that the stream-collide pass has the chip to itself
+        gpu.profile(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(seq_steps):
+            gpu.step(parts)
+            gpu.forces()
+            gpu.dem(parts, n_sub, 1.0 / n_sub, prm)
+            gpu.classify(parts, sync=False)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        gpu.sync()
+        seq = dict(ms_per_step=(t3 - t2) * 1e3 / seq_steps, prof=gpu.profile_read())
+        gpu.profile(False)
     n_solid = int(torch.count_nonzero(gpu.flag[: gpu.ncell]).item())
     counts = gpu.classify(parts)
     gpu.close()
@@ -80,7 +98,7 @@ def run_storage(lat, ps, meta, storage, steps, warmup, profile=True, treatments=
     torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     return dict(ms_per_step=ms, n_solid=n_solid, prof=prof, n_links=int(counts.n_links),
-                n_refill=int(counts.n_refill), n_cand=int(counts.n_candidates))
+                n_refill=int(counts.n_refill), n_cand=int(counts.n_candidates), seq=seq)
 
 
 def _stream_source_hash():
@@ -463,7 +481,7 @@ def main():
     print(f"[bench] workload {meta['name']}: {lat.nx}x{lat.ny}x{lat.nz}, {ps.n} particles",
           file=sys.stderr, flush=True)
     main_res = run_storage(lat, ps, meta, args.storage, args.steps, args.warmup,
-                           lattice=args.lattice)
+                           lattice=args.lattice, seq_steps=min(args.steps, 10))
     print(f"[bench] {args.storage}: {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr,
           flush=True)
     variants, lattices = {}, {}
@@ -520,6 +538,14 @@ def main():
     ceil = copy_ceiling(args.lattice * lat.ncell * BYTES[args.storage])
     line["roofline"]["copy_ceiling"] = dict(achieved=ceil, unit="GB/s",
                                             frac_of_copy=round(line["roofline"]["achieved"] / ceil, 4))
+    if main_res["seq"]:
+        # the stream-collide pass with the chip to itself (lbm_step, then
+        # dem_step), timed after the timed steps over a few more
+        seq = dict(main_res, prof=main_res["seq"]["prof"])
+        alone = bulk_roofline(seq, lat, args.storage, meta["name"], Q=args.lattice)
+        line["roofline"]["alone"] = dict(avg_ms=alone["avg_ms"], achieved=alone["achieved"],
+                                         frac=alone["frac"])
+        line["sequential_ms_per_step"] = round(main_res["seq"]["ms_per_step"], 4)
     for v, r in variants.items():
         line.setdefault("storage_variants", {})[v] = dict(
             mlups=round(ncell / (r["ms_per_step"] * 1e-3) / 1e6, 1),
