@@ -71,15 +71,36 @@ class _Run:
     def __init__(self, prob: Problem, vel, body_force, tau):
         self.prob = prob
         self.vel = np.asarray(vel, float).reshape(prob.ps.n, 3)
-        lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
-                                  tau=float(tau))
-        self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage,
+        self.lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
+                                       tau=float(tau))
+        self.gpu = B.Lattice.for_particles(self.lat, prob.ps, storage=prob.storage,
                                            treatments=prob.treatments, lattice=prob.lattice)
         # every state on the device: poses of the nominal trajectory, velocity v
         self.traj = B.DeviceTrajectory(prob.states(), vel=self.vel)
+        self.second = self.stream2 = None
 
     def parts(self, n):
         return self.traj[n]
+
+    def open_second(self):
+        """A second lattice context on a stream of its own (default
+        priority), which replays the windows of the backward pass beside the
+        adjoint of the window after them; its lists are sized by the
+        classification at the first pose, as the forward pass's were."""
+        torch = self.gpu.torch
+        self.stream2 = torch.cuda.Stream(device=self.gpu.device)
+        with torch.cuda.stream(self.stream2):
+            self.second = B.Lattice.for_particles(self.lat, self.prob.ps,
+                                                  storage=self.prob.storage,
+                                                  treatments=self.prob.treatments,
+                                                  lattice=self.prob.lattice)
+            self.second.classify(self.parts(0))
+
+    def close(self):
+        if self.second is not None:
+            self.second.close()
+            self.second = None
+        self.gpu.close()
 
 
 def _again_with_read_back(fn):
@@ -100,15 +121,29 @@ def _snapshot(run, k):
         run.geo[k] = run.gpu.geometry_save()
 
 
-def _replay_classify(run, k, parts):
+def _replay_classify(run, k, parts, gpu=None):
     """In a replay: the forward pass's geometry of step k if it kept one that
     fits the list capacities of now, else a classification (asynchronous:
     the forward pass sized the lists for the same poses)."""
+    gpu = run.gpu if gpu is None else gpu
     snap = run.geo.get(k)
-    if snap is not None and snap[1] == run.gpu.geometry_bytes()[1]:
-        run.gpu.geometry_load(snap, parts)
+    if snap is not None and snap[1] == gpu.geometry_bytes()[1]:
+        gpu.geometry_load(snap, parts)
     else:
-        run.gpu.classify(parts, sync=False)
+        gpu.classify(parts, sync=False)
+
+
+def _replay(run, gpu, w0, w1):
+    """Restore the checkpoint of step w0 on gpu and run steps w0 .. w1 - 1
+    again with the tape on (asynchronous, on gpu's stream)."""
+    gpu.restore(run.ckpt[w0])
+    # the geometry of the forward pass, or classifications without
+    # read-backs (lbm_adjoint reports anything they latched)
+    _replay_classify(run, w0, run.parts(w0), gpu)   # the geometry at w0, refills nothing
+    gpu.tape_begin(w1 - w0)
+    for k in range(w0, w1):
+        gpu.step(run.parts(k))
+        _replay_classify(run, k + 1, run.parts(k + 1), gpu)
 
 
 def _closing(gpu, body):
@@ -163,31 +198,62 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     a dict for stats, the library's per-phase timers are read into it."""
     prob, gpu = run.prob, run.gpu
     torch = gpu.torch
+    wins = sorted(run.ckpt, reverse=True)
+    # With the forward pass's geometry kept, window i's replay runs on a
+    # second context (its own stream), beside the adjoint of window i - 1 on
+    # the first, alternating; an adjoint call waits for its own stream only,
+    # and the adjoint field and the sums pass from one adjoint call to the
+    # next after the host has waited for the first.  The second context must
+    # load the same snapshots (the same list capacities); otherwise one
+    # context replays and runs the adjoint of each window in turn.
+    two = len(wins) > 1 and prob.keep_geometry
+    if two and run.second is None:
+        run.open_second()
+    if two and run.second.geometry_bytes()[1] != gpu.geometry_bytes()[1]:
+        run.second.close()
+        run.second, two = None, False
+    ctxs = [gpu, run.second] if two else [gpu]
+    streams = [torch.cuda.current_stream(gpu.device), run.stream2]
     if stats is not None:
-        gpu.profile(True)
+        for c in ctxs:
+            c.profile(True)
     lam = gpu.adjoint_field()
     n = prob.ps.n
     g = torch.zeros(4 + 3 * n, dtype=torch.float64, device=gpu.device)
     gx = (torch.zeros((prob.steps + 1, max(n, 1), 6), dtype=torch.float64, device=gpu.device)
           if geometry else None)
-    for w0 in sorted(run.ckpt, reverse=True):
-        w1 = min(w0 + prob.window, prob.steps)
-        gpu.restore(run.ckpt[w0])
-        # the geometry of the forward pass, or classifications without
-        # read-backs (lbm_adjoint reports anything they latched)
-        _replay_classify(run, w0, run.parts(w0))   # the geometry at w0, refills nothing
-        gpu.tape_begin(w1 - w0)
-        for k in range(w0, w1):
-            gpu.step(run.parts(k))
-            _replay_classify(run, k + 1, run.parts(k + 1))
+    torch.cuda.synchronize(gpu.device)   # lam, g and gx are set before either stream reads them
+
+    def span(w0):
+        return w0, min(w0 + prob.window, prob.steps)
+
+    def adjoint(c, w0):
+        w1 = span(w0)[1]
         # poses w0 .. w1 of this window: a contiguous view of gx
-        gpu.adjoint(run.parts(w1), prob.weights, lam, g,
-                    None if gx is None else gx[w0:w1 + 1])
+        c.adjoint(run.parts(w1), prob.weights, lam, g, None if gx is None else gx[w0:w1 + 1])
+
+    if two:
+        with torch.cuda.stream(streams[0]):
+            _replay(run, ctxs[0], *span(wins[0]))
+        for i, w0 in enumerate(wins):
+            if i + 1 < len(wins):
+                with torch.cuda.stream(streams[(i + 1) % 2]):
+                    _replay(run, ctxs[(i + 1) % 2], *span(wins[i + 1]))
+            with torch.cuda.stream(streams[i % 2]):
+                adjoint(ctxs[i % 2], w0)
+    else:
+        for w0 in wins:
+            _replay(run, gpu, *span(w0))
+            adjoint(gpu, w0)
+    torch.cuda.synchronize(gpu.device)
     out = g.cpu().numpy()
     if stats is not None:
-        stats.update(gpu.profile_read())
-        gpu.profile(False)
-    gpu.close()
+        for c in ctxs:
+            for k, (ms, cnt) in c.profile_read().items():
+                a = stats.get(k, (0.0, 0))
+                stats[k] = (a[0] + ms, a[1] + cnt)
+            c.profile(False)
+    run.close()
     res = (out[4:].reshape(n, 3), out[:3].copy(), float(out[3]))
     if geometry:
         res = res + (gx[:, :n].cpu().numpy(),)

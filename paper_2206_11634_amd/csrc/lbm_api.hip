@@ -173,15 +173,9 @@ std::string err_text(uint32_t bits)
 
 void free_tape(lbm_ctx* c)
 {
-    for (auto& t : c->tape) {
-        (void)hipFree(t.f);
-        (void)hipFree(t.own);
-        (void)hipFree(t.links);
-        (void)hipFree(t.cursor);
-        (void)hipFree(t.part);
-        (void)hipFree(t.dem);
-        (void)hipFree(t.dem_key);
-    }
+    for (auto& t : c->tape) (void)hipFree(t.links);
+    for (void* s : c->tape_slabs) (void)hipFree(s);
+    c->tape_slabs.clear();
     c->tape.clear();
     c->tape_len = 0;
     c->tape_steps = 0;
@@ -507,13 +501,7 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->quat_prev);
     (void)hipFree(c->fc);
     (void)hipFree(c->reach);
-    for (auto& t : c->tape) {
-        (void)hipFree(t.f);
-        (void)hipFree(t.own);
-        (void)hipFree(t.links);
-        (void)hipFree(t.cursor);
-        (void)hipFree(t.part);
-    }
+    free_tape(c);
     (void)hipFree(c->adj_scratch);
     (void)hipFree(c->adj_wts);
     (void)hipFree(c->adj_sig);
@@ -1239,23 +1227,41 @@ int lbm_tape_begin(lbm_ctx* c, int max_steps)
     }
     if (c->n_classify == 0) return fail(c, LBM_ESTATE, "classify before taping");
     const int np = c->cfg.n_particles;
-    // entries allocated by an earlier window are reused as they are
+    // entries allocated by an earlier window are reused as they are; the new
+    // ones are carved from one allocation (a window's worth of hipMalloc and
+    // hipFree calls, each of which synchronises, cost more than the steps)
     const size_t have = c->tape.size();
     if (have < (size_t)max_steps) {
+        const size_t np1 = (size_t)std::max(np, 1);
+        const size_t part[6] = {c->sizes.population_bytes, c->sizes.owner_bytes,
+                                sizeof(uint32_t) * kCursorPad * np1,
+                                sizeof(double) * (19 * np1 + 3 * (size_t)c->cfg.n_ctrl),
+                                sizeof(double) * std::max<size_t>(dem_tape_doubles(np), 1),
+                                sizeof(int32_t) * kPairSlots * np1};
+        size_t step = 0;
+        for (size_t b : part) step += align256(b);
+        const size_t add = (size_t)max_steps - have;
+        char* slab = nullptr;
+        if (hipMalloc((void**)&slab, step * add) != hipSuccess) {
+            free_tape(c);
+            return fail(c, LBM_ENOMEM, "tape allocation failed");
+        }
+        c->tape_slabs.push_back(slab);
         c->tape.resize(max_steps);
-        for (size_t k = have; k < c->tape.size(); ++k) {
-            TapeStep& t = c->tape[k];
-            hipError_t e = hipMalloc(&t.f, c->sizes.population_bytes);
-            if (e == hipSuccess) e = alloc(&t.own, c->sizes.owner_bytes / sizeof(uint32_t));
-            if (e == hipSuccess) e = alloc(&t.cursor, (size_t)kCursorPad * std::max(np, 1));
-            if (e == hipSuccess)
-                e = alloc(&t.part, (size_t)19 * std::max(np, 1) + (size_t)3 * c->cfg.n_ctrl);
-            if (e == hipSuccess) e = alloc(&t.dem, dem_tape_doubles(np));
-            if (e == hipSuccess) e = alloc(&t.dem_key, (size_t)kPairSlots * std::max(np, 1));
-            if (e != hipSuccess) {
-                free_tape(c);
-                return fail(c, LBM_ENOMEM, "tape allocation failed");
-            }
+        for (size_t k = 0; k < add; ++k) {
+            TapeStep& t = c->tape[have + k];
+            char* q = slab + k * step;
+            t.f = q;
+            q += align256(part[0]);
+            t.own = reinterpret_cast<uint32_t*>(q);
+            q += align256(part[1]);
+            t.cursor = reinterpret_cast<uint32_t*>(q);
+            q += align256(part[2]);
+            t.part = reinterpret_cast<double*>(q);
+            q += align256(part[3]);
+            t.dem = reinterpret_cast<double*>(q);
+            q += align256(part[4]);
+            t.dem_key = reinterpret_cast<int32_t*>(q);
         }
     }
     c->tape_len = 0;

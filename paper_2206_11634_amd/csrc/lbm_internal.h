@@ -71,6 +71,8 @@ struct RefillRec {
 
 // One recorded lattice step for the adjoint: populations after the link
 // reconstruction (ghost slots filled), owners, links and particle state.
+// One taped step.  Its fixed-size parts (f, own, cursor, part, dem, dem_key)
+// are carved from the context's tape slabs; links are allocated per step.
 struct TapeStep {
     void* f = nullptr;
     uint32_t* own = nullptr;
@@ -218,6 +220,7 @@ struct lbm_ctx {
     // differentiation form
     lbm_sizes sizes{};
     std::vector<mdlbm::TapeStep> tape;
+    std::vector<void*> tape_slabs;  // one allocation per growth of the tape
     int tape_len = 0;    // steps recorded since lbm_tape_begin
     int tape_steps = 0;  // steps to record (tape.size() may be larger)
     bool taping = false;
