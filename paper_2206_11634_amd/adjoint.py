@@ -333,13 +333,14 @@ class FreeProblem:
 class _FreeRun:
     def __init__(self, prob: FreeProblem, body_force, tau):
         self.prob = prob
-        lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
-                                  tau=float(tau))
-        self.gpu = B.Lattice.for_particles(lat, prob.ps, storage=prob.storage,
+        self.lat = dataclasses.replace(prob.lat, body_force=tuple(map(float, body_force)),
+                                       tau=float(tau))
+        self.gpu = B.Lattice.for_particles(self.lat, prob.ps, storage=prob.storage,
                                            treatments=prob.treatments, lattice=prob.lattice)
         self.parts = B.DeviceParticles(prob.ps)
         self.prm = prob.dem()
         self.dt = 1.0 / prob.n_sub
+        self.second = self.parts2 = self.stream2 = None
 
     def state(self):
         """The particle arrays and the DEM's own state (contact histories and
@@ -348,21 +349,46 @@ class _FreeRun:
         st["dem"] = self.gpu.dem_checkpoint()
         return st
 
-    def load(self, st):
+    def load(self, st, gpu=None, parts=None):
+        gpu = self.gpu if gpu is None else gpu
+        parts = self.parts if parts is None else parts
         for k, v in st.items():
             if k == "dem":
-                self.gpu.dem_restore(v)
+                gpu.dem_restore(v)
             else:
-                self.parts.t[k].copy_(v)
+                parts.t[k].copy_(v)
 
-    def advance(self, sync: bool = True, replay_step: int | None = None):
+    def advance(self, sync: bool = True, replay_step: int | None = None, gpu=None, parts=None):
         """dem_step, then the classification of the new poses (in a replay,
         step replay_step's geometry kept by the forward pass, if any)."""
-        self.gpu.dem(self.parts, self.prob.n_sub, self.dt, self.prm)
+        gpu = self.gpu if gpu is None else gpu
+        parts = self.parts if parts is None else parts
+        gpu.dem(parts, self.prob.n_sub, self.dt, self.prm)
         if replay_step is None:
-            self.gpu.classify(self.parts, sync=sync)
+            gpu.classify(parts, sync=sync)
         else:
-            _replay_classify(self, replay_step, self.parts)
+            _replay_classify(self, replay_step, parts, gpu)
+
+    def open_second(self):
+        """A second lattice context with particle arrays of its own, on a
+        stream of its own (default priority), for the replays of the backward
+        pass; its lists are sized at the initial state, as the forward pass's
+        were."""
+        torch = self.gpu.torch
+        self.stream2 = torch.cuda.Stream(device=self.gpu.device)
+        with torch.cuda.stream(self.stream2):
+            self.second = B.Lattice.for_particles(self.lat, self.prob.ps,
+                                                  storage=self.prob.storage,
+                                                  treatments=self.prob.treatments,
+                                                  lattice=self.prob.lattice)
+            self.parts2 = B.DeviceParticles(self.prob.ps)
+            self.second.classify(self.parts2)
+
+    def close(self):
+        if self.second is not None:
+            self.second.close()
+            self.second = None
+        self.gpu.close()
 
 
 def forward_free(prob: FreeProblem, body_force, tau, keep: bool = False):
@@ -410,27 +436,59 @@ def backward_free(run: _FreeRun):
     prob, gpu = run.prob, run.gpu
     torch = gpu.torch
     n = prob.ps.n
+    wins = sorted(run.ckpt, reverse=True)
+    # as in backward: with the forward pass's geometry kept, a second context
+    # (particle arrays and stream of its own) replays window i beside the
+    # adjoint of window i - 1, alternating
+    two = len(wins) > 1 and prob.keep_geometry
+    if two and run.second is None:
+        run.open_second()
+    if two and run.second.geometry_bytes()[1] != gpu.geometry_bytes()[1]:
+        run.second.close()
+        run.second, two = None, False
+    lanes = [(gpu, run.parts), (run.second, run.parts2)] if two else [(gpu, run.parts)]
+    streams = [torch.cuda.current_stream(gpu.device), run.stream2]
     lam = gpu.adjoint_field()
     g = torch.zeros(4, dtype=torch.float64, device=gpu.device)
     sig = torch.zeros((max(n, 1), 12), dtype=torch.float64, device=gpu.device)
     sigc = gpu.contact_adjoint()   # carried contact sums and springs, across windows
-    for w0 in sorted(run.ckpt, reverse=True):
+    torch.cuda.synchronize(gpu.device)   # set before either stream reads them
+
+    def replay(lane, w0):
+        c, parts = lane
         w1 = min(w0 + prob.window, prob.steps)
         ck, st = run.ckpt[w0]
-        gpu.restore(ck)
-        run.load(st)
+        c.restore(ck)
+        run.load(st, c, parts)
         # replayed poses: the forward pass's geometry, or classifications
         # without read-backs (lbm_adjoint_coupled reports anything they latched)
-        _replay_classify(run, w0, run.parts)   # the geometry at w0, refills nothing
-        gpu.tape_begin(w1 - w0)
+        _replay_classify(run, w0, parts, c)   # the geometry at w0, refills nothing
+        c.tape_begin(w1 - w0)
         for k in range(w0, w1):
-            gpu.step(run.parts)
-            run.advance(replay_step=k + 1)
-        gpu.adjoint_coupled(run.parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig,
-                            sigc)
+            c.step(parts)
+            run.advance(replay_step=k + 1, gpu=c, parts=parts)
+
+    def adjoint(lane):
+        c, parts = lane
+        c.adjoint_coupled(parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig, sigc)
+
+    if two:
+        with torch.cuda.stream(streams[0]):
+            replay(lanes[0], wins[0])
+        for i in range(len(wins)):
+            if i + 1 < len(wins):
+                with torch.cuda.stream(streams[(i + 1) % 2]):
+                    replay(lanes[(i + 1) % 2], wins[i + 1])
+            with torch.cuda.stream(streams[i % 2]):
+                adjoint(lanes[i % 2])
+    else:
+        for w0 in wins:
+            replay(lanes[0], w0)
+            adjoint(lanes[0])
+    torch.cuda.synchronize(gpu.device)
     out = g.cpu().numpy()
     s0 = sig[:n].cpu().numpy()
-    gpu.close()
+    run.close()
     return s0, out[:3].copy(), float(out[3])
 
 
