@@ -596,3 +596,29 @@ def test_contact_adjoint_at_the_largest_cluster_and_beyond():
         AD.evaluate_free(prob, F, tau, grad=True)
     assert e.value.code == B.LBM_ESTATE
     assert "cluster" in str(e.value)
+
+
+def test_two_context_backward_matches_one_context():
+    """The backward pass that replays each window on a second context beside
+    the adjoint of the window after it (the forward pass's geometry kept)
+    gives the gradient of the one-context pass (each replay classifying
+    again), for prescribed and for free motion, over several windows."""
+    prob = _problem("f64", steps=30, window=7)
+    v, F, tau = prob.ps.vel.copy(), np.array(prob.lat.body_force), prob.lat.tau
+    a = AD.evaluate(prob, v, F, tau, grad=True)
+    b = AD.evaluate(dataclasses.replace(prob, keep_geometry=False), v, F, tau, grad=True)
+    assert abs(a[0] - b[0]) <= 1e-13 * abs(b[0])
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-10, atol=1e-12 * np.abs(b[1]).max())
+    np.testing.assert_allclose(a[2], b[2], rtol=1e-10)
+    assert abs(a[3] - b[3]) <= 1e-7 * abs(b[3])
+    fp = _free_problem(steps=20, window=6)
+    F, tau = np.array(fp.lat.body_force), fp.lat.tau
+    a = AD.evaluate_free(fp, F, tau, grad=True)
+    b = AD.evaluate_free(dataclasses.replace(fp, keep_geometry=False), F, tau, grad=True)
+    assert abs(a[0] - b[0]) <= 1e-13 * abs(b[0])
+    for k in range(4):
+        blk = slice(3 * k, 3 * k + 3)
+        np.testing.assert_allclose(a[1][:, blk], b[1][:, blk], rtol=1e-9,
+                                   atol=1e-11 * np.abs(b[1][:, blk]).max())
+    np.testing.assert_allclose(a[2], b[2], rtol=1e-9)
+    assert abs(a[3] - b[3]) <= 1e-7 * abs(b[3])
