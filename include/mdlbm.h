@@ -271,9 +271,10 @@ int dem_step(lbm_ctx* ctx, lbm_particles* P, int n_sub, double dt, const dem_par
  * streams of the library's own (default priority; the DEM's on two compute
  * units of each XCD, the stream-collide's on the rest), and the context's
  * stream waits for both.  The populations, forces, particle state and
- * contact histories are those of lbm_step then dem_step.  While taping (the
- * step's output goes to the tape), with no particles or before the first
- * classification it runs the two calls one after the other.  The two streams
+ * contact histories are those of lbm_step then dem_step.  For a step that
+ * is taped (lbm_tape_begin, its output goes to the tape), with no particles
+ * or before the first classification it runs the two calls one after the
+ * other.  The two streams
  * and three events are made on the first call (EDEVICE if that fails) and
  * kept until lbm_destroy.  Argument checks and errors: those of lbm_step
  * and dem_step.  Asynchronous. */

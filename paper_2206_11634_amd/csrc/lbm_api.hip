@@ -852,7 +852,8 @@ int lbm_step_dem(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_p
     const int np = c->cfg.n_particles;
     // a taped step (its output goes to the tape), no particles or no
     // classification yet: the two calls one after the other
-    if (c->taping || np == 0 || c->n_classify == 0) {
+    const bool taped = c->taping && c->tape_len < c->tape_steps;
+    if (taped || np == 0 || c->n_classify == 0) {
         rc = lbm_step(c, P);
         return rc ? rc : dem_step(c, P, n_sub, dt, prm);
     }

@@ -197,7 +197,9 @@ def test_step_dem_matches_step_then_dem(storage):
         gpu.step_dem(parts, 10, 0.1, prm) if fused else (gpu.step(parts), gpu.dem(parts, 10, 0.1, prm))
         gpu.classify(parts)
         F = []
-        for _ in range(30):
+        for k in range(30):
+            if k == 20:
+                gpu.tape_begin(4)   # taped steps: lbm_step_dem runs the two calls in turn
             if fused:
                 gpu.step_dem(parts, 10, 0.1, prm)
                 Fh, Th = gpu.forces()
