@@ -66,11 +66,16 @@ K_STEPS = 3
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_c4_full_size_geometry_and_sampled_bodies(storage):
-    """The timed workload as the benchmark runs it: its treatment bits (1+2+8)
-    and both deviation storages.  The whole-lattice geometry does not depend
-    on the storage and is compared in the FP32 run."""
+    """The timed workload as the benchmark runs it: its treatment bits (1+2+8),
+    both deviation storages, and its launch configuration (lbm_step_dem: the
+    stream-collide pass on its masked stream beside the DEM call; the DEM's
+    update of the particles is overwritten by the prescribed state of the
+    next step).  The whole-lattice geometry does not depend on the storage
+    and is compared in the FP32 run."""
     lat, ps, meta = W.config_c4()
     treat = meta["treatments"]
+    prm = B.DemParams.make(**W.dem_defaults(ps, gravity=meta["gravity"]))
+    n_sub = meta["n_sub"]
     ps = _moving(ps, 14, 0.02, 0.001)
     margin = 2 * K_STEPS + 4
     half_extra = 2 + margin
@@ -89,7 +94,7 @@ def test_c4_full_size_geometry_and_sampled_bodies(storage):
             _compare_geometry(gpu, geo, f"c4 step {t}")
             if t == 1:
                 assert len(geo.refill_nodes) > 0
-        gpu.step(parts)
+        gpu.step_dem(parts, n_sub, 1.0 / n_sub, prm)
         F, T = gpu.forces()
         Fg.append(F.cpu().numpy()[sample].copy())
         Tg.append(T.cpu().numpy()[sample].copy())
