@@ -121,6 +121,18 @@ def _snapshot(run, k):
         run.geo[k] = run.gpu.geometry_save()
 
 
+def _second_fits(run) -> bool:
+    """Whether the device has room for a second context and its tape beside
+    the first context's tape: a window's populations and owner planes, twice,
+    and the second context's own buffers, with a quarter to spare."""
+    gpu = run.gpu
+    z = gpu.sizes
+    tape = run.prob.window * (z.population_bytes + z.owner_bytes + (1 << 20))
+    ctx = 2 * z.population_bytes + 2 * z.owner_bytes + z.flag_bytes + z.moment_bytes
+    free, _ = gpu.torch.cuda.mem_get_info(gpu.device)
+    return free > 1.25 * (2 * tape + ctx)
+
+
 def _replay_classify(run, k, parts, gpu=None):
     """In a replay: the forward pass's geometry of step k if it kept one that
     fits the list capacities of now, else a classification (asynchronous:
@@ -204,9 +216,10 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
     # the first, alternating; an adjoint call waits for its own stream only,
     # and the adjoint field and the sums pass from one adjoint call to the
     # next after the host has waited for the first.  The second context must
-    # load the same snapshots (the same list capacities); otherwise one
-    # context replays and runs the adjoint of each window in turn.
-    two = len(wins) > 1 and prob.keep_geometry
+    # load the same snapshots (the same list capacities) and its tape must
+    # fit beside the first's; otherwise one context replays and runs the
+    # adjoint of each window in turn.
+    two = len(wins) > 1 and prob.keep_geometry and (run.second is not None or _second_fits(run))
     if two and run.second is None:
         run.open_second()
     if two and run.second.geometry_bytes()[1] != gpu.geometry_bytes()[1]:
@@ -440,7 +453,7 @@ def backward_free(run: _FreeRun):
     # as in backward: with the forward pass's geometry kept, a second context
     # (particle arrays and stream of its own) replays window i beside the
     # adjoint of window i - 1, alternating
-    two = len(wins) > 1 and prob.keep_geometry
+    two = len(wins) > 1 and prob.keep_geometry and (run.second is not None or _second_fits(run))
     if two and run.second is None:
         run.open_second()
     if two and run.second.geometry_bytes()[1] != gpu.geometry_bytes()[1]:
