@@ -245,28 +245,30 @@ def backward(run: _Run, stats: dict | None = None, geometry: bool = False):
         # poses w0 .. w1 of this window: a contiguous view of gx
         c.adjoint(run.parts(w1), prob.weights, lam, g, None if gx is None else gx[w0:w1 + 1])
 
-    if two:
-        with torch.cuda.stream(streams[0]):
-            _replay(run, ctxs[0], *span(wins[0]))
-        for i, w0 in enumerate(wins):
-            if i + 1 < len(wins):
-                with torch.cuda.stream(streams[(i + 1) % 2]):
-                    _replay(run, ctxs[(i + 1) % 2], *span(wins[i + 1]))
-            with torch.cuda.stream(streams[i % 2]):
-                adjoint(ctxs[i % 2], w0)
-    else:
-        for w0 in wins:
-            _replay(run, gpu, *span(w0))
-            adjoint(gpu, w0)
-    torch.cuda.synchronize(gpu.device)
-    out = g.cpu().numpy()
-    if stats is not None:
-        for c in ctxs:
-            for k, (ms, cnt) in c.profile_read().items():
-                a = stats.get(k, (0.0, 0))
-                stats[k] = (a[0] + ms, a[1] + cnt)
-            c.profile(False)
-    run.close()
+    try:
+        if two:
+            with torch.cuda.stream(streams[0]):
+                _replay(run, ctxs[0], *span(wins[0]))
+            for i, w0 in enumerate(wins):
+                if i + 1 < len(wins):
+                    with torch.cuda.stream(streams[(i + 1) % 2]):
+                        _replay(run, ctxs[(i + 1) % 2], *span(wins[i + 1]))
+                with torch.cuda.stream(streams[i % 2]):
+                    adjoint(ctxs[i % 2], w0)
+        else:
+            for w0 in wins:
+                _replay(run, gpu, *span(w0))
+                adjoint(gpu, w0)
+        torch.cuda.synchronize(gpu.device)
+        out = g.cpu().numpy()
+        if stats is not None:
+            for c in ctxs:
+                for k, (ms, cnt) in c.profile_read().items():
+                    a = stats.get(k, (0.0, 0))
+                    stats[k] = (a[0] + ms, a[1] + cnt)
+                c.profile(False)
+    finally:
+        run.close()   # waits for both streams
     res = (out[4:].reshape(n, 3), out[:3].copy(), float(out[3]))
     if geometry:
         res = res + (gx[:, :n].cpu().numpy(),)
@@ -485,23 +487,25 @@ def backward_free(run: _FreeRun):
         c, parts = lane
         c.adjoint_coupled(parts, prob.weights, run.prm, prob.n_sub, run.dt, lam, g, sig, sigc)
 
-    if two:
-        with torch.cuda.stream(streams[0]):
-            replay(lanes[0], wins[0])
-        for i in range(len(wins)):
-            if i + 1 < len(wins):
-                with torch.cuda.stream(streams[(i + 1) % 2]):
-                    replay(lanes[(i + 1) % 2], wins[i + 1])
-            with torch.cuda.stream(streams[i % 2]):
-                adjoint(lanes[i % 2])
-    else:
-        for w0 in wins:
-            replay(lanes[0], w0)
-            adjoint(lanes[0])
-    torch.cuda.synchronize(gpu.device)
-    out = g.cpu().numpy()
-    s0 = sig[:n].cpu().numpy()
-    run.close()
+    try:
+        if two:
+            with torch.cuda.stream(streams[0]):
+                replay(lanes[0], wins[0])
+            for i in range(len(wins)):
+                if i + 1 < len(wins):
+                    with torch.cuda.stream(streams[(i + 1) % 2]):
+                        replay(lanes[(i + 1) % 2], wins[i + 1])
+                with torch.cuda.stream(streams[i % 2]):
+                    adjoint(lanes[i % 2])
+        else:
+            for w0 in wins:
+                replay(lanes[0], w0)
+                adjoint(lanes[0])
+        torch.cuda.synchronize(gpu.device)
+        out = g.cpu().numpy()
+        s0 = sig[:n].cpu().numpy()
+    finally:
+        run.close()   # waits for both streams
     return s0, out[:3].copy(), float(out[3])
 
 
