@@ -213,6 +213,10 @@ const char* lbm_last_error(const lbm_ctx* ctx);
  *    time level, with u_new = v + omega x (x_new - x_p) of the particle that
  *    covered it, then collided; the first call after lbm_init refills nothing.
  * Coordinates on a periodic axis are taken at the image nearest x_p.
+ * Each particle's links are held in a segment of the library's link list
+ * sized from that particle's own count at the first call (a quarter and 256
+ * records to spare, in whole 256-record chunks) and grown, alone, when a
+ * later call finds it outgrown.
  * Synchronises the stream to report counts (out may be NULL).  EINVAL when a
  * particle's body reaches beyond box_half, K <= 0, or x_p lies outside
  * [0, n) on a periodic axis; the previous classification then stays in force.
@@ -225,7 +229,7 @@ int lbm_classify_nodes(lbm_ctx* ctx, const lbm_particles* P, lbm_counts* out);
  * lbm_classify_nodes of this context has already sized (the recomputation
  * of an adjoint window, a prescribed trajectory run a second time).  The
  * counts stay on the device: the refill reads its own, and lbm_step runs its
- * link kernel over the whole link capacity.  What lbm_classify_nodes would
+ * link kernel over every particle's segment whole.  What lbm_classify_nodes would
  * have reported is latched on the device instead: a rejected particle (the
  * EINVAL cases above; the owners are then not rebuilt) or a list that
  * outgrew its capacity (ECAPACITY; its extra entries are dropped).  The next
@@ -371,9 +375,10 @@ int lbm_dem_checkpoint_load(lbm_ctx* ctx, const void* src_dev);
 
 /* ---- geometry snapshots (differentiation form) ------------------------- */
 
-/* Bytes of one geometry snapshot for the context's current link and refill
- * list capacities, and a tag naming those capacities (for lbm_geometry_load).
- * A snapshot is about owner_bytes + flag_bytes + 16 B per link slot. */
+/* Bytes of one geometry snapshot for the context's current link layout (the
+ * particles' segments) and refill list capacity, and a tag naming them (for
+ * lbm_geometry_load).  A snapshot is about owner_bytes + flag_bytes + 16 B
+ * per link slot. */
 int lbm_geometry_bytes(const lbm_ctx* ctx, size_t* bytes, uint64_t* tag);
 
 /* Copy the geometry of the last classification -- owner plane, flags, link
@@ -389,7 +394,8 @@ int lbm_geometry_save(lbm_ctx* ctx, void* dst_dev);
  * geometry and its refilled nodes are refilled from the current populations,
  * as that classification did (nothing after lbm_checkpoint_load, as
  * lbm_classify_nodes).  tag: as returned by lbm_geometry_bytes when the
- * snapshot was sized; ESTATE when the list capacities changed since.  The
+ * snapshot was sized; ESTATE when the link layout or the refill capacity
+ * changed since.  The
  * list counts are not read back (as lbm_classify_nodes_async).  A taped
  * step (lbm_tape_begin) whose geometry was loaded records the snapshot's
  * owners and links by reference instead of copying them: keep the snapshot

@@ -547,7 +547,9 @@ template <int S, bool GEO>
 __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __restrict__ f,
                                                    const LinkRec* __restrict__ links,
                                                    const uint32_t* __restrict__ cursor,
-                                                   int64_t cap, const double* pos,
+                                                   const int64_t* __restrict__ loff,
+                                                   const uint32_t* __restrict__ chunk,
+                                                   const double* pos,
                                                    const double* vel, const double* om,
                                                    typename St<S>::A* lam0, const double* wts,
                                                    Geom g, Phys ph, double* grad, GeoArgs ga)
@@ -556,15 +558,17 @@ __global__ __launch_bounds__(256) void k_adj_links(const typename St<S>::T* __re
     constexpr bool DEV = St<S>::dev;
     constexpr int N = GEO ? 14 : 13;  // tangents: 13 link inputs (+ q)
     using DN = Dual<A, N>;
-    const int p = blockIdx.y;
-    const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
-    if (blockIdx.x * 256u >= cnt) return;
-    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    // one workgroup per 256-record chunk of the step's link layout
+    const int p = (int)chunk[blockIdx.x];
+    const int64_t g0 = (int64_t)blockIdx.x * 256;
+    const int64_t cnt = min(loff[p + 1] - loff[p], (int64_t)cursor[(int64_t)p * kCursorPad]);
+    if (g0 - loff[p] >= cnt) return;  // uniform over the block
+    const int64_t l = g0 - loff[p] + threadIdx.x;
     // dJ/dF (3), dJ/dv_p (3), dJ/dx_p (3, GEO), dJ/dtheta_p (3, GEO),
     // dJ/domega_p (3, GEO)
     double acc[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (l < cnt) {
-        const LinkRec r = links[(int64_t)p * cap + l];
+        const LinkRec r = links[g0 + threadIdx.x];
         const int d = r.d, db = opp(d);
         int e[3];
         dir_of(d, e);
@@ -795,19 +799,20 @@ struct RunAdj {
                                ts.own_use, (const A*)lam1, (A*)lam0, pos1, vel1, om1, c->geom, c->phys,
                                grad, ga, list);
         }
-        if ((parts & kAdjLinks) && c->cfg.n_particles > 0 && ts.link_max > 0) {
+        if ((parts & kAdjLinks) && c->cfg.n_particles > 0 && ts.link_max > 0 && ts.lay &&
+            ts.lay->chunks() > 0) {
             const int np = c->cfg.n_particles;
-            dim3 grid(blocks_for(ts.link_max), np);
+            const dim3 grid((uint32_t)ts.lay->chunks());
             if (ga.g_links)
                 hipLaunchKernelGGL((k_adj_links<S, true>), grid, dim3(256), 0, c->stream,
-                                   (const T*)ts.f, ts.links_use, ts.cursor, ts.link_cap, ts.part,
-                                   ts.part + 3 * np, ts.part + 6 * np, (A*)lam0, wts, c->geom,
-                                   c->phys, grad, ga);
+                                   (const T*)ts.f, ts.links_use, ts.cursor, ts.lay->off_dev,
+                                   ts.lay->chunk_dev, ts.part, ts.part + 3 * np,
+                                   ts.part + 6 * np, (A*)lam0, wts, c->geom, c->phys, grad, ga);
             else
                 hipLaunchKernelGGL((k_adj_links<S, false>), grid, dim3(256), 0, c->stream,
-                                   (const T*)ts.f, ts.links_use, ts.cursor, ts.link_cap, ts.part,
-                                   ts.part + 3 * np, ts.part + 6 * np, (A*)lam0, wts, c->geom,
-                                   c->phys, grad, ga);
+                                   (const T*)ts.f, ts.links_use, ts.cursor, ts.lay->off_dev,
+                                   ts.lay->chunk_dev, ts.part, ts.part + 3 * np,
+                                   ts.part + 6 * np, (A*)lam0, wts, c->geom, c->phys, grad, ga);
         }
         return hipGetLastError();
     }

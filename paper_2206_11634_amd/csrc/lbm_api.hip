@@ -171,6 +171,48 @@ std::string err_text(uint32_t bits)
     return s;
 }
 
+// A link layout with segments of the given sizes (multiples of 256
+// records); null when its device tables cannot be allocated.
+std::shared_ptr<const LinkLayout> make_layout(const std::vector<int64_t>& seg)
+{
+    auto L = std::make_shared<LinkLayout>();
+    const size_t np = seg.size();
+    L->off.resize(np + 1);
+    int64_t acc = 0;
+    for (size_t p = 0; p < np; ++p) {
+        L->off[p] = acc;
+        acc += seg[p];
+        L->max_seg = std::max(L->max_seg, seg[p]);
+    }
+    L->off[np] = acc;
+    L->total = acc;
+    std::vector<uint32_t> chunk((size_t)L->chunks());
+    for (size_t p = 0; p < np; ++p)
+        for (int64_t b = L->off[p] / 256; b < L->off[p + 1] / 256; ++b) chunk[(size_t)b] = (uint32_t)p;
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the offsets
+    for (int64_t v : L->off)
+        for (int k = 0; k < 8; ++k) {
+            h ^= (uint64_t)((v >> (8 * k)) & 0xFF);
+            h *= 1099511628211ull;
+        }
+    L->tag = h;
+    if (hipMalloc((void**)&L->off_dev, sizeof(int64_t) * (np + 1)) != hipSuccess) return nullptr;
+    if (hipMalloc((void**)&L->chunk_dev, sizeof(uint32_t) * std::max<size_t>(chunk.size(), 1)) !=
+        hipSuccess)
+        return nullptr;
+    if (hipMemcpy(L->off_dev, L->off.data(), sizeof(int64_t) * (np + 1), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return nullptr;
+    if (!chunk.empty() && hipMemcpy(L->chunk_dev, chunk.data(), sizeof(uint32_t) * chunk.size(),
+                                    hipMemcpyHostToDevice) != hipSuccess)
+        return nullptr;
+    return L;
+}
+
+// The segment of a particle with count links: a quarter and 256 records to
+// spare, in whole chunks.
+int64_t link_segment(int64_t count) { return (count + count / 4 + 256 + 255) / 256 * 256; }
+
 void free_tape(lbm_ctx* c)
 {
     for (auto& t : c->tape) (void)hipFree(t.links);
@@ -231,7 +273,7 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
     if (c->geo_own) {
         t.own_use = c->geo_own;
         t.links_use = c->geo_links;
-        t.link_cap = c->link_cap;
+        t.lay = c->lay;
         t.link_max = c->link_max;
         if (np > 0) HIPCHK(c, LQ(c, launch_tape_small)(c, t, P));
         c->tape_len += 1;
@@ -242,7 +284,7 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
     t.own_use = t.own;
     t.links_use = t.links;
     if (np > 0) {
-        const int64_t need = (int64_t)np * c->link_cap;
+        const int64_t need = std::max<int64_t>(c->lay->total, 1);
         if (t.link_alloc < need) {
             HIPCHK(c, hipFree(t.links));
             t.links = nullptr;
@@ -251,10 +293,10 @@ int record_tape_step(lbm_ctx* c, const lbm_particles* P)
             t.link_alloc = need;
         }
         t.links_use = t.links;
-        t.link_cap = c->link_cap;
+        t.lay = c->lay;
         t.link_max = c->link_max;
-        if (c->link_max > 0)
-            HIPCHK(c, hipMemcpyAsync(t.links, c->links, sizeof(LinkRec) * (size_t)need,
+        if (c->link_max > 0 && c->lay->total > 0)
+            HIPCHK(c, hipMemcpyAsync(t.links, c->links, sizeof(LinkRec) * (size_t)c->lay->total,
                                      hipMemcpyDeviceToDevice, c->stream));
         // cursors, particle state and the DEM state the next dem_step starts
         // from (for the coupled adjoint), in one launch
@@ -417,7 +459,9 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     } else {
         c->dense = cfg->classify_mode == LBM_CLASSIFY_SWEEP;
     }
-    c->link_cap = std::max<int64_t>(256, (32 * S2 + 255) / 256 * 256);
+    // every segment sized for the largest box until a classification has
+    // counted each particle's links
+    const int64_t seg0 = std::max<int64_t>(256, (32 * S2 + 255) / 256 * 256);
     c->cand_cap = std::max<int64_t>(256, (8 * S2 + 255) / 256 * 256);
     c->refill_cap = std::max<int64_t>(1 << 16, (int64_t)np * S2);
     hipError_t e = hipSuccess;
@@ -441,7 +485,12 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
         if (e == hipSuccess) e = alloc(&c->quat_prev, (size_t)4 * np);
         if (e == hipSuccess) e = hipMemsetAsync(c->cand_prev_count, 0, sizeof(uint32_t) * np, c->stream);
     }
-    if (e == hipSuccess && np) e = alloc(&c->links, (size_t)np * c->link_cap);
+    if (e == hipSuccess) {
+        c->lay = make_layout(std::vector<int64_t>((size_t)np, seg0));
+        c->lay_initial = true;
+        if (!c->lay) e = hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess && np) e = alloc(&c->links, (size_t)c->lay->total);
     if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
     if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->fc, (size_t)6 * std::max(np, 1));
@@ -699,7 +748,13 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
             }
             const int64_t nref = c->host_stage[kCtrRefill];
             const bool grow_cand = cmax > c->cand_cap;
-            const bool grow_links = lmax > c->link_cap;
+            // a segment outgrown, or the first counts: every segment sized
+            // from its own particle's count (and never below what it was,
+            // once sized)
+            bool grow_links = c->lay_initial;
+            for (int p = 0; p < np && !grow_links; ++p)
+                grow_links = link_counts[(size_t)p * kCursorPad] >
+                             c->lay->off[p + 1] - c->lay->off[p];
             const bool grow_refill = nref > c->refill_cap;
             if (!grow_cand && !grow_links && !grow_refill) {
                 c->link_max = lmax;
@@ -719,10 +774,20 @@ int lbm_classify_nodes(lbm_ctx* c, const lbm_particles* P, lbm_counts* out)
                 HIPCHK(c, LQ(c, launch_mark)(c, cp.own_new, Pd, cp.slot, cp.inc));  // same owners, full list
             }
             if (grow_links) {
+                std::vector<int64_t> seg((size_t)np);
+                for (int p = 0; p < np; ++p) {
+                    seg[(size_t)p] = link_segment(link_counts[(size_t)p * kCursorPad]);
+                    if (!c->lay_initial)
+                        seg[(size_t)p] = std::max(seg[(size_t)p],
+                                                  c->lay->off[p + 1] - c->lay->off[p]);
+                }
+                auto lay = make_layout(seg);
+                if (!lay) return fail(c, LBM_ENOMEM, "link layout allocation failed");
                 HIPCHK(c, hipFree(c->links));
                 c->links = nullptr;
-                c->link_cap = (lmax + lmax / 4 + 255) / 256 * 256;
-                if (alloc(&c->links, (size_t)np * c->link_cap) != hipSuccess)
+                c->lay = lay;
+                c->lay_initial = false;
+                if (alloc(&c->links, (size_t)std::max<int64_t>(c->lay->total, 1)) != hipSuccess)
                     return fail(c, LBM_ENOMEM, "link list allocation failed");
             }
             if (grow_cand || grow_links) {
@@ -768,7 +833,7 @@ int lbm_classify_nodes_async(lbm_ctx* c, const lbm_particles* P)
         rc = classify_enqueue(c, to_dev(P), cp);
         if (rc) return rc;
         HIPCHK(c, LQ(c, launch_latch_deferred)(c));
-        c->link_max = c->link_cap;  // lbm_step covers the whole capacity
+        c->link_max = c->lay->max_seg;  // lbm_step covers every segment whole
         c->deferred = true;
     } else {
         c->link_max = 0;
@@ -1123,7 +1188,7 @@ static GeometryLayout geometry_layout(const lbm_ctx* c)
     L.own = 0;
     L.flag = L.own + align256(c->sizes.owner_bytes);
     L.links = L.flag + align256(c->sizes.flag_bytes);
-    L.cursors = L.links + align256(sizeof(LinkRec) * np * (size_t)c->link_cap);
+    L.cursors = L.links + align256(sizeof(LinkRec) * (size_t)c->lay->total);
     L.refill_ctr = L.cursors + align256(sizeof(uint32_t) * kCursorPad * np);
     L.refill = L.refill_ctr + 256;
     L.ball = L.refill + align256(sizeof(RefillRec) * (size_t)c->refill_cap);
@@ -1133,7 +1198,7 @@ static GeometryLayout geometry_layout(const lbm_ctx* c)
 
 static uint64_t geometry_tag(const lbm_ctx* c)
 {
-    return ((uint64_t)c->link_cap << 32) ^ (uint64_t)c->refill_cap;
+    return c->lay->tag ^ ((uint64_t)c->refill_cap * 0x9E3779B97F4A7C15ull);
 }
 
 int lbm_geometry_bytes(const lbm_ctx* c, size_t* bytes, uint64_t* tag)
@@ -1160,7 +1225,7 @@ int lbm_geometry_save(lbm_ctx* c, void* dst_dev)
     seg(c->flag, L.flag, c->sizes.flag_bytes);
     if (np > 0) {
         const int slot = (int)((c->n_classify - 1) % 3);
-        seg(c->links, L.links, sizeof(LinkRec) * np * c->link_cap);
+        seg(c->links, L.links, sizeof(LinkRec) * (size_t)c->lay->total);
         seg(c->link_cursor, L.cursors, sizeof(uint32_t) * kCursorPad * np);
         seg(c->refill_cursor, L.refill_ctr, sizeof(uint32_t));
         seg(c->refill, L.refill, sizeof(RefillRec) * c->refill_cap);
@@ -1175,8 +1240,8 @@ int lbm_geometry_load(lbm_ctx* c, const void* src_dev, uint64_t tag, const lbm_p
     if (!c || !src_dev) return fail(c, LBM_EINVAL, "null argument");
     if (c->failed) return fail(c, LBM_ESTATE, "context failed earlier: " + c->last_error);
     if (tag != geometry_tag(c))
-        return fail(c, LBM_ESTATE, "lbm_geometry_load: the link or refill list capacity changed "
-                                   "since the snapshot was sized");
+        return fail(c, LBM_ESTATE, "lbm_geometry_load: the link layout or the refill list "
+                                   "capacity changed since the snapshot was sized");
     int rc = check_particles(c, P, false);
     if (rc) return rc;
     const int np = c->cfg.n_particles;
@@ -1190,7 +1255,7 @@ int lbm_geometry_load(lbm_ctx* c, const void* src_dev, uint64_t tag, const lbm_p
     seg(cp.own_new, L.own, c->sizes.owner_bytes);
     seg(c->flag, L.flag, c->sizes.flag_bytes);
     if (np > 0) {
-        seg(c->links, L.links, sizeof(LinkRec) * np * c->link_cap);
+        seg(c->links, L.links, sizeof(LinkRec) * (size_t)c->lay->total);
         seg(c->link_cursor, L.cursors, sizeof(uint32_t) * kCursorPad * np);
         seg(c->refill_cursor, L.refill_ctr, sizeof(uint32_t));
         seg(c->refill, L.refill, sizeof(RefillRec) * c->refill_cap);
@@ -1203,7 +1268,7 @@ int lbm_geometry_load(lbm_ctx* c, const void* src_dev, uint64_t tag, const lbm_p
             PhaseTimer tm(c, LBM_PHASE_REFILL);
             HIPCHK(c, LQ(c, launch_refill)(c, cp.refill_src, c->f[c->cur], cp.own_prev, to_dev(P)));
         }
-        c->link_max = c->link_cap;  // lbm_step covers the whole capacity
+        c->link_max = c->lay->max_seg;  // lbm_step covers every segment whole
     } else {
         c->link_max = c->link_total = c->refill_total = 0;
     }

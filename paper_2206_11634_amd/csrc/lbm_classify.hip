@@ -601,8 +601,9 @@ __device__ __forceinline__ int select_bit(uint64_t m, uint32_t k)
 __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ err, const uint32_t* own, const double* ball, PartDev P,
                                                Geom g, const uint32_t* cand, int64_t cand_cap,
                                                const uint32_t* cand_cursors, LinkRec* links,
-                                               int64_t cap, uint32_t* cursors, int treat,
-                                               uint32_t gx, uint32_t cpw)
+                                               const int64_t* __restrict__ loff,
+                                               uint32_t* cursors, int treat, uint32_t gx,
+                                               uint32_t cpw)
 {
     if (*err) return;  // the boxes failed their check: leave every plane as it is
     __shared__ double sp[4 * kMaxCtrl];
@@ -614,7 +615,8 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
     const double* B = ball + 4 * p;
     const uint32_t* list = cand + (int64_t)p * cand_cap;
     const uint32_t count = min((uint32_t)cand_cap, cand_cursors[(int64_t)p * kCursorPad]);
-    LinkRec* out = links + (int64_t)p * cap;
+    LinkRec* out = links + loff[p];
+    const int64_t cap = loff[p + 1] - loff[p];  // p's segment
     uint32_t* cursor = cursors + (int64_t)p * kCursorPad;
     const int lane = threadIdx.x & 63;
     const uint32_t chunk = 4u * cpw;  // candidates of one workgroup per round
@@ -824,14 +826,14 @@ __global__ void k_reset_counters(uint32_t* ctr, int np, uint32_t* cand_prev_coun
 // After an asynchronous classification: latch its box check and any list
 // overflow (a count above its capacity) into the deferred word, which no
 // classification clears.
-__global__ void k_latch_deferred(uint32_t* ctr, int np, int np1, uint32_t link_cap,
+__global__ void k_latch_deferred(uint32_t* ctr, int np, int np1, const int64_t* loff,
                                  uint32_t cand_cap, uint32_t refill_cap)
 {
     uint32_t bad = 0;
     for (int p = (int)threadIdx.x; p < np; p += (int)blockDim.x) {
         const uint32_t nl = ctr[kStageHead + (int64_t)p * kCursorPad];
         const uint32_t nc = ctr[kStageHead + (int64_t)(np1 + p) * kCursorPad];
-        if (nl > link_cap || nc > cand_cap) bad = kDeferredOverflow;
+        if ((int64_t)nl > loff[p + 1] - loff[p] || nc > cand_cap) bad = kDeferredOverflow;
     }
     if (threadIdx.x == 0) {
         if (ctr[kCtrRefill] > refill_cap) bad |= kDeferredOverflow;
@@ -848,15 +850,18 @@ __global__ void k_owner_export(const uint32_t* own, int32_t* out, uint32_t ncell
     out[i] = o == kFluid ? 0 : (int32_t)o + 1;
 }
 
-__global__ void k_link_export(const LinkRec* links, const uint32_t* cursors, int64_t cap,
+__global__ void k_link_export(const LinkRec* links, const uint32_t* cursors,
+                              const int64_t* loff, const uint32_t* chunk,
                               const int64_t* offsets, int32_t* node, int8_t* d, int8_t* kind,
                               int32_t* part, double* q)
 {
-    const int p = blockIdx.y;
-    const uint32_t cnt = min((uint32_t)cap, cursors[(int64_t)p * kCursorPad]);
-    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    // one workgroup per 256-record chunk of the layout
+    const int p = (int)chunk[blockIdx.x];
+    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t l = gi - loff[p];
+    const int64_t cnt = min(loff[p + 1] - loff[p], (int64_t)cursors[(int64_t)p * kCursorPad]);
     if (l >= cnt) return;
-    const LinkRec r = links[(int64_t)p * cap + l];
+    const LinkRec r = links[gi];
     const int64_t o = offsets[p] + l;
     node[o] = (int32_t)r.node;
     d[o] = (int8_t)r.d;
@@ -946,8 +951,8 @@ hipError_t launch_links(lbm_ctx* c, const uint32_t* own, const PartDev& P, int s
     const uint32_t nb = (per * (uint32_t)np + 7u) & ~7u;
     hipLaunchKernelGGL(k_links, dim3(nb), dim3(256), 0, c->stream, c->err, own,
                        c->ball_hist + (int64_t)slot * 4 * np, P, c->geom, c->cand, c->cand_cap,
-                       c->cand_cursor, c->links, c->link_cap, c->link_cursor, c->cfg.treatments,
-                       per, cpw);
+                       c->cand_cursor, c->links, c->lay->off_dev, c->link_cursor,
+                       c->cfg.treatments, per, cpw);
     return hipGetLastError();
 }
 
@@ -963,7 +968,7 @@ hipError_t launch_latch_deferred(lbm_ctx* c)
 {
     const int np = c->cfg.n_particles;
     hipLaunchKernelGGL(k_latch_deferred, dim3(1), dim3(256), 0, c->stream, c->ctr, np,
-                       std::max(np, 1), (uint32_t)c->link_cap, (uint32_t)c->cand_cap,
+                       std::max(np, 1), c->lay->off_dev, (uint32_t)c->cand_cap,
                        (uint32_t)c->refill_cap);
     return hipGetLastError();
 }
@@ -979,9 +984,10 @@ hipError_t launch_link_export(const lbm_ctx* c, int32_t* node, int8_t* d, int8_t
                               int32_t* part, double* q, const int64_t* offsets_dev)
 {
     const int np = c->cfg.n_particles;
-    if (np == 0 || c->link_max == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_link_export, dim3(blocks_for(c->link_max), np), dim3(256), 0, c->stream,
-                       c->links, c->link_cursor, c->link_cap, offsets_dev, node, d, kind, part, q);
+    if (np == 0 || c->link_max == 0 || c->lay->chunks() == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_link_export, dim3((uint32_t)c->lay->chunks()), dim3(256), 0, c->stream,
+                       c->links, c->link_cursor, c->lay->off_dev, c->lay->chunk_dev, offsets_dev,
+                       node, d, kind, part, q);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -69,15 +70,36 @@ struct RefillRec {
     uint32_t part;
 };
 
+// Where each particle's link records lie: particle p's segment is
+// [off[p], off[p+1]), a multiple of 256 records sized from its own link
+// count, and chunk_dev[b] is the particle of the 256-record chunk b, so the
+// link kernels run one workgroup per chunk.  A layout is never changed once
+// made (growing the lists makes a new one); the context and every taped step
+// recorded with it hold a reference.
+struct LinkLayout {
+    std::vector<int64_t> off;        // host copy, np + 1 entries
+    int64_t total = 0;               // records: off[np]
+    int64_t max_seg = 0;             // the largest segment
+    int64_t* off_dev = nullptr;      // [np + 1]
+    uint32_t* chunk_dev = nullptr;   // [total / 256]
+    uint64_t tag = 0;                // hash of off
+    int64_t chunks() const { return total / 256; }
+    ~LinkLayout()
+    {
+        (void)hipFree(off_dev);
+        (void)hipFree(chunk_dev);
+    }
+};
+
 // One recorded lattice step for the adjoint: populations after the link
 // reconstruction (ghost slots filled), owners, links and particle state.
-// One taped step.  Its fixed-size parts (f, own, cursor, part, dem, dem_key)
-// are carved from the context's tape slabs; links are allocated per step.
+// Its fixed-size parts (f, own, cursor, part, dem, dem_key) are carved from
+// the context's tape slabs; links are allocated per step.
 struct TapeStep {
     void* f = nullptr;
     uint32_t* own = nullptr;
     LinkRec* links = nullptr;
-    int64_t link_cap = 0;        // per particle, of this record
+    std::shared_ptr<const LinkLayout> lay;  // the layout of this record's links
     int64_t link_alloc = 0;      // records allocated
     uint32_t* cursor = nullptr;  // [np * kCursorPad]
     int64_t link_max = 0;
@@ -184,7 +206,8 @@ struct lbm_ctx {
     double* quat_prev = nullptr;          // [np][4]
     bool inc_ok = false;                  // the previous classification's lists are valid
     mdlbm::LinkRec* links = nullptr;
-    int64_t link_cap = 0;         // per particle
+    std::shared_ptr<const mdlbm::LinkLayout> lay;  // where each particle's links lie
+    bool lay_initial = true;      // the layout sized before any count was known
     uint32_t* link_cursor = nullptr;  // [np * kCursorPad]
     int64_t link_max = 0;         // max links of one particle at the last classification
     int64_t link_total = 0;

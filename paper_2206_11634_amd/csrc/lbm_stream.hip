@@ -214,19 +214,24 @@ template <int S>
 __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict__ f,
                                                   const typename St<S>::M* __restrict__ mom,
                                                   const LinkRec* __restrict__ links,
-                                                  const uint32_t* __restrict__ cursor, int64_t cap,
+                                                  const uint32_t* __restrict__ cursor,
+                                                  const int64_t* __restrict__ loff,
+                                                  const uint32_t* __restrict__ chunk,
                                                   PartDev P, double* __restrict__ FT, Geom g,
                                                   Phys ph, uint32_t* __restrict__ numeric)
 {
     using A = typename St<S>::A;
     constexpr bool DEV = St<S>::dev;
-    const int p = blockIdx.y;
-    const uint32_t cnt = min((uint32_t)cap, cursor[(int64_t)p * kCursorPad]);
-    if (blockIdx.x * 256u >= cnt) return;
-    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    // one workgroup per 256-record chunk of the link layout (chunks do not
+    // straddle particles)
+    const int p = (int)chunk[blockIdx.x];
+    const int64_t g0 = (int64_t)blockIdx.x * 256;
+    const int64_t cnt = min(loff[p + 1] - loff[p], (int64_t)cursor[(int64_t)p * kCursorPad]);
+    if (g0 - loff[p] >= cnt) return;  // uniform over the block
+    const int64_t l = g0 - loff[p] + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     if (l < cnt) {
-        const LinkRec r = links[(int64_t)p * cap + l];
+        const LinkRec r = links[g0 + threadIdx.x];
         const int d = r.d, db = opp(d);
         const int e[3] = {cx(d), cy(d), cz(d)};
         const uint32_t nx = g.n[0], ny = g.n[1];
@@ -553,11 +558,12 @@ template <int S>
 struct RunBC {
     static hipError_t run(lbm_ctx* c, void* f, const PartDev& P)
     {
-        if (c->cfg.n_particles == 0 || c->link_max == 0) return hipSuccess;
-        dim3 grid(blocks_for(c->link_max), c->cfg.n_particles);
-        hipLaunchKernelGGL(k_boundary<S>, grid, dim3(256), 0, c->stream, (typename St<S>::T*)f,
-                           (const typename St<S>::M*)c->mom, c->links, c->link_cursor, c->link_cap,
-                           P, c->FT, c->geom, c->phys, c->numeric);
+        if (c->cfg.n_particles == 0 || c->link_max == 0 || c->lay->chunks() == 0)
+            return hipSuccess;
+        hipLaunchKernelGGL(k_boundary<S>, dim3((uint32_t)c->lay->chunks()), dim3(256), 0,
+                           c->stream, (typename St<S>::T*)f, (const typename St<S>::M*)c->mom,
+                           c->links, c->link_cursor, c->lay->off_dev, c->lay->chunk_dev, P, c->FT,
+                           c->geom, c->phys, c->numeric);
         return hipGetLastError();
     }
 };
