@@ -329,7 +329,29 @@ int dem_alloc(lbm_ctx* c)
     HIPCHK(c, hipMemsetAsync(c->hist_pp, 0, sizeof(double) * slots * 8, c->stream));
     HIPCHK(c, hipMemsetAsync(c->hist_key, 0, sizeof(int32_t) * slots, c->stream));
     HIPCHK(c, hipMemsetAsync(c->hist_pw, 0, sizeof(double) * np * 6 * 8, c->stream));
+    if (np >= (size_t)kGridMinParticles) {
+        // counts and starts, cursors, the binned particles, the grid's shape
+        c->grid_cap = (int64_t)std::max<size_t>(4096, 4 * np);
+        const size_t words = 2 * (size_t)c->grid_cap + 1 + np + 4;
+        if (alloc(&c->grid, words) != hipSuccess || alloc(&c->grid_size, 3) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "broad-phase grid allocation failed");
+    }
     return LBM_OK;
+}
+
+// The work space of a dem_step call on the context.
+DemScratch dem_scratch(lbm_ctx* c)
+{
+    DemScratch ws{c->pairs, c->pair_count, c->reach};
+    if (c->grid) {
+        ws.gcount = c->grid;
+        ws.gcursor = c->grid + c->grid_cap + 1;
+        ws.gitem = c->grid + 2 * c->grid_cap + 1;
+        ws.gdim = reinterpret_cast<int32_t*>(ws.gitem + c->cfg.n_particles);
+        ws.gsize = c->grid_size;
+        ws.gcap = c->grid_cap;
+    }
+    return ws;
 }
 
 // Bytes of the DEM state saved by lbm_dem_checkpoint_save, in its order: the
@@ -560,6 +582,8 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->hist_key);
     (void)hipFree(c->pairs);
     (void)hipFree(c->pair_count);
+    (void)hipFree(c->grid);
+    (void)hipFree(c->grid_size);
     (void)hipFree(c->hist_pw);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
     for (hipStream_t s : {c->s_bulk, c->s_dem})
@@ -901,7 +925,7 @@ int dem_step(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_param
     const int np = c->cfg.n_particles;
     if (np == 0) return LBM_OK;
     PhaseTimer tm(c, LBM_PHASE_DEM);
-    HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm, DemScratch{c->pairs, c->pair_count, c->reach}));
+    HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm, dem_scratch(c)));
     return LBM_OK;
 }
 
@@ -946,7 +970,7 @@ int lbm_step_dem(lbm_ctx* c, lbm_particles* P, int n_sub, double dt, const dem_p
         OnStream os(c, c->s_dem);
         PhaseTimer tm(c, LBM_PHASE_DEM);
         HIPCHK(c, launch_dem(c, to_dev(P), n_sub, dt, *prm,
-                             DemScratch{c->pairs, c->pair_count, c->reach}));
+                             dem_scratch(c)));
         HIPCHK(c, hipEventRecord(c->ev_dem, c->s_dem));
     }
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_bulk, 0));

@@ -493,6 +493,188 @@ __global__ __launch_bounds__(256) void k_pairs(PartDev P, int32_t* key, double T
     }
 }
 
+// ---------------------------------------------------------------------------
+// Broad phase on a cell grid (many particles): every pair that
+// pair_candidate accepts is at most H = 2 max_p (reach_p + R_s,p) + 2 max_p
+// |v_p| T + 1/2 apart, so with cells at least H wide (fewer cells than the
+// arrays hold: wider) its particles lie in the same or adjacent cells.  The
+// same pairs, records and latch as k_pairs; only the list's order differs,
+// and the contact forces are summed by atomics in any order either way.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int grid_cell(const PartDev& P, int p, const Geom& g,
+                                         const int32_t* gdim, const double* gsize, int c3[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double x = P.pos[3 * p + a];
+        if (g.per[a]) x -= (double)g.n[a] * floor(x / (double)g.n[a]);  // into [0, n]
+        int k = (int)floor(x / gsize[a]);
+        c3[a] = min(max(k, 0), gdim[a] - 1);
+    }
+    return c3[0] + gdim[0] * (c3[1] + gdim[1] * c3[2]);
+}
+
+// One workgroup: the cell width from the particles, the grid's shape, and
+// the counts cleared.
+__global__ __launch_bounds__(1024) void k_grid_setup(PartDev P, double T, Geom g, int32_t* gdim,
+                                                     double* gsize, uint32_t* gcount, int64_t gcap)
+{
+    __shared__ double red[2][16];
+    __shared__ int ncell;
+    double h = 0.0, v = 0.0;
+    for (int p = (int)threadIdx.x; p < P.n; p += (int)blockDim.x) {
+        h = fmax(h, reach(P, p) + P.rs[p]);
+        const double* vp = P.vel + 3 * p;
+        v = fmax(v, sqrt(dot3(vp, vp)));
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        h = fmax(h, __shfl_xor(h, m, 64));
+        v = fmax(v, __shfl_xor(v, m, 64));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = h;
+        red[1][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double hm = 0.0, vm = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            hm = fmax(hm, red[0][w]);
+            vm = fmax(vm, red[1][w]);
+        }
+        // the largest accepted distance, with a margin for rounding
+        double H = (2.0 * hm + 2.0 * vm * T + 0.5) * (1.0 + 1e-9) + 1e-9;
+        int nc[3];
+        int64_t total = 1;
+        for (int it = 0; it < 64; ++it) {
+            total = 1;
+            for (int a = 0; a < 3; ++a) {
+                nc[a] = max(1, (int)floor((double)g.n[a] / H));
+                total *= nc[a];
+            }
+            if (total <= gcap) break;
+            H *= 1.25;  // more cells than the arrays hold: wider cells
+        }
+        for (int a = 0; a < 3; ++a) {
+            gdim[a] = nc[a];
+            gsize[a] = (double)g.n[a] / (double)nc[a];
+        }
+        gdim[3] = (int32_t)total;
+        ncell = (int)total;
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i <= ncell; i += (int)blockDim.x) gcount[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_grid_count(PartDev P, Geom g, const int32_t* gdim,
+                                                    const double* gsize, uint32_t* gcount)
+{
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= P.n) return;
+    int c3[3];
+    atomicAdd(gcount + grid_cell(P, p, g, gdim, gsize, c3), 1u);
+}
+
+// One workgroup: exclusive starts of the cells in place (gcount[C] = n),
+// and the scatter cursors.
+__global__ __launch_bounds__(1024) void k_grid_scan(const int32_t* gdim, uint32_t* gcount,
+                                                    uint32_t* gcursor)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    const int C = gdim[3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0u;
+    __syncthreads();
+    for (int b0 = 0; b0 < C; b0 += (int)blockDim.x) {
+        const int i = b0 + (int)threadIdx.x;
+        const uint32_t x = i < C ? gcount[i] : 0u;
+        uint32_t incl = x;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        const uint32_t excl = before + incl - x;
+        __syncthreads();  // every thread has read carry and wsum
+        if (i < C) {
+            gcount[i] = excl;
+            gcursor[i] = excl;
+        }
+        if (threadIdx.x == blockDim.x - 1) carry = excl + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gcount[C] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_grid_scatter(PartDev P, Geom g, const int32_t* gdim,
+                                                      const double* gsize, uint32_t* gcursor,
+                                                      uint32_t* gitem)
+{
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= P.n) return;
+    int c3[3];
+    const uint32_t slot = atomicAdd(gcursor + grid_cell(P, p, g, gdim, gsize, c3), 1u);
+    gitem[slot] = (uint32_t)p;
+}
+
+// The cells around one along an axis: c - 1, c, c + 1, wrapped on a
+// periodic axis, clipped at walls, each once.
+__device__ __forceinline__ int around(int c, int nc, int per, int out[3])
+{
+    int m = 0;
+    for (int d = -1; d <= 1; ++d) {
+        int k = c + d;
+        if (k < 0 || k >= nc) {
+            if (!per) continue;
+            k = (k + nc) % nc;
+        }
+        bool seen = false;
+        for (int t = 0; t < m; ++t) seen = seen || out[t] == k;
+        if (!seen) out[m++] = k;
+    }
+    return m;
+}
+
+// One thread per particle i: the partners j > i in the cells around i's.
+__global__ __launch_bounds__(256) void k_pairs_grid(PartDev P, int32_t* key, double T, Geom g,
+                                                    const int32_t* gdim, const double* gsize,
+                                                    const uint32_t* gstart, const uint32_t* gitem,
+                                                    uint64_t* list, uint32_t* count,
+                                                    uint32_t* deferred)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= P.n) return;
+    int c3[3];
+    grid_cell(P, i, g, gdim, gsize, c3);
+    int ax[3][3], na[3];
+    for (int a = 0; a < 3; ++a) na[a] = around(c3[a], gdim[a], g.per[a], ax[a]);
+    int32_t* ki = key + (int64_t)i * kPairSlots;
+    for (int u = 0; u < na[2]; ++u)
+        for (int t = 0; t < na[1]; ++t)
+            for (int s = 0; s < na[0]; ++s) {
+                const int cell = ax[0][s] + gdim[0] * (ax[1][t] + gdim[1] * ax[2][u]);
+                for (uint32_t k = gstart[cell]; k < gstart[cell + 1]; ++k) {
+                    const int j = (int)gitem[k];
+                    if (j <= i || !pair_candidate(P, i, j, T, g)) continue;
+                    int slot = -1;
+                    for (int q = 0; q < kPairSlots && slot < 0; ++q)
+                        if (ki[q] == j + 1) slot = q;
+                    for (int q = 0; q < kPairSlots && slot < 0; ++q)
+                        if (atomicCAS(ki + q, 0, j + 1) == 0) slot = q;
+                    if (slot < 0) {
+                        atomicOr(deferred, kDeferredSlots);
+                        continue;
+                    }
+                    const uint32_t at = atomicAdd(count, 1u);
+                    list[at] = ((uint64_t)slot << 32) | ((uint64_t)i << 16) | (uint64_t)j;
+                }
+            }
+}
+
 // One substep's contacts: the walls of every body (6 n items), then the
 // listed pairs; thread t of nthreads strides over both.
 __device__ void contacts(const PartDev& P, double* hist, double* hist_w, double* fc,
@@ -660,8 +842,23 @@ hipError_t launch_dem(lbm_ctx* ctx, const PartDev& P, int n_sub, double dt, cons
     const uint32_t bq = (uint32_t)(((int64_t)np * np + 255) / 256);
     hipLaunchKernelGGL(k_pair_release, dim3(br), dim3(256), 0, ctx->stream, P, ctx->hist_pp,
                        ctx->hist_key, T, ctx->geom, ws.count);
-    hipLaunchKernelGGL(k_pairs, dim3(bq), dim3(256), 0, ctx->stream, P, ctx->hist_key, T,
-                       ctx->geom, ws.pairs, ws.count, ctx->ctr + kCtrDeferred);
+    if (ws.gcount && np >= kGridMinParticles) {
+        const uint32_t bn = (uint32_t)((np + 255) / 256);
+        hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(1024), 0, ctx->stream, P, T, ctx->geom,
+                           ws.gdim, ws.gsize, ws.gcount, ws.gcap);
+        hipLaunchKernelGGL(k_grid_count, dim3(bn), dim3(256), 0, ctx->stream, P, ctx->geom, ws.gdim,
+                           ws.gsize, ws.gcount);
+        hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, ctx->stream, ws.gdim, ws.gcount,
+                           ws.gcursor);
+        hipLaunchKernelGGL(k_grid_scatter, dim3(bn), dim3(256), 0, ctx->stream, P, ctx->geom, ws.gdim,
+                           ws.gsize, ws.gcursor, ws.gitem);
+        hipLaunchKernelGGL(k_pairs_grid, dim3(bn), dim3(256), 0, ctx->stream, P, ctx->hist_key, T,
+                           ctx->geom, ws.gdim, ws.gsize, ws.gcount, ws.gitem, ws.pairs, ws.count,
+                           ctx->ctr + kCtrDeferred);
+    } else {
+        hipLaunchKernelGGL(k_pairs, dim3(bq), dim3(256), 0, ctx->stream, P, ctx->hist_key, T,
+                           ctx->geom, ws.pairs, ws.count, ctx->ctr + kCtrDeferred);
+    }
     const int64_t most = 6 * (int64_t)np + (int64_t)np * kPairSlots;
     const uint32_t bc = (uint32_t)std::min<int64_t>((most + 255) / 256, 1024);
     // first half, then per substep the contacts and the two half kicks

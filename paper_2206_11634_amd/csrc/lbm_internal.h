@@ -230,6 +230,9 @@ struct lbm_ctx {
     uint32_t* numeric = nullptr;  // set by a step whose force or torque sums are not finite
     uint64_t* pairs = nullptr;    // [np kPairSlots] candidate pairs of a dem_step call
     uint32_t* pair_count = nullptr;
+    uint32_t* grid = nullptr;     // the broad phase's cell grid (kGridMinParticles or more)
+    double* grid_size = nullptr;
+    int64_t grid_cap = 0;
     // kernel timing
     bool prof = false;
     struct Timed {
@@ -295,11 +298,23 @@ namespace q15 {
 // Launchers (lbm_dem.hip, lbm_dem_adjoint.hip)
 // Work space of one dem_step call: the candidate pairs (i, j, history slot),
 // their count, and each particle's broad-phase reach.
+// The work space of one dem_step call.  With the cell grid (gcount not
+// null), the broad phase bins the particles into cells at least as wide as
+// the largest pair distance it can accept and tests each particle against
+// the 27 cells around its own, instead of all n^2 pairs.
 struct DemScratch {
     uint64_t* pairs;
     uint32_t* count;
     double* reach;
+    uint32_t* gcount = nullptr;   // [gcap + 1]: counts per cell, then their starts
+    uint32_t* gcursor = nullptr;  // [gcap]
+    uint32_t* gitem = nullptr;    // [n]: particles by cell
+    int32_t* gdim = nullptr;      // cells per axis, and their product
+    double* gsize = nullptr;      // cell widths
+    int64_t gcap = 0;             // cells the arrays hold
 };
+// Particle counts from which dem_step uses the cell grid.
+constexpr int kGridMinParticles = 2048;
 hipError_t launch_dem(lbm_ctx* c, const PartDev& P, int n_sub, double dt, const dem_params& prm,
                       const DemScratch& s);
 // Most particles dem_step_noalloc takes (its static work space holds the

@@ -141,6 +141,39 @@ def test_c4_dem_full_size():
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
 
 
+def test_dem_cell_grid_dense_spheres():
+    """2548 spheres (d = 5.2) on a jittered 5-unit lattice filling a 70^3 box
+    periodic in x and y: every body presses on its neighbours, across the
+    periodic faces too, so the broad phase on the cell grid (taken from 2048
+    particles on) must find the same pairs as the oracle's all-pairs test."""
+    rng = np.random.default_rng(21)
+    lat = W.LatticeSpec(70, 70, 70, (1, 1, 0), tau=0.6)
+    sh = W.sphere_shape(5.2, 0.1)
+    g = (np.arange(14) + 0.5) * 5.0
+    z = 4.0 + 5.0 * np.arange(13)
+    X, Y, Z = np.meshgrid(g, g, z, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], -1) + rng.normal(size=(14 * 14 * 13, 3)) * 0.15
+    n = len(pos)
+    quats = np.array([W.random_quaternion(rng) for _ in range(n)])
+    ps = W.make_particles([sh] * n, pos, quats, 1.5)
+    ps = _moving(ps, 22, 0.02, 0.002)
+    kw = W.dem_defaults(ps, gravity=(0.0, 0.0, -1e-4))
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    dem = O.OracleDEM(ps, lat)
+    P = ps.copy()
+    zero = np.zeros((n, 3))
+    for _ in range(8):
+        gpu.dem(parts, 10, 0.1, B.DemParams.make(**kw))
+        dem.step(P, zero, zero, O.DemParams(**kw), 10, 0.1)
+    G = parts.to_host(ps)
+    gpu.close()
+    assert np.abs(P.pos - ps.pos).max() > 1e-3  # the contacts moved the bodies
+    for k in ("pos", "vel", "omega", "quat", "world_pts"):
+        a, b = getattr(G, k), getattr(P, k)
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
+
+
 # ---------------------------------------------------------------------------
 # long replay runs against the oracle's stored series
 # (tests/golden/make_drag_reference.py writes them with the oracle alone)
