@@ -71,6 +71,27 @@ typedef enum {
                              2q > 1 and 1 - 2q < 0; off: Eq. (neqd) for every q */
 } lbm_treatment;
 
+/* How the link pass sums the momentum-exchange terms of Eq. (mem) over each
+ * particle's links (Sec. 2.3.2); the per-link terms are the same FP64 values
+ * either way. */
+typedef enum {
+    LBM_FORCE_SUM_ATOMIC = 0, /* FP64 sums per wave and workgroup, then FP64 atomics
+                                 per particle: the order of the atomic additions,
+                                 and so the last bits of F and T, can change from
+                                 run to run (about 1e-16 relative) */
+    LBM_FORCE_SUM_EXACT = 1   /* every term rounded toward zero to a multiple
+                                 of 2^-80 and summed exactly in 128-bit
+                                 integers (two 64-bit atomics per workgroup and
+                                 component), then rounded to double: the same bits
+                                 on every run whatever the order of the links
+                                 (which classification appends with atomics).
+                                 Terms must lie below 2^46 in magnitude and sums
+                                 below 2^47; a term outside, or not finite, counts
+                                 as zero and latches LBM_ENUMERIC like a non-finite
+                                 sum.  For debugging and reproducibility checks;
+                                 12 * n_particles more 8-byte words of device memory */
+} lbm_force_sum;
+
 typedef enum {
     LBM_LINK_VIBB = 0,    /* x_f and x_ff fluid: VIBB reconstruction */
     LBM_LINK_HALFWAY = 1, /* x_f fluid, x_ff not: halfway bounce-back (treatment 1) */
@@ -95,6 +116,7 @@ typedef struct {
     int32_t classify_mode; /* lbm_classify_mode; the same owners, links and refill
                               sets either way, only the work differs */
     int32_t lattice;       /* lbm_lattice; 0 selects D3Q19 */
+    int32_t force_sum;     /* lbm_force_sum; 0: FP64 atomics */
 } lbm_config;
 
 typedef enum {

@@ -23,6 +23,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ECAPACITY, LBM_ENUMERIC, LBM_EDEVICE, LBM_ES
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 TREAT_VIBB, TREAT_MISSING, TREAT_EXACT_Q, TREAT_NEQ_SPLIT = 1, 2, 4, 8
 LINK_VIBB, LINK_HALFWAY, LINK_MISSING = 0, 1, 2
+FORCE_SUM_ATOMIC, FORCE_SUM_EXACT = 0, 1
 
 _P = ctypes.c_void_p
 
@@ -35,7 +36,7 @@ class LbmConfig(ctypes.Structure):
                 ("treatments", ctypes.c_int32), ("n_particles", ctypes.c_int32),
                 ("n_ctrl", ctypes.c_int32), ("box_half", ctypes.c_int32),
                 ("h16_scale", ctypes.c_double), ("stream", _P), ("classify_mode", ctypes.c_int32),
-                ("lattice", ctypes.c_int32)]
+                ("lattice", ctypes.c_int32), ("force_sum", ctypes.c_int32)]
 
 
 class LbmSizes(ctypes.Structure):
@@ -311,8 +312,10 @@ class Lattice:
 
     def __init__(self, lat, n_particles=0, n_ctrl=0, box_half=2, storage="f32",
                  treatments=TREAT_VIBB | TREAT_MISSING, h16_scale=0.0, device="cuda",
-                 classify="auto", lattice=19):
-        """lattice: 19 (D3Q19) or 15 (D3Q15, the paper's Sec. 2.2)."""
+                 classify="auto", lattice=19, exact_forces=False):
+        """lattice: 19 (D3Q19) or 15 (D3Q15, the paper's Sec. 2.2); exact_forces:
+        sum the link pass's momentum exchange exactly in 128-bit integers, so
+        that forces and torques are the same bits on every run."""
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -332,6 +335,7 @@ class Lattice:
         cfg.h16_scale = float(h16_scale)
         cfg.classify_mode = CLASSIFY[classify]
         cfg.lattice = int(lattice)
+        cfg.force_sum = FORCE_SUM_EXACT if exact_forces else FORCE_SUM_ATOMIC
         self.Q = 15 if int(lattice) == 15 else 19
         with torch.cuda.device(self.device):
             cfg.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)

@@ -408,6 +408,8 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (!cfg || !bufs || !out) return fail(nullptr, LBM_EINVAL, "null argument");
     if (cfg->classify_mode < LBM_CLASSIFY_AUTO || cfg->classify_mode > LBM_CLASSIFY_BALLS)
         return fail(nullptr, LBM_EINVAL, "unknown classify_mode");
+    if (cfg->force_sum != LBM_FORCE_SUM_ATOMIC && cfg->force_sum != LBM_FORCE_SUM_EXACT)
+        return fail(nullptr, LBM_EINVAL, "unknown force_sum");
     if (cfg->treatments &
         ~(LBM_TREAT_VIBB | LBM_TREAT_MISSING | LBM_TREAT_EXACT_Q | LBM_TREAT_NEQ_SPLIT))
         return fail(nullptr, LBM_EINVAL, "unknown treatment bits");
@@ -515,6 +517,8 @@ int lbm_init(const lbm_config* cfg, const lbm_buffers* bufs, lbm_ctx** out)
     if (e == hipSuccess && np) e = alloc(&c->links, (size_t)c->lay->total);
     if (e == hipSuccess) e = alloc(&c->refill, (size_t)c->refill_cap);
     if (e == hipSuccess) e = alloc(&c->FT, (size_t)6 * std::max(np, 1));
+    if (e == hipSuccess && np && cfg->force_sum == LBM_FORCE_SUM_EXACT)
+        e = alloc(&c->FX, (size_t)12 * np);
     if (e == hipSuccess) e = alloc(&c->fc, (size_t)6 * std::max(np, 1));
     if (e == hipSuccess) e = alloc(&c->reach, (size_t)std::max(np, 1));
     if (e == hipSuccess)
@@ -567,6 +571,7 @@ int lbm_destroy(lbm_ctx* c)
     (void)hipFree(c->refill);
     (void)hipFree(c->ctr);
     (void)hipFree(c->FT);
+    (void)hipFree(c->FX);
     (void)hipFree(c->cand_prev);
     (void)hipFree(c->cand_prev_count);
     (void)hipFree(c->quat_prev);

@@ -220,6 +220,7 @@ struct lbm_ctx {
     uint32_t* ctr = nullptr;      // the counter block: refill_cursor, err, numeric,
                                   // link_cursor and cand_cursor point into it
     double* FT = nullptr;         // [np][6] force, torque of the last step
+    unsigned long long* FX = nullptr;  // [np][6][lo, hi]: exact sums (LBM_FORCE_SUM_EXACT)
     uint32_t* host_stage = nullptr; // pinned staging for counters
     // DEM
     double* hist_pp = nullptr;    // [np][kPairSlots][8] pair histories

@@ -210,14 +210,42 @@ __global__ __launch_bounds__(256, 6) void k_stream_collide_x2(const typename St<
 // ---------------------------------------------------------------------------
 // Links: one thread per link record of one particle (blockIdx.y).
 // ---------------------------------------------------------------------------
-template <int S>
+// Exact force sums: a term v becomes the 128-bit two's-complement integer
+// v * 2^80 rounded toward zero (hi: the signed upper word, lo: the lower);
+// integer sums do not depend on their order.  Returns true, with v taken as
+// zero, for a term that is not finite or not below 2^46.
+__device__ __forceinline__ bool to_fixed(double v, uint64_t& lo, int64_t& hi)
+{
+    const bool bad = !(fabs(v) < 0x1p46);
+    const double a = bad ? 0.0 : fabs(v) * 0x1p16;  // exact: a power of two
+    const double h = floor(a);
+    const uint64_t H = (uint64_t)h;
+    const uint64_t L = (uint64_t)((a - h) * 0x1p64);  // a - h in [0, 1), exact for a >= 0
+    if (v < 0.0 && !bad) {
+        lo = 0ull - L;
+        hi = (int64_t)(0ull - H - (L != 0ull ? 1ull : 0ull));
+    } else {
+        lo = L;
+        hi = (int64_t)H;
+    }
+    return bad;
+}
+__device__ __forceinline__ void add128(uint64_t& lo, int64_t& hi, uint64_t blo, int64_t bhi)
+{
+    const uint64_t s = lo + blo;
+    hi = (int64_t)((uint64_t)hi + (uint64_t)bhi + (s < lo ? 1u : 0u));
+    lo = s;
+}
+
+template <int S, bool EXACT>
 __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict__ f,
                                                   const typename St<S>::M* __restrict__ mom,
                                                   const LinkRec* __restrict__ links,
                                                   const uint32_t* __restrict__ cursor,
                                                   const int64_t* __restrict__ loff,
                                                   const uint32_t* __restrict__ chunk,
-                                                  PartDev P, double* __restrict__ FT, Geom g,
+                                                  PartDev P, double* __restrict__ FT,
+                                                  unsigned long long* __restrict__ FX, Geom g,
                                                   Phys ph, uint32_t* __restrict__ numeric)
 {
     using A = typename St<S>::A;
@@ -326,20 +354,64 @@ __global__ __launch_bounds__(256) void k_boundary(typename St<S>::T* __restrict_
         acc[4] = rr[2] * t[0] - rr[0] * t[2];
         acc[5] = rr[0] * t[1] - rr[1] * t[0];
     }
-    __shared__ double red[4][6];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if constexpr (EXACT) {
+        // per link in 128-bit integers, then wave, workgroup and the
+        // particle's accumulator (the carry of the low word's atomic goes
+        // into the high word's)
+        __shared__ uint64_t rlo[4][6];
+        __shared__ int64_t rhi[4][6];
+        bool bad = false;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const double s = dsum_wave(acc[k]);
-        if (lane == 0) red[wv][k] = s;
+        for (int k = 0; k < 6; ++k) {
+            uint64_t lo;
+            int64_t hi;
+            bad = to_fixed(acc[k], lo, hi) || bad;
+            for (int m = 32; m >= 1; m >>= 1) {
+                const uint64_t blo = __shfl_xor((unsigned long long)lo, m, 64);
+                const int64_t bhi = __shfl_xor((long long)hi, m, 64);
+                add128(lo, hi, blo, bhi);
+            }
+            if (lane == 0) {
+                rlo[wv][k] = lo;
+                rhi[wv][k] = hi;
+            }
+        }
+        if (__ballot(bad) && lane == 0) atomicOr(numeric, 1u);  // reported by the next classification
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            uint64_t lo = rlo[0][threadIdx.x];
+            int64_t hi = rhi[0][threadIdx.x];
+            for (int w = 1; w < 4; ++w) add128(lo, hi, rlo[w][threadIdx.x], rhi[w][threadIdx.x]);
+            unsigned long long* a = FX + 2 * (6 * (int64_t)p + threadIdx.x);
+            const unsigned long long old = atomicAdd(a, (unsigned long long)lo);
+            const unsigned long long carry = old + lo < old ? 1ull : 0ull;
+            atomicAdd(a + 1, (unsigned long long)hi + carry);
+        }
+    } else {
+        __shared__ double red[4][6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double s = dsum_wave(acc[k]);
+            if (lane == 0) red[wv][k] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                             (red[2][threadIdx.x] + red[3][threadIdx.x]);
+            atomicAdd(FT + 6 * p + threadIdx.x, s);
+            if (!isfinite(s)) atomicOr(numeric, 1u);  // reported by the next classification
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                         (red[2][threadIdx.x] + red[3][threadIdx.x]);
-        atomicAdd(FT + 6 * p + threadIdx.x, s);
-        if (!isfinite(s)) atomicOr(numeric, 1u);  // reported by the next classification
-    }
+}
+
+// The exact sums as doubles (rounded once each word).
+__global__ __launch_bounds__(256) void k_fixed_to_f64(const unsigned long long* __restrict__ FX,
+                                                      double* __restrict__ FT, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    FT[i] = (double)(int64_t)FX[2 * i + 1] * 0x1p-16 + (double)FX[2 * i] * 0x1p-80;
 }
 
 // ---------------------------------------------------------------------------
@@ -560,10 +632,23 @@ struct RunBC {
     {
         if (c->cfg.n_particles == 0 || c->link_max == 0 || c->lay->chunks() == 0)
             return hipSuccess;
-        hipLaunchKernelGGL(k_boundary<S>, dim3((uint32_t)c->lay->chunks()), dim3(256), 0,
-                           c->stream, (typename St<S>::T*)f, (const typename St<S>::M*)c->mom,
-                           c->links, c->link_cursor, c->lay->off_dev, c->lay->chunk_dev, P, c->FT,
-                           c->geom, c->phys, c->numeric);
+        const dim3 grid((uint32_t)c->lay->chunks());
+        if (c->FX) {
+            const int64_t n6 = 6 * (int64_t)c->cfg.n_particles;
+            hipLaunchKernelGGL(k_zero, dim3(blocks_for(2 * n6)), dim3(256), 0, c->stream,
+                               reinterpret_cast<double*>(c->FX), 2 * n6);
+            hipLaunchKernelGGL((k_boundary<S, true>), grid, dim3(256), 0, c->stream,
+                               (typename St<S>::T*)f, (const typename St<S>::M*)c->mom, c->links,
+                               c->link_cursor, c->lay->off_dev, c->lay->chunk_dev, P, c->FT, c->FX,
+                               c->geom, c->phys, c->numeric);
+            hipLaunchKernelGGL(k_fixed_to_f64, dim3(blocks_for(n6)), dim3(256), 0, c->stream, c->FX,
+                               c->FT, n6);
+        } else {
+            hipLaunchKernelGGL((k_boundary<S, false>), grid, dim3(256), 0, c->stream,
+                               (typename St<S>::T*)f, (const typename St<S>::M*)c->mom, c->links,
+                               c->link_cursor, c->lay->off_dev, c->lay->chunk_dev, P, c->FT,
+                               nullptr, c->geom, c->phys, c->numeric);
+        }
         return hipGetLastError();
     }
 };

@@ -72,6 +72,15 @@ def test_init_rejects_unknown_classify_mode(lib):
     assert b"classify_mode" in lib.lbm_last_error(None)
 
 
+def test_init_rejects_unknown_force_sum(lib):
+    bufs = B.LbmBuffers()
+    ctx = ctypes.c_void_p()
+    cfg = _cfg()
+    cfg.force_sum = 2
+    assert lib.lbm_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.byref(ctx)) == B.LBM_EINVAL
+    assert b"force_sum" in lib.lbm_last_error(None)
+
+
 def test_init_rejects_unknown_treatment_bits(lib):
     bufs = B.LbmBuffers()
     ctx = ctypes.c_void_p()

@@ -39,9 +39,9 @@ def _compare_geometry(gpu, ora, tag):
 
 
 def _run(lat, ps, storage, steps, treat=3, check_geometry=True, tag="", classify="auto",
-         lattice=19):
+         lattice=19, exact_forces=False):
     gpu = B.Lattice.for_particles(lat, ps, storage=storage, treatments=treat, classify=classify,
-                                  lattice=lattice)
+                                  lattice=lattice, exact_forces=exact_forces)
     parts = B.DeviceParticles(ps)
     ora = O.Oracle(lat, Q=lattice, treat=treat)
     Fo_all, Fg_all, To_all, Tg_all = [], [], [], []
@@ -550,3 +550,48 @@ def test_dem_more_candidate_partners_than_history_records_is_reported():
         gpu.dem(parts, 2, 0.1, B.DemParams.make(**W.dem_defaults(ps)))
     assert e.value.code == B.LBM_ESTATE
     gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_exact_force_sum_matches_oracle(storage):
+    """LBM_FORCE_SUM_EXACT: the same per-link terms summed in 128-bit
+    integers; forces, torques and populations within the storage's bars."""
+    case = GEOM_CASES[1]
+    lat, ps = W.tiny_case(case["seed"], dims=case["dims"], periodic=case["periodic"],
+                          n_particles=case["n_particles"], diameter_range=(4.0, 7.0),
+                          speed=0.06, spin=0.006, u0=(0.02, -0.01, 0.005))
+    r = _run(lat, ps, storage, 6, exact_forces=True, tag="exact")
+    assert r["pop_err"] <= POP_TOL[storage] and r["F"] <= FORCE_TOL[storage] \
+        and r["T"] <= FORCE_TOL[storage], r
+
+
+def _force_series(lat, ps, steps, exact):
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32", treatments=11, exact_forces=exact)
+    parts = B.DeviceParticles(ps)
+    out = []
+    for n in range(steps):
+        parts.set_state(W.prescribed_state(ps, lat, float(n)))
+        gpu.classify(parts)
+        gpu.step(parts)
+        F, T = gpu.forces()
+        out.append(np.concatenate([F.cpu().numpy(), T.cpu().numpy()], 1))
+    gpu.close()
+    return np.array(out)
+
+
+def test_exact_force_sum_repeats_bit_for_bit():
+    """Sixty bodies on a 128^3 lattice, hundreds of link workgroups per body:
+    two contexts with exact sums give the same bits every step (the link
+    lists' order comes from atomics and differs between them).  The FP64
+    atomic sums differ from them by their own rounding, which the cancellation
+    between a body's link terms (each ~0.1, the net force ~1e-4) magnifies
+    relative to the force: bounded here far inside the FP32 storage bar."""
+    lat, ps, _ = W.config_c3(n_particles=60, n=128)
+    a = _force_series(lat, ps, 3, True)
+    b = _force_series(lat, ps, 3, True)
+    c = _force_series(lat, ps, 3, False)
+    assert np.array_equal(a, b)
+    scale = np.abs(c).max(axis=(0, 2), keepdims=True)
+    err = (np.abs(a - c) / scale).max()
+    print(f"exact vs atomic sums: largest difference {err:.3e} of the body's force scale")
+    assert err <= 1e-8, err
