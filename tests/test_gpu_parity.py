@@ -32,6 +32,10 @@ def _compare_geometry(gpu, ora, tag):
     assert np.array_equal(L["kind"], R.kind), tag
     assert np.array_equal(L["part"], R.part), tag
     assert np.array_equal(L["q"].view(np.uint64), R.q.view(np.uint64)), f"{tag}: q not bit-exact"
+    # no two reconstructing links write the same ghost slot (node, d-bar)
+    w = L["kind"] != B.LINK_MISSING
+    key = L["node"][w].astype(np.int64) * 32 + L["d"][w]
+    assert np.unique(key).size == key.size, f"{tag}: two links write one ghost slot"
     nodes, parts = gpu.refill()
     assert np.array_equal(nodes, ora.refill_nodes), f"{tag}: refill sets differ"
     if len(nodes):
@@ -575,22 +579,30 @@ def _force_series(lat, ps, steps, exact):
         gpu.step(parts)
         F, T = gpu.forces()
         out.append(np.concatenate([F.cpu().numpy(), T.cpu().numpy()], 1))
+    geo = (gpu.owner(), gpu.links(), gpu.refill())
     gpu.close()
-    return np.array(out)
+    return np.array(out), geo
 
 
 def test_exact_force_sum_repeats_bit_for_bit():
     """Sixty bodies on a 128^3 lattice, hundreds of link workgroups per body:
-    two contexts with exact sums give the same bits every step (the link
+    two contexts give the same owners, links and refill set, and with exact
+    sums the same force and torque bits every step (the link
     lists' order comes from atomics and differs between them).  The FP64
     atomic sums differ from them by their own rounding, which the cancellation
     between a body's link terms (each ~0.1, the net force ~1e-4) magnifies
     relative to the force: bounded here far inside the FP32 storage bar."""
     lat, ps, _ = W.config_c3(n_particles=60, n=128)
-    a = _force_series(lat, ps, 3, True)
-    b = _force_series(lat, ps, 3, True)
-    c = _force_series(lat, ps, 3, False)
+    a, ga = _force_series(lat, ps, 3, True)
+    b, gb = _force_series(lat, ps, 3, True)
+    c, _ = _force_series(lat, ps, 3, False)
     assert np.array_equal(a, b)
+    # the geometry of the last classification repeats too (lists compared in
+    # canonical order; their order in memory comes from atomics)
+    assert np.array_equal(ga[0], gb[0])
+    for k in ga[1]:
+        assert np.array_equal(ga[1][k].view(np.uint8), gb[1][k].view(np.uint8)), k
+    assert np.array_equal(ga[2][0], gb[2][0]) and np.array_equal(ga[2][1], gb[2][1])
     scale = np.abs(c).max(axis=(0, 2), keepdims=True)
     err = (np.abs(a - c) / scale).max()
     print(f"exact vs atomic sums: largest difference {err:.3e} of the body's force scale")

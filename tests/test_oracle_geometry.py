@@ -132,6 +132,12 @@ def test_links_cover_wrap_walls_and_gaps():
         o = O.Oracle(lat)
         o.classify(ps)
         kinds += np.bincount(o.links.kind, minlength=3)
+        # every link that reconstructs writes ghost slot d-bar of its solid
+        # node x_s, and that slot is pulled by x_s - e_d alone: no two
+        # writing links share a (node, d)
+        w = o.links.kind != 2
+        key = o.links.node[w].astype(np.int64) * 32 + o.links.d[w]
+        assert np.unique(key).size == key.size
     assert np.all(kinds > 0), kinds
 
 
