@@ -174,6 +174,41 @@ def test_dem_cell_grid_dense_spheres():
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
 
 
+def test_dem_cell_grid_thin_periodic_axis():
+    """2048 spheres in two sheets on a periodic axis only 15 nodes long, so the
+    grid has two cells along it and both neighbours of a cell are the same
+    cell (visited once, or every pair across it would be listed twice);
+    contacts across the sheets and across the periodic y faces."""
+    rng = np.random.default_rng(31)
+    sh = W.sphere_shape(5.2, 0.1)
+    y = (np.arange(32) + 0.5) * 5.0
+    z = 4.0 + 5.0 * np.arange(32)
+    Y, Z = np.meshgrid(y, z, indexing="ij")
+    pos = np.concatenate([np.stack([np.full(Y.size, x0), Y.ravel(), Z.ravel()], -1)
+                          for x0 in (3.0, 8.0)])
+    pos = pos + rng.normal(size=pos.shape) * 0.15
+    n = len(pos)
+    ps = W.make_particles([sh] * n, pos, np.array([W.random_quaternion(rng) for _ in range(n)]),
+                          1.5)
+    ps = _moving(ps, 32, 0.02, 0.002)
+    lat = W.LatticeSpec(15, 160, 167, (1, 1, 0), tau=0.6)
+    kw = W.dem_defaults(ps, gravity=(0.0, 0.0, -1e-4))
+    gpu = B.Lattice.for_particles(lat, ps, storage="f32")
+    parts = B.DeviceParticles(ps)
+    dem = O.OracleDEM(ps, lat)
+    P = ps.copy()
+    zero = np.zeros((n, 3))
+    for _ in range(6):
+        gpu.dem(parts, 10, 0.1, B.DemParams.make(**kw))
+        dem.step(P, zero, zero, O.DemParams(**kw), 10, 0.1)
+    G = parts.to_host(ps)
+    gpu.close()
+    assert np.abs(P.pos - ps.pos).max() > 1e-3
+    for k in ("pos", "vel", "omega", "quat", "world_pts"):
+        a, b = getattr(G, k), getattr(P, k)
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
+
+
 # ---------------------------------------------------------------------------
 # long replay runs against the oracle's stored series
 # (tests/golden/make_drag_reference.py writes them with the oracle alone)
