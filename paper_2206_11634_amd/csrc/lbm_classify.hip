@@ -622,7 +622,7 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
     const uint32_t chunk = 4u * cpw;  // candidates of one workgroup per round
     for (uint32_t base0 = bx * chunk; base0 < count; base0 += gx * chunk) {
         const uint32_t k = base0 + (threadIdx.x >> 6) * cpw + (uint32_t)lane;
-        uint32_t node = 0, mask = 0;
+        uint32_t node = 0, mask = 0, fmask = 0;  // link directions; those with x_f fluid
         int c[3] = {0, 0, 0};
         double X = 0.0, Y = 0.0, Z = 0.0;
         if ((uint32_t)lane < cpw && k < count) {
@@ -652,6 +652,7 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
                     if (ok && on == (uint32_t)p) continue;
                     if (ok && on == kFluid) {
                         mask |= 1u << d;
+                        fmask |= 1u << d;
                     } else if (treat & LBM_TREAT_MISSING) {
                         const double Mn = metaball(sp, n, X - cx(d), Y - cy(d), Z - cz(d));
                         if (Mn < c0) mask |= 1u << d;
@@ -691,13 +692,14 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
             const int sc[3] = {__shfl(c[0], src, 64), __shfl(c[1], src, 64), __shfl(c[2], src, 64)};
             const double sX = __shfl(X, src, 64), sY = __shfl(Y, src, 64), sZ = __shfl(Z, src, 64);
             const double sMs = __shfl(Ms, src, 64);
+            const uint32_t sfmask = __shfl(fmask, src, 64);
             if (j < total) {
                 const int ex = cx(d), ey = cy(d), ez = cz(d);
                 const double Mn = metaball(sp, n, sX - ex, sY - ey, sZ - ez);
-                int cn[3];
-                const bool ok = neighbour(sc, ex, ey, ez, g, cn);
                 int kind = LBM_LINK_MISSING;
-                if (ok && own[node_idx(cn, g)] == kFluid) {
+                if ((sfmask >> d) & 1u) {  // x_f exists and is fluid
+                    int cn[3];
+                    neighbour(sc, ex, ey, ez, g, cn);
                     int cff[3];
                     const bool okf = neighbour(cn, ex, ey, ez, g, cff);
                     const bool ff = okf && own[node_idx(cff, g)] == kFluid;
