@@ -360,16 +360,18 @@ __global__ __launch_bounds__(256, 8) void k_mark(const uint32_t* __restrict__ er
         sf[i] = make_float4((float)(sp[4 * i + 0] - (double)ox), (float)(sp[4 * i + 1] - (double)oy),
                             (float)(dz * dz), (float)sp[4 * i + 3]);
     }
-    // row table: thread t takes rows 4t .. 4t + 3
+    // row table: thread t takes rows rpt t .. rpt t + rpt - 1, rpt = 1 for
+    // S <= 256 (so every wave shares the FP64 row bounds), up to 4
+    const int rpt = (S + 255) >> 8;
     const double dzc = (double)zi - bz;
     const double r2z = R * R - dzc * dzc;
     int len[4];
     int tsum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int r = 4 * (int)threadIdx.x + k;
+        const int r = rpt * (int)threadIdx.x + k;
         len[k] = 0;
-        if (r < S && r2z >= 0.0) {
+        if (k < rpt && r < S && r2z >= 0.0) {
             const int yi = oy - h + r;
             const double dyc = (double)yi - by;
             const double r2x = r2z - dyc * dyc;
@@ -413,8 +415,8 @@ __global__ __launch_bounds__(256, 8) void k_mark(const uint32_t* __restrict__ er
     const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int r = 4 * (int)threadIdx.x + k;
-        if (r < S) rstart[r] = off;
+        const int r = rpt * (int)threadIdx.x + k;
+        if (k < rpt && r < S) rstart[r] = off;
         off += len[k];
     }
     if (threadIdx.x == 0) {
