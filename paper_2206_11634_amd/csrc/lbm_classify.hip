@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
     const int p = (int)by;
     const int n = stage_ctrl(P, p, sp);
     const double c0 = P.c0[p];
-    const double* B = ball + 4 * p;
+    const double B[3] = {ball[4 * p], ball[4 * p + 1], ball[4 * p + 2]};  // loaded once
     const uint32_t* list = cand + (int64_t)p * cand_cap;
     const uint32_t count = min((uint32_t)cand_cap, cand_cursors[(int64_t)p * kCursorPad]);
     LinkRec* out = links + loff[p];
@@ -645,12 +645,24 @@ __global__ __launch_bounds__(256, 6) void k_links(const uint32_t* __restrict__ e
                 Xc[a] = v;
             }
             X = Xc[0], Y = Xc[1], Z = Xc[2];
-            if (own[node] == (uint32_t)p) {
+            // the node's owner and its neighbours' in one batch of loads
+            // (each from a valid address), before any branch on them
+            const uint32_t self = own[node];
+            uint32_t onv[kQ];
+            uint32_t okm = 0;
+#pragma unroll
+            for (int d = 1; d < kQ; ++d) {
+                int cn[3];
+                const bool ok = neighbour(c, cx(d), cy(d), cz(d), g, cn);
+                const uint32_t v = own[ok ? node_idx(cn, g) : node];
+                okm |= ok ? 1u << d : 0u;
+                onv[d] = ok ? v : kFluid;
+            }
+            if (self == (uint32_t)p) {
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
-                    int cn[3];
-                    const bool ok = neighbour(c, cx(d), cy(d), cz(d), g, cn);
-                    const uint32_t on = ok ? own[node_idx(cn, g)] : kFluid;
+                    const bool ok = (okm >> d) & 1u;
+                    const uint32_t on = onv[d];
                     if (ok && on == (uint32_t)p) continue;
                     if (ok && on == kFluid) {
                         mask |= 1u << d;
