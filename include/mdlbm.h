@@ -282,7 +282,10 @@ int lbm_particle_forces(const lbm_ctx* ctx, double* F_dev, double* T_dev);
  * linear spring-dashpot normal force and a Coulomb-limited tangential spring.
  * Updates P->pos, quat, vel, omega and world_pts in place and the contact
  * histories held by the context (allocated by lbm_init: 32 pair records per
- * particle, for its candidate partners of higher index, and one per wall).
+ * particle, for its candidate partners of higher index, and one per wall;
+ * from 2048 particles on also a cell grid of at most max(4096, 4 n) cells
+ * for the broad phase, which then tests only the 27 cells around each
+ * particle instead of every pair: the same candidates either way).
  * EINVAL on n_sub < 1 or dt <= 0.  A particle with more than 32 candidate
  * partners in one call (centres within the bodies' reach plus the call's
  * displacement) has the extra pairs left out; that is latched and reported
