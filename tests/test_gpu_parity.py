@@ -106,9 +106,9 @@ TREAT_TIMED = B.TREAT_VIBB | B.TREAT_MISSING | B.TREAT_NEQ_SPLIT   # the 512^3 w
 @pytest.mark.parametrize("treat", [TREAT_PLAIN, TREAT_TIMED], ids=["bits3", "bits11"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_deviation_storage_parity(storage, treat, classify):
-    """With the lattice sweep the collision writes moments only in the band
-    the next link step reads (links outside it take them from the
-    populations); with ball walks it writes them everywhere."""
+    """FP32 and FP16 deviation storage against the FP64 oracle under both
+    classification schemes and both treatment sets (bits 1+2, and 1+2+8 as
+    the 512^3 workload runs)."""
     lat, ps = W.tiny_case(7, dims=(28, 22, 27), periodic=(1, 0, 1), n_particles=4,
                           diameter_range=(5.0, 8.0), speed=0.05, spin=0.005,
                           u0=(0.03, 0.0, 0.01), body_force=(1e-5, 0.0, 0.0))
@@ -556,15 +556,15 @@ def test_dem_more_candidate_partners_than_history_records_is_reported():
     gpu.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_exact_force_sum_matches_oracle(storage):
+@pytest.mark.parametrize("storage,lattice", [("f64", 19), ("f32", 19), ("f16", 19), ("f32", 15)])
+def test_exact_force_sum_matches_oracle(storage, lattice):
     """LBM_FORCE_SUM_EXACT: the same per-link terms summed in 128-bit
     integers; forces, torques and populations within the storage's bars."""
     case = GEOM_CASES[1]
     lat, ps = W.tiny_case(case["seed"], dims=case["dims"], periodic=case["periodic"],
                           n_particles=case["n_particles"], diameter_range=(4.0, 7.0),
                           speed=0.06, spin=0.006, u0=(0.02, -0.01, 0.005))
-    r = _run(lat, ps, storage, 6, exact_forces=True, tag="exact")
+    r = _run(lat, ps, storage, 6, exact_forces=True, tag="exact", lattice=lattice)
     assert r["pop_err"] <= POP_TOL[storage] and r["F"] <= FORCE_TOL[storage] \
         and r["T"] <= FORCE_TOL[storage], r
 
