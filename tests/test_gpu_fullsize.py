@@ -141,13 +141,15 @@ def test_c4_dem_full_size():
         assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), k
 
 
-def test_dem_cell_grid_dense_spheres():
-    """2548 spheres (d = 5.2) on a jittered 5-unit lattice filling a 70^3 box
-    periodic in x and y: every body presses on its neighbours, across the
-    periodic faces too, so the broad phase on the cell grid (taken from 2048
-    particles on) must find the same pairs as the oracle's all-pairs test."""
+@pytest.mark.parametrize("periodic", [(1, 1, 0), (0, 0, 0)], ids=["xy_periodic", "walls"])
+def test_dem_cell_grid_dense_spheres(periodic):
+    """2548 spheres (d = 5.2) on a jittered 5-unit lattice filling a 70^3 box,
+    periodic in x and y or walled on every side: every body presses on its
+    neighbours (across the periodic faces too), so the broad phase on the
+    cell grid (taken from 2048 particles on) must find the same pairs as the
+    oracle's all-pairs test."""
     rng = np.random.default_rng(21)
-    lat = W.LatticeSpec(70, 70, 70, (1, 1, 0), tau=0.6)
+    lat = W.LatticeSpec(70, 70, 70, periodic, tau=0.6)
     sh = W.sphere_shape(5.2, 0.1)
     g = (np.arange(14) + 0.5) * 5.0
     z = 4.0 + 5.0 * np.arange(13)
