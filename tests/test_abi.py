@@ -146,3 +146,38 @@ def test_calls_reject_a_null_context_without_touching_the_device(lib):
     assert lib.lbm_geometry_bytes(None, ctypes.byref(n), ctypes.byref(tag)) == B.LBM_EINVAL
     assert lib.lbm_geometry_save(None, None) == B.LBM_EINVAL
     assert lib.lbm_geometry_load(None, None, 0, ctypes.byref(p)) == B.LBM_EINVAL
+
+
+# the binding's ctypes mirrors of the header's structs, field by field
+STRUCTS = {
+    "lbm_config": B.LbmConfig, "lbm_sizes": B.LbmSizes, "lbm_buffers": B.LbmBuffers,
+    "lbm_particles": B.LbmParticles, "lbm_counts": B.LbmCounts, "dem_params": B.DemParams,
+    "lbm_profile": B.LbmProfile,
+}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Compile a C program against include/mdlbm.h that prints sizeof and
+    every field's offsetof, and compare with the ctypes structures."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mdlbm.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
