@@ -333,7 +333,7 @@ int dem_alloc(lbm_ctx* c)
         // counts and starts, cursors, the binned particles, the grid's shape
         c->grid_cap = (int64_t)std::max<size_t>(4096, 4 * np);
         const size_t words = 2 * (size_t)c->grid_cap + 1 + np + 4;
-        if (alloc(&c->grid, words) != hipSuccess || alloc(&c->grid_size, 3) != hipSuccess)
+        if (alloc(&c->grid, words) != hipSuccess || alloc(&c->grid_size, 4) != hipSuccess)
             return fail(c, LBM_ENOMEM, "broad-phase grid allocation failed");
     }
     return LBM_OK;

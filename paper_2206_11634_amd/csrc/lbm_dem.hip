@@ -559,6 +559,7 @@ __global__ __launch_bounds__(1024) void k_grid_setup(PartDev P, double T, Geom g
             gdim[a] = nc[a];
             gsize[a] = (double)g.n[a] / (double)nc[a];
         }
+        gsize[3] = H;
         gdim[3] = (int32_t)total;
         ncell = (int)total;
     }
@@ -653,13 +654,27 @@ __global__ __launch_bounds__(256) void k_pairs_grid(PartDev P, int32_t* key, dou
     int ax[3][3], na[3];
     for (int a = 0; a < 3; ++a) na[a] = around(c3[a], gdim[a], g.per[a], ax[a]);
     int32_t* ki = key + (int64_t)i * kPairSlots;
+    // every accepted pair lies within H (gsize[3]): a cheaper distance test
+    // first, then pair_candidate's own decision
+    const double hb2 = gsize[3] * gsize[3];
     for (int u = 0; u < na[2]; ++u)
         for (int t = 0; t < na[1]; ++t)
             for (int s = 0; s < na[0]; ++s) {
                 const int cell = ax[0][s] + gdim[0] * (ax[1][t] + gdim[1] * ax[2][u]);
                 for (uint32_t k = gstart[cell]; k < gstart[cell + 1]; ++k) {
                     const int j = (int)gitem[k];
-                    if (j <= i || !pair_candidate(P, i, j, T, g)) continue;
+                    if (j <= i) continue;
+                    double d2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double d = P.pos[3 * j + a] - P.pos[3 * i + a];
+                        if (g.per[a]) {
+                            const double L = g.n[a];
+                            if (d > 0.5 * L) d -= L;
+                            else if (d < -0.5 * L) d += L;
+                        }
+                        d2 += d * d;
+                    }
+                    if (!(d2 <= hb2) || !pair_candidate(P, i, j, T, g)) continue;
                     int slot = -1;
                     for (int q = 0; q < kPairSlots && slot < 0; ++q)
                         if (ki[q] == j + 1) slot = q;

@@ -311,7 +311,7 @@ struct DemScratch {
     uint32_t* gcursor = nullptr;  // [gcap]
     uint32_t* gitem = nullptr;    // [n]: particles by cell
     int32_t* gdim = nullptr;      // cells per axis, and their product
-    double* gsize = nullptr;      // cell widths
+    double* gsize = nullptr;      // cell widths, then H (the largest accepted distance)
     int64_t gcap = 0;             // cells the arrays hold
 };
 // Particle counts from which dem_step uses the cell grid.
